@@ -1,0 +1,231 @@
+"""Python access to the CPU oracle (``skim_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: the reference the HIP library is checked against.
+Only the tests, the smoke check and the bench's CPU-baseline leg may import
+this package.  It shares no code with the HIP path.
+
+Every function takes a ``workloads.Graph``-like object (n, row_ptr, col, thr)
+and numpy arrays; results come back as numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "skim_oracle.c")
+_LIB = os.path.join(_HERE, "libskim_oracle.so")
+
+UINT64_MAX = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (IEEE doubles: no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-fPIC", "-shared", "-pthread",
+                               "-fno-fast-math", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class BuildCounters(C.Structure):
+    _fields_ = [("n_ins", C.c_uint64), ("w_live", C.c_uint64),
+                ("n_exp", C.c_uint64), ("c_min", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+class SkimCounters(C.Structure):
+    _fields_ = [("insertions", C.c_uint64), ("pairs_scanned", C.c_uint64),
+                ("reverse_bfs", C.c_uint64), ("covered", C.c_uint64),
+                ("decrements", C.c_uint64), ("fallback", C.c_uint64)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
+
+
+_lib = None
+P64 = C.POINTER(C.c_uint64)
+P32 = C.POINTER(C.c_uint32)
+PI32 = C.POINTER(C.c_int32)
+PD = C.POINTER(C.c_double)
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = C.CDLL(_LIB)
+        lib.or_sm64.restype = C.c_uint64
+        lib.or_sm64.argtypes = [C.c_uint64, C.c_uint64]
+        lib.or_rank.restype = C.c_uint64
+        lib.or_rank.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32]
+        lib.or_live.restype = C.c_int
+        lib.or_live.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32,
+                                C.c_uint32]
+        lib.or_ranks.restype = None
+        lib.or_ranks.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, P64]
+        lib.or_live_batch.restype = None
+        lib.or_live_batch.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, P32, P32, P32, P32,
+                                      C.POINTER(C.c_uint8)]
+        lib.or_influence.restype = C.c_uint64
+        lib.or_influence.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32, P32,
+                                     C.c_uint64, P64]
+        lib.or_sketch_brute.restype = None
+        lib.or_sketch_brute.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32,
+                                        C.c_uint32, P32, C.c_uint64, P64, P32, P64]
+        lib.or_build_alg2.restype = C.c_int
+        lib.or_build_alg2.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32,
+                                      C.c_uint32, C.c_uint32, P64, P32, C.POINTER(BuildCounters)]
+        lib.or_estimates.restype = None
+        lib.or_estimates.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, P64, P32, PD]
+        for fn in (lib.or_union_query, lib.or_ck_query):
+            fn.restype = None
+            fn.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, P64, P32, C.c_uint64, P64, P32,
+                           PD, PI32]
+        lib.or_skim.restype = C.c_int
+        lib.or_skim.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32, C.c_uint32,
+                                C.c_uint32, P32, P64, C.POINTER(SkimCounters)]
+        _lib = lib
+    return _lib
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def _g(g):
+    rp = np.ascontiguousarray(g.row_ptr, dtype=np.uint64)
+    col = np.ascontiguousarray(g.col, dtype=np.uint32)
+    thr = np.ascontiguousarray(g.thr, dtype=np.uint32)
+    if col.size == 0:  # keep valid pointers for empty graphs
+        col = np.zeros(1, dtype=np.uint32)
+        thr = np.zeros(1, dtype=np.uint32)
+    return rp, col, thr
+
+
+def sm64(seed: int, counter: int) -> int:
+    return int(_load().or_sm64(seed, counter))
+
+
+def rank(seed: int, v: int, i: int) -> int:
+    return int(_load().or_rank(seed, v, i))
+
+
+def live(seed: int, n: int, u: int, v: int, i: int, thr: int) -> bool:
+    return bool(_load().or_live(seed, n, u, v, i, thr))
+
+
+def ranks(seed: int, n: int, ell: int) -> np.ndarray:
+    """All ranks r(v, i) as an [n, l] uint64 array."""
+    out = np.empty(n * ell, dtype=np.uint64)
+    _load().or_ranks(seed, n, ell, _p(out, P64))
+    return out.reshape(n, ell)
+
+
+def live_batch(seed: int, n: int, u, v, inst, thr) -> np.ndarray:
+    """Live-edge coins for arrays of (u, v, i, thr)."""
+    u = np.ascontiguousarray(u, dtype=np.uint32)
+    v = np.ascontiguousarray(v, dtype=np.uint32)
+    inst = np.ascontiguousarray(inst, dtype=np.uint32)
+    thr = np.ascontiguousarray(np.broadcast_to(thr, u.shape), dtype=np.uint32)
+    out = np.empty(u.size, dtype=np.uint8)
+    _load().or_live_batch(seed, n, u.size, _p(u, P32), _p(v, P32), _p(inst, P32), _p(thr, P32),
+                          out.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return out.astype(bool)
+
+
+def influence(g, seed: int, ell: int, S, per_instance: bool = False):
+    """l * Inf({G^(i)}, S) as an exact integer (and per-instance counts)."""
+    rp, col, thr = _g(g)
+    S = np.ascontiguousarray(S, dtype=np.uint32)
+    Sp = S if S.size else np.zeros(1, dtype=np.uint32)
+    per = np.zeros(max(ell, 1), dtype=np.uint64)
+    tot = _load().or_influence(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell,
+                               _p(Sp, P32), S.size, _p(per, P64))
+    return (int(tot), per[:ell]) if per_instance else int(tot)
+
+
+def sketch_brute(g, seed: int, ell: int, k: int, nodes=None):
+    """Sketches by the plain definition, for the given nodes (default all)."""
+    rp, col, thr = _g(g)
+    nodes = np.arange(g.n, dtype=np.uint32) if nodes is None else \
+        np.ascontiguousarray(nodes, dtype=np.uint32)
+    ranks = np.empty(nodes.size * k, dtype=np.uint64)
+    size = np.empty(nodes.size, dtype=np.uint32)
+    reach = np.empty(nodes.size, dtype=np.uint64)
+    _load().or_sketch_brute(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell, k,
+                            _p(nodes, P32), nodes.size, _p(ranks, P64), _p(size, P32),
+                            _p(reach, P64))
+    return ranks.reshape(nodes.size, k), size, reach
+
+
+def build_alg2(g, seed: int, ell: int, k: int, threads: int | None = None):
+    """Sketches of every node by Algorithm 2 -> (ranks[n,k], size[n], counters)."""
+    rp, col, thr = _g(g)
+    ranks = np.empty(g.n * k, dtype=np.uint64)
+    size = np.empty(g.n, dtype=np.uint32)
+    cnt = BuildCounters()
+    if threads is None:
+        threads = os.cpu_count() or 1
+    rc = _load().or_build_alg2(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell, k,
+                               threads, _p(ranks, P64), _p(size, P32), C.byref(cnt))
+    if rc != 0:
+        raise ValueError("or_build_alg2: bad arguments")
+    return ranks.reshape(g.n, k), size, cnt.as_dict()
+
+
+def estimates(ranks: np.ndarray, size: np.ndarray, k: int, ell: int) -> np.ndarray:
+    n = size.shape[0]
+    r = np.ascontiguousarray(ranks, dtype=np.uint64).reshape(-1)
+    s = np.ascontiguousarray(size, dtype=np.uint32)
+    out = np.empty(n, dtype=np.float64)
+    _load().or_estimates(n, k, ell, _p(r, P64), _p(s, P32), _p(out, PD))
+    return out
+
+
+def _query(fn, ranks, size, k, ell, offsets, nodes):
+    n = size.shape[0]
+    r = np.ascontiguousarray(ranks, dtype=np.uint64).reshape(-1)
+    s = np.ascontiguousarray(size, dtype=np.uint32)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nd = np.ascontiguousarray(nodes, dtype=np.uint32)
+    if nd.size == 0:
+        nd = np.zeros(1, dtype=np.uint32)
+    Q = off.size - 1
+    est = np.empty(max(Q, 1), dtype=np.float64)
+    st = np.empty(max(Q, 1), dtype=np.int32)
+    fn(n, k, ell, _p(r, P64), _p(s, P32), Q, _p(off, P64), _p(nd, P32), _p(est, PD),
+       _p(st, PI32))
+    return est[:Q], st[:Q]
+
+
+def union_query(ranks, size, k, ell, offsets, nodes):
+    """Bottom-k-of-the-union estimates (divided by l) and per-query status."""
+    return _query(_load().or_union_query, ranks, size, k, ell, offsets, nodes)
+
+
+def ck_query(ranks, size, k, ell, offsets, nodes):
+    """Cohen-Kaplan union estimates (divided by l) and per-query status."""
+    return _query(_load().or_ck_query, ranks, size, k, ell, offsets, nodes)
+
+
+def skim(g, seed: int, ell: int, k: int, s: int):
+    """SKIM seeds, exact newly-covered pair counts, counters."""
+    rp, col, thr = _g(g)
+    seeds = np.zeros(max(s, 1), dtype=np.uint32)
+    gain = np.zeros(max(s, 1), dtype=np.uint64)
+    cnt = SkimCounters()
+    rc = _load().or_skim(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell, k, s,
+                         _p(seeds, P32), _p(gain, P64), C.byref(cnt))
+    if rc == -1:
+        raise ValueError("or_skim: bad arguments")
+    if rc == -2:
+        raise AssertionError("or_skim: reverse search met a covered pair")
+    return seeds[:s], gain[:s], cnt.as_dict()

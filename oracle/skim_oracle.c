@@ -1,0 +1,665 @@
+/*
+ * skim_oracle.c -- plain, slow, obviously-correct CPU oracle for
+ * sketch-based influence computation (Cohen, Delling, Pajor, Werneck,
+ * "Sketch-based Influence Maximization and Computation", 2014).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the reference the HIP library is
+ * checked against.  Only the test suite, the smoke check and the bench's CPU
+ * baseline may load it.  It shares no code, header or table with the HIP
+ * path; the two meet only by comparing outputs.
+ *
+ * Conventions fixed here (the paper leaves them open; both sides implement
+ * them independently):
+ *
+ *  - Randomness is SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output c
+ *    (c = 0, 1, ...) of the stream seeded with s is mix64(s + (c+1)*GAMMA),
+ *    GAMMA = 0x9E3779B97F4A7C15, where mix64 is Stafford's "variant 13"
+ *    finaliser (xor-shift 30, multiply, xor-shift 27, multiply, xor-shift 31).
+ *  - Rank of node-instance pair (v, i): r(v,i) = SM(seed, 64*v + i), a uint64.
+ *    mix64 is a bijection and GAMMA is odd, so all ranks are distinct; the
+ *    paper's U[0,1] rank (Section 3) is the real reading of this integer.
+ *  - Live edge (u -> v) in instance i (binary IC, Section 1 and 2):
+ *    h = SM(seed, 2^62 + 32*(u*n + v) + floor(i/2)); the 32-bit coin is the
+ *    high half of h for even i and the low half for odd i; the edge is live
+ *    iff coin <= thr, so P[live] = (thr + 1) / 2^32.
+ *  - Estimate from threshold rank T: rho(T) = ((T >> 11) + 1) * 2^-53.
+ *
+ * Functions and the passages they follow:
+ *   or_sm64, or_rank, or_live ............. Section 3 (random ranks), Section 1
+ *                                          (binary IC live edges)
+ *   or_influence .......................... Section 2, eq. (Inf) and (timedinf)
+ *   or_sketch_brute ....................... Section 3, eq. (combinedrs): the
+ *                                          plain definition, by forward search
+ *   or_build_alg2 ......................... Section 5.2, Algorithm 2
+ *   or_estimates .......................... Section 3, eq. (combinedthresh) and
+ *                                          the bottom-k estimator; Section 5.1
+ *                                          (divide by l)
+ *   or_union_query ........................ Section 5.1, bottom-k of the union
+ *   or_ck_query ........................... Section 5.1, eq. (unionest)
+ *   or_skim ............................... Section 4, Algorithm 1
+ *
+ * Parameter limits: 1 <= l <= 64, k >= 1, n < 2^27.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define OR_GAMMA 0x9E3779B97F4A7C15ULL
+#define OR_EDGE_BASE (1ULL << 62)
+#define OR_NONE UINT64_MAX
+
+/* ---------------------------------------------------------------- random */
+
+static uint64_t or_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+uint64_t or_sm64(uint64_t seed, uint64_t counter)
+{
+    return or_mix64(seed + (counter + 1) * OR_GAMMA);
+}
+
+uint64_t or_rank(uint64_t seed, uint32_t v, uint32_t i)
+{
+    return or_sm64(seed, (uint64_t)v * 64 + i);
+}
+
+int or_live(uint64_t seed, uint32_t n, uint32_t u, uint32_t v, uint32_t i, uint32_t thr)
+{
+    uint64_t key = (uint64_t)u * n + v;
+    uint64_t h = or_sm64(seed, OR_EDGE_BASE + key * 32 + (i >> 1));
+    uint32_t coin = (i & 1) ? (uint32_t)h : (uint32_t)(h >> 32);
+    return coin <= thr;
+}
+
+/* All ranks, node-major: out[v*l + i] = r(v, i). */
+void or_ranks(uint64_t seed, uint32_t n, uint32_t ell, uint64_t *out)
+{
+    for (uint32_t v = 0; v < n; v++)
+        for (uint32_t i = 0; i < ell; i++) out[(uint64_t)v * ell + i] = or_rank(seed, v, i);
+}
+
+/* Live-edge coins for a batch of (u, v, i, thr) tuples. */
+void or_live_batch(uint64_t seed, uint32_t n, uint64_t cnt, const uint32_t *u,
+                   const uint32_t *v, const uint32_t *inst, const uint32_t *thr, uint8_t *out)
+{
+    for (uint64_t j = 0; j < cnt; j++) out[j] = (uint8_t)or_live(seed, n, u[j], v[j], inst[j], thr[j]);
+}
+
+/* ---------------------------------------------------------------- graph */
+
+typedef struct {
+    uint32_t n;
+    const uint64_t *row_ptr; /* [n+1] forward CSR */
+    const uint32_t *col;     /* heads */
+    const uint32_t *thr;     /* thresholds aligned with col */
+} or_graph;
+
+/* ------------------------------------------- influence by forward search */
+
+/* Nodes reached from the set S in instance i (Section 2: u in S counts). */
+static uint64_t reach_count(const or_graph *g, uint64_t seed, uint32_t i,
+                            const uint32_t *S, uint64_t ns, uint8_t *seen, uint32_t *queue)
+{
+    uint64_t head = 0, tail = 0;
+    for (uint64_t j = 0; j < ns; j++) {
+        uint32_t s = S[j];
+        if (!seen[s]) { seen[s] = 1; queue[tail++] = s; }
+    }
+    while (head < tail) {
+        uint32_t u = queue[head++];
+        for (uint64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++) {
+            uint32_t v = g->col[e];
+            if (!seen[v] && or_live(seed, g->n, u, v, i, g->thr[e])) {
+                seen[v] = 1;
+                queue[tail++] = v;
+            }
+        }
+    }
+    for (uint64_t j = 0; j < tail; j++) seen[queue[j]] = 0;
+    return tail;
+}
+
+/* sum over instances of |reach_i(S)|, i.e. l * Inf({G^(i)}, S); per-instance
+ * counts go to per_inst[l] when it is not NULL.  Returns 0 on bad input. */
+uint64_t or_influence(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                      const uint32_t *thr, uint64_t seed, uint32_t ell,
+                      const uint32_t *S, uint64_t ns, uint64_t *per_inst)
+{
+    or_graph g = {n, row_ptr, col, thr};
+    for (uint64_t j = 0; j < ns; j++) if (S[j] >= n) return 0;
+    uint8_t *seen = calloc(n ? n : 1, 1);
+    uint32_t *queue = malloc(sizeof(uint32_t) * (n ? n : 1));
+    uint64_t total = 0;
+    for (uint32_t i = 0; i < ell; i++) {
+        uint64_t c = reach_count(&g, seed, i, S, ns, seen, queue);
+        if (per_inst) per_inst[i] = c;
+        total += c;
+    }
+    free(seen);
+    free(queue);
+    return total;
+}
+
+/* ------------------------------------------------ sketches by definition */
+
+static int cmp_u64(const void *a, const void *b)
+{
+    uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* X_u = the k smallest ranks r(v,i) over all (v,i) with u ~>_i v
+ * (eq. combinedrs), computed by a full forward search in every instance.
+ * out_ranks[j*k .. j*k+k) ascending, padded with UINT64_MAX; out_size[j] =
+ * min(k, |R_u|); out_reach[j] (may be NULL) = |R_u|. */
+void or_sketch_brute(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                     const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
+                     const uint32_t *nodes, uint64_t nq,
+                     uint64_t *out_ranks, uint32_t *out_size, uint64_t *out_reach)
+{
+    or_graph g = {n, row_ptr, col, thr};
+    uint8_t *seen = calloc(n, 1);
+    uint32_t *queue = malloc(sizeof(uint32_t) * n);
+    uint64_t cap = 1024, cnt;
+    uint64_t *all = malloc(sizeof(uint64_t) * cap);
+    for (uint64_t j = 0; j < nq; j++) {
+        uint32_t u = nodes[j];
+        cnt = 0;
+        for (uint32_t i = 0; i < ell; i++) {
+            uint64_t reached = reach_count(&g, seed, i, &u, 1, seen, queue);
+            /* reach_count leaves the reached nodes in queue[0..reached) */
+            if (cnt + reached > cap) {
+                while (cnt + reached > cap) cap *= 2;
+                all = realloc(all, sizeof(uint64_t) * cap);
+            }
+            for (uint64_t t = 0; t < reached; t++) all[cnt++] = or_rank(seed, queue[t], i);
+        }
+        qsort(all, cnt, sizeof(uint64_t), cmp_u64);
+        uint32_t s = (uint32_t)(cnt < k ? cnt : k);
+        for (uint32_t t = 0; t < k; t++) out_ranks[j * k + t] = t < s ? all[t] : OR_NONE;
+        out_size[j] = s;
+        if (out_reach) out_reach[j] = cnt;
+    }
+    free(all);
+    free(seen);
+    free(queue);
+}
+
+/* --------------------------------------------------- Algorithm 2 (5.2) */
+
+typedef struct {
+    uint64_t n_ins;   /* sum_{v,i} min(k, |R_i(v)|): rank insertions      */
+    uint64_t w_live;  /* sum_{v,i} min(k,|R_i(v)|) * live indeg_i(v)     */
+    uint64_t n_exp;   /* sum_v max_i min(k, |R_i(v)|)                     */
+    uint64_t c_min;   /* sum_v max_i min(k, |R_i(v)|) * indeg(v)          */
+} or_build_counters;
+
+typedef struct {
+    const or_graph *g;
+    uint64_t seed;
+    uint32_t ell, k;
+    uint64_t *X;          /* [n*k] global sketches */
+    uint32_t *Xs;         /* [n]   global sizes    */
+    uint8_t *emax;        /* [n]   max_i E_{v,i} (under lock) */
+    pthread_mutex_t *locks;
+    uint32_t nlocks;
+    uint32_t next_inst;   /* work counter (under qlock) */
+    pthread_mutex_t qlock;
+    uint64_t n_ins, w_live;  /* under qlock */
+} alg2_ctx;
+
+typedef struct { uint64_t r; uint32_t v; } rank_node;
+
+static int cmp_rank_node(const void *a, const void *b)
+{
+    uint64_t x = ((const rank_node *)a)->r, y = ((const rank_node *)b)->r;
+    return (x > y) - (x < y);
+}
+
+static void *alg2_worker(void *arg)
+{
+    alg2_ctx *c = arg;
+    const or_graph *g = c->g;
+    uint32_t n = g->n, k = c->k;
+    uint64_t m = g->row_ptr[n];
+    /* instance-local buffers */
+    uint8_t *live = malloc(m ? m : 1);
+    uint64_t *lptr = malloc(sizeof(uint64_t) * (n + 1));
+    uint32_t *lsrc = malloc(sizeof(uint32_t) * (m ? m : 1));
+    uint64_t *fill = malloc(sizeof(uint64_t) * (n + 1));
+    rank_node *order = malloc(sizeof(rank_node) * n);
+    uint32_t *cnt = malloc(sizeof(uint32_t) * n);
+    uint32_t *stamp = malloc(sizeof(uint32_t) * n);
+    uint32_t *queue = malloc(sizeof(uint32_t) * n);
+    uint64_t rcap = (uint64_t)n * 4 + 16, nrec;
+    uint32_t *rec_v = malloc(sizeof(uint32_t) * rcap);   /* records in the   */
+    uint64_t *rec_r = malloc(sizeof(uint64_t) * rcap);   /* order they occur */
+    uint64_t *sorted = NULL;
+    uint64_t scap = 0;
+    uint64_t *merged = malloc(sizeof(uint64_t) * k);
+
+    for (;;) {
+        pthread_mutex_lock(&c->qlock);
+        uint32_t i = c->next_inst++;
+        pthread_mutex_unlock(&c->qlock);
+        if (i >= c->ell) break;
+
+        /* The live reverse graph of instance i: in-lists of live edges. */
+        memset(lptr, 0, sizeof(uint64_t) * (n + 1));
+        for (uint32_t u = 0; u < n; u++)
+            for (uint64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++) {
+                live[e] = (uint8_t)or_live(c->seed, n, u, g->col[e], i, g->thr[e]);
+                if (live[e]) lptr[g->col[e] + 1]++;
+            }
+        for (uint32_t v = 0; v < n; v++) lptr[v + 1] += lptr[v];
+        memcpy(fill, lptr, sizeof(uint64_t) * (n + 1));
+        for (uint32_t u = 0; u < n; u++)
+            for (uint64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++)
+                if (live[e]) lsrc[fill[g->col[e]]++] = u;
+
+        /* Pairs (u, i) of this instance by increasing rank. */
+        for (uint32_t u = 0; u < n; u++) {
+            order[u].r = or_rank(c->seed, u, i);
+            order[u].v = u;
+        }
+        qsort(order, n, sizeof(rank_node), cmp_rank_node);
+        for (uint32_t v = 0; v < n; v++) { cnt[v] = 0; stamp[v] = UINT32_MAX; }
+        nrec = 0;
+
+        /* Pruned reverse searches: a scanned node whose local sketch already
+         * holds k ranks is pruned (not recorded, not expanded). */
+        for (uint32_t t = 0; t < n; t++) {
+            uint32_t u = order[t].v;
+            uint64_t r = order[t].r;
+            uint64_t head = 0, tail = 0;
+            stamp[u] = t;
+            if (cnt[u] == k) continue;
+            queue[tail++] = u;
+            while (head < tail) {
+                uint32_t v = queue[head++];
+                /* v is scanned and not pruned: record r in local[v] */
+                cnt[v]++;
+                if (nrec == rcap) {
+                    rcap *= 2;
+                    rec_v = realloc(rec_v, sizeof(uint32_t) * rcap);
+                    rec_r = realloc(rec_r, sizeof(uint64_t) * rcap);
+                }
+                rec_v[nrec] = v;
+                rec_r[nrec] = r;
+                nrec++;
+                for (uint64_t e = lptr[v]; e < lptr[v + 1]; e++) {
+                    uint32_t w = lsrc[e];
+                    if (stamp[w] == t) continue;
+                    stamp[w] = t;
+                    if (cnt[w] == k) continue;
+                    queue[tail++] = w;
+                }
+            }
+        }
+
+        /* Group the records by node, keeping their order: sources went by
+         * increasing rank, so every local sketch comes out sorted. */
+        if (nrec > scap) {
+            scap = nrec;
+            sorted = realloc(sorted, sizeof(uint64_t) * scap);
+        }
+        fill[0] = 0;
+        for (uint32_t v = 0; v < n; v++) fill[v + 1] = fill[v] + cnt[v];
+        for (uint64_t t = 0; t < nrec; t++) sorted[fill[rec_v[t]]++] = rec_r[t];
+
+        /* Merge local sketches into the global sketches and trim to k. */
+        uint64_t ins = 0, wl = 0, base = 0;
+        for (uint32_t v = 0; v < n; v++) {
+            uint32_t lc = cnt[v];
+            const uint64_t *L = sorted + base;
+            base += lc;
+            ins += lc;
+            wl += (uint64_t)lc * (lptr[v + 1] - lptr[v]);
+            if (lc == 0) continue;
+            pthread_mutex_t *lk = &c->locks[v % c->nlocks];
+            pthread_mutex_lock(lk);
+            uint64_t *X = c->X + (uint64_t)v * k;
+            uint32_t a = 0, b = 0, o = 0, xs = c->Xs[v];
+            while (o < k && (a < xs || b < lc)) {
+                if (b >= lc || (a < xs && X[a] < L[b])) merged[o++] = X[a++];
+                else merged[o++] = L[b++];
+            }
+            memcpy(X, merged, sizeof(uint64_t) * o);
+            c->Xs[v] = o;
+            if (lc > c->emax[v]) c->emax[v] = (uint8_t)lc;
+            pthread_mutex_unlock(lk);
+        }
+        pthread_mutex_lock(&c->qlock);
+        c->n_ins += ins;
+        c->w_live += wl;
+        pthread_mutex_unlock(&c->qlock);
+    }
+    free(live); free(lptr); free(lsrc); free(fill); free(order); free(cnt); free(stamp);
+    free(queue); free(rec_v); free(rec_r); free(sorted); free(merged);
+    return NULL;
+}
+
+/* Combined bottom-k sketches of every node by Algorithm 2.
+ * out_ranks[n*k] ascending with UINT64_MAX padding, out_size[n].
+ * Returns 0 on success, -1 on bad arguments. */
+int or_build_alg2(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                  const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
+                  uint32_t nthreads, uint64_t *out_ranks, uint32_t *out_size,
+                  or_build_counters *counters)
+{
+    if (ell < 1 || ell > 64 || k < 1 || k > 255 || n == 0) return -1;
+    or_graph g = {n, row_ptr, col, thr};
+    alg2_ctx c;
+    memset(&c, 0, sizeof c);
+    c.g = &g; c.seed = seed; c.ell = ell; c.k = k;
+    c.X = out_ranks; c.Xs = out_size;
+    for (uint64_t j = 0; j < (uint64_t)n * k; j++) out_ranks[j] = OR_NONE;
+    for (uint32_t v = 0; v < n; v++) out_size[v] = 0;
+    c.emax = calloc(n, 1);
+    c.nlocks = 4096;
+    c.locks = malloc(sizeof(pthread_mutex_t) * c.nlocks);
+    for (uint32_t j = 0; j < c.nlocks; j++) pthread_mutex_init(&c.locks[j], NULL);
+    pthread_mutex_init(&c.qlock, NULL);
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > ell) nthreads = ell;
+    pthread_t *th = malloc(sizeof(pthread_t) * nthreads);
+    for (uint32_t t = 0; t < nthreads; t++) pthread_create(&th[t], NULL, alg2_worker, &c);
+    for (uint32_t t = 0; t < nthreads; t++) pthread_join(th[t], NULL);
+    if (counters) {
+        counters->n_ins = c.n_ins;
+        counters->w_live = c.w_live;
+        counters->n_exp = 0;
+        counters->c_min = 0;
+        for (uint32_t v = 0; v < n; v++) counters->n_exp += c.emax[v];
+        uint64_t *indeg = calloc(n, sizeof(uint64_t));
+        for (uint64_t e = 0; e < row_ptr[n]; e++) indeg[col[e]]++;
+        for (uint32_t v = 0; v < n; v++) counters->c_min += (uint64_t)c.emax[v] * indeg[v];
+        free(indeg);
+    }
+    for (uint32_t j = 0; j < c.nlocks; j++) pthread_mutex_destroy(&c.locks[j]);
+    pthread_mutex_destroy(&c.qlock);
+    free(c.locks); free(c.emax); free(th);
+    return 0;
+}
+
+/* ------------------------------------------------------------ estimates */
+
+static double or_rho(uint64_t T)
+{
+    return (double)((T >> 11) + 1) * 0x1p-53;
+}
+
+/* Bottom-k cardinality estimate divided by l: |X|/l when |X| < k, else
+ * ((k-1)/rho(tau))/l with tau the k-th smallest rank. */
+static double or_estimate_one(uint64_t size, uint64_t tau, uint32_t k, uint32_t ell)
+{
+    if (size < k) return (double)size / (double)ell;
+    return ((double)(k - 1) / or_rho(tau)) / (double)ell;
+}
+
+void or_estimates(uint32_t n, uint32_t k, uint32_t ell, const uint64_t *ranks,
+                  const uint32_t *size, double *out_est)
+{
+    for (uint32_t v = 0; v < n; v++)
+        out_est[v] = or_estimate_one(size[v], ranks[(uint64_t)v * k + k - 1], k, ell);
+}
+
+/* ---------------------------------------------------- union queries 5.1 */
+
+/* For each seed set S_q = nodes[offsets[q] .. offsets[q+1]): the k smallest
+ * distinct ranks of the union of the sketches of S_q; estimate by the same
+ * bottom-k rule.  Duplicate nodes act once; an empty set gives 0; a node id
+ * >= n gives status -1 and estimate 0 for that query only. */
+void or_union_query(uint32_t n, uint32_t k, uint32_t ell, const uint64_t *ranks,
+                    const uint32_t *size, uint64_t Q, const uint64_t *offsets,
+                    const uint32_t *nodes, double *out_est, int32_t *out_status)
+{
+    uint64_t cap = 1024;
+    uint64_t *buf = malloc(sizeof(uint64_t) * cap);
+    for (uint64_t q = 0; q < Q; q++) {
+        uint64_t a = offsets[q], b = offsets[q + 1], cnt = 0;
+        int bad = 0;
+        for (uint64_t j = a; j < b; j++) if (nodes[j] >= n) bad = 1;
+        if (bad) { out_est[q] = 0.0; if (out_status) out_status[q] = -1; continue; }
+        if ((b - a) * k > cap) {
+            while ((b - a) * k > cap) cap *= 2;
+            buf = realloc(buf, sizeof(uint64_t) * cap);
+        }
+        for (uint64_t j = a; j < b; j++) {
+            uint32_t u = nodes[j];
+            for (uint32_t t = 0; t < size[u]; t++) buf[cnt++] = ranks[(uint64_t)u * k + t];
+        }
+        qsort(buf, cnt, sizeof(uint64_t), cmp_u64);
+        uint64_t d = 0;
+        for (uint64_t t = 0; t < cnt; t++)
+            if (d == 0 || buf[t] != buf[d - 1]) buf[d++] = buf[t];
+        out_est[q] = or_estimate_one(d < k ? d : k, d >= k ? buf[k - 1] : 0, k, ell);
+        if (out_status) out_status[q] = 0;
+    }
+    free(buf);
+}
+
+/* Cohen-Kaplan union estimator, eq. (unionest), divided by l.  Each node's
+ * threshold tau_u is its k-th rank when the sketch is full, and 1 (the top
+ * of the rank range) otherwise; the tau element itself is excluded from a
+ * full sketch.  Every distinct remaining rank z contributes
+ * 1 / rho(max tau_u over the sketches holding z as a non-tau element); a
+ * non-full holder contributes weight exactly 1.  Contributions are summed in
+ * increasing order of z.  Status as in or_union_query. */
+void or_ck_query(uint32_t n, uint32_t k, uint32_t ell, const uint64_t *ranks,
+                 const uint32_t *size, uint64_t Q, const uint64_t *offsets,
+                 const uint32_t *nodes, double *out_est, int32_t *out_status)
+{
+    uint64_t cap = 1024;
+    uint64_t *buf = malloc(sizeof(uint64_t) * cap * 2);
+    for (uint64_t q = 0; q < Q; q++) {
+        uint64_t a = offsets[q], b = offsets[q + 1], cnt = 0;
+        int bad = 0;
+        for (uint64_t j = a; j < b; j++) if (nodes[j] >= n) bad = 1;
+        if (bad) { out_est[q] = 0.0; if (out_status) out_status[q] = -1; continue; }
+        if ((b - a) * k > cap) {
+            while ((b - a) * k > cap) cap *= 2;
+            buf = realloc(buf, sizeof(uint64_t) * cap * 2);
+        }
+        /* (rank, holder's threshold) pairs; a non-full holder's threshold is
+         * encoded as UINT64_MAX, meaning rho = 1. */
+        for (uint64_t j = a; j < b; j++) {
+            uint32_t u = nodes[j];
+            uint32_t s = size[u];
+            int full = (s == k);
+            uint64_t tau = full ? ranks[(uint64_t)u * k + k - 1] : OR_NONE;
+            uint32_t lim = full ? k - 1 : s;
+            for (uint32_t t = 0; t < lim; t++) {
+                buf[2 * cnt] = ranks[(uint64_t)u * k + t];
+                buf[2 * cnt + 1] = tau;
+                cnt++;
+            }
+        }
+        qsort(buf, cnt, 2 * sizeof(uint64_t), cmp_u64); /* by rank (first word) */
+        double sum = 0.0;
+        uint64_t x = 0;
+        while (x < cnt) {
+            uint64_t r = buf[2 * x], tmax = buf[2 * x + 1];
+            uint64_t y = x + 1;
+            while (y < cnt && buf[2 * y] == r) {
+                if (buf[2 * y + 1] > tmax) tmax = buf[2 * y + 1];
+                y++;
+            }
+            sum += (tmax == OR_NONE) ? 1.0 : 1.0 / or_rho(tmax);
+            x = y;
+        }
+        out_est[q] = sum / (double)ell;
+        if (out_status) out_status[q] = 0;
+    }
+    free(buf);
+}
+
+/* ------------------------------------------------------ Algorithm 1 (4) */
+
+typedef struct {
+    uint64_t insertions;   /* size[v]++ operations (rank insertions)       */
+    uint64_t pairs_scanned;/* pairs taken from the rank order               */
+    uint64_t reverse_bfs;  /* reverse searches run (uncovered pairs)        */
+    uint64_t covered;      /* pairs covered by the residual updates         */
+    uint64_t decrements;   /* size[w]-- operations                          */
+    uint64_t fallback;     /* seeds chosen by the exhaustion argmax         */
+} or_skim_counters;
+
+/* Per-instance live adjacency: forward and reverse CSR of live edges. */
+typedef struct { uint64_t *fptr, *rptr; uint32_t *fadj, *radj; } live_inst;
+
+static void build_live(const or_graph *g, uint64_t seed, uint32_t i, live_inst *L)
+{
+    uint32_t n = g->n;
+    uint64_t m = g->row_ptr[n];
+    L->fptr = calloc(n + 1, sizeof(uint64_t));
+    L->rptr = calloc(n + 1, sizeof(uint64_t));
+    uint8_t *live = malloc(m ? m : 1);
+    uint64_t cntl = 0;
+    for (uint32_t u = 0; u < n; u++)
+        for (uint64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++) {
+            live[e] = (uint8_t)or_live(seed, n, u, g->col[e], i, g->thr[e]);
+            if (live[e]) { L->fptr[u + 1]++; L->rptr[g->col[e] + 1]++; cntl++; }
+        }
+    for (uint32_t v = 0; v < n; v++) { L->fptr[v + 1] += L->fptr[v]; L->rptr[v + 1] += L->rptr[v]; }
+    L->fadj = malloc(sizeof(uint32_t) * (cntl ? cntl : 1));
+    L->radj = malloc(sizeof(uint32_t) * (cntl ? cntl : 1));
+    uint64_t *rf = calloc(n, sizeof(uint64_t));
+    uint64_t fo = 0;
+    for (uint32_t u = 0; u < n; u++)
+        for (uint64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++)
+            if (live[e]) {
+                uint32_t v = g->col[e];
+                L->fadj[fo++] = v;
+                L->radj[L->rptr[v] + rf[v]++] = u;
+            }
+    free(rf);
+    free(live);
+}
+
+/* SKIM (Algorithm 1) for s seeds.  Ties: among the nodes whose size reaches
+ * k during the reverse search of one pair, the smallest id is selected; the
+ * exhaustion fallback takes the largest size among unselected nodes,
+ * smallest id on ties.  out_seeds[s], out_gain[s] = newly covered pairs
+ * (l times the marginal influence).  Returns 0, or -1 on bad arguments,
+ * or -2 if the reverse search of an uncovered pair met a covered pair (an
+ * internal invariant; cannot happen). */
+int or_skim(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, const uint32_t *thr,
+            uint64_t seed, uint32_t ell, uint32_t k, uint32_t s,
+            uint32_t *out_seeds, uint64_t *out_gain, or_skim_counters *counters)
+{
+    if (ell < 1 || ell > 64 || k < 1 || s > n || n == 0) return -1;
+    or_graph g = {n, row_ptr, col, thr};
+    uint64_t npairs = (uint64_t)n * ell;
+    live_inst *L = malloc(sizeof(live_inst) * ell);
+    for (uint32_t i = 0; i < ell; i++) build_live(&g, seed, i, &L[i]);
+
+    /* "shuffle the n*l pairs": the random order is increasing rank */
+    rank_node *pairs = malloc(sizeof(rank_node) * npairs);
+    for (uint32_t u = 0; u < n; u++)
+        for (uint32_t i = 0; i < ell; i++) {
+            pairs[(uint64_t)u * ell + i].r = or_rank(seed, u, i);
+            pairs[(uint64_t)u * ell + i].v = u * 64 + i; /* packed (u, i) */
+        }
+    qsort(pairs, npairs, sizeof(rank_node), cmp_rank_node);
+
+    uint8_t *covered = calloc(npairs, 1);           /* [u*ell + i] */
+    uint32_t *size = calloc(n, sizeof(uint32_t));
+    uint8_t *selected = calloc(n, 1);
+    /* index[(u,i)]: nodes whose partial sketch holds r(u,i) */
+    uint32_t **idx = calloc(npairs, sizeof(uint32_t *));
+    uint32_t *idxn = calloc(npairs, sizeof(uint32_t));
+    uint64_t *stamp = malloc(sizeof(uint64_t) * n);
+    uint32_t *queue = malloc(sizeof(uint32_t) * n);
+    uint8_t *seen = calloc(n, 1);
+    for (uint32_t v = 0; v < n; v++) stamp[v] = 0;
+    or_skim_counters cc;
+    memset(&cc, 0, sizeof cc);
+    uint64_t cursor = 0;
+    int rc = 0;
+
+    for (uint32_t it = 0; it < s; it++) {
+        int64_t x = -1;
+        /* Build sketches: pairs by increasing rank, skipping covered ones. */
+        while (x < 0 && cursor < npairs) {
+            uint32_t packed = pairs[cursor].v;
+            uint32_t u = packed / 64, i = packed % 64;
+            uint64_t pid = (uint64_t)u * ell + i;
+            cursor++;
+            cc.pairs_scanned++;
+            if (covered[pid]) continue;
+            cc.reverse_bfs++;
+            /* complete reverse search from u in G^(i) */
+            uint64_t head = 0, tail = 0;
+            uint64_t tag = cursor; /* >= 1 and distinct per search */
+            stamp[u] = tag;
+            queue[tail++] = u;
+            while (head < tail) {
+                uint32_t v = queue[head++];
+                for (uint64_t e = L[i].rptr[v]; e < L[i].rptr[v + 1]; e++) {
+                    uint32_t w = L[i].radj[e];
+                    if (stamp[w] != tag) { stamp[w] = tag; queue[tail++] = w; }
+                }
+            }
+            idx[pid] = malloc(sizeof(uint32_t) * tail);
+            idxn[pid] = (uint32_t)tail;
+            for (uint64_t t = 0; t < tail; t++) {
+                uint32_t v = queue[t];
+                if (covered[(uint64_t)v * ell + i]) { rc = -2; goto done; }
+                size[v]++;
+                cc.insertions++;
+                idx[pid][t] = v;
+                if (size[v] == k && (x < 0 || v < (uint32_t)x)) x = v;
+            }
+        }
+        if (x < 0) {
+            /* every rank processed: largest partial sketch, unselected */
+            uint32_t best = 0;
+            for (uint32_t v = 0; v < n; v++) {
+                if (selected[v]) continue;
+                if (x < 0 || size[v] > best) { best = size[v]; x = v; }
+            }
+            cc.fallback++;
+        }
+        /* Residual problem: cover what x reaches in every instance. */
+        uint64_t gain = 0;
+        for (uint32_t i = 0; i < ell; i++) {
+            if (covered[(uint64_t)x * ell + i]) continue;
+            uint64_t head = 0, tail = 0;
+            seen[x] = 1;
+            queue[tail++] = (uint32_t)x;
+            while (head < tail) {
+                uint32_t v = queue[head++];
+                uint64_t pid = (uint64_t)v * ell + i;
+                covered[pid] = 1;
+                gain++;
+                for (uint32_t t = 0; t < idxn[pid]; t++) { size[idx[pid][t]]--; cc.decrements++; }
+                free(idx[pid]);
+                idx[pid] = NULL;
+                idxn[pid] = 0;
+                for (uint64_t e = L[i].fptr[v]; e < L[i].fptr[v + 1]; e++) {
+                    uint32_t w = L[i].fadj[e];
+                    if (!seen[w] && !covered[(uint64_t)w * ell + i]) { seen[w] = 1; queue[tail++] = w; }
+                }
+            }
+            for (uint64_t t = 0; t < tail; t++) seen[queue[t]] = 0;
+        }
+        cc.covered += gain;
+        selected[x] = 1;
+        out_seeds[it] = (uint32_t)x;
+        out_gain[it] = gain;
+    }
+done:
+    if (counters) *counters = cc;
+    for (uint64_t p = 0; p < npairs; p++) free(idx[p]);
+    free(idx); free(idxn); free(stamp); free(queue); free(seen);
+    free(covered); free(size); free(selected); free(pairs);
+    for (uint32_t i = 0; i < ell; i++) { free(L[i].fptr); free(L[i].rptr); free(L[i].fadj); free(L[i].radj); }
+    free(L);
+    return rc;
+}

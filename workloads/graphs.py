@@ -1,0 +1,193 @@
+"""Synthetic directed graphs shaped like the paper's workloads (Section 6).
+
+The paper measures on SNAP / WebGraph social, collaboration and web networks,
+which are heavy-tailed.  Those datasets are not available here, so seeded
+synthetic graphs stand in for them:
+
+* Erdos-Renyi: exactly m distinct ordered pairs (u, v), u != v.
+* Chung-Lu: expected degrees w_i ~ (i+1)^(-1/(gamma-1)) for in- and
+  out-degrees, each behind its own seeded node permutation; edges are sampled
+  source ~ out-weight, head ~ in-weight, then self-loops and duplicates are
+  dropped and the sample is topped up until exactly m distinct edges remain.
+* R-MAT: 2^scale nodes, a fixed number of recursive quadrant samples with
+  probabilities (a, b, c, d), a seeded node permutation, then self-loops and
+  duplicates dropped (the final edge count is reported, not topped up).
+
+Every graph is returned as a forward CSR (out-edges): row_ptr uint64[n+1],
+col uint32[m] with strictly increasing heads inside each row, no self-loops,
+no duplicates.  Per-edge probabilities are uint32 thresholds aligned with col.
+
+Edge-probability schemes (Section 6, the IC setup): uniform p, weighted cascade
+p_uv = 1 / indeg(v), and the trivalency scheme {0.1, 0.01, 0.001}.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+UINT32_MAX = np.uint64(0xFFFFFFFF)
+
+
+@dataclass
+class Graph:
+    n: int
+    row_ptr: np.ndarray  # uint64[n+1]
+    col: np.ndarray      # uint32[m]
+    thr: np.ndarray      # uint32[m]
+    name: str = ""
+
+    @property
+    def m(self) -> int:
+        return int(self.col.shape[0])
+
+    def edges(self):
+        """(src, dst) arrays in CSR order."""
+        deg = np.diff(self.row_ptr.astype(np.int64))
+        src = np.repeat(np.arange(self.n, dtype=np.uint32), deg)
+        return src, self.col
+
+    def in_degree(self) -> np.ndarray:
+        return np.bincount(self.col, minlength=self.n).astype(np.int64)
+
+
+def _csr_from_keys(n: int, keys: np.ndarray):
+    """Sorted unique keys src*n+dst -> (row_ptr, col)."""
+    keys = np.asarray(keys, dtype=np.uint64)
+    src = (keys // np.uint64(n)).astype(np.int64)
+    dst = (keys % np.uint64(n)).astype(np.uint32)
+    counts = np.bincount(src, minlength=n)
+    row_ptr = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(counts, out=row_ptr[1:])
+    return row_ptr, dst
+
+
+def from_edges(n: int, src, dst, thr=None, name: str = "") -> Graph:
+    """Build a Graph from explicit edge lists (used by small tests).
+
+    Duplicates and self-loops are rejected, not silently dropped, so that a
+    test always knows the exact graph it built.  ``thr`` may be a scalar or an
+    array aligned with (src, dst); it is permuted into CSR order.
+    """
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    if src.shape != dst.shape:
+        raise ValueError("src/dst length mismatch")
+    if src.size and (src.min() < 0 or dst.min() < 0 or src.max() >= n or dst.max() >= n):
+        raise ValueError("node id out of range")
+    if np.any(src == dst):
+        raise ValueError("self-loop")
+    keys = src.astype(np.uint64) * np.uint64(n) + dst.astype(np.uint64)
+    order = np.argsort(keys, kind="stable")
+    skeys = keys[order]
+    if skeys.size > 1 and np.any(skeys[1:] == skeys[:-1]):
+        raise ValueError("duplicate edge")
+    row_ptr, col = _csr_from_keys(n, skeys)
+    if thr is None:
+        t = np.full(col.shape[0], 0xFFFFFFFF, dtype=np.uint32)
+    elif np.isscalar(thr):
+        t = np.full(col.shape[0], int(thr), dtype=np.uint32)
+    else:
+        t = np.asarray(thr, dtype=np.uint32)[order]
+    return Graph(n, row_ptr, col.astype(np.uint32), t, name)
+
+
+def uniform_thresholds(m: int, denom: int) -> np.ndarray:
+    """Uniform scheme p = 1/denom for every edge: thr = (2^32-1) // denom."""
+    if denom < 1:
+        raise ValueError("denom >= 1")
+    return np.full(m, 0xFFFFFFFF // int(denom), dtype=np.uint32)
+
+
+def wc_thresholds(row_ptr: np.ndarray, col: np.ndarray, n: int) -> np.ndarray:
+    """Weighted cascade: p_uv = 1 / indeg(v), thr = (2^32-1) // indeg(v)."""
+    indeg = np.bincount(col, minlength=n).astype(np.uint64)
+    d = indeg[col]
+    return (UINT32_MAX // d).astype(np.uint32)
+
+
+def trivalency_thresholds(m: int, seed: int) -> np.ndarray:
+    """Trivalency: p drawn uniformly from {0.1, 0.01, 0.001} per edge."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    choices = np.array([0xFFFFFFFF // 10, 0xFFFFFFFF // 100, 0xFFFFFFFF // 1000],
+                       dtype=np.uint32)
+    return choices[rng.integers(0, 3, size=m)]
+
+
+def er_graph(n: int, m: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Exactly m distinct ordered pairs (u, v) with u != v, uniformly."""
+    if m > n * (n - 1):
+        raise ValueError("m too large")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    code = rng.choice(n * (n - 1), size=m, replace=False).astype(np.int64)
+    u = code // (n - 1)
+    v = code % (n - 1)
+    v = v + (v >= u)  # skip the diagonal
+    keys = np.sort(u.astype(np.uint64) * np.uint64(n) + v.astype(np.uint64))
+    return _csr_from_keys(n, keys)
+
+
+def _sample_categorical(rng, cdf: np.ndarray, size: int) -> np.ndarray:
+    u = rng.random(size)
+    return np.searchsorted(cdf, u, side="right").clip(0, cdf.shape[0] - 1)
+
+
+def chung_lu_graph(n: int, m: int, gamma: float, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """Chung-Lu directed graph with power-law in/out expected degrees."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
+    w /= w.sum()
+    perm_out = rng.permutation(n)
+    perm_in = rng.permutation(n)
+    w_out = np.empty(n)
+    w_in = np.empty(n)
+    w_out[perm_out] = w
+    w_in[perm_in] = w
+    cdf_out = np.cumsum(w_out)
+    cdf_in = np.cumsum(w_in)
+    cdf_out /= cdf_out[-1]
+    cdf_in /= cdf_in[-1]
+    keys = np.empty(0, dtype=np.uint64)
+    need = m
+    while need > 0:
+        batch = int(need * 1.25) + 1024
+        s = _sample_categorical(rng, cdf_out, batch).astype(np.uint64)
+        d = _sample_categorical(rng, cdf_in, batch).astype(np.uint64)
+        ok = s != d
+        new = s[ok] * np.uint64(n) + d[ok]
+        # keep first occurrences in sample order, then drop keys already held
+        _, first = np.unique(new, return_index=True)
+        new = new[np.sort(first)]
+        new = new[~np.isin(new, keys)]
+        keys = np.concatenate([keys, new[:need]])
+        need = m - keys.shape[0]
+    return _csr_from_keys(n, np.sort(keys))
+
+
+def rmat_graph(scale: int, samples: int, abcd, seed: int,
+               chunk: int = 1 << 24) -> tuple[np.ndarray, np.ndarray]:
+    """R-MAT with a seeded node permutation; self-loops/duplicates dropped."""
+    a, b, c, d = abcd
+    n = 1 << scale
+    rng = np.random.Generator(np.random.PCG64(seed))
+    perm = rng.permutation(n).astype(np.uint64)
+    parts = []
+    done = 0
+    t_ab = a + b
+    while done < samples:
+        cnt = min(chunk, samples - done)
+        src = np.zeros(cnt, dtype=np.uint64)
+        dst = np.zeros(cnt, dtype=np.uint64)
+        for _ in range(scale):
+            u = rng.random(cnt)
+            down = u >= t_ab                      # quadrants c, d
+            right = np.where(down, u >= t_ab + c, (u >= a))  # b or d
+            src = (src << np.uint64(1)) | down.astype(np.uint64)
+            dst = (dst << np.uint64(1)) | right.astype(np.uint64)
+        src = perm[src]
+        dst = perm[dst]
+        ok = src != dst
+        parts.append(np.unique(src[ok] * np.uint64(n) + dst[ok]))
+        done += cnt
+    keys = np.unique(np.concatenate(parts))
+    return _csr_from_keys(n, keys)
