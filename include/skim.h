@@ -1,0 +1,165 @@
+/*
+ * skim.h -- C ABI of the MI355X (gfx950) library for sketch-based influence
+ * computation under binary Independent Cascade (Cohen, Delling, Pajor,
+ * Werneck, "Sketch-based Influence Maximization and Computation", 2014).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Graph: a directed graph as a forward CSR (out-edges).  row_ptr[n+1]
+ *   (uint64, row_ptr[0] = 0, non-decreasing, row_ptr[n] = m), col[m] (uint32
+ *   heads, strictly increasing within a row: no duplicate edges), no
+ *   self-loops, every head < n.  n >= 1, n * 64 < 2^32.
+ * Edge probabilities (binary IC, Section 1 and 2 of the paper): thr[m]
+ *   (uint32) encodes p = (thr + 1) / 2^32; the edge (u -> v) is live in
+ *   instance i iff the 32-bit coin of (seed, u, v, i) is <= thr.  A
+ *   probability p is encoded as floor((2^32 - 1) * p); p = 1 is 0xFFFFFFFF.
+ * Instances: l in [1, 64] Monte-Carlo instances G^(i) (Section 2); they are
+ *   never stored by the caller: ranks and coins come from SplitMix64
+ *   (Steele, Lea, Flood 2014) seeded with `seed`:
+ *     SM(c)   = mix64(seed + (c + 1) * 0x9E3779B97F4A7C15)
+ *     r(v, i) = SM(64 v + i)                      rank of node-instance pair
+ *     coin    = high (i even) / low (i odd) 32 bits of
+ *               SM(2^62 + 32 (u n + v) + floor(i / 2))
+ * Sketch k: 2 <= k <= 256.
+ * Pointers: every array argument is a DEVICE pointer (HIP global memory on
+ *   the current device) unless stated otherwise.  The caller owns every
+ *   buffer; inputs must stay valid and unmodified until the stream reaches
+ *   the end of the call's work.  `stream` is a hipStream_t (NULL = the
+ *   default stream).
+ * Errors: argument and graph validation runs before any result is written;
+ *   on failure the call returns SKIM_EINVAL and leaves outputs untouched.
+ *   A HIP runtime failure returns SKIM_EDEVICE; an allocation failure
+ *   SKIM_ENOMEM.  skim_last_error() describes the last failure of the
+ *   calling thread.  Nothing throws across this boundary.
+ * Synchronisation: each call may synchronise `stream` internally (it reads
+ *   small device counters to schedule its work); results are complete when
+ *   the call returns SKIM_OK.
+ * Determinism: for the same inputs every call returns the same bits, on any
+ *   stream and in any batch mix.
+ */
+#ifndef SKIM_H
+#define SKIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SKIM_ABI_VERSION 1u
+
+typedef enum {
+    SKIM_OK = 0,
+    SKIM_EINVAL = 1,       /* bad argument or invalid graph               */
+    SKIM_ENOMEM = 2,       /* device allocation failed                    */
+    SKIM_EDEVICE = 3,      /* HIP runtime or kernel failure               */
+    SKIM_EBUSY = 4,        /* server queue / budget full, retry later     */
+    SKIM_EUNSUPPORTED = 5  /* valid request outside the supported limits  */
+} skim_status;
+
+typedef struct {
+    uint32_t n;               /* nodes                                     */
+    uint64_t m;               /* edges                                     */
+    const uint64_t *row_ptr;  /* [n+1] device                              */
+    const uint32_t *col;      /* [m]   device                              */
+    const uint32_t *thr;      /* [m]   device                              */
+} skim_graph;
+
+/* ABI version (SKIM_ABI_VERSION of the built library). */
+uint32_t skim_abi_version(void);
+
+/* Text of the last failure on the calling thread ("" if none). */
+const char *skim_last_error(void);
+
+/*
+ * skim_build_sketches -- combined bottom-k reachability sketches of every
+ * node over l instances (Section 3, eq. combinedrs; built as Section 5.2,
+ * Algorithm 2, describes: per instance, pairs by increasing rank, reverse
+ * searches pruned at nodes whose instance-local sketch already holds k
+ * ranks, merged into the global bottom-k sketch) and, optionally, the
+ * influence estimate of every node (Section 3, eq. combinedthresh; Section
+ * 5.1 divides by l).
+ *
+ *   ranks [n*k] out, device: row v = X_v ascending, padded with UINT64_MAX.
+ *   size  [n]   out, device: |X_v| = min(k, |R_v|).
+ *   est   [n]   out, device, may be NULL: |X_v| / l if |X_v| < k, else
+ *         ((k-1) / rho(tau_v)) / l with tau_v = ranks[v*k + k-1] and
+ *         rho(T) = ((T >> 11) + 1) * 2^-53 (IEEE double, correctly rounded).
+ *   work  [4]   out, HOST, may be NULL: work the device did, in order:
+ *         items (node-instance-source visits), live-edge scans, records
+ *         kept for the merge, rank windows processed.
+ */
+skim_status skim_build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+                                uint64_t *ranks, uint32_t *size, double *est,
+                                uint64_t *work, void *stream);
+
+/*
+ * skim_estimates -- per-node estimates from existing sketches, same formula
+ * as the `est` output of skim_build_sketches.
+ *   ranks [n*k], size [n] in, device; est [n] out, device.
+ */
+skim_status skim_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
+                           uint32_t ell, double *est, void *stream);
+
+/*
+ * skim_query_batch -- influence of q seed sets from the sketches (Section
+ * 5.1).  Set j is qnodes[qoff[j] .. qoff[j+1]) (duplicates act once).
+ *   estimator 0: bottom-k of the union of the sketches: U = the distinct
+ *     ranks of the union; |U| / l if |U| < k, else ((k-1)/rho(U[k-1])) / l.
+ *   estimator 1: Cohen-Kaplan (eq. unionest): each distinct rank z that a
+ *     member sketch holds as a non-threshold element weighs
+ *     1 / rho(max tau_u over such holders), a non-full sketch weighing 1;
+ *     the weights are summed in increasing order of z, then divided by l.
+ *   ranks [n*k], size [n]: sketches as skim_build_sketches writes them.
+ *   qoff [q+1] (qoff[0] = 0, non-decreasing), qnodes [qoff[q]]: device.
+ *   est [q] out, device.  qstatus [q] out, device, may be NULL: 0, or -1
+ *   when the set names a node >= n, or -2 when it has more than 1024
+ *   entries (that query's est is 0; the rest of the batch is unaffected).
+ *   An empty set gives est 0, status 0.
+ *   mode 0: one persistent launch for the whole batch (default);
+ *   mode 1: one launch per query (the plain path, for comparison).
+ */
+skim_status skim_query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
+                             uint32_t k, uint32_t ell, uint64_t q, const uint64_t *qoff,
+                             const uint32_t *qnodes, uint32_t estimator, uint32_t mode,
+                             double *est, int32_t *qstatus, void *stream);
+
+/*
+ * skim_greedy -- SKIM seed selection (Section 4, Algorithm 1) for s seeds.
+ * Pairs are taken by increasing rank; each uncovered pair runs a complete
+ * reverse search that adds one to size[v] of every node it reaches; the
+ * first node whose size reaches k (smallest id among nodes reaching k on
+ * the same pair) is the next seed; once every rank is processed the seed is
+ * the unselected node of largest size (smallest id on ties).  The residual
+ * problem then covers every pair the seed reaches (forward search per
+ * instance, not entering covered pairs) and removes their ranks from the
+ * partial sketches.
+ *   seeds      [s] out, device: selected nodes in order.
+ *   gain_pairs [s] out, device: newly covered node-instance pairs of each
+ *              seed (l times its exact marginal influence, Section 4.1.1).
+ *   gain       [s] out, device, may be NULL: gain_pairs / l.
+ *   state: NULL = one-shot.  Otherwise *state = NULL starts a fresh run and
+ *     returns its state in *state; a non-NULL *state resumes that run and
+ *     selects the next s seeds (g, l, k, seed must be those of the run;
+ *     the graph buffers must stay valid while the state lives).  Resuming
+ *     in steps gives exactly the one-shot sequence.  s may not exceed the
+ *     number of unselected nodes.
+ */
+typedef struct skim_greedy_state skim_greedy_state;
+
+skim_status skim_greedy(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed, uint32_t s,
+                        uint32_t *seeds, uint64_t *gain_pairs, double *gain,
+                        skim_greedy_state **state, void *stream);
+
+/* Release a state returned by skim_greedy (NULL is ignored). */
+void skim_greedy_state_free(skim_greedy_state *state);
+
+/* Seeds selected so far by a state (0 for NULL). */
+uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKIM_H */

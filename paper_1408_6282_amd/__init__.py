@@ -1,0 +1,186 @@
+"""Python binding of the gfx950 sketch-based influence library (C ABI in include/skim.h).
+
+Argument marshalling only: every step runs in the HIP library.  Device
+buffers are torch tensors on a HIP device; streams are torch streams.  There
+is no CPU fallback: importing works without a GPU, but every call needs the
+built ``libskim_hip.so`` and raises if it is missing or a call fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libskim_hip.so")
+
+SKIM_OK, SKIM_EINVAL, SKIM_ENOMEM, SKIM_EDEVICE, SKIM_EBUSY, SKIM_EUNSUPPORTED = range(6)
+_STATUS = {0: "SKIM_OK", 1: "SKIM_EINVAL", 2: "SKIM_ENOMEM", 3: "SKIM_EDEVICE", 4: "SKIM_EBUSY",
+           5: "SKIM_EUNSUPPORTED"}
+
+EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_estimates",
+           "skim_query_batch", "skim_greedy", "skim_greedy_state_free",
+           "skim_greedy_state_selected"]
+
+
+class SkimError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn}: {_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class skim_graph(C.Structure):
+    _fields_ = [("n", C.c_uint32), ("m", C.c_uint64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("thr", C.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path: str | None = None):
+    """Load libskim_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run __graft_entry__.build() or python -m paper_1408_6282_amd.build)")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    lib.skim_abi_version.restype = C.c_uint32
+    lib.skim_abi_version.argtypes = []
+    lib.skim_last_error.restype = C.c_char_p
+    lib.skim_last_error.argtypes = []
+    lib.skim_build_sketches.restype = C.c_int
+    lib.skim_build_sketches.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint32, C.c_uint64,
+                                        vp, vp, vp, C.POINTER(C.c_uint64), vp]
+    lib.skim_estimates.restype = C.c_int
+    lib.skim_estimates.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, vp, vp]
+    lib.skim_query_batch.restype = C.c_int
+    lib.skim_query_batch.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64, vp,
+                                     vp, C.c_uint32, C.c_uint32, vp, vp, vp]
+    lib.skim_greedy.restype = C.c_int
+    lib.skim_greedy.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint32, C.c_uint64,
+                                C.c_uint32, vp, vp, vp, C.POINTER(vp), vp]
+    lib.skim_greedy_state_free.restype = None
+    lib.skim_greedy_state_free.argtypes = [vp]
+    lib.skim_greedy_state_selected.restype = C.c_uint32
+    lib.skim_greedy_state_selected.argtypes = [vp]
+    _lib = lib
+    return lib
+
+
+def _check(fn: str, status: int):
+    if status != SKIM_OK:
+        msg = _lib.skim_last_error().decode(errors="replace") if _lib else ""
+        raise SkimError(fn, status, msg)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class DeviceGraph:
+    """A forward-CSR graph resident in device memory (torch tensors) plus its ABI struct."""
+
+    def __init__(self, n: int, row_ptr, col, thr):
+        self.n = int(n)
+        self.row_ptr, self.col, self.thr = row_ptr, col, thr
+        self.m = int(col.numel())
+        self.struct = skim_graph(self.n, self.m, row_ptr.data_ptr(),
+                                 col.data_ptr() if self.m else None,
+                                 thr.data_ptr() if self.m else None)
+
+    @classmethod
+    def from_host(cls, g, device="cuda"):
+        """Upload a ``workloads.Graph`` (numpy arrays) to the device."""
+        import torch
+        rp = torch.from_numpy(np.ascontiguousarray(g.row_ptr).view(np.int64)).to(device)
+        col = torch.from_numpy(np.ascontiguousarray(g.col).view(np.int32)).to(device)
+        thr = torch.from_numpy(np.ascontiguousarray(g.thr).view(np.int32)).to(device)
+        return cls(g.n, rp, col, thr)
+
+
+def skim_abi_version() -> int:
+    return int(load_library().skim_abi_version())
+
+
+def skim_last_error() -> str:
+    return load_library().skim_last_error().decode(errors="replace")
+
+
+def skim_build_sketches(graph: DeviceGraph, ell: int, k: int, seed: int, ranks, size, est=None,
+                        stream=None):
+    """Fill ranks [n*k] (int64 view of uint64), size [n] (int32 view of uint32) and est [n].
+
+    Returns the device work counters (items, live-edge scans, records, windows).
+    """
+    lib = load_library()
+    work = (C.c_uint64 * 4)()
+    st = lib.skim_build_sketches(C.byref(graph.struct), ell, k, seed & 0xFFFFFFFFFFFFFFFF,
+                                 _ptr(ranks), _ptr(size), _ptr(est), work, _stream(stream))
+    _check("skim_build_sketches", st)
+    return {"items": int(work[0]), "scans": int(work[1]), "records": int(work[2]),
+            "windows": int(work[3])}
+
+
+def skim_estimates(ranks, size, n: int, k: int, ell: int, est, stream=None):
+    lib = load_library()
+    st = lib.skim_estimates(_ptr(ranks), _ptr(size), n, k, ell, _ptr(est), _stream(stream))
+    _check("skim_estimates", st)
+
+
+def skim_query_batch(ranks, size, n: int, k: int, ell: int, qoff, qnodes, est, qstatus=None,
+                     estimator: int = 0, mode: int = 0, stream=None):
+    """Estimates for the seed sets qnodes[qoff[j]:qoff[j+1]] (device tensors)."""
+    lib = load_library()
+    q = int(qoff.numel()) - 1
+    st = lib.skim_query_batch(_ptr(ranks), _ptr(size), n, k, ell, max(q, 0), _ptr(qoff),
+                              _ptr(qnodes) if qnodes is not None and qnodes.numel() else None,
+                              estimator, mode, _ptr(est), _ptr(qstatus), _stream(stream))
+    _check("skim_query_batch", st)
+
+
+class GreedyState:
+    """Owner of a resumable SKIM state (freed with skim_greedy_state_free)."""
+
+    def __init__(self):
+        self.handle = C.c_void_p(None)
+
+    @property
+    def selected(self) -> int:
+        return int(load_library().skim_greedy_state_selected(self.handle))
+
+    def free(self):
+        if self.handle:
+            load_library().skim_greedy_state_free(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def skim_greedy(graph: DeviceGraph, ell: int, k: int, seed: int, s: int, seeds, gain_pairs,
+                gain=None, state: GreedyState | None = None, stream=None):
+    """Select s seeds (resuming `state` when given) into device tensors."""
+    lib = load_library()
+    ref = C.byref(state.handle) if state is not None else None
+    st = lib.skim_greedy(C.byref(graph.struct), ell, k, seed & 0xFFFFFFFFFFFFFFFF, s, _ptr(seeds),
+                         _ptr(gain_pairs), _ptr(gain), ref, _stream(stream))
+    _check("skim_greedy", st)
+
+
+def skim_greedy_state_free(state: GreedyState):
+    state.free()

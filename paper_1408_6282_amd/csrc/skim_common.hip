@@ -1,0 +1,326 @@
+// skim_common.hip -- host plumbing shared by every entry point: errors,
+// stream-ordered scratch, fills, exclusive scan, graph validation, and the
+// per-node estimate entry point.
+#include "skim_internal.h"
+
+#include <cstring>
+#include <mutex>
+#include <string>
+
+namespace skim {
+
+namespace {
+thread_local char g_err[512] = "";
+std::mutex g_pool_mu;
+bool g_pool_ready[64] = {};
+}  // namespace
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+static void ensure_pool() {
+    int dev = 0;
+    SKIM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_ready[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = ~0ull;  // keep freed scratch cached between calls
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+    g_pool_ready[dev] = true;
+}
+
+Arena::Arena(hipStream_t s, bool persistent) : s_(s), persistent_(persistent) { ensure_pool(); }
+
+Arena::~Arena() {
+    for (void *p : bufs_)
+        if (p) (void)(persistent_ ? hipFree(p) : hipFreeAsync(p, s_));
+}
+
+void *Arena::get(size_t bytes) {
+    void *p = nullptr;
+    if (bytes == 0) bytes = 8;
+    bytes = (bytes + 255) & ~(size_t)255;
+    hipError_t e = persistent_ ? hipMalloc(&p, bytes) : hipMallocAsync(&p, bytes, s_);
+    if (e != hipSuccess || !p) {
+        (void)hipGetLastError();
+        set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+        throw Fail{SKIM_ENOMEM};
+    }
+    bufs_.push_back(p);
+    return p;
+}
+
+void Arena::release(void *p) {
+    for (auto &b : bufs_)
+        if (b == p) {
+            if (persistent_) {
+                (void)hipStreamSynchronize(s_);
+                (void)hipFree(b);
+            } else {
+                (void)hipFreeAsync(b, s_);
+            }
+            b = nullptr;
+        }
+}
+
+void *pinned_scratch(size_t bytes) {
+    thread_local void *buf = nullptr;
+    thread_local size_t cap = 0;
+    if (bytes > cap) {
+        if (buf) (void)hipHostFree(buf);
+        buf = nullptr;
+        cap = 0;
+        size_t want = bytes < 4096 ? 4096 : bytes;
+        SKIM_HIP(hipHostMalloc(&buf, want, hipHostMallocDefault));
+        cap = want;
+    }
+    return buf;
+}
+
+void read_back(void *host, const void *dev, size_t bytes, hipStream_t s) {
+    void *pin = pinned_scratch(bytes);
+    SKIM_HIP(hipMemcpyAsync(pin, dev, bytes, hipMemcpyDeviceToHost, s));
+    SKIM_HIP(hipStreamSynchronize(s));
+    std::memcpy(host, pin, bytes);
+}
+
+// ------------------------------------------------------------------- fills
+__global__ void k_fill_u32(uint32_t *p, uint32_t v, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_u64(uint64_t *p, uint64_t v, uint64_t n) {
+    for (uint64_t i = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+void fill_u32(uint32_t *p, uint32_t value, uint64_t count, hipStream_t s) {
+    if (!count) return;
+    k_fill_u32<<<grid_for(count, 256, 8192), 256, 0, s>>>(p, value, count);
+    SKIM_LAUNCH_CHECK();
+}
+void fill_u64(uint64_t *p, uint64_t value, uint64_t count, hipStream_t s) {
+    if (!count) return;
+    k_fill_u64<<<grid_for(count, 256, 8192), 256, 0, s>>>(p, value, count);
+    SKIM_LAUNCH_CHECK();
+}
+
+// -------------------------------------------------------------------- scan
+// Three phases: per-tile sums, scan of the tile sums, per-tile scan + offset.
+constexpr int kScanBlock = 256;
+constexpr int kScanPer = 16;
+constexpr uint64_t kScanTile = (uint64_t)kScanBlock * kScanPer;
+
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t x, uint64_t *sh, uint64_t *total) {
+    // inclusive Hillis-Steele in shared memory, then shift
+    const int t = threadIdx.x;
+    sh[t] = x;
+    __syncthreads();
+    for (int off = 1; off < kScanBlock; off <<= 1) {
+        uint64_t y = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += y;
+        __syncthreads();
+    }
+    uint64_t incl = sh[t];
+    *total = sh[kScanBlock - 1];
+    __syncthreads();
+    return incl - x;
+}
+
+__global__ void k_scan_tiles(const uint32_t *in, uint64_t n, uint64_t *tile_sum) {
+    __shared__ uint64_t sh[kScanBlock];
+    const uint64_t base = blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+    uint64_t s = 0;
+    for (int j = 0; j < kScanPer; ++j) {
+        uint64_t i = base + j;
+        if (i < n) s += in[i];
+    }
+    uint64_t tot;
+    block_excl_scan(s, sh, &tot);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_sums(uint64_t *tile_sum, uint64_t ntiles) {
+    __shared__ uint64_t sh[kScanBlock];
+    __shared__ uint64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t b = 0; b < ntiles; b += kScanBlock) {
+        uint64_t i = b + threadIdx.x;
+        uint64_t x = i < ntiles ? tile_sum[i] : 0;
+        uint64_t tot;
+        uint64_t ex = block_excl_scan(x, sh, &tot);
+        if (i < ntiles) tile_sum[i] = ex + carry;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) tile_sum[ntiles] = carry;
+}
+
+__global__ void k_scan_apply(const uint32_t *in, uint64_t n, const uint64_t *tile_sum,
+                             uint64_t *out) {
+    __shared__ uint64_t sh[kScanBlock];
+    const uint64_t base = blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanPer;
+    uint32_t v[kScanPer];
+    uint64_t s = 0;
+    for (int j = 0; j < kScanPer; ++j) {
+        uint64_t i = base + j;
+        v[j] = i < n ? in[i] : 0;
+        s += v[j];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl_scan(s, sh, &tot) + tile_sum[blockIdx.x];
+    for (int j = 0; j < kScanPer; ++j) {
+        uint64_t i = base + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+__global__ void k_scan_total(uint64_t *out, uint64_t n, const uint64_t *tile_sum, uint64_t ntiles) {
+    out[n] = tile_sum[ntiles];
+}
+
+void exclusive_scan_u32(const uint32_t *in, uint64_t *out, uint64_t n, Arena &a) {
+    hipStream_t s = a.stream();
+    const uint64_t ntiles = (n + kScanTile - 1) / kScanTile;
+    uint64_t *ts = a.alloc<uint64_t>(ntiles + 1);
+    if (ntiles) {
+        if (ntiles > 0x7FFFFFFFull) {
+            set_error("scan too large");
+            throw Fail{SKIM_EUNSUPPORTED};
+        }
+        k_scan_tiles<<<(unsigned)ntiles, kScanBlock, 0, s>>>(in, n, ts);
+        SKIM_LAUNCH_CHECK();
+    }
+    k_scan_sums<<<1, kScanBlock, 0, s>>>(ts, ntiles);
+    SKIM_LAUNCH_CHECK();
+    if (ntiles) {
+        k_scan_apply<<<(unsigned)ntiles, kScanBlock, 0, s>>>(in, n, ts, out);
+        SKIM_LAUNCH_CHECK();
+    }
+    k_scan_total<<<1, 1, 0, s>>>(out, n, ts, ntiles);
+    SKIM_LAUNCH_CHECK();
+    a.release(ts);
+}
+
+// --------------------------------------------------------------- validation
+__global__ void k_check_rows(const uint64_t *rp, uint32_t n, uint64_t m, uint32_t *err) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t a = rp[v], b = rp[v + 1];
+        uint32_t bad = 0;
+        if (a > b || b > m) bad |= 1u;
+        if (v == 0 && a != 0) bad |= 2u;
+        if (v == n - 1 && b != m) bad |= 4u;
+        if (bad) atomicOr(err, bad);
+    }
+}
+
+// Source of every edge by binary search on row_ptr (indices stay in range
+// even when row_ptr is invalid; such a graph is rejected anyway).
+__global__ void k_check_edges(const uint64_t *rp, const uint32_t *col, uint32_t n, uint64_t m,
+                              uint32_t *esrc, uint32_t *err) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = n;  // largest u with rp[u] <= e
+        while (hi - lo > 1) {
+            uint32_t mid = lo + (hi - lo) / 2;
+            if (rp[mid] <= e) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t u = lo;
+        const uint32_t v = col[e];
+        uint32_t bad = 0;
+        if (v >= n) bad |= 8u;
+        if (v == u) bad |= 16u;
+        if (e + 1 < m && e + 1 < rp[u + 1] && !(v < col[e + 1])) bad |= 32u;
+        if (bad) atomicOr(err, bad);
+        if (esrc) esrc[e] = u;
+    }
+}
+
+void validate_graph(const skim_graph *g, uint32_t *esrc, Arena &a) {
+    SKIM_REQUIRE(g != nullptr, "graph is NULL");
+    SKIM_REQUIRE(g->n >= 1, "n must be >= 1");
+    SKIM_REQUIRE((uint64_t)g->n * kPairStride < 0xFFFFFFFFull, "n too large (need 64 n < 2^32)");
+    SKIM_REQUIRE(g->row_ptr != nullptr, "row_ptr is NULL");
+    SKIM_REQUIRE(g->m == 0 || (g->col != nullptr && g->thr != nullptr), "col/thr is NULL");
+    hipStream_t s = a.stream();
+    uint32_t *err = a.alloc<uint32_t>(1);
+    fill_u32(err, 0, 1, s);
+    k_check_rows<<<grid_for(g->n, 256, 4096), 256, 0, s>>>(g->row_ptr, g->n, g->m, err);
+    SKIM_LAUNCH_CHECK();
+    if (g->m) {
+        k_check_edges<<<grid_for(g->m, 256, 16384), 256, 0, s>>>(g->row_ptr, g->col, g->n, g->m,
+                                                                 esrc, err);
+        SKIM_LAUNCH_CHECK();
+    }
+    uint32_t herr = 0;
+    read_back(&herr, err, sizeof herr, s);
+    a.release(err);
+    if (herr) {
+        std::string why;
+        if (herr & 7u) why += " row_ptr not a valid offset array;";
+        if (herr & 8u) why += " head id >= n;";
+        if (herr & 16u) why += " self-loop;";
+        if (herr & 32u) why += " heads not strictly increasing within a row (unsorted or duplicate);";
+        set_error("invalid graph:%s", why.c_str());
+        throw Fail{SKIM_EINVAL};
+    }
+}
+
+// ---------------------------------------------------------------- estimates
+__global__ void k_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
+                            uint32_t ell, double *est) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t sz = size[v];
+        const uint64_t tau = sz >= k ? ranks[v * k + (k - 1)] : 0;
+        est[v] = bottomk_estimate(sz, tau, k, ell);
+    }
+}
+
+void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
+                      uint32_t ell, double *est, hipStream_t s) {
+    k_estimates<<<grid_for(n, 256, 8192), 256, 0, s>>>(ranks, size, n, k, ell, est);
+    SKIM_LAUNCH_CHECK();
+}
+
+}  // namespace skim
+
+using namespace skim;
+
+extern "C" uint32_t skim_abi_version(void) { return SKIM_ABI_VERSION; }
+
+extern "C" const char *skim_last_error(void) { return g_err; }
+
+extern "C" skim_status skim_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n,
+                                      uint32_t k, uint32_t ell, double *est, void *stream) {
+    clear_error();
+    try {
+        SKIM_REQUIRE(ranks && size && est, "NULL pointer argument");
+        SKIM_REQUIRE(n >= 1 && k >= 2 && k <= 256 && ell >= 1 && ell <= 64,
+                     "need n >= 1, 2 <= k <= 256, 1 <= l <= 64");
+        hipStream_t s = (hipStream_t)stream;
+        launch_estimates(ranks, size, n, k, ell, est, s);
+        SKIM_HIP(hipStreamSynchronize(s));
+        return SKIM_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    }
+}

@@ -1,0 +1,427 @@
+// skim_greedy.hip -- SKIM greedy seed selection (Section 4, Algorithm 1).
+//
+// State on the device: live reverse and forward lists of every pair, the
+// pairs sorted by rank, covered[pair], size[node], and the inverted index
+// (for every processed pair, the nodes its reverse search reached).
+//
+// One persistent workgroup runs the whole selection loop (the loop is
+// sequential per seed; the state of the configurations this serves fits
+// on-chip caches):
+//  * scan: the next B pairs in rank order each run their complete reverse
+//    search in parallel (one thread per pair; an uncovered pair never reaches
+//    a covered one, so the searches are independent of each other's
+//    increments).  The first prefix length T at which some node's size
+//    reaches k is found by binary search over prefixes; pairs [0, T) are
+//    committed (size increments, index entries), the rest are re-scanned
+//    later.  The nodes that reached k all sit in pair T-1's search; the
+//    smallest id among them is the seed.
+//  * exhaustion: with every rank processed, the unselected node with the
+//    largest size (smallest id on ties) is the seed.
+//  * residual: one thread per instance runs the forward search from the seed
+//    over live out-edges, not entering covered pairs; every newly covered
+//    pair counts towards the seed's gain and decrements the size of every
+//    node in its index entry, which is then erased.
+#include "skim_internal.h"
+
+#include <rocprim/device/device_radix_sort.hpp>
+
+#include <memory>
+
+namespace skim {
+
+namespace {
+
+constexpr int kSkimBlock = 1024;
+constexpr uint32_t kFlagPool = 1u;
+
+struct SkCtl {
+    unsigned long long cursor;     // next position in the rank order
+    unsigned long long pool_used;  // index entries in use
+    unsigned long long need;       // pool entries a failed batch needed
+    uint32_t done;                 // seeds completed by the last launch
+    uint32_t flags;
+};
+
+struct SkArgs {
+    uint32_t n, ell, k;
+    uint64_t nsrc;
+    const uint64_t *rptr;
+    const uint32_t *radj;
+    const uint64_t *fptr;
+    const uint32_t *fadj;
+    const uint32_t *order;  // pair ids by increasing rank
+    uint32_t *covered;      // [64 n] 0/1
+    uint32_t *size;         // [n]
+    uint32_t *sel;          // [n] 0/1
+    uint32_t *idx_off;      // [64 n]
+    uint32_t *idx_cnt;      // [64 n], 0 = no entry
+    uint32_t *pool;
+    uint64_t pool_cap;
+    uint32_t *bcnt;         // [n] per-batch increment counters
+    uint32_t *queues;       // [kSkimBlock * n]
+    SkCtl *ctl;
+};
+
+__device__ __forceinline__ bool in_queue(const uint32_t *Q, uint32_t cnt, uint32_t w) {
+    for (uint32_t j = 0; j < cnt; ++j)
+        if (Q[j] == w) return true;
+    return false;
+}
+
+// State shared between the block's threads goes through agent-scope atomic
+// loads and stores, so no thread reads a stale cached copy of it.
+template <class T> __device__ __forceinline__ T ld(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ void st(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, uint32_t *seeds,
+                                                     uint64_t *gains, double *gain_d) {
+    __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_total;
+    __shared__ int s_x;
+    __shared__ uint32_t s_found, s_stop;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t n = A.n, k = A.k;
+    uint32_t *Q = A.queues + (uint64_t)tid * n;
+    if (tid == 0) {
+        s_cursor = A.ctl->cursor;
+        s_pool = A.ctl->pool_used;
+        s_stop = 0;
+        s_found = 0;
+    }
+    __syncthreads();
+    uint32_t done = 0;
+    for (uint32_t it = 0; it < goal; ++it) {
+        if (tid == 0) s_x = -1;
+        __syncthreads();
+        // ------------------------------------------------ scan pairs by rank
+        while (s_x < 0 && s_cursor < A.nsrc) {
+            const uint64_t cursor = s_cursor;
+            const uint64_t left = A.nsrc - cursor;
+            const uint32_t B = left < (uint64_t)kSkimBlock ? (uint32_t)left : (uint32_t)kSkimBlock;
+            uint32_t cnt = 0, p = 0;
+            if (tid < B) {
+                p = A.order[cursor + tid];
+                if (!ld(A.covered + p)) {
+                    const uint32_t i = p % kPairStride;
+                    Q[0] = p / kPairStride;
+                    cnt = 1;
+                    for (uint32_t head = 0; head < cnt; ++head) {
+                        const uint32_t q = Q[head] * kPairStride + i;
+                        for (uint64_t e = A.rptr[q]; e < A.rptr[q + 1]; ++e) {
+                            const uint32_t w = A.radj[e];
+                            if (!in_queue(Q, cnt, w)) Q[cnt++] = w;
+                        }
+                    }
+                }
+            }
+            // Does some node reach k within the first T pairs?  Sizes are
+            // below k at the start of a batch and grow by one per pair, so
+            // the smallest such T is found by binary search over prefixes.
+            bool filled = false;
+            uint32_t lo = 0, hi = B, T = B;
+            for (;;) {
+                if (tid < T)
+                    for (uint32_t j = 0; j < cnt; ++j) atomicAdd(A.bcnt + Q[j], 1u);
+                __syncthreads();
+                bool cand = false;
+                if (tid < T)
+                    for (uint32_t j = 0; j < cnt; ++j) cand |= ld(A.size + Q[j]) + ld(A.bcnt + Q[j]) >= k;
+                if (cand) atomicOr(&s_found, 1u);
+                __syncthreads();
+                const bool f = s_found != 0;
+                if (tid < T)
+                    for (uint32_t j = 0; j < cnt; ++j) st(A.bcnt + Q[j], 0u);
+                __syncthreads();
+                if (tid == 0) s_found = 0;
+                __syncthreads();
+                if (T == B) {
+                    filled = f;
+                    if (!f) break;
+                } else if (f) {
+                    hi = T;
+                } else {
+                    lo = T;
+                }
+                if (hi - lo <= 1) break;
+                T = lo + (hi - lo) / 2;
+            }
+            T = hi;  // B when nothing fills; else the first filling prefix
+            // does the committed prefix fit in the index pool?
+            if (tid == 0) s_total = 0;
+            __syncthreads();
+            if (tid < T && cnt) atomicAdd(&s_total, (unsigned long long)cnt);
+            __syncthreads();
+            if (s_pool + s_total > A.pool_cap) {
+                if (tid == 0) {
+                    A.ctl->flags |= kFlagPool;
+                    A.ctl->need = s_pool + s_total;
+                    s_stop = 1;
+                }
+                __syncthreads();
+                break;
+            }
+            if (tid < T && cnt) {
+                const unsigned long long off = atomicAdd(&s_pool, (unsigned long long)cnt);
+                for (uint32_t j = 0; j < cnt; ++j) {
+                    st(A.pool + off + j, Q[j]);
+                    atomicAdd(A.size + Q[j], 1u);
+                }
+                st(A.idx_off + p, (uint32_t)off);
+                st(A.idx_cnt + p, cnt);
+            }
+            __syncthreads();
+            if (filled && tid == T - 1) {
+                // the nodes that just reached k are in this pair's search
+                int x = -1;
+                for (uint32_t j = 0; j < cnt; ++j)
+                    if (ld(A.size + Q[j]) >= k && (x < 0 || Q[j] < (uint32_t)x)) x = (int)Q[j];
+                s_x = x;
+            }
+            if (tid == 0) s_cursor = cursor + T;
+            __syncthreads();
+        }
+        if (s_stop) break;
+        // --------------------------------------------------- exhaustion rule
+        if (s_x < 0) {
+            if (tid == 0) s_best = 0;
+            __syncthreads();
+            unsigned long long best = 0;
+            for (uint32_t v = tid; v < n; v += kSkimBlock)
+                if (!ld(A.sel + v)) {
+                    const unsigned long long key =
+                        ((unsigned long long)ld(A.size + v) << 32) | (0xFFFFFFFFu - v);
+                    best = key > best ? key : best;
+                }
+            atomicMax(&s_best, best);
+            __syncthreads();
+            // an unselected node always exists (the host checks s); keep the
+            // index in range regardless
+            if (tid == 0) {
+                const uint32_t v = 0xFFFFFFFFu - (uint32_t)s_best;
+                s_x = (s_best && v < n) ? (int)v : 0;
+            }
+            __syncthreads();
+        }
+        // ------------------------------------------------- residual problem
+        const uint32_t x = (uint32_t)s_x;
+        if (tid == 0) s_gain = 0;
+        __syncthreads();
+        if (tid < A.ell) {
+            const uint32_t i = tid;
+            const uint32_t px = x * kPairStride + i;
+            if (!ld(A.covered + px)) {
+                st(A.covered + px, 1u);
+                Q[0] = x;
+                uint32_t cnt = 1;
+                for (uint32_t head = 0; head < cnt; ++head) {
+                    const uint32_t v = Q[head];
+                    const uint32_t q = v * kPairStride + i;
+                    const uint32_t c = ld(A.idx_cnt + q);
+                    if (c) {
+                        const uint32_t o = ld(A.idx_off + q);
+                        for (uint32_t j = 0; j < c; ++j) atomicSub(A.size + ld(A.pool + o + j), 1u);
+                        st(A.idx_cnt + q, 0u);
+                    }
+                    for (uint64_t e = A.fptr[q]; e < A.fptr[q + 1]; ++e) {
+                        const uint32_t w = A.fadj[e];
+                        const uint32_t qw = w * kPairStride + i;
+                        if (!ld(A.covered + qw)) {
+                            st(A.covered + qw, 1u);
+                            Q[cnt++] = w;
+                        }
+                    }
+                }
+                atomicAdd(&s_gain, (unsigned long long)cnt);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            st(A.sel + x, 1u);
+            seeds[it] = x;
+            gains[it] = s_gain;
+            if (gain_d) gain_d[it] = (double)s_gain / (double)A.ell;
+        }
+        ++done;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        A.ctl->cursor = s_cursor;
+        A.ctl->pool_used = s_pool;
+        A.ctl->done = done;
+    }
+}
+
+__global__ void k_pair_keys(uint32_t n, uint32_t ell, uint64_t seed, uint64_t *keys,
+                            uint32_t *vals) {
+    const uint64_t total = (uint64_t)n * ell;
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < total;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = (uint32_t)(t / ell) * kPairStride + (uint32_t)(t % ell);
+        keys[t] = pair_rank(seed, p);
+        vals[t] = p;
+    }
+}
+
+}  // namespace
+
+}  // namespace skim
+
+struct skim_greedy_state {
+    int device = 0;
+    std::unique_ptr<skim::Arena> mem;
+    uint32_t n = 0, ell = 0, k = 0;
+    uint64_t seed = 0, m = 0;
+    const uint64_t *row_ptr = nullptr;
+    const uint32_t *col = nullptr;
+    const uint32_t *thr = nullptr;
+    uint32_t selected = 0;
+    skim::SkArgs args{};
+};
+
+namespace skim {
+
+static skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+                                        hipStream_t s) {
+    SKIM_REQUIRE(ell >= 1 && ell <= 64, "l must be in [1, 64]");
+    SKIM_REQUIRE(k >= 2, "k must be >= 2");
+    SKIM_REQUIRE(g != nullptr, "graph is NULL");
+    if ((uint64_t)g->n * kSkimBlock * 4 > (1ull << 30)) {
+        set_error("skim_greedy supports n <= 262144 (per-thread search queues)");
+        throw Fail{SKIM_EUNSUPPORTED};
+    }
+    auto st = std::make_unique<skim_greedy_state>();
+    SKIM_HIP(hipGetDevice(&st->device));
+    st->mem = std::make_unique<Arena>(s, /*persistent=*/true);
+    Arena &M = *st->mem;
+    const uint32_t n = g->n;
+    {
+        Arena T(s);
+        uint32_t *esrc = T.alloc<uint32_t>(g->m ? g->m : 1);
+        validate_graph(g, esrc, T);
+        LiveLists fwd;
+        LiveLists rev = build_live_lists(g, ell, seed, esrc, /*forward=*/false, M, &fwd);
+        st->args.rptr = rev.ptr;
+        st->args.radj = rev.adj;
+        st->args.fptr = fwd.ptr;
+        st->args.fadj = fwd.adj;
+        // pairs by increasing rank
+        const uint64_t nsrc = (uint64_t)n * ell;
+        uint64_t *keys = T.alloc<uint64_t>(nsrc);
+        uint64_t *keys2 = T.alloc<uint64_t>(nsrc);
+        uint32_t *vals = T.alloc<uint32_t>(nsrc);
+        uint32_t *order = M.alloc<uint32_t>(nsrc);
+        k_pair_keys<<<grid_for(nsrc, 256, 8192), 256, 0, s>>>(n, ell, seed, keys, vals);
+        SKIM_LAUNCH_CHECK();
+        size_t tmp_bytes = 0;
+        SKIM_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, keys2, vals, order, (size_t)nsrc,
+                                           0, 64, s));
+        void *tmp = T.get(tmp_bytes);
+        SKIM_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys2, vals, order, (size_t)nsrc, 0,
+                                           64, s));
+        SKIM_HIP(hipStreamSynchronize(s));
+        st->args.order = order;
+        st->args.nsrc = nsrc;
+    }
+    const uint64_t npairs = (uint64_t)n * kPairStride;
+    SkArgs &A = st->args;
+    A.n = n;
+    A.ell = ell;
+    A.k = k;
+    A.covered = M.alloc<uint32_t>(npairs);
+    A.size = M.alloc<uint32_t>(n);
+    A.sel = M.alloc<uint32_t>(n);
+    A.idx_off = M.alloc<uint32_t>(npairs);
+    A.idx_cnt = M.alloc<uint32_t>(npairs);
+    A.bcnt = M.alloc<uint32_t>(n);
+    A.queues = M.alloc<uint32_t>((uint64_t)kSkimBlock * n);
+    A.pool_cap = std::max<uint64_t>(1ull << 16, 2 * A.nsrc);
+    A.pool = M.alloc<uint32_t>(A.pool_cap);
+    A.ctl = M.alloc<SkCtl>(1);
+    fill_u32(A.covered, 0, npairs, s);
+    fill_u32(A.size, 0, n, s);
+    fill_u32(A.sel, 0, n, s);
+    fill_u32(A.idx_cnt, 0, npairs, s);
+    fill_u32(A.bcnt, 0, n, s);
+    fill_u64((uint64_t *)A.ctl, 0, sizeof(SkCtl) / 8, s);
+    st->n = n;
+    st->ell = ell;
+    st->k = k;
+    st->seed = seed;
+    st->m = g->m;
+    st->row_ptr = g->row_ptr;
+    st->col = g->col;
+    st->thr = g->thr;
+    SKIM_HIP(hipStreamSynchronize(s));
+    return st.release();
+}
+
+static void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_t *gains,
+                       double *gain_d, hipStream_t s) {
+    SkArgs &A = st->args;
+    uint32_t done = 0;
+    for (int attempt = 0; done < s_goal; ++attempt) {
+        SKIM_REQUIRE(attempt < 40, "SKIM index pool did not converge");
+        k_skim<<<1, kSkimBlock, 0, s>>>(A, s_goal - done, seeds + done, gains + done,
+                                        gain_d ? gain_d + done : nullptr);
+        SKIM_LAUNCH_CHECK();
+        SkCtl c;
+        read_back(&c, A.ctl, sizeof c, s);
+        done += c.done;
+        st->selected += c.done;
+        if (c.flags & kFlagPool) {
+            // grow the inverted-index pool, keep its contents, continue
+            const uint64_t cap = std::max<uint64_t>(2 * A.pool_cap, c.need + c.need / 2);
+            uint32_t *np = st->mem->alloc<uint32_t>(cap);
+            SKIM_HIP(hipMemcpyAsync(np, A.pool, c.pool_used * sizeof(uint32_t),
+                                    hipMemcpyDeviceToDevice, s));
+            st->mem->release(A.pool);
+            A.pool = np;
+            A.pool_cap = cap;
+            fill_u32(&A.ctl->flags, 0, 1, s);
+        } else if (done < s_goal) {
+            set_error("SKIM stopped early");
+            throw Fail{SKIM_EDEVICE};
+        }
+    }
+}
+
+}  // namespace skim
+
+extern "C" skim_status skim_greedy(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+                                   uint32_t s, uint32_t *seeds, uint64_t *gain_pairs, double *gain,
+                                   skim_greedy_state **state, void *stream) {
+    skim::clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    skim_greedy_state *own = nullptr;
+    try {
+        SKIM_REQUIRE(s == 0 || (seeds && gain_pairs), "seeds/gain_pairs is NULL");
+        skim_greedy_state *st = state ? *state : nullptr;
+        if (st) {
+            SKIM_REQUIRE(g && g->n == st->n && g->m == st->m && g->row_ptr == st->row_ptr &&
+                             g->col == st->col && g->thr == st->thr && ell == st->ell &&
+                             k == st->k && seed == st->seed,
+                         "resumed state belongs to a different graph or parameters");
+        } else {
+            st = skim::greedy_create(g, ell, k, seed, hs);
+            own = st;
+        }
+        SKIM_REQUIRE(s <= st->n - st->selected, "s exceeds the number of unselected nodes");
+        if (s) skim::greedy_run(st, s, seeds, gain_pairs, gain, hs);
+        SKIM_HIP(hipStreamSynchronize(hs));
+        if (state) *state = st;
+        else delete st;
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        if (own && !(state && *state == own)) delete own;
+        return f.st;
+    }
+}
+
+extern "C" void skim_greedy_state_free(skim_greedy_state *state) { delete state; }
+
+extern "C" uint32_t skim_greedy_state_selected(const skim_greedy_state *state) {
+    return state ? state->selected : 0;
+}

@@ -1,0 +1,237 @@
+// skim_query.hip -- influence queries from the sketches (Section 5.1).
+//
+// One wave per query.  The member sketches are sorted, so the distinct ranks
+// of their union come out in increasing order from a k-way merge: each step
+// takes the minimum head over the members (lane-local minimum, then a wave
+// minimum), then advances every member whose head equals it.
+//  * bottom-k estimator: stop at the k-th distinct value tau (or when the
+//    union runs out), estimate as for a single sketch;
+//  * Cohen-Kaplan (eq. unionest): run over every distinct non-threshold
+//    value; its weight is 1/rho(max tau_u over the members holding it), a
+//    non-full member counting as rho = 1; lane 0 adds the weights in
+//    increasing order of the value.
+// The batched path is one persistent launch whose waves pull queries from a
+// device counter; the plain path launches the same device code once per
+// query.
+#include "skim_internal.h"
+
+namespace skim {
+
+namespace {
+
+constexpr uint32_t kMaxMembers = 1024;  // members per query (LDS state)
+constexpr int kQBlock = 64;             // one wave per block
+
+struct QArgs {
+    const uint64_t *ranks;
+    const uint32_t *size;
+    uint32_t n, k, ell;
+    const uint64_t *qoff;
+    const uint32_t *qnodes;
+    double *est;
+    int32_t *qstatus;
+    uint32_t estimator;
+};
+
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)x, off);
+        const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), off);
+        const uint64_t y = ((uint64_t)hi << 32) | lo;
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)x, off);
+        const uint32_t hi = __shfl_xor((uint32_t)(x >> 32), off);
+        const uint64_t y = ((uint64_t)hi << 32) | lo;
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+// Answer query j with the calling wave (all 64 lanes, converged).
+__device__ void answer_query(const QArgs &Q, uint64_t j, uint32_t *mnode, uint16_t *mpos,
+                             uint16_t *mlim) {
+    const uint32_t lane = lane_id();
+    const uint64_t a = Q.qoff[j], b = Q.qoff[j + 1];
+    const uint64_t S = b - a;
+    const uint32_t k = Q.k;
+    // membership checks (node ids are validated per query)
+    bool bad = false;
+    for (uint64_t t = a + lane; t < b; t += 64) bad |= Q.qnodes[t] >= Q.n;
+    bad = __ballot(bad) != 0;
+    if (bad || S > kMaxMembers) {
+        if (lane == 0) {
+            Q.est[j] = 0.0;
+            if (Q.qstatus) Q.qstatus[j] = bad ? -1 : -2;
+        }
+        return;
+    }
+    if (S == 0) {
+        if (lane == 0) {
+            Q.est[j] = 0.0;
+            if (Q.qstatus) Q.qstatus[j] = 0;
+        }
+        return;
+    }
+    if (S == 1 && Q.estimator == 0) {
+        if (lane == 0) {
+            const uint32_t u = Q.qnodes[a];
+            const uint32_t sz = Q.size[u];
+            Q.est[j] = bottomk_estimate(sz, sz >= k ? Q.ranks[(uint64_t)u * k + k - 1] : 0, k, Q.ell);
+            if (Q.qstatus) Q.qstatus[j] = 0;
+        }
+        return;
+    }
+    // member state: node, next position, usable length
+    for (uint32_t t = lane; t < S; t += 64) {
+        const uint32_t u = Q.qnodes[a + t];
+        const uint32_t sz = Q.size[u];
+        mnode[t] = u;
+        mpos[t] = 0;
+        // CK ignores the threshold element of a full sketch
+        mlim[t] = (uint16_t)(Q.estimator == 1 && sz >= k ? k - 1 : (sz < k ? sz : k));
+    }
+    __syncthreads();
+    uint32_t d = 0;
+    uint64_t tau = 0;
+    double sum = 0.0;
+    for (;;) {
+        uint64_t lmin = kNone;
+        for (uint32_t t = lane; t < S; t += 64) {
+            const uint32_t p = mpos[t];
+            if (p < mlim[t]) {
+                const uint64_t h = Q.ranks[(uint64_t)mnode[t] * k + p];
+                lmin = h < lmin ? h : lmin;
+            }
+        }
+        const uint64_t g = wave_min_u64(lmin);
+        if (g == kNone) break;
+        // advance the holders of g; for CK also find their largest threshold
+        uint64_t tmax = 0;
+        for (uint32_t t = lane; t < S; t += 64) {
+            const uint32_t p = mpos[t];
+            if (p < mlim[t]) {
+                const uint32_t u = mnode[t];
+                if (Q.ranks[(uint64_t)u * k + p] == g) {
+                    mpos[t] = (uint16_t)(p + 1);
+                    if (Q.estimator == 1) {
+                        const uint64_t tu = Q.size[u] >= k ? Q.ranks[(uint64_t)u * k + k - 1] : kNone;
+                        tmax = tu > tmax ? tu : tmax;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (Q.estimator == 1) {
+            tmax = wave_max_u64(tmax);
+            if (lane == 0) sum += tmax == kNone ? 1.0 : 1.0 / rank_real(tmax);
+        } else {
+            ++d;
+            if (d == k) {
+                tau = g;
+                break;
+            }
+        }
+    }
+    if (lane == 0) {
+        Q.est[j] = Q.estimator == 1 ? sum / (double)Q.ell : bottomk_estimate(d, tau, k, Q.ell);
+        if (Q.qstatus) Q.qstatus[j] = 0;
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kQBlock) k_query_persistent(QArgs Q, uint64_t q,
+                                                               unsigned long long *next) {
+    __shared__ uint32_t mnode[kMaxMembers];
+    __shared__ uint16_t mpos[kMaxMembers];
+    __shared__ uint16_t mlim[kMaxMembers];
+    __shared__ unsigned long long jcur;
+    for (;;) {
+        if (threadIdx.x == 0) jcur = atomicAdd(next, 1ull);
+        __syncthreads();
+        const uint64_t j = jcur;
+        __syncthreads();
+        if (j >= q) break;
+        answer_query(Q, j, mnode, mpos, mlim);
+    }
+}
+
+__global__ void __launch_bounds__(kQBlock) k_query_one(QArgs Q, uint64_t j) {
+    __shared__ uint32_t mnode[kMaxMembers];
+    __shared__ uint16_t mpos[kMaxMembers];
+    __shared__ uint16_t mlim[kMaxMembers];
+    answer_query(Q, j, mnode, mpos, mlim);
+}
+
+__global__ void k_check_offsets(const uint64_t *qoff, uint64_t q, uint32_t *err) {
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j <= q;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        if (j == 0 && qoff[0] != 0) atomicOr(err, 1u);
+        if (j < q && qoff[j + 1] < qoff[j]) atomicOr(err, 2u);
+    }
+}
+
+}  // namespace
+
+static void query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
+                        uint32_t ell, uint64_t q, const uint64_t *qoff, const uint32_t *qnodes,
+                        uint32_t estimator, uint32_t mode, double *est, int32_t *qstatus,
+                        hipStream_t s) {
+    SKIM_REQUIRE(ranks && size, "sketches are NULL");
+    SKIM_REQUIRE(n >= 1 && k >= 2 && k <= 256 && ell >= 1 && ell <= 64,
+                 "need n >= 1, 2 <= k <= 256, 1 <= l <= 64");
+    SKIM_REQUIRE(estimator <= 1, "estimator must be 0 (bottom-k) or 1 (Cohen-Kaplan)");
+    SKIM_REQUIRE(mode <= 1, "mode must be 0 (batched) or 1 (one launch per query)");
+    if (q == 0) return;
+    SKIM_REQUIRE(qoff && est, "qoff/est is NULL");
+    Arena A(s);
+    uint32_t *err = A.alloc<uint32_t>(1);
+    fill_u32(err, 0, 1, s);
+    k_check_offsets<<<grid_for(q + 1, 256, 4096), 256, 0, s>>>(qoff, q, err);
+    SKIM_LAUNCH_CHECK();
+    uint32_t herr = 0;
+    read_back(&herr, err, sizeof herr, s);
+    SKIM_REQUIRE(herr == 0, "qoff must start at 0 and be non-decreasing");
+    uint64_t total = 0;
+    read_back(&total, qoff + q, sizeof total, s);
+    SKIM_REQUIRE(total == 0 || qnodes, "qnodes is NULL");
+    QArgs Q{ranks, size, n, k, ell, qoff, qnodes, est, qstatus, estimator};
+    if (mode == 0) {
+        unsigned long long *next = A.alloc<unsigned long long>(1);
+        fill_u64((uint64_t *)next, 0, 1, s);
+        int dev = 0, cus = 256;
+        SKIM_HIP(hipGetDevice(&dev));
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const uint64_t want = (uint64_t)cus * 16;
+        const unsigned grid = (unsigned)(q < want ? q : want);
+        k_query_persistent<<<grid, kQBlock, 0, s>>>(Q, q, next);
+        SKIM_LAUNCH_CHECK();
+    } else {
+        for (uint64_t j = 0; j < q; ++j) {
+            k_query_one<<<1, kQBlock, 0, s>>>(Q, j);
+            SKIM_LAUNCH_CHECK();
+        }
+    }
+    SKIM_HIP(hipStreamSynchronize(s));
+}
+
+}  // namespace skim
+
+extern "C" skim_status skim_query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
+                                        uint32_t k, uint32_t ell, uint64_t q, const uint64_t *qoff,
+                                        const uint32_t *qnodes, uint32_t estimator, uint32_t mode,
+                                        double *est, int32_t *qstatus, void *stream) {
+    skim::clear_error();
+    try {
+        skim::query_batch(ranks, size, n, k, ell, q, qoff, qnodes, estimator, mode, est, qstatus,
+                          (hipStream_t)stream);
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}

@@ -1,0 +1,68 @@
+"""GPU parity of skim_greedy against the oracle's Algorithm 1: bit-exact seed
+sequences and newly-covered pair counts, resumed runs equal to one-shot runs,
+the exhaustion (exact-greedy) regime, and the served-SKIM configuration."""
+import numpy as np
+import pytest
+
+from workloads import from_edges
+from workloads.configs import make_config, make_graph
+from brute import random_small_graph
+from gpu_util import gpu_greedy, log
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_skim_config_200_seeds(oracle_lib):
+    cfg = make_config("served-skim")
+    g = make_graph(cfg)
+    log("served-skim 200 seeds one-shot")
+    seeds, gains, gd, sel = gpu_greedy(g, cfg["ell"], cfg["k"], cfg["seed"], [200])
+    ws, wg, _ = oracle_lib.skim(g, cfg["seed"], cfg["ell"], cfg["k"], 200)
+    assert np.array_equal(seeds, ws)
+    assert np.array_equal(gains, wg)
+    assert np.array_equal(gd, wg.astype(np.float64) / cfg["ell"])
+    assert sel == 200
+    log("served-skim 4 x 50 resumed")
+    s2, g2, _, _ = gpu_greedy(g, cfg["ell"], cfg["k"], cfg["seed"], [50, 50, 50, 50])
+    assert np.array_equal(s2, seeds) and np.array_equal(g2, gains)
+
+
+@pytest.mark.parametrize("ell,k", [(1, 2), (4, 3), (16, 8), (64, 64)])
+def test_random_graphs(oracle_lib, ell, k):
+    rng = np.random.default_rng(ell * 7 + k)
+    for trial in range(4):
+        n = int(rng.integers(2, 80))
+        src, dst, thr = random_small_graph(rng, n, int(rng.integers(0, 3 * n)),
+                                           [0xFFFFFFFF, 0xFFFFFFFF // 2, 0xFFFFFFFF // 10])
+        g = from_edges(n, src, dst, thr)
+        seed = int(rng.integers(0, 2 ** 62))
+        s = int(rng.integers(1, n + 1))
+        log(f"skim ell={ell} k={k} n={n} m={g.m} s={s} seed={seed}")
+        seeds, gains, _, _ = gpu_greedy(g, ell, k, seed, [s])
+        ws, wg, _ = oracle_lib.skim(g, seed, ell, k, s)
+        assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+
+
+def test_exhaustion_full_permutation(oracle_lib):
+    rng = np.random.default_rng(4)
+    n = 60
+    src, dst, thr = random_small_graph(rng, n, 150, [0xFFFFFFFF // 2])
+    g = from_edges(n, src, dst, thr)
+    ell, k = 8, 10_000  # no sketch ever fills: every seed by the exhaustion rule
+    seeds, gains, _, _ = gpu_greedy(g, ell, k, 7, [20, 40])
+    ws, wg, cnt = oracle_lib.skim(g, 7, ell, k, n)
+    assert cnt["fallback"] == n
+    assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+    assert int(gains.sum()) == n * ell
+
+
+def test_too_many_seeds_rejected():
+    import torch
+    import paper_1408_6282_amd as sk
+    g = from_edges(5, [0, 1], [1, 2])
+    G = sk.DeviceGraph.from_host(g, "cuda:0")
+    a = torch.empty(6, dtype=torch.int32, device="cuda:0")
+    b = torch.empty(6, dtype=torch.int64, device="cuda:0")
+    with pytest.raises(sk.SkimError) as ei:
+        sk.skim_greedy(G, 4, 4, 1, 6, a, b)
+    assert ei.value.status == sk.SKIM_EINVAL
