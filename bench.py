@@ -1,0 +1,241 @@
+#!/usr/bin/env python
+"""Benchmark of the sketch-based influence hot path on one MI355X.
+
+A step is one combined-sketch build (live lists, rank windows, pruned
+reverse searches, bottom-k merge, per-node estimates) of the 1M-node
+Chung-Lu weighted-cascade workload (l = 64, k = 64) whose inputs are already
+resident in HBM.  `value` is live-edge traversals per second, the numerator
+being the oracle's exact count W_live for that workload (Algorithm 2's
+work), not the kernels' own counts.
+
+Beside it the same JSON line reports the roofline of the dominant kernel
+(timed live with HIP events), the CPU oracle on a bounded sample, batched vs
+one-launch-per-query throughput on the lognormal query workload, SKIM on
+the served-SKIM configuration, and served-query latency.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "live-edge traversals/s (sketch build); batched vs plain queries/s, p99 latency"
+DOMINANT = "k_expand"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def graph_digest(g):
+    import hashlib
+    h = hashlib.sha256()
+    for a in (g.row_ptr, g.col, g.thr):
+        h.update(memoryview(a).cast("B"))
+    return h.hexdigest()
+
+
+def oracle_counters(name, g, cfg):
+    """The oracle's Algorithm-2 counters for this exact graph (stored, else computed)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name.replace('-', '_')}_counters.json")
+    dig = graph_digest(g)
+    if os.path.exists(path):
+        with open(path) as f:
+            d = json.load(f)
+        if (d["graph_sha256"] == dig and d["ell"] == cfg["ell"] and d["k"] == cfg["k"]
+                and d["seed"] == cfg["seed"]):
+            return d["counters"]
+    log("stored oracle counters do not match this graph; running the oracle")
+    import oracle
+    _, _, cnt = oracle.build_alg2(g, cfg["seed"], cfg["ell"], cfg["k"])
+    return cnt
+
+
+def algorithmic_bytes_expand(cnt):
+    """Bytes the pruned reverse search must move (Algorithm 2's work).
+
+    Per rank insertion (an accepted node-instance-source visit): read the
+    visit (8 B) and its live-list bounds (16 B), write the pair state on
+    claim (8 B) and the new visit (8 B).  Per live-edge traversal: read the
+    live source id (4 B) and the visited pair's state word (8 B).
+    """
+    return cnt["n_ins"] * (8 + 16 + 8 + 8) + cnt["w_live"] * (4 + 8)
+
+
+def cpu_baseline(g, cfg, max_threads=16):
+    """The oracle's Algorithm 2 on a bounded sample: the first C instances."""
+    import oracle
+    cores = max(1, min(max_threads, os.cpu_count() or 1))
+    ell_s = min(cfg["ell"], cores)
+    t = time.perf_counter()
+    _, _, cnt = oracle.build_alg2(g, cfg["seed"], ell_s, cfg["k"], threads=cores)
+    dt = time.perf_counter() - t
+    return {"value": cnt["w_live"] / dt, "unit": "live-edge traversals/s", "cores": min(cores, ell_s),
+            "kind": "oracle", "seconds": round(dt, 3),
+            "sample": f"Algorithm 2 over instances 0..{ell_s - 1} of the {cfg['ell']} "
+                      f"(same graph, k={cfg['k']}, seed {cfg['seed']}); W_live of the sample "
+                      f"= {cnt['w_live']}"}
+
+
+def bench_build(args, torch, sk, g, cfg):
+    dev = torch.device("cuda:0")
+    G = sk.DeviceGraph.from_host(g, dev)
+    n, ell, k, seed = g.n, cfg["ell"], cfg["k"], cfg["seed"]
+    ranks = torch.empty(n * k, dtype=torch.int64, device=dev)
+    size = torch.empty(n, dtype=torch.int32, device=dev)
+    est = torch.empty(n, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        work = sk.skim_build_sketches(G, ell, k, seed, ranks, size, est, stream=stream)
+        log(f"warmup {w}: {work}")
+    sk.skim_timing_reset()
+    sk.skim_timing_enable(DOMINANT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        work = sk.skim_build_sketches(G, ell, k, seed, ranks, size, est, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sk.skim_timing_enable(None)
+    kms, klaunch = sk.skim_timing_read(DOMINANT)
+    log(f"timed {args.steps} steps: {(t1 - t0) * 1e3 / args.steps:.3f} ms/step; {work}")
+    return (t1 - t0) / args.steps, work, kms, klaunch
+
+
+def bench_queries(torch, sk, reps=5, plain_q=20000):
+    from workloads import lognormal_query_sets
+    from workloads.configs import make_config, make_graph
+    cfg = make_config("batched-query")
+    g = make_graph(cfg)
+    dev = torch.device("cuda:0")
+    G = sk.DeviceGraph.from_host(g, dev)
+    n, ell, k = g.n, cfg["ell"], cfg["k"]
+    ranks = torch.empty(n * k, dtype=torch.int64, device=dev)
+    size = torch.empty(n, dtype=torch.int32, device=dev)
+    sk.skim_build_sketches(G, ell, k, cfg["seed"], ranks, size)
+    off, nodes = lognormal_query_sets(cfg["Q"], n, cfg["qseed"])
+    qo = torch.from_numpy(off.view(np.int64)).to(dev)
+    qn = torch.from_numpy(nodes.view(np.int32)).to(dev)
+    Q = cfg["Q"]
+    est = torch.empty(Q, dtype=torch.float64, device=dev)
+    sk.skim_query_batch(ranks, size, n, k, ell, qo, qn, est)  # warm-up
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sk.skim_query_batch(ranks, size, n, k, ell, qo, qn, est)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    tb = float(np.median(times))
+    # plain path: one launch per query, on the first plain_q queries
+    po = qo[:plain_q + 1].clone()
+    pest = torch.empty(plain_q, dtype=torch.float64, device=dev)
+    sk.skim_query_batch(ranks, size, n, k, ell, po, qn, pest, mode=1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sk.skim_query_batch(ranks, size, n, k, ell, po, qn, pest, mode=1)
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t
+    same = bool(torch.equal(pest, est[:plain_q]))
+    sizes = np.diff(off.astype(np.int64))
+    return {"workload": "batched-query", "queries": Q, "mean_set_size": round(float(sizes.mean()), 3),
+            "batched_queries_per_s": Q / tb, "batched_ms": tb * 1e3,
+            "plain_queries_per_s": plain_q / tp, "plain_sample": plain_q,
+            "batched_over_plain": (Q / tb) / (plain_q / tp), "identical_estimates": same}
+
+
+def bench_skim(torch, sk, reps=3):
+    from workloads.configs import make_config, make_graph
+    cfg = make_config("served-skim")
+    g = make_graph(cfg)
+    dev = torch.device("cuda:0")
+    G = sk.DeviceGraph.from_host(g, dev)
+    s = cfg["s"]
+    seeds = torch.empty(s, dtype=torch.int32, device=dev)
+    gains = torch.empty(s, dtype=torch.int64, device=dev)
+    sk.skim_greedy(G, cfg["ell"], cfg["k"], cfg["seed"], s, seeds, gains)
+    times = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sk.skim_greedy(G, cfg["ell"], cfg["k"], cfg["seed"], s, seeds, gains)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    t = float(np.median(times))
+    return {"workload": "served-skim", "seeds": s, "ms": t * 1e3, "seeds_per_s": s / t,
+            "influence_pairs": int(gains.sum().item())}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="chung-lu-1m")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="build only (no query/SKIM legs)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1408_6282_amd as sk
+    from workloads.configs import make_config, make_graph
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    sk.load_library()
+    cfg = make_config(args.workload)
+    log(f"generating {args.workload}")
+    g = make_graph(cfg)
+    cnt = oracle_counters(args.workload, g, cfg)
+    log(f"oracle counters {cnt}")
+
+    sec, work, kms, klaunch = bench_build(args, torch, sk, g, cfg)
+    value = cnt["w_live"] / sec
+    alg_bytes = algorithmic_bytes_expand(cnt)
+    roof = None
+    if klaunch:
+        per_launch_bytes = alg_bytes * args.steps / klaunch
+        avg_s = kms / klaunch / 1e3
+        achieved = per_launch_bytes / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": DOMINANT, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "launches_per_step": klaunch / args.steps, "avg_launch_us": avg_s * 1e6,
+                "kernel_ms_per_step": kms / args.steps,
+                "algorithmic_bytes_per_step": alg_bytes}
+    out = {
+        "metric": METRIC, "value": value, "unit": "live-edge traversals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "graph": "Chung-Lu power law, gamma 2.1",
+                   "n": g.n, "m": g.m, "ell": cfg["ell"], "k": cfg["k"], "seed": cfg["seed"],
+                   "probabilities": "weighted cascade 1/indeg(head)",
+                   "parallelism": "single GPU"},
+        "oracle_counters": cnt, "device_work": work, "roofline": roof,
+    }
+    if not args.no_extras:
+        log("queries")
+        out["queries"] = bench_queries(torch, sk)
+        log("skim")
+        out["skim"] = bench_skim(torch, sk)
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline(g, cfg)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -158,6 +158,19 @@ void skim_greedy_state_free(skim_greedy_state *state);
 /* Seeds selected so far by a state (0 for NULL). */
 uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
 
+/*
+ * Kernel timing, for measurement: while a kernel name is enabled, every
+ * launch of that kernel (e.g. "k_expand", the level expansion of the pruned
+ * reverse search) made by the calling thread is bracketed by HIP events on
+ * the call's stream.  Totals accumulate across calls until reset.
+ *   skim_timing_enable(name): time launches of `name` (NULL = off).
+ *   skim_timing_read(name, total_ms, launches): totals so far (HOST
+ *   pointers, may be NULL); returns 1 if the kernel has entries, else 0.
+ */
+void skim_timing_enable(const char *kernel);
+void skim_timing_reset(void);
+int skim_timing_read(const char *kernel, double *total_ms, uint64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -205,7 +205,7 @@ typedef struct {
     uint32_t ell, k;
     uint64_t *X;          /* [n*k] global sketches */
     uint32_t *Xs;         /* [n]   global sizes    */
-    uint8_t *emax;        /* [n]   max_i E_{v,i} (under lock) */
+    uint16_t *emax;       /* [n]   max_i E_{v,i} (under lock) */
     pthread_mutex_t *locks;
     uint32_t nlocks;
     uint32_t next_inst;   /* work counter (under qlock) */
@@ -331,7 +331,7 @@ static void *alg2_worker(void *arg)
             }
             memcpy(X, merged, sizeof(uint64_t) * o);
             c->Xs[v] = o;
-            if (lc > c->emax[v]) c->emax[v] = (uint8_t)lc;
+            if (lc > c->emax[v]) c->emax[v] = (uint16_t)lc;
             pthread_mutex_unlock(lk);
         }
         pthread_mutex_lock(&c->qlock);
@@ -352,7 +352,7 @@ int or_build_alg2(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
                   uint32_t nthreads, uint64_t *out_ranks, uint32_t *out_size,
                   or_build_counters *counters)
 {
-    if (ell < 1 || ell > 64 || k < 1 || k > 255 || n == 0) return -1;
+    if (ell < 1 || ell > 64 || k < 1 || k > 65535 || n == 0) return -1;
     or_graph g = {n, row_ptr, col, thr};
     alg2_ctx c;
     memset(&c, 0, sizeof c);
@@ -360,7 +360,7 @@ int or_build_alg2(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
     c.X = out_ranks; c.Xs = out_size;
     for (uint64_t j = 0; j < (uint64_t)n * k; j++) out_ranks[j] = OR_NONE;
     for (uint32_t v = 0; v < n; v++) out_size[v] = 0;
-    c.emax = calloc(n, 1);
+    c.emax = calloc(n, sizeof(uint16_t));
     c.nlocks = 4096;
     c.locks = malloc(sizeof(pthread_mutex_t) * c.nlocks);
     for (uint32_t j = 0; j < c.nlocks; j++) pthread_mutex_init(&c.locks[j], NULL);

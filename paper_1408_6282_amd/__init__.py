@@ -21,7 +21,8 @@ _STATUS = {0: "SKIM_OK", 1: "SKIM_EINVAL", 2: "SKIM_ENOMEM", 3: "SKIM_EDEVICE", 
 
 EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_estimates",
            "skim_query_batch", "skim_greedy", "skim_greedy_state_free",
-           "skim_greedy_state_selected"]
+           "skim_greedy_state_selected", "skim_timing_enable", "skim_timing_reset",
+           "skim_timing_read"]
 
 
 class SkimError(RuntimeError):
@@ -68,6 +69,12 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_free.argtypes = [vp]
     lib.skim_greedy_state_selected.restype = C.c_uint32
     lib.skim_greedy_state_selected.argtypes = [vp]
+    lib.skim_timing_enable.restype = None
+    lib.skim_timing_enable.argtypes = [C.c_char_p]
+    lib.skim_timing_reset.restype = None
+    lib.skim_timing_reset.argtypes = []
+    lib.skim_timing_read.restype = C.c_int
+    lib.skim_timing_read.argtypes = [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
     _lib = lib
     return lib
 
@@ -184,3 +191,19 @@ def skim_greedy(graph: DeviceGraph, ell: int, k: int, seed: int, s: int, seeds, 
 
 def skim_greedy_state_free(state: GreedyState):
     state.free()
+
+
+def skim_timing_enable(kernel: str | None):
+    load_library().skim_timing_enable(kernel.encode() if kernel else None)
+
+
+def skim_timing_reset():
+    load_library().skim_timing_reset()
+
+
+def skim_timing_read(kernel: str):
+    """(total milliseconds, launches) of the timed kernel so far."""
+    ms = C.c_double(0)
+    n = C.c_uint64(0)
+    load_library().skim_timing_read(kernel.encode(), C.byref(ms), C.byref(n))
+    return float(ms.value), int(n.value)

@@ -492,14 +492,20 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
             SKIM_LAUNCH_CHECK();
 
             WinArgs WA{words, items, items_cap, hset, logcap, ws, we, k, ctl};
-            k_seed_window<<<grid_for(nw, kBlock, 8192), kBlock, 0, s>>>(WA, sources);
+            {
+                LaunchTimer t("k_seed_window", s);
+                k_seed_window<<<grid_for(nw, kBlock, 8192), kBlock, 0, s>>>(WA, sources);
+            }
             SKIM_LAUNCH_CHECK();
             k_advance<<<1, 1, 0, s>>>(ctl, (uint32_t)-1);  // lb[1] = count (level -1 -> slot 1)
             SKIM_LAUNCH_CHECK();
             uint32_t level = 0, batch = 2;
             for (;;) {
                 for (uint32_t j = 0; j < batch; ++j, ++level) {
-                    k_expand<<<2048, kBlock, 0, s>>>(WA, lptr, lsrc, level);
+                    {
+                        LaunchTimer t("k_expand", s);
+                        k_expand<<<2048, kBlock, 0, s>>>(WA, lptr, lsrc, level);
+                    }
                     SKIM_LAUNCH_CHECK();
                     k_advance<<<1, 1, 0, s>>>(ctl, level);
                     SKIM_LAUNCH_CHECK();
@@ -525,8 +531,11 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
         const uint64_t rec_before = h.records;
         for (int attempt = 0;; ++attempt) {
             SKIM_REQUIRE(attempt < 8, "record buffer did not fit");
-            k_records<<<grid_for(count, kBlock, 8192), kBlock, 0, s>>>(items, count, xcnt, xadd, k,
-                                                                       rec, rec_cap, ctl);
+            {
+                LaunchTimer t("k_records", s);
+                k_records<<<grid_for(count, kBlock, 8192), kBlock, 0, s>>>(items, count, xcnt, xadd,
+                                                                           k, rec, rec_cap, ctl);
+            }
             SKIM_LAUNCH_CHECK();
             read_back(&h, ctl, sizeof h, s);
             if (!(h.flags & kOvfRecords)) break;
@@ -545,7 +554,10 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
         }
         k_fold<<<grid_for(n, kBlock, 8192), kBlock, 0, s>>>(xcnt, xadd, n, k, ctl);
         SKIM_LAUNCH_CHECK();
-        k_count_arrivals<<<grid_for(count, kBlock, 16384), kBlock, 0, s>>>(items, count, words);
+        {
+            LaunchTimer t("k_count_arrivals", s);
+            k_count_arrivals<<<grid_for(count, kBlock, 16384), kBlock, 0, s>>>(items, count, words);
+        }
         SKIM_LAUNCH_CHECK();
         ++windows_done;
     }
@@ -561,14 +573,19 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     uint64_t *seg = A.alloc<uint64_t>(nrec ? nrec : 1);
     fill_u32(xadd, 0, n + 1, s);
     if (nrec) {
+        LaunchTimer t("k_group", s);
         k_group<<<grid_for(nrec, kBlock, 16384), kBlock, 0, s>>>(rec, nrec, sources, seed, goff, xadd,
                                                                  seg);
         SKIM_LAUNCH_CHECK();
     }
-    k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(goff, seg, n, k, ranks_out, size_out);
+    {
+        LaunchTimer t("k_select", s);
+        k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(goff, seg, n, k, ranks_out, size_out);
+    }
     SKIM_LAUNCH_CHECK();
     if (est_out) launch_estimates(ranks_out, size_out, n, k, ell, est_out, s);
     SKIM_HIP(hipStreamSynchronize(s));
+    timing_resolve();
     if (work) {
         work[0] = total_items;
         work[1] = total_scans;

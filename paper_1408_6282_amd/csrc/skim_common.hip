@@ -4,6 +4,7 @@
 #include "skim_internal.h"
 
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 
@@ -92,6 +93,61 @@ void read_back(void *host, const void *dev, size_t bytes, hipStream_t s) {
     SKIM_HIP(hipMemcpyAsync(pin, dev, bytes, hipMemcpyDeviceToHost, s));
     SKIM_HIP(hipStreamSynchronize(s));
     std::memcpy(host, pin, bytes);
+}
+
+// ------------------------------------------------------------ kernel timing
+namespace {
+std::mutex g_time_mu;
+std::string g_time_kernel;  // empty = timing off
+struct TimeAcc {
+    double ms = 0;
+    uint64_t launches = 0;
+};
+std::map<std::string, TimeAcc> g_time_acc;
+struct PendingTime {
+    std::string name;
+    hipEvent_t a, b;
+};
+thread_local std::vector<PendingTime> g_pending;
+}  // namespace
+
+LaunchTimer::LaunchTimer(const char *kernel, hipStream_t s) : s_(s), name_(kernel) {
+    {
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        if (g_time_kernel.empty() || g_time_kernel != kernel) return;
+    }
+    if (hipEventCreate(&a_) != hipSuccess || hipEventRecord(a_, s_) != hipSuccess) {
+        (void)hipGetLastError();
+        a_ = nullptr;
+    }
+}
+
+LaunchTimer::~LaunchTimer() {
+    if (!a_) return;
+    hipEvent_t b = nullptr;
+    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s_) == hipSuccess) {
+        g_pending.push_back({name_, a_, b});
+    } else {
+        (void)hipGetLastError();
+        (void)hipEventDestroy(a_);
+        if (b) (void)hipEventDestroy(b);
+    }
+}
+
+void timing_resolve() {
+    for (auto &p : g_pending) {
+        float ms = 0;
+        if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            std::lock_guard<std::mutex> lk(g_time_mu);
+            auto &acc = g_time_acc[p.name];
+            acc.ms += ms;
+            acc.launches += 1;
+        }
+        (void)hipGetLastError();
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g_pending.clear();
 }
 
 // ------------------------------------------------------------------- fills
@@ -306,6 +362,29 @@ void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, u
 using namespace skim;
 
 extern "C" uint32_t skim_abi_version(void) { return SKIM_ABI_VERSION; }
+
+extern "C" void skim_timing_enable(const char *kernel) {
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    g_time_kernel = kernel ? kernel : "";
+}
+
+extern "C" void skim_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    g_time_acc.clear();
+}
+
+extern "C" int skim_timing_read(const char *kernel, double *total_ms, uint64_t *launches) {
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    auto it = g_time_acc.find(kernel ? kernel : "");
+    if (it == g_time_acc.end()) {
+        if (total_ms) *total_ms = 0;
+        if (launches) *launches = 0;
+        return 0;
+    }
+    if (total_ms) *total_ms = it->second.ms;
+    if (launches) *launches = it->second.launches;
+    return 1;
+}
 
 extern "C" const char *skim_last_error(void) { return g_err; }
 

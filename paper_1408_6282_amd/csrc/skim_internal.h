@@ -178,6 +178,21 @@ struct LiveLists {
 LiveLists build_live_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
                            bool forward, Arena &a, LiveLists *also_other = nullptr);
 
+// Optional per-kernel timing: while a kernel name is enabled, each launch of
+// that kernel is bracketed by HIP events on its stream; durations are folded
+// into the totals when the owning call resolves them after its final sync.
+class LaunchTimer {
+  public:
+    LaunchTimer(const char *kernel, hipStream_t s);
+    ~LaunchTimer();
+
+  private:
+    hipEvent_t a_ = nullptr;
+    hipStream_t s_;
+    const char *name_;
+};
+void timing_resolve();  // call after the stream has been synchronised
+
 // Validate a forward CSR on the device; throws Fail{SKIM_EINVAL} if invalid.
 // On success writes esrc[m] (source node of every edge) when esrc != nullptr.
 void validate_graph(const skim_graph *g, uint32_t *esrc, Arena &a);

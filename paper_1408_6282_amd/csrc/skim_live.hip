@@ -77,6 +77,7 @@ LiveLists build_live_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     const unsigned grid = grid_for(m, 256, 32768);
     if (m) {
         masks = a.alloc<uint64_t>(m);
+        LaunchTimer t("k_live_masks", s);
         k_live_masks<<<grid, 256, 0, s>>>(esrc, g->col, g->thr, m, n, ell, seed, masks, rcnt, fcnt);
         SKIM_LAUNCH_CHECK();
     }
@@ -97,6 +98,7 @@ LiveLists build_live_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
         fwd.adj = a.alloc<uint32_t>(tot ? tot : 1);
     }
     if (m) {
+        LaunchTimer t("k_live_fill", s);
         k_live_fill<<<grid, 256, 0, s>>>(esrc, g->col, masks, m, rev.ptr, rcnt, rev.adj, fwd.ptr,
                                          fcnt, fwd.adj);
         SKIM_LAUNCH_CHECK();

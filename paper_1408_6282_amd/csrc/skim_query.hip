@@ -209,6 +209,7 @@ static void query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         const uint64_t want = (uint64_t)cus * 16;
         const unsigned grid = (unsigned)(q < want ? q : want);
+        LaunchTimer t("k_query_persistent", s);
         k_query_persistent<<<grid, kQBlock, 0, s>>>(Q, q, next);
         SKIM_LAUNCH_CHECK();
     } else {
@@ -218,6 +219,7 @@ static void query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
         }
     }
     SKIM_HIP(hipStreamSynchronize(s));
+    timing_resolve();
 }
 
 }  // namespace skim

@@ -7,8 +7,8 @@ synthetic graphs stand in for them:
 * Erdos-Renyi: exactly m distinct ordered pairs (u, v), u != v.
 * Chung-Lu: expected degrees w_i ~ (i+1)^(-1/(gamma-1)) for in- and
   out-degrees, each behind its own seeded node permutation; edges are sampled
-  source ~ out-weight, head ~ in-weight, then self-loops and duplicates are
-  dropped and the sample is topped up until exactly m distinct edges remain.
+  source ~ out-weight, head ~ in-weight, self-loops and duplicates dropped,
+  and a seeded subset of exactly m distinct edges kept.
 * R-MAT: 2^scale nodes, a fixed number of recursive quadrant samples with
   probabilities (a, b, c, d), a seeded node permutation, then self-loops and
   duplicates dropped (the final edge count is reported, not topped up).
@@ -127,41 +127,42 @@ def er_graph(n: int, m: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return _csr_from_keys(n, keys)
 
 
-def _sample_categorical(rng, cdf: np.ndarray, size: int) -> np.ndarray:
+def _sample_powerlaw_rank(rng, n: int, expo: float, size: int) -> np.ndarray:
+    """Rank j in [0, n) with P(j) ~ (j+1)^-expo, by inverting the continuous
+    cumulative weight int_0^x (t+1)^-expo dt (a discretised power law)."""
     u = rng.random(size)
-    return np.searchsorted(cdf, u, side="right").clip(0, cdf.shape[0] - 1)
+    one = 1.0 - expo
+    top = (n + 1.0) ** one - 1.0
+    x = np.power(1.0 + u * top, 1.0 / one) - 1.0
+    return np.minimum(x.astype(np.int64), n - 1)
 
 
 def chung_lu_graph(n: int, m: int, gamma: float, seed: int) -> tuple[np.ndarray, np.ndarray]:
-    """Chung-Lu directed graph with power-law in/out expected degrees."""
+    """Chung-Lu directed graph with power-law in/out expected degrees.
+
+    Out- and in-weights follow (j+1)^(-1/(gamma-1)) over ranks j, mapped to
+    nodes by two independent seeded permutations.  Edges are sampled
+    source ~ out-weight, head ~ in-weight; self-loops and duplicates are
+    dropped; a seeded random subset of exactly m distinct edges is kept.
+    """
     rng = np.random.Generator(np.random.PCG64(seed))
-    w = (np.arange(n, dtype=np.float64) + 1.0) ** (-1.0 / (gamma - 1.0))
-    w /= w.sum()
-    perm_out = rng.permutation(n)
-    perm_in = rng.permutation(n)
-    w_out = np.empty(n)
-    w_in = np.empty(n)
-    w_out[perm_out] = w
-    w_in[perm_in] = w
-    cdf_out = np.cumsum(w_out)
-    cdf_in = np.cumsum(w_in)
-    cdf_out /= cdf_out[-1]
-    cdf_in /= cdf_in[-1]
+    expo = 1.0 / (gamma - 1.0)
+    perm_out = rng.permutation(n).astype(np.uint64)
+    perm_in = rng.permutation(n).astype(np.uint64)
     keys = np.empty(0, dtype=np.uint64)
-    need = m
-    while need > 0:
-        batch = int(need * 1.25) + 1024
-        s = _sample_categorical(rng, cdf_out, batch).astype(np.uint64)
-        d = _sample_categorical(rng, cdf_in, batch).astype(np.uint64)
-        ok = s != d
-        new = s[ok] * np.uint64(n) + d[ok]
-        # keep first occurrences in sample order, then drop keys already held
-        _, first = np.unique(new, return_index=True)
-        new = new[np.sort(first)]
-        new = new[~np.isin(new, keys)]
-        keys = np.concatenate([keys, new[:need]])
-        need = m - keys.shape[0]
-    return _csr_from_keys(n, np.sort(keys))
+    batch = int(m * 1.35) + 1024
+    while True:
+        src = perm_out[_sample_powerlaw_rank(rng, n, expo, batch)]
+        dst = perm_in[_sample_powerlaw_rank(rng, n, expo, batch)]
+        new = (src * np.uint64(n) + dst)[src != dst]
+        keys = np.unique(np.concatenate([keys, new]))
+        if keys.size >= m:
+            break
+        batch = int((m - keys.size) * 2) + 1024
+    if keys.size > m:
+        keep = rng.choice(keys.size, size=m, replace=False)
+        keys = np.sort(keys[keep])
+    return _csr_from_keys(n, keys)
 
 
 def rmat_graph(scale: int, samples: int, abcd, seed: int,
