@@ -159,6 +159,66 @@ void skim_greedy_state_free(skim_greedy_state *state);
 uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
 
 /*
+ * Serving: a request loop over resident sketches.  Union queries are
+ * admitted when their bytes (4 per node + 20) fit the free part of
+ * budget_bytes, else SKIM_EBUSY (retry later); a request that can never fit
+ * gives SKIM_EUNSUPPORTED.  A worker thread keeps up to `streams` batches in
+ * flight and packs every waiting query that fits a free slot (max_batch sets,
+ * budget_bytes / 4 / streams nodes) into one persistent launch as soon as
+ * the slot frees up (continuous batching); incremental SKIM requests run in
+ * order on their own stream, resuming one device-resident state, and overlap
+ * with the query batches.  Each result is the one the batch call gives for
+ * the same input.  Latencies run from arrival to completion seen by the host.
+ * The sketches (ranks, size: device, caller-owned) and the SKIM graph must
+ * stay valid while the server lives.  Calls on one server are thread-safe.
+ */
+typedef struct skim_server skim_server;
+
+typedef struct {
+    uint64_t budget_bytes;  /* bytes of admitted, unfinished query requests */
+    uint32_t max_batch;     /* queries per launch                           */
+    uint32_t streams;       /* batches in flight, 1..16                     */
+    uint32_t estimator;     /* 0 bottom-k, 1 Cohen-Kaplan                   */
+} skim_server_config;
+
+skim_status skim_server_create(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
+                               uint32_t ell, const skim_server_config *cfg, skim_server **out);
+void skim_server_destroy(skim_server *server);
+
+/* Submit one seed set (HOST array of count node ids); returns a ticket. */
+skim_status skim_server_submit(skim_server *server, const uint32_t *nodes, uint32_t count,
+                               uint64_t *ticket);
+
+/* SKIM_OK with the result (HOST pointers, may be NULL; status as in
+ * skim_query_batch) and the ticket retired; SKIM_EBUSY while in flight;
+ * SKIM_EINVAL for an unknown ticket. */
+skim_status skim_server_poll(skim_server *server, uint64_t ticket, double *est, int32_t *status,
+                             double *latency_us);
+
+/* Attach the graph for SKIM requests (once per server). */
+skim_status skim_server_set_graph(skim_server *server, const skim_graph *g, uint32_t ell,
+                                  uint32_t k, uint64_t seed);
+
+/* Request the next s seeds of the server's SKIM run (skim_greedy semantics). */
+skim_status skim_server_submit_greedy(skim_server *server, uint32_t s, uint64_t *ticket);
+
+/* seeds [s], gain_pairs [s]: HOST arrays; SKIM_EBUSY while running. */
+skim_status skim_server_poll_greedy(skim_server *server, uint64_t ticket, uint32_t *seeds,
+                                    uint64_t *gain_pairs, double *latency_us);
+
+/*
+ * Open-loop replay, for measurement: submits set j (HOST offsets[q+1],
+ * nodes) at arrival_s[j] seconds after the call starts (retrying on
+ * SKIM_EBUSY; latency still counts from the scheduled arrival) and collects
+ * every result into HOST arrays est[q], status[q] (-4 = rejected),
+ * latency_us[q] (may be NULL).  busy_retries (HOST, may be NULL) counts
+ * admission refusals.
+ */
+skim_status skim_server_replay(skim_server *server, uint64_t q, const uint64_t *offsets,
+                               const uint32_t *nodes, const double *arrival_s, double *est,
+                               int32_t *status, double *latency_us, uint64_t *busy_retries);
+
+/*
  * Kernel timing, for measurement: while a kernel name is enabled, every
  * launch of that kernel (e.g. "k_expand", the level expansion of the pruned
  * reverse search) made by the calling thread is bracketed by HIP events on

@@ -22,13 +22,20 @@ _STATUS = {0: "SKIM_OK", 1: "SKIM_EINVAL", 2: "SKIM_ENOMEM", 3: "SKIM_EDEVICE", 
 EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_estimates",
            "skim_query_batch", "skim_greedy", "skim_greedy_state_free",
            "skim_greedy_state_selected", "skim_timing_enable", "skim_timing_reset",
-           "skim_timing_read"]
+           "skim_timing_read", "skim_server_create", "skim_server_destroy", "skim_server_submit",
+           "skim_server_poll", "skim_server_set_graph", "skim_server_submit_greedy",
+           "skim_server_poll_greedy", "skim_server_replay"]
 
 
 class SkimError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn}: {_STATUS.get(status, status)}: {msg}")
         self.status = status
+
+
+class skim_server_config(C.Structure):
+    _fields_ = [("budget_bytes", C.c_uint64), ("max_batch", C.c_uint32), ("streams", C.c_uint32),
+                ("estimator", C.c_uint32)]
 
 
 class skim_graph(C.Structure):
@@ -69,6 +76,26 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_free.argtypes = [vp]
     lib.skim_greedy_state_selected.restype = C.c_uint32
     lib.skim_greedy_state_selected.argtypes = [vp]
+    P64 = C.POINTER(C.c_uint64)
+    PD = C.POINTER(C.c_double)
+    lib.skim_server_create.restype = C.c_int
+    lib.skim_server_create.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32,
+                                       C.POINTER(skim_server_config), C.POINTER(vp)]
+    lib.skim_server_destroy.restype = None
+    lib.skim_server_destroy.argtypes = [vp]
+    lib.skim_server_submit.restype = C.c_int
+    lib.skim_server_submit.argtypes = [vp, vp, C.c_uint32, P64]
+    lib.skim_server_poll.restype = C.c_int
+    lib.skim_server_poll.argtypes = [vp, C.c_uint64, PD, C.POINTER(C.c_int32), PD]
+    lib.skim_server_set_graph.restype = C.c_int
+    lib.skim_server_set_graph.argtypes = [vp, C.POINTER(skim_graph), C.c_uint32, C.c_uint32,
+                                          C.c_uint64]
+    lib.skim_server_submit_greedy.restype = C.c_int
+    lib.skim_server_submit_greedy.argtypes = [vp, C.c_uint32, P64]
+    lib.skim_server_poll_greedy.restype = C.c_int
+    lib.skim_server_poll_greedy.argtypes = [vp, C.c_uint64, vp, vp, PD]
+    lib.skim_server_replay.restype = C.c_int
+    lib.skim_server_replay.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, vp, vp, P64]
     lib.skim_timing_enable.restype = None
     lib.skim_timing_enable.argtypes = [C.c_char_p]
     lib.skim_timing_reset.restype = None
@@ -207,3 +234,84 @@ def skim_timing_read(kernel: str):
     n = C.c_uint64(0)
     load_library().skim_timing_read(kernel.encode(), C.byref(ms), C.byref(n))
     return float(ms.value), int(n.value)
+
+
+class Server:
+    """A serving loop over resident sketches (see skim_server_* in include/skim.h)."""
+
+    def __init__(self, ranks, size, n: int, k: int, ell: int, budget_bytes: int = 64 << 20,
+                 max_batch: int = 4096, streams: int = 4, estimator: int = 0):
+        lib = load_library()
+        self._keep = (ranks, size)
+        cfg = skim_server_config(budget_bytes, max_batch, streams, estimator)
+        self.handle = C.c_void_p(None)
+        _check("skim_server_create", lib.skim_server_create(_ptr(ranks), _ptr(size), n, k, ell,
+                                                            C.byref(cfg), C.byref(self.handle)))
+
+    def submit(self, nodes) -> int:
+        """Submit one set (host array); returns a ticket.  Raises SkimError on EBUSY."""
+        a = np.ascontiguousarray(nodes, dtype=np.uint32)
+        t = C.c_uint64(0)
+        _check("skim_server_submit", _lib.skim_server_submit(
+            self.handle, a.ctypes.data_as(C.c_void_p) if a.size else None, a.size, C.byref(t)))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """(est, status, latency_us) when done, else None."""
+        e, s, l = C.c_double(0), C.c_int32(0), C.c_double(0)
+        st = _lib.skim_server_poll(self.handle, ticket, C.byref(e), C.byref(s), C.byref(l))
+        if st == SKIM_EBUSY:
+            return None
+        _check("skim_server_poll", st)
+        return float(e.value), int(s.value), float(l.value)
+
+    def set_graph(self, graph: DeviceGraph, ell: int, k: int, seed: int):
+        self._graph = graph
+        _check("skim_server_set_graph", _lib.skim_server_set_graph(
+            self.handle, C.byref(graph.struct), ell, k, seed & 0xFFFFFFFFFFFFFFFF))
+
+    def submit_greedy(self, s: int) -> int:
+        t = C.c_uint64(0)
+        _check("skim_server_submit_greedy", _lib.skim_server_submit_greedy(self.handle, s,
+                                                                           C.byref(t)))
+        return int(t.value)
+
+    def poll_greedy(self, ticket: int, s: int):
+        """(seeds, gain_pairs, latency_us) when done, else None."""
+        seeds = np.zeros(max(s, 1), dtype=np.uint32)
+        gains = np.zeros(max(s, 1), dtype=np.uint64)
+        l = C.c_double(0)
+        st = _lib.skim_server_poll_greedy(self.handle, ticket, seeds.ctypes.data_as(C.c_void_p),
+                                          gains.ctypes.data_as(C.c_void_p), C.byref(l))
+        if st == SKIM_EBUSY:
+            return None
+        _check("skim_server_poll_greedy", st)
+        return seeds[:s], gains[:s], float(l.value)
+
+    def replay(self, offsets, nodes, arrival_s):
+        """Open-loop replay of host query sets; returns (est, status, latency_us, retries)."""
+        off = np.ascontiguousarray(offsets, dtype=np.uint64)
+        nd = np.ascontiguousarray(nodes, dtype=np.uint32)
+        arr = np.ascontiguousarray(arrival_s, dtype=np.float64)
+        q = off.size - 1
+        est = np.zeros(max(q, 1))
+        st = np.zeros(max(q, 1), dtype=np.int32)
+        lat = np.zeros(max(q, 1))
+        retries = C.c_uint64(0)
+        vp = C.c_void_p
+        _check("skim_server_replay", _lib.skim_server_replay(
+            self.handle, q, off.ctypes.data_as(vp), nd.ctypes.data_as(vp) if nd.size else None,
+            arr.ctypes.data_as(vp), est.ctypes.data_as(vp), st.ctypes.data_as(vp),
+            lat.ctypes.data_as(vp), C.byref(retries)))
+        return est[:q], st[:q], lat[:q], int(retries.value)
+
+    def close(self):
+        if self.handle:
+            _lib.skim_server_destroy(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

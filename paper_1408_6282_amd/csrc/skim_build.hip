@@ -51,6 +51,8 @@ struct Ctl {
     unsigned long long records;   // records appended (all windows)
     unsigned long long full;      // nodes holding k records
     uint32_t flags;               // overflow bits
+    uint32_t done_blocks;         // blocks finished in the current level
+    uint32_t level;               // next level after a tail launch
     uint32_t pad;
 };
 
@@ -148,7 +150,7 @@ struct WinArgs {
 };
 
 // Visit of pair p by source s: 1 if new, 0 if pruned or already visited by s.
-__device__ __forceinline__ int claim(const WinArgs &A, uint32_t p, uint32_t s, bool &hashed) {
+__device__ __forceinline__ int claim(const WinArgs &A, uint32_t p, uint32_t s, uint32_t &hashed) {
     uint64_t old = load_relaxed(A.words + p);
     for (;;) {
         if ((uint32_t)(old >> 32) >= A.k) return 0;  // instance-local sketch full: prune
@@ -161,82 +163,169 @@ __device__ __forceinline__ int claim(const WinArgs &A, uint32_t p, uint32_t s, b
             old = prev;
             continue;
         }
-        hashed = true;
         const int r = hset_insert(A.hset, A.logcap, ((uint64_t)p << 32) | s);
         if (r < 0) {
             atomicOr(&A.ctl->flags, kOvfHash);
             return 0;
         }
+        hashed += r;
         return r;
     }
 }
 
-__device__ __forceinline__ void push_item(const WinArgs &A, bool want, uint64_t item) {
-    const uint64_t pos = wave_reserve(&A.ctl->count, want);
-    if (want) {
-        if (pos < A.items_cap) A.items[pos] = item;
-        else atomicOr(&A.ctl->flags, kOvfItems);
+// Block-aggregated appends: threads stage new entries in LDS; one global
+// reservation per flush moves them to the output array (coalesced).
+constexpr uint32_t kChunk = 1024;        // input entries per block per round
+constexpr uint32_t kStage = 4096;        // staged outputs per round (32 KiB)
+
+struct Stage {
+    uint64_t buf[kStage];
+    uint32_t n;
+    unsigned long long base;
+};
+
+__device__ __forceinline__ void stage_push(Stage &S, uint64_t v, uint64_t *out, uint64_t cap,
+                                           unsigned long long *count, uint32_t *flags,
+                                           uint32_t ovf_bit) {
+    const uint32_t pos = atomicAdd(&S.n, 1u);
+    if (pos < kStage) {
+        S.buf[pos] = v;
+        return;
     }
+    const unsigned long long g = atomicAdd(count, 1ull);  // rare: stage full
+    if (g < cap) out[g] = v;
+    else atomicOr(flags, ovf_bit);
 }
 
-__global__ void k_seed_window(WinArgs A, const uint32_t *sources) {
-    const uint32_t lane = lane_id();
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t first = A.ws + (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x - lane);
-    for (uint64_t t0 = first; t0 < A.we; t0 += stride) {
-        const uint64_t t = t0 + lane;
-        bool neu = false;
-        uint64_t item = 0;
-        if (t < A.we) {
+// Called by every thread of the block.
+__device__ __forceinline__ void stage_flush(Stage &S, uint64_t *out, uint64_t cap,
+                                            unsigned long long *count, uint32_t *flags,
+                                            uint32_t ovf_bit) {
+    __syncthreads();
+    const uint32_t m = S.n < kStage ? S.n : kStage;
+    if (threadIdx.x == 0) S.base = m ? atomicAdd(count, (unsigned long long)m) : 0;
+    __syncthreads();
+    const unsigned long long base = S.base;
+    if (m && base + m > cap && threadIdx.x == 0) atomicOr(flags, ovf_bit);
+    for (uint32_t j = threadIdx.x; j < m; j += blockDim.x)
+        if (base + j < cap) out[base + j] = S.buf[j];
+    __syncthreads();
+    if (threadIdx.x == 0) S.n = 0;
+    __syncthreads();
+}
+
+// Sources of the window start their searches.  Each source pair is claimed
+// only by its own source here, so the claim is a plain store.
+__global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_t *sources) {
+    __shared__ Stage S;
+    if (threadIdx.x == 0) S.n = 0;
+    __syncthreads();
+    for (uint64_t c = A.ws + (uint64_t)blockIdx.x * kChunk; c < A.we;
+         c += (uint64_t)gridDim.x * kChunk) {
+        const uint64_t end = c + kChunk < A.we ? c + kChunk : A.we;
+        for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
             const uint32_t s = (uint32_t)t;
             const uint32_t p = sources[s];
-            bool hashed = false;
-            neu = claim(A, p, s, hashed) == 1;
-            item = ((uint64_t)p << 32) | s;
+            const uint64_t w = A.words[p];
+            if ((uint32_t)(w >> 32) >= A.k) continue;  // pruned
+            reinterpret_cast<uint32_t *>(A.words + p)[0] = s;
+            stage_push(S, ((uint64_t)p << 32) | s, A.items, A.items_cap, &A.ctl->count,
+                       &A.ctl->flags, kOvfItems);
         }
-        push_item(A, neu, item);
+        stage_flush(S, A.items, A.items_cap, &A.ctl->count, &A.ctl->flags, kOvfItems);
     }
 }
 
-__global__ void k_expand(WinArgs A, const uint64_t *lptr, const uint32_t *lsrc, uint32_t level) {
-    if (A.ctl->flags) return;  // this window will be redone with more room
-    const uint64_t a = A.ctl->lb[level & 3], b = A.ctl->lb[(level + 1) & 3];
-    const uint32_t lane = lane_id();
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint32_t scans = 0, hashed_n = 0;
-    for (uint64_t t0 = a + (blockIdx.x * (uint64_t)blockDim.x + threadIdx.x - lane); t0 < b;
-         t0 += stride) {
-        const uint64_t t = t0 + lane;
-        uint64_t e = 0, eend = 0;
-        uint32_t s = 0, i = 0;
-        if (t < b) {
+// Expand the frontier items[a, b) over live in-edges of their instance.
+__device__ __forceinline__ void expand_range(const WinArgs &A, const uint64_t *lptr,
+                                             const uint32_t *lsrc, uint64_t a, uint64_t b,
+                                             uint64_t first, uint64_t stride, Stage &S,
+                                             uint32_t &scans, uint32_t &hashed) {
+    for (uint64_t c = a + first; c < b; c += stride) {
+        const uint64_t end = c + kChunk < b ? c + kChunk : b;
+        for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
             const uint64_t it = A.items[t];
             const uint32_t p = (uint32_t)(it >> 32);
-            s = (uint32_t)it;
-            i = p % kPairStride;
-            e = lptr[p];
-            eend = lptr[p + 1];
-        }
-        while (__ballot(e < eend)) {
-            bool neu = false;
-            uint64_t item = 0;
-            if (e < eend) {
-                const uint32_t w = lsrc[e++];
-                const uint32_t q = w * kPairStride + i;
-                bool hashed = false;
-                neu = claim(A, q, s, hashed) == 1;
-                hashed_n += hashed && neu;
-                item = ((uint64_t)q << 32) | s;
+            const uint32_t s = (uint32_t)it;
+            const uint32_t i = p % kPairStride;
+            const uint64_t e1 = lptr[p + 1];
+            for (uint64_t e = lptr[p]; e < e1; ++e) {
+                const uint32_t q = lsrc[e] * kPairStride + i;
                 ++scans;
+                if (claim(A, q, s, hashed) == 1)
+                    stage_push(S, ((uint64_t)q << 32) | s, A.items, A.items_cap, &A.ctl->count,
+                               &A.ctl->flags, kOvfItems);
             }
-            push_item(A, neu, item);
         }
+        stage_flush(S, A.items, A.items_cap, &A.ctl->count, &A.ctl->flags, kOvfItems);
     }
-    wave_add(&A.ctl->scans, scans);
-    wave_add(&A.ctl->hinserts, hashed_n);
 }
 
-__global__ void k_advance(Ctl *ctl, uint32_t level) { ctl->lb[(level + 2) & 3] = ctl->count; }
+// One level with the whole grid; the last block to finish publishes the
+// next frontier boundary.
+__global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, const uint64_t *lptr,
+                                                   const uint32_t *lsrc, uint32_t level) {
+    __shared__ Stage S;
+    __shared__ uint32_t s_flags;
+    if (threadIdx.x == 0) {
+        S.n = 0;
+        s_flags = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    uint32_t scans = 0, hashed = 0;
+    if (!s_flags) {  // after an overflow the window is redone with more room
+        const uint64_t a = A.ctl->lb[level & 3], b = A.ctl->lb[(level + 1) & 3];
+        expand_range(A, lptr, lsrc, a, b, (uint64_t)blockIdx.x * kChunk,
+                     (uint64_t)gridDim.x * kChunk, S, scans, hashed);
+    }
+    wave_add(&A.ctl->scans, scans);
+    wave_add(&A.ctl->hinserts, hashed);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(&A.ctl->done_blocks, 1u);
+        if (prev == gridDim.x - 1) {
+            A.ctl->lb[(level + 2) & 3] =
+                __hip_atomic_load(&A.ctl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            A.ctl->done_blocks = 0;
+            __threadfence();
+        }
+    }
+}
+
+// Small frontiers: one workgroup runs level after level until the frontier
+// is empty, grows past `max_frontier`, or an overflow is flagged.
+__global__ void __launch_bounds__(1024) k_expand_tail(WinArgs A, const uint64_t *lptr,
+                                                      const uint32_t *lsrc, uint32_t level,
+                                                      uint64_t max_frontier) {
+    __shared__ Stage S;
+    __shared__ unsigned long long s_a, s_b;
+    __shared__ uint32_t s_stop;
+    if (threadIdx.x == 0) S.n = 0;
+    uint32_t scans = 0, hashed = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_a = A.ctl->lb[level & 3];
+            s_b = A.ctl->lb[(level + 1) & 3];
+            const uint32_t f =
+                __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_stop = f || s_a == s_b || s_b - s_a > max_frontier;
+        }
+        __syncthreads();
+        if (s_stop) break;
+        expand_range(A, lptr, lsrc, s_a, s_b, 0, kChunk, S, scans, hashed);
+        if (threadIdx.x == 0) {
+            __threadfence();
+            A.ctl->lb[(level + 2) & 3] =
+                __hip_atomic_load(&A.ctl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ++level;
+        __syncthreads();
+    }
+    wave_add(&A.ctl->scans, scans);
+    wave_add(&A.ctl->hinserts, hashed);
+    if (threadIdx.x == 0) A.ctl->level = level;
+}
 
 // Start of an attempt at a window: clear the per-window fields.
 __global__ void k_ctl_begin(Ctl *ctl) {
@@ -245,7 +334,11 @@ __global__ void k_ctl_begin(Ctl *ctl) {
     ctl->scans = 0;
     ctl->hinserts = 0;
     ctl->flags = 0;
+    ctl->done_blocks = 0;
+    ctl->level = 0;
 }
+
+__global__ void k_seed_done(Ctl *ctl) { ctl->lb[1] = ctl->count; }
 
 // Roll the record counter back (after growing the record buffer).
 __global__ void k_ctl_records(Ctl *ctl, unsigned long long records) {
@@ -273,29 +366,27 @@ __global__ void k_unclaim(uint64_t *words, uint64_t npairs, uint32_t ws, uint32_
 
 // ---------------------------------------------------------- 4. records
 
-__global__ void k_records(const uint64_t *items, uint64_t count, const uint32_t *xcnt,
-                          uint32_t *xadd, uint32_t k, uint64_t *rec, uint64_t rec_cap, Ctl *ctl) {
-    const uint32_t lane = lane_id();
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t t0 = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x - lane; t0 < count;
-         t0 += stride) {
-        const uint64_t t = t0 + lane;
-        bool want = false;
-        uint64_t r = 0;
-        if (t < count) {
+// Keep a record of every visit of a node that held fewer than k ranks at the
+// window start (xcnt is the node's record count before this window).
+__global__ void __launch_bounds__(kBlock) k_records(const uint64_t *items, uint64_t count,
+                                                    const uint32_t *xcnt, uint32_t *xadd,
+                                                    uint32_t k, uint64_t *rec, uint64_t rec_cap,
+                                                    Ctl *ctl) {
+    __shared__ Stage S;
+    if (threadIdx.x == 0) S.n = 0;
+    __syncthreads();
+    for (uint64_t c = (uint64_t)blockIdx.x * kChunk; c < count; c += (uint64_t)gridDim.x * kChunk) {
+        const uint64_t end = c + kChunk < count ? c + kChunk : count;
+        for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
             const uint64_t it = items[t];
             const uint32_t v = (uint32_t)(it >> 32) / kPairStride;
             if (xcnt[v] < k) {
-                want = true;
-                r = ((uint64_t)v << 32) | (uint32_t)it;
                 atomicAdd(xadd + v, 1u);
+                stage_push(S, ((uint64_t)v << 32) | (uint32_t)it, rec, rec_cap, &ctl->records,
+                           &ctl->flags, kOvfRecords);
             }
         }
-        const uint64_t pos = wave_reserve(&ctl->records, want);
-        if (want) {
-            if (pos < rec_cap) rec[pos] = r;
-            else atomicOr(&ctl->flags, kOvfRecords);
-        }
+        stage_flush(S, rec, rec_cap, &ctl->records, &ctl->flags, kOvfRecords);
     }
 }
 
@@ -463,6 +554,8 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     uint64_t items_cap = 0, hcap = 0;
     uint64_t *items = nullptr, *hset = nullptr;
     uint64_t total_items = 0, total_scans = 0, windows_done = 0;
+    uint64_t prev_items = 0, prev_hash = 0;
+    constexpr uint64_t kTail = 16384;  // frontiers this small go to the one-workgroup loop
     Ctl h;
 
     for (uint32_t w = 0; w < W; ++w) {
@@ -471,10 +564,14 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
         read_back(&h, ctl, sizeof h, s);
         if (h.full >= n) break;  // every sketch holds k ranks: later ranks cannot enter
         const uint64_t nw = we - ws;
-        uint64_t want_items = std::max<uint64_t>(1ull << 16, 4 * nw);
-        uint64_t want_hash = next_pow2(std::max<uint64_t>(1ull << 14, nw));
+        // windows double in size: predict from the previous one
+        uint64_t want_items = std::max<uint64_t>({1ull << 16, 3 * nw, 3 * prev_items});
+        uint64_t want_hash = next_pow2(std::max<uint64_t>({1ull << 14, nw / 2, 8 * prev_hash}));
         for (int attempt = 0;; ++attempt) {
-            SKIM_REQUIRE(attempt < 24, "window %u did not fit after %d attempts", w, attempt);
+            if (attempt >= 24) {
+                set_error("window %u did not fit after %d attempts", w, attempt);
+                throw Fail{SKIM_EDEVICE};
+            }
             if (want_items > items_cap) {
                 if (items) A.release(items);
                 items_cap = want_items;
@@ -494,26 +591,32 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
             WinArgs WA{words, items, items_cap, hset, logcap, ws, we, k, ctl};
             {
                 LaunchTimer t("k_seed_window", s);
-                k_seed_window<<<grid_for(nw, kBlock, 8192), kBlock, 0, s>>>(WA, sources);
+                k_seed_window<<<grid_for(nw, kChunk, 4096), kBlock, 0, s>>>(WA, sources);
             }
             SKIM_LAUNCH_CHECK();
-            k_advance<<<1, 1, 0, s>>>(ctl, (uint32_t)-1);  // lb[1] = count (level -1 -> slot 1)
+            k_seed_done<<<1, 1, 0, s>>>(ctl);
             SKIM_LAUNCH_CHECK();
-            uint32_t level = 0, batch = 2;
+            uint32_t level = 0;
             for (;;) {
-                for (uint32_t j = 0; j < batch; ++j, ++level) {
-                    {
-                        LaunchTimer t("k_expand", s);
-                        k_expand<<<2048, kBlock, 0, s>>>(WA, lptr, lsrc, level);
-                    }
-                    SKIM_LAUNCH_CHECK();
-                    k_advance<<<1, 1, 0, s>>>(ctl, level);
-                    SKIM_LAUNCH_CHECK();
-                }
                 read_back(&h, ctl, sizeof h, s);
                 if (h.flags) break;
-                if (h.lb[(level + 1) & 3] == h.lb[level & 3]) break;  // empty frontier
-                if (batch < 16) batch *= 2;
+                const uint64_t fa = h.lb[level & 3], fb = h.lb[(level + 1) & 3];
+                if (fa == fb) break;  // empty frontier: window done
+                if (fb - fa <= kTail) {
+                    LaunchTimer t("k_expand_tail", s);
+                    k_expand_tail<<<1, 1024, 0, s>>>(WA, lptr, lsrc, level, 4 * kTail);
+                    SKIM_LAUNCH_CHECK();
+                    read_back(&h, ctl, sizeof h, s);
+                    level = h.level;
+                    continue;
+                }
+                // big frontier: a few whole-grid levels before looking again
+                for (int j = 0; j < 3; ++j, ++level) {
+                    const unsigned grid = j == 0 ? grid_for(fb - fa, kChunk, 2048) : 2048;
+                    LaunchTimer t("k_expand", s);
+                    k_expand<<<grid, kBlock, 0, s>>>(WA, lptr, lsrc, level);
+                    SKIM_LAUNCH_CHECK();
+                }
             }
             if (h.flags & (kOvfItems | kOvfHash)) {
                 k_unclaim<<<grid_for(npairs, kBlock, 8192), kBlock, 0, s>>>(words, npairs, ws, we);
@@ -525,15 +628,20 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
             break;
         }
         const uint64_t count = h.count;
+        prev_items = count;
+        prev_hash = h.hinserts;
         total_items += count;
         total_scans += h.scans;
         // records of nodes that held fewer than k ranks at the window start
         const uint64_t rec_before = h.records;
         for (int attempt = 0;; ++attempt) {
-            SKIM_REQUIRE(attempt < 8, "record buffer did not fit");
+            if (attempt >= 8) {
+                set_error("record buffer did not fit");
+                throw Fail{SKIM_EDEVICE};
+            }
             {
                 LaunchTimer t("k_records", s);
-                k_records<<<grid_for(count, kBlock, 8192), kBlock, 0, s>>>(items, count, xcnt, xadd,
+                k_records<<<grid_for(count, kChunk, 4096), kBlock, 0, s>>>(items, count, xcnt, xadd,
                                                                            k, rec, rec_cap, ctl);
             }
             SKIM_LAUNCH_CHECK();

@@ -283,7 +283,7 @@ struct skim_greedy_state {
 
 namespace skim {
 
-static skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
                                         hipStream_t s) {
     SKIM_REQUIRE(ell >= 1 && ell <= 64, "l must be in [1, 64]");
     SKIM_REQUIRE(k >= 2, "k must be >= 2");
@@ -358,7 +358,7 @@ static skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint3
     return st.release();
 }
 
-static void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_t *gains,
+void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_t *gains,
                        double *gain_d, hipStream_t s) {
     SkArgs &A = st->args;
     uint32_t done = 0;

@@ -193,6 +193,21 @@ class LaunchTimer {
 };
 void timing_resolve();  // call after the stream has been synchronised
 
+// Union queries (skim_query.hip): sketches, sets in CSR form, outputs.
+struct QueryArgs {
+    const uint64_t *ranks;
+    const uint32_t *size;
+    uint32_t n, k, ell;
+    const uint64_t *qoff;
+    const uint32_t *qnodes;
+    double *est;
+    int32_t *qstatus;
+    uint32_t estimator;
+};
+// Launch the persistent query kernel for q sets on `s` without waiting;
+// `next` is a device work counter (zeroed here on the stream).
+void launch_queries_async(const QueryArgs &Q, uint64_t q, unsigned long long *next, hipStream_t s);
+
 // Validate a forward CSR on the device; throws Fail{SKIM_EINVAL} if invalid.
 // On success writes esrc[m] (source node of every edge) when esrc != nullptr.
 void validate_graph(const skim_graph *g, uint32_t *esrc, Arena &a);

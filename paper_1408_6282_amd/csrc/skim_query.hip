@@ -22,16 +22,7 @@ namespace {
 constexpr uint32_t kMaxMembers = 1024;  // members per query (LDS state)
 constexpr int kQBlock = 64;             // one wave per block
 
-struct QArgs {
-    const uint64_t *ranks;
-    const uint32_t *size;
-    uint32_t n, k, ell;
-    const uint64_t *qoff;
-    const uint32_t *qnodes;
-    double *est;
-    int32_t *qstatus;
-    uint32_t estimator;
-};
+using QArgs = QueryArgs;
 
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
     for (int off = 32; off > 0; off >>= 1) {
@@ -178,6 +169,25 @@ __global__ void k_check_offsets(const uint64_t *qoff, uint64_t q, uint32_t *err)
 
 }  // namespace
 
+unsigned query_grid(uint64_t q) {
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipGetLastError();
+    }
+    const uint64_t want = (uint64_t)cus * 16;
+    return (unsigned)(q < want ? (q ? q : 1) : want);
+}
+
+void launch_queries_async(const QueryArgs &Q, uint64_t q, unsigned long long *next, hipStream_t s) {
+    fill_u64((uint64_t *)next, 0, 1, s);
+    k_query_persistent<<<query_grid(q), kQBlock, 0, s>>>(Q, q, next);
+    SKIM_LAUNCH_CHECK();
+}
+
 static void query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
                         uint32_t ell, uint64_t q, const uint64_t *qoff, const uint32_t *qnodes,
                         uint32_t estimator, uint32_t mode, double *est, int32_t *qstatus,
@@ -203,15 +213,8 @@ static void query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
     QArgs Q{ranks, size, n, k, ell, qoff, qnodes, est, qstatus, estimator};
     if (mode == 0) {
         unsigned long long *next = A.alloc<unsigned long long>(1);
-        fill_u64((uint64_t *)next, 0, 1, s);
-        int dev = 0, cus = 256;
-        SKIM_HIP(hipGetDevice(&dev));
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        const uint64_t want = (uint64_t)cus * 16;
-        const unsigned grid = (unsigned)(q < want ? q : want);
         LaunchTimer t("k_query_persistent", s);
-        k_query_persistent<<<grid, kQBlock, 0, s>>>(Q, q, next);
-        SKIM_LAUNCH_CHECK();
+        launch_queries_async(Q, q, next, s);
     } else {
         for (uint64_t j = 0; j < q; ++j) {
             k_query_one<<<1, kQBlock, 0, s>>>(Q, j);
