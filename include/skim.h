@@ -86,9 +86,10 @@ const char *skim_last_error(void);
  *   est   [n]   out, device, may be NULL: |X_v| / l if |X_v| < k, else
  *         ((k-1) / rho(tau_v)) / l with tau_v = ranks[v*k + k-1] and
  *         rho(T) = ((T >> 11) + 1) * 2^-53 (IEEE double, correctly rounded).
- *   work  [4]   out, HOST, may be NULL: work the device did, in order:
- *         items (node-instance-source visits), live-edge scans, records
- *         kept for the merge, rank windows processed.
+ *   work  [6]   out, HOST, may be NULL: work the device did, in order:
+ *         accepted visits (node-instance-source), live-edge scans, records
+ *         kept for the merge, rank windows processed, restarts of the
+ *         window phase after a buffer overflow, and the overflow bits.
  */
 skim_status skim_build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
                                 uint64_t *ranks, uint32_t *size, double *est,

@@ -159,12 +159,12 @@ def skim_build_sketches(graph: DeviceGraph, ell: int, k: int, seed: int, ranks, 
     Returns the device work counters (items, live-edge scans, records, windows).
     """
     lib = load_library()
-    work = (C.c_uint64 * 4)()
+    work = (C.c_uint64 * 6)()
     st = lib.skim_build_sketches(C.byref(graph.struct), ell, k, seed & 0xFFFFFFFFFFFFFFFF,
                                  _ptr(ranks), _ptr(size), _ptr(est), work, _stream(stream))
     _check("skim_build_sketches", st)
-    return {"items": int(work[0]), "scans": int(work[1]), "records": int(work[2]),
-            "windows": int(work[3])}
+    return {"visits": int(work[0]), "scans": int(work[1]), "records": int(work[2]),
+            "windows": int(work[3]), "restarts": int(work[4]), "restart_flags": int(work[5])}
 
 
 def skim_estimates(ranks, size, n: int, k: int, ell: int, est, stream=None):

@@ -10,26 +10,31 @@
 //     materialised as one CSR (lptr / lsrc).  Every expansion later reads
 //     only live in-edges of its own instance.
 //  2. Rank windows.  All pairs are bucketed by rank into W windows: window 0
-//     holds ranks below 2^(65-W), window j >= 1 the ranks in
-//     [2^(64-W+j), 2^(65-W+j)).  Windows are processed in increasing order.
+//     holds about k/2 sources per instance, each later window four times as
+//     many ranks as the one before.  Windows are processed in increasing
+//     order.
 //  3. Pruned reverse searches, window by window.  Every source pair (u, i)
-//     of the window starts a reverse search in G^(i).  A visited pair (w, i)
-//     is pruned when it already received k ranks in earlier windows (the
-//     paper's rule: its instance-local sketch is full); all sources of a
-//     window run together, level-synchronously.  Because every pair on a
-//     path to an unpruned pair reaches a subset of what it reaches, the
+//     of the window runs a reverse search in G^(i).  A visited pair (w, i)
+//     is pruned when it received k ranks in earlier windows (the paper's
+//     rule: its instance-local sketch is full).  Because every pair on a
+//     path to an unpruned pair reaches a subset of what it reaches, an
 //     unpruned pair receives every rank of its instance in the window, so
-//     the rule is exact.  Visits are deduplicated per source exactly: the
-//     first visitor of a pair in the window claims its word; later visitors
-//     go through a hash set keyed by (pair, source).
+//     the rule is exact whatever order the window's searches run in.  All
+//     searches of a window advance together, level by level (whole-grid
+//     launches for large frontiers, one workgroup looping over levels for
+//     small ones).  Visits are deduplicated per source exactly: the first
+//     visitor of a pair in the window claims the pair's state word; later
+//     visitors go through a hash set keyed by (pair, source).  The same word
+//     counts the pair's arrivals.
 //  4. Records.  A visit of node v is recorded while v held fewer than k
-//     ranks at the window start; windows go up in rank, so the first k
-//     records (by rank) of v are its sketch.
+//     ranks at the window start; windows go up in rank, so the k smallest
+//     records of v are its sketch.
 //  5. Merge.  Records are grouped by node and each node keeps its k
 //     smallest in LDS (bitonic sort), written ascending.
 #include "skim_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 namespace skim {
@@ -39,34 +44,44 @@ void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, u
 
 namespace {
 
-constexpr uint32_t kOvfItems = 1u, kOvfHash = 2u, kOvfRecords = 4u;
+constexpr uint32_t kOvfHash = 2u, kOvfRecords = 4u, kOvfSpill = 8u;
 constexpr int kBlock = 256;
+
+// Thrown inside the build when a buffer was too small; the windows restart
+// from scratch with larger buffers.
+struct Retry {
+    uint32_t flags;
+};
 
 // Device control block read back by the host at synchronisation points.
 struct Ctl {
-    unsigned long long lb[4];     // ring of level boundaries into items[]
-    unsigned long long count;     // items appended in this window
+    unsigned long long cur;       // size of the current level (in front[parity])
+    unsigned long long count;     // entries of the next level appended so far
     unsigned long long scans;     // live in-edges scanned (work counter)
     unsigned long long hinserts;  // hash-set insertions in this window
     unsigned long long records;   // records appended (all windows)
     unsigned long long full;      // nodes holding k records
+    unsigned long long visits;    // accepted visits (work counter)
+    unsigned long long levels;    // levels expanded in this window
     uint32_t flags;               // overflow bits
     uint32_t done_blocks;         // blocks finished in the current level
-    uint32_t level;               // next level after a tail launch
+    uint32_t parity;              // front[parity] holds the current level
     uint32_t pad;
 };
 
 // ------------------------------------------------------- 2. rank windows
 
-__device__ __forceinline__ uint32_t window_of(uint64_t r, uint32_t W) {
+// Window of a rank: window 0 holds ranks of at most `b0` bits; window j >= 1
+// the ranks of b0 + 2(j-1) + 1 or b0 + 2j bits (each window four times the
+// previous one).
+__device__ __forceinline__ uint32_t window_of(uint64_t r, uint32_t b0) {
     const int bits = r ? 64 - __clzll((long long)r) : 0;
-    const int w = bits + (int)W - 65;
-    return w < 0 ? 0u : (uint32_t)w;
+    return bits <= (int)b0 ? 0u : 1u + (uint32_t)(bits - (int)b0 - 1) / 2u;
 }
 
 constexpr int kRankPer = 8;  // pairs per thread in the bucketing kernels
 
-__global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W,
+__global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W, uint32_t b0,
                             unsigned long long *whist) {
     __shared__ uint32_t h[64];
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
@@ -77,14 +92,14 @@ __global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W,
         const uint64_t t = base + (uint64_t)j * kBlock + threadIdx.x;
         if (t < total) {
             const uint32_t v = (uint32_t)(t / ell), i = (uint32_t)(t % ell);
-            atomicAdd(&h[window_of(pair_rank(seed, v * kPairStride + i), W)], 1u);
+            atomicAdd(&h[window_of(pair_rank(seed, v * kPairStride + i), b0)], 1u);
         }
     }
     __syncthreads();
     if (threadIdx.x < W && h[threadIdx.x]) atomicAdd(&whist[threadIdx.x], h[threadIdx.x]);
 }
 
-__global__ void k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W,
+__global__ void k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W, uint32_t b0,
                                const unsigned long long *wbase, unsigned long long *wfill,
                                uint32_t *sources) {
     __shared__ uint32_t h[64];
@@ -100,7 +115,7 @@ __global__ void k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed, uint32_t
         if (t < total) {
             const uint32_t v = (uint32_t)(t / ell), i = (uint32_t)(t % ell);
             pid[j] = v * kPairStride + i;
-            win[j] = window_of(pair_rank(seed, pid[j]), W);
+            win[j] = window_of(pair_rank(seed, pid[j]), b0);
             slot[j] = atomicAdd(&h[win[j]], 1u);
         }
     }
@@ -112,7 +127,25 @@ __global__ void k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed, uint32_t
         if (win[j] != 0xFFFFFFFFu) sources[off[win[j]] + slot[j]] = pid[j];
 }
 
-// ------------------------------------------------ 3. pruned reverse search
+// --------------------------------------------------- pair state words
+// One 64-bit word per pair p = 64 v + i:
+//   bits  0..31  stamp: source pair of the first visitor in window `tag`
+//   bits 32..39  tag:   window of the last visit (0xFF: never visited)
+//   bits 40..51  arr:   sources that visited the pair in window `tag`
+//   bits 52..63  cnt:   sources that visited it before window `tag`
+// Both counts saturate at 4095 (> every k).  The pair's count of received
+// ranks at the start of window w is cnt, plus arr when tag < w.
+constexpr uint64_t kWordInit = 0xFFull << 32;
+constexpr uint32_t kSat = 4095;
+
+__device__ __forceinline__ uint32_t w_tag(uint64_t w) { return (uint32_t)(w >> 32) & 0xFFu; }
+__device__ __forceinline__ uint32_t w_arr(uint64_t w) { return (uint32_t)(w >> 40) & 0xFFFu; }
+__device__ __forceinline__ uint32_t w_cnt(uint64_t w) { return (uint32_t)(w >> 52); }
+
+__device__ __forceinline__ uint32_t prior_count(uint64_t w, uint32_t win) {
+    const uint32_t c = w_cnt(w) + (w_tag(w) != win ? w_arr(w) : 0u);
+    return c < kSat ? c : kSat;
+}
 
 __device__ __forceinline__ uint64_t hmix(uint64_t x) {
     x ^= x >> 31;
@@ -139,44 +172,66 @@ __device__ int hset_insert(uint64_t *T, uint32_t logcap, uint64_t key) {
 }
 
 struct WinArgs {
-    uint64_t *words;      // [64 n]: hi32 = ranks received so far, lo32 = first visitor
-    uint64_t *items;      // visits of this window: (pair << 32) | source index
-    uint64_t items_cap;
+    uint64_t *words;       // [64 n] pair state words
+    const uint64_t *lptr;  // live in-lists
+    const uint32_t *lsrc;
     uint64_t *hset;
     uint32_t logcap;
-    uint32_t ws, we;      // sources [ws, we) of this window
+    uint32_t win;          // window id (tag)
     uint32_t k;
+    const uint32_t *xcnt;  // records per node before this window
+    uint32_t *xadd;        // records per node in this window
+    uint64_t *rec;         // records: (node << 32) | source pair
+    uint64_t rec_cap;
+    uint64_t *front[2];    // current / next level: (pair << 32) | source pair
+    uint64_t front_cap;
     Ctl *ctl;
 };
 
-// Visit of pair p by source s: 1 if new, 0 if pruned or already visited by s.
-__device__ __forceinline__ int claim(const WinArgs &A, uint32_t p, uint32_t s, uint32_t &hashed) {
-    uint64_t old = load_relaxed(A.words + p);
+// Visit of pair q by the search of source pair src: 1 if it is a new visit
+// (and counts as one more rank received by q), 0 if pruned or repeated.
+__device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
+                                     uint32_t &hashed) {
+    uint64_t old = load_relaxed(A.words + q);
     for (;;) {
-        if ((uint32_t)(old >> 32) >= A.k) return 0;  // instance-local sketch full: prune
-        const uint32_t st = (uint32_t)old;
-        if (st == s) return 0;
-        if (st < A.ws || st >= A.we) {
-            const uint64_t nw = (old & 0xFFFFFFFF00000000ull) | s;
-            const uint64_t prev = atomicCAS((unsigned long long *)(A.words + p), old, nw);
+        if (prior_count(old, A.win) >= A.k) return 0;  // instance-local sketch full: prune
+        if (w_tag(old) != A.win) {
+            const uint64_t nw = (uint64_t)src | ((uint64_t)A.win << 32) | (1ull << 40) |
+                                ((uint64_t)prior_count(old, A.win) << 52);
+            const uint64_t prev = atomicCAS((unsigned long long *)(A.words + q), old, nw);
             if (prev == old) return 1;
             old = prev;
             continue;
         }
-        const int r = hset_insert(A.hset, A.logcap, ((uint64_t)p << 32) | s);
-        if (r < 0) {
-            atomicOr(&A.ctl->flags, kOvfHash);
+        if ((uint32_t)old == src) return 0;
+        const int r = hset_insert(A.hset, A.logcap, ((uint64_t)q << 32) | src);
+        if (r <= 0) {
+            if (r < 0) atomicOr(&A.ctl->flags, kOvfHash);
             return 0;
         }
-        hashed += r;
-        return r;
+        // one more source reached q in this window (the stamp no longer
+        // changes, only the arrival count)
+        while (w_arr(old) < kSat) {
+            const uint64_t prev =
+                atomicCAS((unsigned long long *)(A.words + q), old, old + (1ull << 40));
+            if (prev == old) break;
+            old = prev;
+        }
+        ++hashed;
+        return 1;
     }
 }
 
+// Record a visit of node v when v held fewer than k ranks at the window start.
+__device__ __forceinline__ bool wants_record(const WinArgs &A, uint32_t v) {
+    return A.xcnt[v] < A.k;
+}
+
+// ------------------------------------ 3. level-synchronous window search
 // Block-aggregated appends: threads stage new entries in LDS; one global
 // reservation per flush moves them to the output array (coalesced).
-constexpr uint32_t kChunk = 1024;        // input entries per block per round
-constexpr uint32_t kStage = 4096;        // staged outputs per round (32 KiB)
+constexpr uint32_t kChunk = 1024;
+constexpr uint32_t kStage = 2048;
 
 struct Stage {
     uint64_t buf[kStage];
@@ -197,7 +252,6 @@ __device__ __forceinline__ void stage_push(Stage &S, uint64_t v, uint64_t *out, 
     else atomicOr(flags, ovf_bit);
 }
 
-// Called by every thread of the block.
 __device__ __forceinline__ void stage_flush(Stage &S, uint64_t *out, uint64_t cap,
                                             unsigned long long *count, uint32_t *flags,
                                             uint32_t ovf_bit) {
@@ -214,79 +268,110 @@ __device__ __forceinline__ void stage_flush(Stage &S, uint64_t *out, uint64_t ca
     __syncthreads();
 }
 
-// Sources of the window start their searches.  Each source pair is claimed
-// only by its own source here, so the claim is a plain store.
-__global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_t *sources) {
-    __shared__ Stage S;
-    if (threadIdx.x == 0) S.n = 0;
-    __syncthreads();
-    for (uint64_t c = A.ws + (uint64_t)blockIdx.x * kChunk; c < A.we;
-         c += (uint64_t)gridDim.x * kChunk) {
-        const uint64_t end = c + kChunk < A.we ? c + kChunk : A.we;
-        for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
-            const uint32_t s = (uint32_t)t;
-            const uint32_t p = sources[s];
-            const uint64_t w = A.words[p];
-            if ((uint32_t)(w >> 32) >= A.k) continue;  // pruned
-            reinterpret_cast<uint32_t *>(A.words + p)[0] = s;
-            stage_push(S, ((uint64_t)p << 32) | s, A.items, A.items_cap, &A.ctl->count,
-                       &A.ctl->flags, kOvfItems);
-        }
-        stage_flush(S, A.items, A.items_cap, &A.ctl->count, &A.ctl->flags, kOvfItems);
-    }
-}
-
-// Expand the frontier items[a, b) over live in-edges of their instance.
-__device__ __forceinline__ void expand_range(const WinArgs &A, const uint64_t *lptr,
-                                             const uint32_t *lsrc, uint64_t a, uint64_t b,
-                                             uint64_t first, uint64_t stride, Stage &S,
-                                             uint32_t &scans, uint32_t &hashed) {
-    for (uint64_t c = a + first; c < b; c += stride) {
+// Expand front[a, b) (already claimed and recorded) over live in-edges;
+// new visits are recorded and appended as the next level.
+__device__ __forceinline__ void expand_range(const WinArgs &A, const uint64_t *cur, uint64_t *next,
+                                             uint64_t b, uint64_t first, uint64_t stride, Stage &F,
+                                             Stage &R, uint32_t &scans, uint32_t &hashed,
+                                             uint32_t &visits) {
+    for (uint64_t c = first; c < b; c += stride) {
         const uint64_t end = c + kChunk < b ? c + kChunk : b;
         for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
-            const uint64_t it = A.items[t];
+            const uint64_t it = cur[t];
             const uint32_t p = (uint32_t)(it >> 32);
-            const uint32_t s = (uint32_t)it;
+            const uint32_t src = (uint32_t)it;
             const uint32_t i = p % kPairStride;
-            const uint64_t e1 = lptr[p + 1];
-            for (uint64_t e = lptr[p]; e < e1; ++e) {
-                const uint32_t q = lsrc[e] * kPairStride + i;
+            const uint64_t e1 = A.lptr[p + 1];
+            for (uint64_t e = A.lptr[p]; e < e1; ++e) {
+                const uint32_t w = A.lsrc[e];
+                const uint32_t q = w * kPairStride + i;
                 ++scans;
-                if (claim(A, q, s, hashed) == 1)
-                    stage_push(S, ((uint64_t)q << 32) | s, A.items, A.items_cap, &A.ctl->count,
-                               &A.ctl->flags, kOvfItems);
+                if (claim(A, q, src, hashed) == 1) {
+                    ++visits;
+                    stage_push(F, ((uint64_t)q << 32) | src, next, A.front_cap, &A.ctl->count,
+                               &A.ctl->flags, kOvfSpill);
+                    if (wants_record(A, w)) {
+                        atomicAdd(A.xadd + w, 1u);
+                        stage_push(R, ((uint64_t)w << 32) | src, A.rec, A.rec_cap,
+                                   &A.ctl->records, &A.ctl->flags, kOvfRecords);
+                    }
+                }
             }
         }
-        stage_flush(S, A.items, A.items_cap, &A.ctl->count, &A.ctl->flags, kOvfItems);
+        stage_flush(F, next, A.front_cap, &A.ctl->count, &A.ctl->flags, kOvfSpill);
+        stage_flush(R, A.rec, A.rec_cap, &A.ctl->records, &A.ctl->flags, kOvfRecords);
     }
 }
 
-// One level with the whole grid; the last block to finish publishes the
-// next frontier boundary.
-__global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, const uint64_t *lptr,
-                                                   const uint32_t *lsrc, uint32_t level) {
-    __shared__ Stage S;
-    __shared__ uint32_t s_flags;
+struct ExpandShared {
+    Stage F, R;
+};
+
+// Level 0: the window's sources visit their own pairs.  Each source pair is
+// reached only by its own source at this point, so the claim is a store.
+__global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_t *sources,
+                                                        uint64_t ws, uint64_t we) {
+    __shared__ ExpandShared X;
+    if (threadIdx.x == 0) X.F.n = X.R.n = 0;
+    __syncthreads();
+    uint32_t visits = 0;
+    for (uint64_t c = ws + (uint64_t)blockIdx.x * kChunk; c < we;
+         c += (uint64_t)gridDim.x * kChunk) {
+        const uint64_t end = c + kChunk < we ? c + kChunk : we;
+        for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
+            const uint32_t p = sources[t];
+            const uint64_t old = A.words[p];
+            const uint32_t prior = prior_count(old, A.win);
+            if (prior >= A.k) continue;  // pruned
+            A.words[p] = (uint64_t)p | ((uint64_t)A.win << 32) | (1ull << 40) |
+                         ((uint64_t)prior << 52);
+            ++visits;
+            stage_push(X.F, ((uint64_t)p << 32) | p, A.front[0], A.front_cap, &A.ctl->count,
+                       &A.ctl->flags, kOvfSpill);
+            const uint32_t v = p / kPairStride;
+            if (wants_record(A, v)) {
+                atomicAdd(A.xadd + v, 1u);
+                stage_push(X.R, ((uint64_t)v << 32) | p, A.rec, A.rec_cap, &A.ctl->records,
+                           &A.ctl->flags, kOvfRecords);
+            }
+        }
+        stage_flush(X.F, A.front[0], A.front_cap, &A.ctl->count, &A.ctl->flags, kOvfSpill);
+        stage_flush(X.R, A.rec, A.rec_cap, &A.ctl->records, &A.ctl->flags, kOvfRecords);
+    }
+    wave_add(&A.ctl->visits, visits);
+}
+
+// One level with the whole grid; the last block to finish makes the next
+// level current.
+__global__ void __launch_bounds__(kBlock) k_expand(WinArgs A) {
+    __shared__ ExpandShared X;
+    __shared__ uint32_t s_flags, s_parity;
+    __shared__ unsigned long long s_cur;
     if (threadIdx.x == 0) {
-        S.n = 0;
+        X.F.n = X.R.n = 0;
         s_flags = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_parity = A.ctl->parity;
+        s_cur = A.ctl->cur;
     }
     __syncthreads();
-    uint32_t scans = 0, hashed = 0;
-    if (!s_flags) {  // after an overflow the window is redone with more room
-        const uint64_t a = A.ctl->lb[level & 3], b = A.ctl->lb[(level + 1) & 3];
-        expand_range(A, lptr, lsrc, a, b, (uint64_t)blockIdx.x * kChunk,
-                     (uint64_t)gridDim.x * kChunk, S, scans, hashed);
+    uint32_t scans = 0, hashed = 0, visits = 0;
+    if (!s_flags) {  // after an overflow the windows are redone with more room
+        expand_range(A, A.front[s_parity], A.front[s_parity ^ 1], s_cur,
+                     (uint64_t)blockIdx.x * kChunk, (uint64_t)gridDim.x * kChunk, X.F, X.R, scans,
+                     hashed, visits);
     }
     wave_add(&A.ctl->scans, scans);
     wave_add(&A.ctl->hinserts, hashed);
+    wave_add(&A.ctl->visits, visits);
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         const uint32_t prev = atomicAdd(&A.ctl->done_blocks, 1u);
         if (prev == gridDim.x - 1) {
-            A.ctl->lb[(level + 2) & 3] =
-                __hip_atomic_load(&A.ctl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            A.ctl->cur = __hip_atomic_load(&A.ctl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            A.ctl->count = 0;
+            A.ctl->parity = s_parity ^ 1;
+            A.ctl->levels += 1;
             A.ctl->done_blocks = 0;
             __threadfence();
         }
@@ -295,55 +380,53 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, const uint64_t *lp
 
 // Small frontiers: one workgroup runs level after level until the frontier
 // is empty, grows past `max_frontier`, or an overflow is flagged.
-__global__ void __launch_bounds__(1024) k_expand_tail(WinArgs A, const uint64_t *lptr,
-                                                      const uint32_t *lsrc, uint32_t level,
-                                                      uint64_t max_frontier) {
-    __shared__ Stage S;
-    __shared__ unsigned long long s_a, s_b;
-    __shared__ uint32_t s_stop;
-    if (threadIdx.x == 0) S.n = 0;
-    uint32_t scans = 0, hashed = 0;
+__global__ void __launch_bounds__(1024) k_expand_tail(WinArgs A, uint64_t max_frontier) {
+    __shared__ ExpandShared X;
+    __shared__ unsigned long long s_cur;
+    __shared__ uint32_t s_stop, s_parity;
+    if (threadIdx.x == 0) X.F.n = X.R.n = 0;
+    uint32_t scans = 0, hashed = 0, visits = 0;
     for (;;) {
         if (threadIdx.x == 0) {
-            s_a = A.ctl->lb[level & 3];
-            s_b = A.ctl->lb[(level + 1) & 3];
+            s_cur = A.ctl->cur;
+            s_parity = A.ctl->parity;
             const uint32_t f =
                 __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_stop = f || s_a == s_b || s_b - s_a > max_frontier;
+            s_stop = f || s_cur == 0 || s_cur > max_frontier;
         }
         __syncthreads();
         if (s_stop) break;
-        expand_range(A, lptr, lsrc, s_a, s_b, 0, kChunk, S, scans, hashed);
+        expand_range(A, A.front[s_parity], A.front[s_parity ^ 1], s_cur, 0, kChunk, X.F, X.R,
+                     scans, hashed, visits);
         if (threadIdx.x == 0) {
             __threadfence();
-            A.ctl->lb[(level + 2) & 3] =
-                __hip_atomic_load(&A.ctl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            A.ctl->cur = __hip_atomic_load(&A.ctl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            A.ctl->count = 0;
+            A.ctl->parity = s_parity ^ 1;
+            A.ctl->levels += 1;
         }
-        ++level;
         __syncthreads();
     }
     wave_add(&A.ctl->scans, scans);
     wave_add(&A.ctl->hinserts, hashed);
-    if (threadIdx.x == 0) A.ctl->level = level;
+    wave_add(&A.ctl->visits, visits);
 }
 
-// Start of an attempt at a window: clear the per-window fields.
+// Start of a window: clear the per-window fields.
 __global__ void k_ctl_begin(Ctl *ctl) {
-    ctl->lb[0] = ctl->lb[1] = ctl->lb[2] = ctl->lb[3] = 0;
+    ctl->levels = 0;
+    ctl->cur = 0;
     ctl->count = 0;
-    ctl->scans = 0;
     ctl->hinserts = 0;
-    ctl->flags = 0;
     ctl->done_blocks = 0;
-    ctl->level = 0;
+    ctl->parity = 0;
 }
 
-__global__ void k_seed_done(Ctl *ctl) { ctl->lb[1] = ctl->count; }
-
-// Roll the record counter back (after growing the record buffer).
-__global__ void k_ctl_records(Ctl *ctl, unsigned long long records) {
-    ctl->records = records;
-    ctl->flags = 0;
+// The sources' own visits (in front[0]) are the current level.
+__global__ void k_seed_done(Ctl *ctl) {
+    ctl->cur = ctl->count;
+    ctl->count = 0;
+    ctl->parity = 0;
 }
 
 struct WinBases {
@@ -354,41 +437,7 @@ __global__ void k_set_bases(unsigned long long *dst, WinBases wb) {
     if (threadIdx.x < 64) dst[threadIdx.x] = wb.b[threadIdx.x];
 }
 
-// Undo the claims of an aborted attempt at window [ws, we).
-__global__ void k_unclaim(uint64_t *words, uint64_t npairs, uint32_t ws, uint32_t we) {
-    for (uint64_t p = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; p < npairs;
-         p += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t w = words[p];
-        const uint32_t st = (uint32_t)w;
-        if (st >= ws && st < we) words[p] = (w & 0xFFFFFFFF00000000ull) | kNoSrc;
-    }
-}
-
 // ---------------------------------------------------------- 4. records
-
-// Keep a record of every visit of a node that held fewer than k ranks at the
-// window start (xcnt is the node's record count before this window).
-__global__ void __launch_bounds__(kBlock) k_records(const uint64_t *items, uint64_t count,
-                                                    const uint32_t *xcnt, uint32_t *xadd,
-                                                    uint32_t k, uint64_t *rec, uint64_t rec_cap,
-                                                    Ctl *ctl) {
-    __shared__ Stage S;
-    if (threadIdx.x == 0) S.n = 0;
-    __syncthreads();
-    for (uint64_t c = (uint64_t)blockIdx.x * kChunk; c < count; c += (uint64_t)gridDim.x * kChunk) {
-        const uint64_t end = c + kChunk < count ? c + kChunk : count;
-        for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
-            const uint64_t it = items[t];
-            const uint32_t v = (uint32_t)(it >> 32) / kPairStride;
-            if (xcnt[v] < k) {
-                atomicAdd(xadd + v, 1u);
-                stage_push(S, ((uint64_t)v << 32) | (uint32_t)it, rec, rec_cap, &ctl->records,
-                           &ctl->flags, kOvfRecords);
-            }
-        }
-        stage_flush(S, rec, rec_cap, &ctl->records, &ctl->flags, kOvfRecords);
-    }
-}
 
 __global__ void k_fold(uint32_t *xcnt, uint32_t *xadd, uint32_t n, uint32_t k, Ctl *ctl) {
     uint32_t crossed = 0;
@@ -405,26 +454,16 @@ __global__ void k_fold(uint32_t *xcnt, uint32_t *xadd, uint32_t n, uint32_t k, C
     wave_add(&ctl->full, crossed);
 }
 
-// Pair (v, i) received one more rank (its instance-local count).
-__global__ void k_count_arrivals(const uint64_t *items, uint64_t count, uint64_t *words) {
-    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < count;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t p = (uint32_t)(items[t] >> 32);
-        atomicAdd((uint32_t *)(words + p) + 1, 1u);  // high half of the little-endian word
-    }
-}
-
 // ------------------------------------------------------------- 5. merge
 
-__global__ void k_group(const uint64_t *rec, uint64_t nrec, const uint32_t *sources,
-                        uint64_t seed, const uint64_t *goff, uint32_t *gfill, uint64_t *seg) {
+__global__ void k_group(const uint64_t *rec, uint64_t nrec, uint64_t seed, const uint64_t *goff,
+                        uint32_t *gfill, uint64_t *seg) {
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nrec;
          t += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t r = rec[t];
         const uint32_t v = (uint32_t)(r >> 32);
-        const uint32_t s = (uint32_t)r;
         const uint64_t pos = goff[v] + atomicAdd(gfill + v, 1u);
-        seg[pos] = pair_rank(seed, sources[s]);
+        seg[pos] = pair_rank(seed, (uint32_t)r);
     }
 }
 
@@ -480,12 +519,14 @@ __global__ void __launch_bounds__(64) k_select(const uint64_t *goff, const uint6
     }
 }
 
-uint32_t choose_windows(uint32_t n, uint32_t k) {
-    // window 0 holds about k/2 sources per instance; later windows double
-    double x = 2.0 * n / (double)k;
-    uint32_t W = 1;
-    while (W < 48 && (double)(1ull << (W - 1)) < x) ++W;
-    return W;
+// Window 0 holds about k/2 sources per instance (ranks of at most b0 bits,
+// a fraction 2^(b0-64) of all); the windows after it grow fourfold.
+void choose_windows(uint32_t n, uint32_t k, uint32_t &W, uint32_t &b0) {
+    const double x = 2.0 * n / (double)k;  // 1 / (window-0 fraction)
+    uint32_t lg = 0;
+    while (lg < 63 && (double)(1ull << lg) < x) ++lg;
+    b0 = 64 - lg;
+    W = 1 + (lg + 1) / 2;
 }
 
 uint64_t next_pow2(uint64_t x) {
@@ -494,7 +535,133 @@ uint64_t next_pow2(uint64_t x) {
     return p;
 }
 
+struct Capacity {
+    uint64_t rec, front, hash;
+    bool hash_full;  // use the whole hash table in every window
+};
+
 }  // namespace
+
+// One attempt at the windows and the merge; throws Retry when a buffer was
+// too small (the caller's outputs are written only by the merge).
+static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const LiveLists &live,
+                        const uint32_t *sources, const unsigned long long *wb, uint32_t W,
+                        const Capacity &cap, uint64_t *ranks_out, uint32_t *size_out,
+                        uint64_t *work, Arena &A) {
+    hipStream_t s = A.stream();
+    const uint32_t n = g->n;
+    const uint64_t npairs = (uint64_t)n * kPairStride;
+    uint64_t *words = A.alloc<uint64_t>(npairs);
+    fill_u64(words, kWordInit, npairs, s);
+    uint32_t *xcnt = A.alloc<uint32_t>(n + 1);
+    uint32_t *xadd = A.alloc<uint32_t>(n + 1);
+    fill_u32(xcnt, 0, n + 1, s);
+    fill_u32(xadd, 0, n + 1, s);
+    Ctl *ctl = A.alloc<Ctl>(1);
+    fill_u64((uint64_t *)ctl, 0, sizeof(Ctl) / 8, s);
+    uint64_t *rec = A.alloc<uint64_t>(cap.rec);
+    uint64_t *front0 = A.alloc<uint64_t>(cap.front);
+    uint64_t *front1 = A.alloc<uint64_t>(cap.front);
+    uint64_t *hset = A.alloc<uint64_t>(cap.hash);
+    uint64_t windows_done = 0, prev_hash = 0, prev_nw = 0;
+    constexpr uint64_t kTail = 8192;  // frontiers this small: one-workgroup loop
+    Ctl h;
+    for (uint32_t w = 0; w < W; ++w) {
+        const uint64_t ws = wb[w], we = wb[w + 1];
+        if (ws == we) continue;
+        read_back(&h, ctl, sizeof h, s);
+        if (h.flags) throw Retry{h.flags};
+        if (h.full >= n) break;  // every sketch holds k ranks: later ranks cannot enter
+        const uint64_t nw = we - ws;
+        // A pair is often visited by several sources of one window; every
+        // visit after the first goes through the hash set.  Hashed visits
+        // per source fall from window to window (pruning takes hold), so the
+        // previous window's rate bounds this one's; window 0 assumes 16.
+        const double pred = w == 0 || prev_nw == 0
+                                ? 16.0 * (double)nw
+                                : 1.5 * (double)prev_hash * (double)nw / (double)prev_nw + (double)nw;
+        const uint64_t hsize =
+            cap.hash_full ? cap.hash
+                          : std::min<uint64_t>(cap.hash, next_pow2(std::max<uint64_t>(
+                                                             1ull << 16, (uint64_t)(2.5 * pred))));
+        uint32_t logcap = 0;
+        while ((1ull << logcap) < hsize) ++logcap;
+        fill_u64(hset, kNone, hsize, s);
+        k_ctl_begin<<<1, 1, 0, s>>>(ctl);
+        SKIM_LAUNCH_CHECK();
+        WinArgs WA{words, live.ptr, live.adj, hset, logcap, w, k, xcnt, xadd, rec, cap.rec,
+                   {front0, front1}, cap.front, ctl};
+        {
+            LaunchTimer t("k_seed_window", s);
+            k_seed_window<<<grid_for(nw, kChunk, 4096), kBlock, 0, s>>>(WA, sources, ws, we);
+        }
+        SKIM_LAUNCH_CHECK();
+        k_seed_done<<<1, 1, 0, s>>>(ctl);
+        SKIM_LAUNCH_CHECK();
+        for (;;) {
+            read_back(&h, ctl, sizeof h, s);
+            if (h.flags) {
+                if (std::getenv("SKIM_DEBUG"))
+                    std::fprintf(stderr, "skim window %u overflow %u: hashed %llu table %llu\n", w,
+                                 h.flags, h.hinserts, (unsigned long long)hsize);
+                throw Retry{h.flags};
+            }
+            const uint64_t f = h.cur;
+            if (f == 0) break;  // empty frontier: window done
+            if (f <= kTail) {
+                LaunchTimer t("k_expand_tail", s);
+                k_expand_tail<<<1, 1024, 0, s>>>(WA, 4 * kTail);
+                SKIM_LAUNCH_CHECK();
+                continue;
+            }
+            for (int j = 0; j < 3; ++j) {
+                const unsigned grid = j == 0 ? grid_for(f, kChunk, 2048) : 2048;
+                LaunchTimer t("k_expand", s);
+                k_expand<<<grid, kBlock, 0, s>>>(WA);
+                SKIM_LAUNCH_CHECK();
+            }
+        }
+        prev_hash = h.hinserts;
+        prev_nw = nw;
+        if (std::getenv("SKIM_DEBUG"))
+            std::fprintf(stderr, "skim window %u: sources %llu visits-so-far %llu hashed %llu "
+                                 "table %llu levels %llu records %llu\n",
+                         w, (unsigned long long)nw, h.visits, h.hinserts,
+                         (unsigned long long)hsize, h.levels, h.records);
+        k_fold<<<grid_for(n, kBlock, 8192), kBlock, 0, s>>>(xcnt, xadd, n, k, ctl);
+        SKIM_LAUNCH_CHECK();
+        ++windows_done;
+    }
+    read_back(&h, ctl, sizeof h, s);
+    if (h.flags) throw Retry{h.flags};
+    const uint64_t nrec = h.records;
+
+    // ---- 5. merge: group records by node, keep the k smallest
+    A.release(words);
+    A.release(front0);
+    A.release(front1);
+    A.release(hset);
+    uint64_t *goff = A.alloc<uint64_t>((uint64_t)n + 1);
+    exclusive_scan_u32(xcnt, goff, n, A);
+    uint64_t *seg = A.alloc<uint64_t>(nrec ? nrec : 1);
+    fill_u32(xadd, 0, n + 1, s);
+    if (nrec) {
+        LaunchTimer t("k_group", s);
+        k_group<<<grid_for(nrec, kBlock, 16384), kBlock, 0, s>>>(rec, nrec, seed, goff, xadd, seg);
+        SKIM_LAUNCH_CHECK();
+    }
+    {
+        LaunchTimer t("k_select", s);
+        k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(goff, seg, n, k, ranks_out, size_out);
+    }
+    SKIM_LAUNCH_CHECK();
+    if (work) {
+        work[0] = h.visits;
+        work[1] = h.scans;
+        work[2] = nrec;
+        work[3] = windows_done;
+    }
+}
 
 // Host orchestration of one sketch build.
 static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
@@ -508,23 +675,20 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     const uint64_t m = g->m;
     uint32_t *esrc = A.alloc<uint32_t>(m ? m : 1);
     validate_graph(g, esrc, A);
-
-    const uint64_t npairs = (uint64_t)n * kPairStride;  // pair-id space (stride 64)
-    const uint64_t nsrc = (uint64_t)n * ell;            // actual pairs
+    const uint64_t nsrc = (uint64_t)n * ell;  // actual pairs
 
     // ---- 1. live lists (reverse: in-edges of every pair)
     LiveLists live = build_live_lists(g, ell, seed, esrc, /*forward=*/false, A);
-    const uint64_t *lptr = live.ptr;
-    const uint32_t *lsrc = live.adj;
     A.release(esrc);
 
     // ---- 2. rank windows
-    const uint32_t W = choose_windows(n, k);
+    uint32_t W = 1, b0 = 64;
+    choose_windows(n, k, W, b0);
     unsigned long long *wbuf = A.alloc<unsigned long long>(2 * 64);
     fill_u64((uint64_t *)wbuf, 0, 128, s);
     const unsigned rblocks = (unsigned)((nsrc + (uint64_t)kBlock * kRankPer - 1) /
                                         ((uint64_t)kBlock * kRankPer));
-    k_rank_hist<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, wbuf);
+    k_rank_hist<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, wbuf);
     SKIM_LAUNCH_CHECK();
     unsigned long long hw[64] = {};
     read_back(hw, wbuf, sizeof(unsigned long long) * 64, s);
@@ -534,172 +698,45 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     std::memcpy(bases.b, wb, sizeof bases.b);
     k_set_bases<<<1, 64, 0, s>>>(wbuf, bases);
     SKIM_LAUNCH_CHECK();
-    fill_u64((uint64_t *)wbuf + 64, 0, 64, s);
     uint32_t *sources = A.alloc<uint32_t>(nsrc);
-    k_rank_scatter<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, wbuf, wbuf + 64, sources);
+    k_rank_scatter<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, wbuf, wbuf + 64, sources);
     SKIM_LAUNCH_CHECK();
 
-    // ---- 3./4. windows
-    uint64_t *words = A.alloc<uint64_t>(npairs);
-    fill_u64(words, (uint64_t)kNoSrc, npairs, s);  // 0 ranks received, no visitor
-    uint32_t *xcnt = A.alloc<uint32_t>(n + 1);
-    uint32_t *xadd = A.alloc<uint32_t>(n + 1);
-    fill_u32(xcnt, 0, n + 1, s);
-    fill_u32(xadd, 0, n + 1, s);
-    Ctl *ctl = A.alloc<Ctl>(1);
-    fill_u64((uint64_t *)ctl, 0, sizeof(Ctl) / 8, s);
-
-    uint64_t rec_cap = std::max<uint64_t>(1ull << 20, (uint64_t)n * k + (uint64_t)n * 4);
-    uint64_t *rec = A.alloc<uint64_t>(rec_cap);
-    uint64_t items_cap = 0, hcap = 0;
-    uint64_t *items = nullptr, *hset = nullptr;
-    uint64_t total_items = 0, total_scans = 0, windows_done = 0;
-    uint64_t prev_items = 0, prev_hash = 0;
-    constexpr uint64_t kTail = 16384;  // frontiers this small go to the one-workgroup loop
-    Ctl h;
-
-    for (uint32_t w = 0; w < W; ++w) {
-        const uint32_t ws = (uint32_t)wb[w], we = (uint32_t)wb[w + 1];
-        if (ws == we) continue;
-        read_back(&h, ctl, sizeof h, s);
-        if (h.full >= n) break;  // every sketch holds k ranks: later ranks cannot enter
-        const uint64_t nw = we - ws;
-        // windows double in size: predict from the previous one
-        uint64_t want_items = std::max<uint64_t>({1ull << 16, 3 * nw, 3 * prev_items});
-        uint64_t want_hash = next_pow2(std::max<uint64_t>({1ull << 14, nw / 2, 8 * prev_hash}));
-        for (int attempt = 0;; ++attempt) {
-            if (attempt >= 24) {
-                set_error("window %u did not fit after %d attempts", w, attempt);
-                throw Fail{SKIM_EDEVICE};
-            }
-            if (want_items > items_cap) {
-                if (items) A.release(items);
-                items_cap = want_items;
-                items = A.alloc<uint64_t>(items_cap);
-            }
-            if (want_hash > hcap) {
-                if (hset) A.release(hset);
-                hcap = want_hash;
-                hset = A.alloc<uint64_t>(hcap);
-            }
-            uint32_t logcap = 0;
-            while ((1ull << logcap) < hcap) ++logcap;
-            fill_u64(hset, kNone, hcap, s);
-            k_ctl_begin<<<1, 1, 0, s>>>(ctl);
-            SKIM_LAUNCH_CHECK();
-
-            WinArgs WA{words, items, items_cap, hset, logcap, ws, we, k, ctl};
-            {
-                LaunchTimer t("k_seed_window", s);
-                k_seed_window<<<grid_for(nw, kChunk, 4096), kBlock, 0, s>>>(WA, sources);
-            }
-            SKIM_LAUNCH_CHECK();
-            k_seed_done<<<1, 1, 0, s>>>(ctl);
-            SKIM_LAUNCH_CHECK();
-            uint32_t level = 0;
-            for (;;) {
-                read_back(&h, ctl, sizeof h, s);
-                if (h.flags) break;
-                const uint64_t fa = h.lb[level & 3], fb = h.lb[(level + 1) & 3];
-                if (fa == fb) break;  // empty frontier: window done
-                if (fb - fa <= kTail) {
-                    LaunchTimer t("k_expand_tail", s);
-                    k_expand_tail<<<1, 1024, 0, s>>>(WA, lptr, lsrc, level, 4 * kTail);
-                    SKIM_LAUNCH_CHECK();
-                    read_back(&h, ctl, sizeof h, s);
-                    level = h.level;
-                    continue;
-                }
-                // big frontier: a few whole-grid levels before looking again
-                for (int j = 0; j < 3; ++j, ++level) {
-                    const unsigned grid = j == 0 ? grid_for(fb - fa, kChunk, 2048) : 2048;
-                    LaunchTimer t("k_expand", s);
-                    k_expand<<<grid, kBlock, 0, s>>>(WA, lptr, lsrc, level);
-                    SKIM_LAUNCH_CHECK();
-                }
-            }
-            if (h.flags & (kOvfItems | kOvfHash)) {
-                k_unclaim<<<grid_for(npairs, kBlock, 8192), kBlock, 0, s>>>(words, npairs, ws, we);
-                SKIM_LAUNCH_CHECK();
-                if (h.flags & kOvfItems) want_items = std::max<uint64_t>(2 * items_cap, h.count + nw);
-                if (h.flags & kOvfHash) want_hash = 2 * hcap;
-                continue;
-            }
+    // ---- 3./4./5. windows and merge; restart with more room on overflow
+    uint64_t biggest = 0;
+    for (uint32_t w = 0; w < W; ++w) biggest = std::max<uint64_t>(biggest, hw[w]);
+    Capacity cap{std::max<uint64_t>(1ull << 20, 2 * (uint64_t)n * k),
+                 std::max<uint64_t>(1ull << 20, 2 * biggest),
+                 next_pow2(std::max<uint64_t>(1ull << 16, 8 * biggest)), false};
+    uint32_t retry_flags = 0;
+    int attempt = 0;
+    for (;; ++attempt) {
+        try {
+            Arena B(s);
+            run_windows(g, k, seed, live, sources, wb, W, cap, ranks_out, size_out, work, B);
             break;
-        }
-        const uint64_t count = h.count;
-        prev_items = count;
-        prev_hash = h.hinserts;
-        total_items += count;
-        total_scans += h.scans;
-        // records of nodes that held fewer than k ranks at the window start
-        const uint64_t rec_before = h.records;
-        for (int attempt = 0;; ++attempt) {
-            if (attempt >= 8) {
-                set_error("record buffer did not fit");
-                throw Fail{SKIM_EDEVICE};
+        } catch (const Retry &r) {
+            retry_flags |= r.flags;
+            if (attempt >= 6) {
+                set_error("sketch build buffers did not fit after %d attempts (flags %u)", attempt,
+                          r.flags);
+                throw Fail{SKIM_ENOMEM};
             }
-            {
-                LaunchTimer t("k_records", s);
-                k_records<<<grid_for(count, kChunk, 4096), kBlock, 0, s>>>(items, count, xcnt, xadd,
-                                                                           k, rec, rec_cap, ctl);
+            if (r.flags & kOvfRecords) cap.rec *= 2;
+            if (r.flags & kOvfSpill) cap.front *= 2;
+            if (r.flags & kOvfHash) {
+                if (cap.hash_full) cap.hash *= 2;
+                cap.hash_full = true;
             }
-            SKIM_LAUNCH_CHECK();
-            read_back(&h, ctl, sizeof h, s);
-            if (!(h.flags & kOvfRecords)) break;
-            // grow the record buffer, keep what earlier windows wrote, retry
-            const uint64_t need = h.records;
-            uint64_t new_cap = std::max<uint64_t>(2 * rec_cap, need + need / 4);
-            uint64_t *nrec = A.alloc<uint64_t>(new_cap);
-            SKIM_HIP(hipMemcpyAsync(nrec, rec, rec_before * sizeof(uint64_t),
-                                    hipMemcpyDeviceToDevice, s));
-            A.release(rec);
-            rec = nrec;
-            rec_cap = new_cap;
-            fill_u32(xadd, 0, n + 1, s);
-            k_ctl_records<<<1, 1, 0, s>>>(ctl, rec_before);
-            SKIM_LAUNCH_CHECK();
         }
-        k_fold<<<grid_for(n, kBlock, 8192), kBlock, 0, s>>>(xcnt, xadd, n, k, ctl);
-        SKIM_LAUNCH_CHECK();
-        {
-            LaunchTimer t("k_count_arrivals", s);
-            k_count_arrivals<<<grid_for(count, kBlock, 16384), kBlock, 0, s>>>(items, count, words);
-        }
-        SKIM_LAUNCH_CHECK();
-        ++windows_done;
     }
-    read_back(&h, ctl, sizeof h, s);
-    const uint64_t nrec = h.records;
-
-    // ---- 5. merge: group records by node, keep the k smallest
-    A.release(words);
-    if (items) A.release(items);
-    if (hset) A.release(hset);
-    uint64_t *goff = A.alloc<uint64_t>((uint64_t)n + 1);
-    exclusive_scan_u32(xcnt, goff, n, A);
-    uint64_t *seg = A.alloc<uint64_t>(nrec ? nrec : 1);
-    fill_u32(xadd, 0, n + 1, s);
-    if (nrec) {
-        LaunchTimer t("k_group", s);
-        k_group<<<grid_for(nrec, kBlock, 16384), kBlock, 0, s>>>(rec, nrec, sources, seed, goff, xadd,
-                                                                 seg);
-        SKIM_LAUNCH_CHECK();
+    if (work) {
+        work[4] = (uint64_t)attempt;
+        work[5] = retry_flags;
     }
-    {
-        LaunchTimer t("k_select", s);
-        k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(goff, seg, n, k, ranks_out, size_out);
-    }
-    SKIM_LAUNCH_CHECK();
     if (est_out) launch_estimates(ranks_out, size_out, n, k, ell, est_out, s);
     SKIM_HIP(hipStreamSynchronize(s));
     timing_resolve();
-    if (work) {
-        work[0] = total_items;
-        work[1] = total_scans;
-        work[2] = nrec;
-        work[3] = windows_done;
-    }
 }
 
 }  // namespace skim

@@ -69,7 +69,8 @@ def test_powerlaw_many_windows(oracle_lib):
     g = Graph(20000, rp, col, wc_thresholds(rp, col, 20000))
     log("chung-lu 20k wc l=64 k=64")
     work = _check(oracle_lib, g, 64, 64, 1)
-    assert work["windows"] > 8
+    log(f"work {work}")
+    assert work["windows"] >= 4 and work["restarts"] == 0
     log("chung-lu 20k uniform p=0.1 l=32 k=16")
     g2 = Graph(20000, rp, col, np.full(col.size, 0xFFFFFFFF // 10, dtype=np.uint32))
     _check(oracle_lib, g2, 32, 16, 2)
