@@ -54,18 +54,17 @@ struct Retry {
 };
 
 // Device control block read back by the host at synchronisation points.
+// Level L of a window's search reads front[L % 2] (size[L % 3] entries) and
+// appends level L + 1 to front[(L + 1) % 2], counting in size[(L + 1) % 3];
+// it also clears size[(L + 2) % 3] for the level after.
 struct Ctl {
-    unsigned long long cur;       // size of the current level (in front[parity])
-    unsigned long long count;     // entries of the next level appended so far
+    unsigned long long size[3];   // frontier sizes, ring over levels
     unsigned long long scans;     // live in-edges scanned (work counter)
     unsigned long long hinserts;  // hash-set insertions in this window
     unsigned long long records;   // records appended (all windows)
     unsigned long long full;      // nodes holding k records
     unsigned long long visits;    // accepted visits (work counter)
-    unsigned long long levels;    // levels expanded in this window
     uint32_t flags;               // overflow bits
-    uint32_t done_blocks;         // blocks finished in the current level
-    uint32_t parity;              // front[parity] holds the current level
     uint32_t pad;
 };
 
@@ -133,8 +132,9 @@ __global__ void k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed, uint32_t
 //   bits 32..39  tag:   window of the last visit (0xFF: never visited)
 //   bits 40..51  arr:   sources that visited the pair in window `tag`
 //   bits 52..63  cnt:   sources that visited it before window `tag`
-// Both counts saturate at 4095 (> every k).  The pair's count of received
-// ranks at the start of window w is cnt, plus arr when tag < w.
+// Counts are at most 4095 (> every k); see claim() for arrivals beyond.  The
+// pair's count of received ranks at the start of window w is cnt, plus arr
+// when tag < w.
 constexpr uint64_t kWordInit = 0xFFull << 32;
 constexpr uint32_t kSat = 4095;
 
@@ -209,14 +209,11 @@ __device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
             if (r < 0) atomicOr(&A.ctl->flags, kOvfHash);
             return 0;
         }
-        // one more source reached q in this window (the stamp no longer
-        // changes, only the arrival count)
-        while (w_arr(old) < kSat) {
-            const uint64_t prev =
-                atomicCAS((unsigned long long *)(A.words + q), old, old + (1ull << 40));
-            if (prev == old) break;
-            old = prev;
-        }
+        // One more source reached q in this window.  A carry out of the
+        // 12-bit arrival field (4096 arrivals) turns into +1 on cnt, and cnt
+        // itself can wrap: both only ever undercount, which can only weaken
+        // pruning, never make it wrong.
+        atomicAdd((unsigned long long *)(A.words + q), 1ull << 40);
         ++hashed;
         return 1;
     }
@@ -230,8 +227,8 @@ __device__ __forceinline__ bool wants_record(const WinArgs &A, uint32_t v) {
 // ------------------------------------ 3. level-synchronous window search
 // Block-aggregated appends: threads stage new entries in LDS; one global
 // reservation per flush moves them to the output array (coalesced).
-constexpr uint32_t kChunk = 1024;
-constexpr uint32_t kStage = 2048;
+constexpr uint32_t kChunk = 1024;  // frontier entries per block per round
+constexpr uint32_t kStage = 2048;  // staged outputs per round (16 KiB per stage)
 
 struct Stage {
     uint64_t buf[kStage];
@@ -252,30 +249,39 @@ __device__ __forceinline__ void stage_push(Stage &S, uint64_t v, uint64_t *out, 
     else atomicOr(flags, ovf_bit);
 }
 
-__device__ __forceinline__ void stage_flush(Stage &S, uint64_t *out, uint64_t cap,
-                                            unsigned long long *count, uint32_t *flags,
-                                            uint32_t ovf_bit) {
+// Flush both stages; the two reservations are issued by different waves so
+// they are in flight together.  Called by every thread of the block.
+__device__ __forceinline__ void stage_flush2(Stage &F, uint64_t *fout, uint64_t fcap,
+                                             unsigned long long *fcount, Stage &R, uint64_t *rout,
+                                             uint64_t rcap, unsigned long long *rcount,
+                                             uint32_t *flags) {
     __syncthreads();
-    const uint32_t m = S.n < kStage ? S.n : kStage;
-    if (threadIdx.x == 0) S.base = m ? atomicAdd(count, (unsigned long long)m) : 0;
+    const uint32_t mf = F.n < kStage ? F.n : kStage;
+    const uint32_t mr = R.n < kStage ? R.n : kStage;
+    if (threadIdx.x == 0) F.base = mf ? atomicAdd(fcount, (unsigned long long)mf) : 0;
+    if (threadIdx.x == 64) R.base = mr ? atomicAdd(rcount, (unsigned long long)mr) : 0;
     __syncthreads();
-    const unsigned long long base = S.base;
-    if (m && base + m > cap && threadIdx.x == 0) atomicOr(flags, ovf_bit);
-    for (uint32_t j = threadIdx.x; j < m; j += blockDim.x)
-        if (base + j < cap) out[base + j] = S.buf[j];
+    const unsigned long long fb = F.base, rb = R.base;
+    if (threadIdx.x == 0 && mf && fb + mf > fcap) atomicOr(flags, kOvfSpill);
+    if (threadIdx.x == 64 && mr && rb + mr > rcap) atomicOr(flags, kOvfRecords);
+    for (uint32_t j = threadIdx.x; j < mf; j += blockDim.x)
+        if (fb + j < fcap) fout[fb + j] = F.buf[j];
+    for (uint32_t j = threadIdx.x; j < mr; j += blockDim.x)
+        if (rb + j < rcap) rout[rb + j] = R.buf[j];
     __syncthreads();
-    if (threadIdx.x == 0) S.n = 0;
+    if (threadIdx.x == 0) F.n = R.n = 0;
     __syncthreads();
 }
 
-// Expand front[a, b) (already claimed and recorded) over live in-edges;
-// new visits are recorded and appended as the next level.
+// Expand cur[0, b) (already claimed and recorded) over live in-edges; new
+// visits are recorded and appended to next (counted in *next_count).
 __device__ __forceinline__ void expand_range(const WinArgs &A, const uint64_t *cur, uint64_t *next,
-                                             uint64_t b, uint64_t first, uint64_t stride, Stage &F,
-                                             Stage &R, uint32_t &scans, uint32_t &hashed,
-                                             uint32_t &visits) {
-    for (uint64_t c = first; c < b; c += stride) {
-        const uint64_t end = c + kChunk < b ? c + kChunk : b;
+                                             unsigned long long *next_count, uint64_t b,
+                                             uint32_t chunk, Stage &F, Stage &R, uint32_t &scans,
+                                             uint32_t &hashed, uint32_t &visits) {
+    const uint64_t stride = (uint64_t)gridDim.x * chunk;
+    for (uint64_t c = (uint64_t)blockIdx.x * chunk; c < b; c += stride) {
+        const uint64_t end = c + chunk < b ? c + chunk : b;
         for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
             const uint64_t it = cur[t];
             const uint32_t p = (uint32_t)(it >> 32);
@@ -288,7 +294,7 @@ __device__ __forceinline__ void expand_range(const WinArgs &A, const uint64_t *c
                 ++scans;
                 if (claim(A, q, src, hashed) == 1) {
                     ++visits;
-                    stage_push(F, ((uint64_t)q << 32) | src, next, A.front_cap, &A.ctl->count,
+                    stage_push(F, ((uint64_t)q << 32) | src, next, A.front_cap, next_count,
                                &A.ctl->flags, kOvfSpill);
                     if (wants_record(A, w)) {
                         atomicAdd(A.xadd + w, 1u);
@@ -298,8 +304,8 @@ __device__ __forceinline__ void expand_range(const WinArgs &A, const uint64_t *c
                 }
             }
         }
-        stage_flush(F, next, A.front_cap, &A.ctl->count, &A.ctl->flags, kOvfSpill);
-        stage_flush(R, A.rec, A.rec_cap, &A.ctl->records, &A.ctl->flags, kOvfRecords);
+        stage_flush2(F, next, A.front_cap, next_count, R, A.rec, A.rec_cap, &A.ctl->records,
+                     &A.ctl->flags);
     }
 }
 
@@ -326,7 +332,7 @@ __global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_
             A.words[p] = (uint64_t)p | ((uint64_t)A.win << 32) | (1ull << 40) |
                          ((uint64_t)prior << 52);
             ++visits;
-            stage_push(X.F, ((uint64_t)p << 32) | p, A.front[0], A.front_cap, &A.ctl->count,
+            stage_push(X.F, ((uint64_t)p << 32) | p, A.front[0], A.front_cap, &A.ctl->size[0],
                        &A.ctl->flags, kOvfSpill);
             const uint32_t v = p / kPairStride;
             if (wants_record(A, v)) {
@@ -335,77 +341,29 @@ __global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_
                            &A.ctl->flags, kOvfRecords);
             }
         }
-        stage_flush(X.F, A.front[0], A.front_cap, &A.ctl->count, &A.ctl->flags, kOvfSpill);
-        stage_flush(X.R, A.rec, A.rec_cap, &A.ctl->records, &A.ctl->flags, kOvfRecords);
+        stage_flush2(X.F, A.front[0], A.front_cap, &A.ctl->size[0], X.R, A.rec, A.rec_cap,
+                     &A.ctl->records, &A.ctl->flags);
     }
     wave_add(&A.ctl->visits, visits);
 }
 
-// One level with the whole grid; the last block to finish makes the next
-// level current.
-__global__ void __launch_bounds__(kBlock) k_expand(WinArgs A) {
+// Level L of the window's search, on the whole grid; each block takes
+// `chunk` (<= kChunk) frontier entries per round.
+__global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32_t chunk) {
     __shared__ ExpandShared X;
-    __shared__ uint32_t s_flags, s_parity;
-    __shared__ unsigned long long s_cur;
+    __shared__ uint32_t s_flags;
+    __shared__ unsigned long long s_size;
     if (threadIdx.x == 0) {
         X.F.n = X.R.n = 0;
         s_flags = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_parity = A.ctl->parity;
-        s_cur = A.ctl->cur;
+        s_size = A.ctl->size[L % 3];
+        if (blockIdx.x == 0) A.ctl->size[(L + 2) % 3] = 0;  // counter of level L + 2
     }
     __syncthreads();
     uint32_t scans = 0, hashed = 0, visits = 0;
     if (!s_flags) {  // after an overflow the windows are redone with more room
-        expand_range(A, A.front[s_parity], A.front[s_parity ^ 1], s_cur,
-                     (uint64_t)blockIdx.x * kChunk, (uint64_t)gridDim.x * kChunk, X.F, X.R, scans,
-                     hashed, visits);
-    }
-    wave_add(&A.ctl->scans, scans);
-    wave_add(&A.ctl->hinserts, hashed);
-    wave_add(&A.ctl->visits, visits);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t prev = atomicAdd(&A.ctl->done_blocks, 1u);
-        if (prev == gridDim.x - 1) {
-            A.ctl->cur = __hip_atomic_load(&A.ctl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            A.ctl->count = 0;
-            A.ctl->parity = s_parity ^ 1;
-            A.ctl->levels += 1;
-            A.ctl->done_blocks = 0;
-            __threadfence();
-        }
-    }
-}
-
-// Small frontiers: one workgroup runs level after level until the frontier
-// is empty, grows past `max_frontier`, or an overflow is flagged.
-__global__ void __launch_bounds__(1024) k_expand_tail(WinArgs A, uint64_t max_frontier) {
-    __shared__ ExpandShared X;
-    __shared__ unsigned long long s_cur;
-    __shared__ uint32_t s_stop, s_parity;
-    if (threadIdx.x == 0) X.F.n = X.R.n = 0;
-    uint32_t scans = 0, hashed = 0, visits = 0;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            s_cur = A.ctl->cur;
-            s_parity = A.ctl->parity;
-            const uint32_t f =
-                __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_stop = f || s_cur == 0 || s_cur > max_frontier;
-        }
-        __syncthreads();
-        if (s_stop) break;
-        expand_range(A, A.front[s_parity], A.front[s_parity ^ 1], s_cur, 0, kChunk, X.F, X.R,
-                     scans, hashed, visits);
-        if (threadIdx.x == 0) {
-            __threadfence();
-            A.ctl->cur = __hip_atomic_load(&A.ctl->count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            A.ctl->count = 0;
-            A.ctl->parity = s_parity ^ 1;
-            A.ctl->levels += 1;
-        }
-        __syncthreads();
+        expand_range(A, A.front[L & 1], A.front[(L + 1) & 1], &A.ctl->size[(L + 1) % 3], s_size,
+                     chunk, X.F, X.R, scans, hashed, visits);
     }
     wave_add(&A.ctl->scans, scans);
     wave_add(&A.ctl->hinserts, hashed);
@@ -414,19 +372,8 @@ __global__ void __launch_bounds__(1024) k_expand_tail(WinArgs A, uint64_t max_fr
 
 // Start of a window: clear the per-window fields.
 __global__ void k_ctl_begin(Ctl *ctl) {
-    ctl->levels = 0;
-    ctl->cur = 0;
-    ctl->count = 0;
+    ctl->size[0] = ctl->size[1] = ctl->size[2] = 0;
     ctl->hinserts = 0;
-    ctl->done_blocks = 0;
-    ctl->parity = 0;
-}
-
-// The sources' own visits (in front[0]) are the current level.
-__global__ void k_seed_done(Ctl *ctl) {
-    ctl->cur = ctl->count;
-    ctl->count = 0;
-    ctl->parity = 0;
 }
 
 struct WinBases {
@@ -564,7 +511,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     uint64_t *front1 = A.alloc<uint64_t>(cap.front);
     uint64_t *hset = A.alloc<uint64_t>(cap.hash);
     uint64_t windows_done = 0, prev_hash = 0, prev_nw = 0;
-    constexpr uint64_t kTail = 8192;  // frontiers this small: one-workgroup loop
+    constexpr uint64_t kSmall = 65536;  // frontiers handled in batches of 8 levels
     Ctl h;
     for (uint32_t w = 0; w < W; ++w) {
         const uint64_t ws = wb[w], we = wb[w + 1];
@@ -596,8 +543,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
             k_seed_window<<<grid_for(nw, kChunk, 4096), kBlock, 0, s>>>(WA, sources, ws, we);
         }
         SKIM_LAUNCH_CHECK();
-        k_seed_done<<<1, 1, 0, s>>>(ctl);
-        SKIM_LAUNCH_CHECK();
+        uint32_t L = 0;
         for (;;) {
             read_back(&h, ctl, sizeof h, s);
             if (h.flags) {
@@ -606,18 +552,20 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                                  h.flags, h.hinserts, (unsigned long long)hsize);
                 throw Retry{h.flags};
             }
-            const uint64_t f = h.cur;
+            const uint64_t f = h.size[L % 3];
             if (f == 0) break;  // empty frontier: window done
-            if (f <= kTail) {
-                LaunchTimer t("k_expand_tail", s);
-                k_expand_tail<<<1, 1024, 0, s>>>(WA, 4 * kTail);
-                SKIM_LAUNCH_CHECK();
-                continue;
-            }
-            for (int j = 0; j < 3; ++j) {
-                const unsigned grid = j == 0 ? grid_for(f, kChunk, 2048) : 2048;
+            // One frontier entry per thread while the frontier fits the grid,
+            // 1024-entry chunks per block beyond.  Small frontiers (the long
+            // tail of a window) go in batches of 8 levels; a level that finds
+            // an empty frontier does nothing.  Frontiers shrink level by level
+            // in the tail, so the batch keeps the first level's grid.
+            const bool small = f <= kSmall;
+            const int batch = small ? 8 : 3;
+            const uint32_t chunk = f <= (uint64_t)kBlock * 2048 ? kBlock : kChunk;
+            for (int j = 0; j < batch; ++j, ++L) {
+                const unsigned grid = j == 0 || small ? grid_for(f, chunk, 2048) : 2048;
                 LaunchTimer t("k_expand", s);
-                k_expand<<<grid, kBlock, 0, s>>>(WA);
+                k_expand<<<grid, kBlock, 0, s>>>(WA, L, j == 0 || small ? chunk : kChunk);
                 SKIM_LAUNCH_CHECK();
             }
         }
@@ -625,9 +573,9 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
         prev_nw = nw;
         if (std::getenv("SKIM_DEBUG"))
             std::fprintf(stderr, "skim window %u: sources %llu visits-so-far %llu hashed %llu "
-                                 "table %llu levels %llu records %llu\n",
+                                 "table %llu levels %u records %llu\n",
                          w, (unsigned long long)nw, h.visits, h.hinserts,
-                         (unsigned long long)hsize, h.levels, h.records);
+                         (unsigned long long)hsize, L, h.records);
         k_fold<<<grid_for(n, kBlock, 8192), kBlock, 0, s>>>(xcnt, xadd, n, k, ctl);
         SKIM_LAUNCH_CHECK();
         ++windows_done;
