@@ -29,6 +29,11 @@ import numpy as np  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 METRIC = "live-edge traversals/s (sketch build); batched vs plain queries/s, p99 latency"
 DOMINANT = "k_expand"
+# Sources of the dominant kernel: measured HBM traffic is reported only while
+# these are unchanged since the counters were taken.
+DOMINANT_SOURCES = ["paper_1408_6282_amd/csrc/skim_build.hip",
+                    "paper_1408_6282_amd/csrc/skim_internal.h"]
+CALIBRATION_BYTES = 1 << 30
 
 
 def log(msg):
@@ -57,6 +62,46 @@ def oracle_counters(name, g, cfg):
     import oracle
     _, _, cnt = oracle.build_alg2(g, cfg["seed"], cfg["ell"], cfg["k"])
     return cnt
+
+
+def dominant_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for p in DOMINANT_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None
+    when the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"{DOMINANT}_{workload.replace('-', '_')}_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    d = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                key, val = line.split(":", 1)
+                d[key.strip()] = val.strip()
+    if d.get("kernel_source_sha256") != dominant_source_digest():
+        return None
+    return float(d["traffic_bytes_per_launch"])
+
+
+def calibrate_copy():
+    """A plain copy of known size (read and write CALIBRATION_BYTES each), run
+    under rocprofv3 --pmc to scale FETCH_SIZE / WRITE_SIZE to bytes."""
+    import torch
+    a = torch.ones(CALIBRATION_BYTES // 4, dtype=torch.int32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.add(a, 1, out=b)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "int32 add, out of place", "read_bytes": CALIBRATION_BYTES,
+                      "write_bytes": CALIBRATION_BYTES, "launches": 3}), flush=True)
 
 
 def algorithmic_bytes_expand(cnt):
@@ -228,6 +273,8 @@ def main():
     ap.add_argument("--workload", default="chung-lu-1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="build only (no query/SKIM legs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB copy (for PMC byte calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -241,6 +288,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     sk.load_library()
     cfg = make_config(args.workload)
     log(f"generating {args.workload}")
@@ -257,7 +307,8 @@ def main():
         avg_s = kms / klaunch / 1e3
         achieved = per_launch_bytes / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": DOMINANT, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "traffic": measured_traffic(args.workload),
                 "launches_per_step": klaunch / args.steps, "avg_launch_us": avg_s * 1e6,
                 "kernel_ms_per_step": kms / args.steps,
                 "algorithmic_bytes_per_step": alg_bytes}
