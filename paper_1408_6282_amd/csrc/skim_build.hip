@@ -29,9 +29,12 @@
 //  4. Records.  A visit of node v is recorded while v held fewer than k
 //     ranks at the window start; windows go up in rank, so the k smallest
 //     records of v are its sketch.
-//  5. Merge.  Records are grouped by node and each node keeps its k
-//     smallest in LDS (bitonic sort), written ascending.
+//  5. Merge.  Records are sorted by node (radix sort on the node bits) and
+//     each node keeps its k smallest ranks in LDS (bitonic sort), written
+//     ascending.
 #include "skim_internal.h"
+
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cstdlib>
@@ -228,7 +231,7 @@ __device__ __forceinline__ bool wants_record(const WinArgs &A, uint32_t v) {
 // Block-aggregated appends: threads stage new entries in LDS; one global
 // reservation per flush moves them to the output array (coalesced).
 constexpr uint32_t kChunk = 1024;  // frontier entries per block per round
-constexpr uint32_t kStage = 2048;  // staged outputs per round (16 KiB per stage)
+constexpr uint32_t kStage = 2040;  // staged outputs per round (5 workgroups fit in 160 KiB of LDS)
 
 struct Stage {
     uint64_t buf[kStage];
@@ -403,17 +406,6 @@ __global__ void k_fold(uint32_t *xcnt, uint32_t *xadd, uint32_t n, uint32_t k, C
 
 // ------------------------------------------------------------- 5. merge
 
-__global__ void k_group(const uint64_t *rec, uint64_t nrec, uint64_t seed, const uint64_t *goff,
-                        uint32_t *gfill, uint64_t *seg) {
-    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nrec;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t r = rec[t];
-        const uint32_t v = (uint32_t)(r >> 32);
-        const uint64_t pos = goff[v] + atomicAdd(gfill + v, 1u);
-        seg[pos] = pair_rank(seed, (uint32_t)r);
-    }
-}
-
 // Bitonic sort of P (power of two, <= 512) keys in LDS by one 64-lane block.
 __device__ void lds_bitonic(uint64_t *x, uint32_t P) {
     for (uint32_t size = 2; size <= P; size <<= 1) {
@@ -433,10 +425,11 @@ __device__ void lds_bitonic(uint64_t *x, uint32_t P) {
     }
 }
 
-// One block (one wave) per node: keep the k smallest of the node's records.
+// One block (one wave) per node: keep the k smallest ranks of the node's
+// records seg[goff[v], goff[v+1]) (records sorted by node).
 __global__ void __launch_bounds__(64) k_select(const uint64_t *goff, const uint64_t *seg,
-                                               uint32_t n, uint32_t k, uint64_t *ranks,
-                                               uint32_t *size) {
+                                               uint32_t n, uint32_t k, uint64_t seed,
+                                               uint64_t *ranks, uint32_t *size) {
     __shared__ uint64_t buf[512];
     for (uint32_t v = blockIdx.x; v < n; v += gridDim.x) {
         const uint64_t a = goff[v], b = goff[v + 1];
@@ -445,7 +438,8 @@ __global__ void __launch_bounds__(64) k_select(const uint64_t *goff, const uint6
         if (S <= 512) {
             uint32_t P = 64;
             while (P < S) P <<= 1;
-            for (uint32_t j = threadIdx.x; j < P; j += blockDim.x) buf[j] = j < S ? seg[a + j] : kNone;
+            for (uint32_t j = threadIdx.x; j < P; j += blockDim.x)
+                buf[j] = j < S ? pair_rank(seed, (uint32_t)seg[a + j]) : kNone;
             __syncthreads();
             if (S > 1) lds_bitonic(buf, P);
             keep = (uint32_t)(S < k ? S : k);
@@ -453,7 +447,7 @@ __global__ void __launch_bounds__(64) k_select(const uint64_t *goff, const uint6
             for (uint32_t j = threadIdx.x; j < 256; j += blockDim.x) buf[j] = kNone;
             for (uint64_t c = a; c < b; c += 256) {
                 for (uint32_t j = threadIdx.x; j < 256; j += blockDim.x)
-                    buf[256 + j] = c + j < b ? seg[c + j] : kNone;
+                    buf[256 + j] = c + j < b ? pair_rank(seed, (uint32_t)seg[c + j]) : kNone;
                 __syncthreads();
                 lds_bitonic(buf, 512);
             }
@@ -592,15 +586,19 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     uint64_t *goff = A.alloc<uint64_t>((uint64_t)n + 1);
     exclusive_scan_u32(xcnt, goff, n, A);
     uint64_t *seg = A.alloc<uint64_t>(nrec ? nrec : 1);
-    fill_u32(xadd, 0, n + 1, s);
     if (nrec) {
-        LaunchTimer t("k_group", s);
-        k_group<<<grid_for(nrec, kBlock, 16384), kBlock, 0, s>>>(rec, nrec, seed, goff, xadd, seg);
-        SKIM_LAUNCH_CHECK();
+        // stable radix sort of the records on their node bits
+        int nb = 1;
+        while (nb < 32 && (1ull << nb) < n) ++nb;
+        size_t tmp_bytes = 0;
+        SKIM_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, rec, seg, (size_t)nrec, 32, 32 + nb, s));
+        void *tmp = A.get(tmp_bytes ? tmp_bytes : 1);
+        LaunchTimer t("sort_records", s);
+        SKIM_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, rec, seg, (size_t)nrec, 32, 32 + nb, s));
     }
     {
         LaunchTimer t("k_select", s);
-        k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(goff, seg, n, k, ranks_out, size_out);
+        k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(goff, seg, n, k, seed, ranks_out, size_out);
     }
     SKIM_LAUNCH_CHECK();
     if (work) {
