@@ -109,6 +109,36 @@ struct PendingTime {
     hipEvent_t a, b;
 };
 thread_local std::vector<PendingTime> g_pending;
+// Events are reused (creating and destroying two per launch costs more host
+// time than the launch); one free list per device.
+thread_local std::map<int, std::vector<hipEvent_t>> g_free_events;
+
+hipEvent_t take_event() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    auto &pool = g_free_events[dev];
+    if (!pool.empty()) {
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+void give_event(hipEvent_t e) {
+    int dev = 0;
+    if (!e) return;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return;
+    }
+    g_free_events[dev].push_back(e);
+}
 }  // namespace
 
 LaunchTimer::LaunchTimer(const char *kernel, hipStream_t s) : s_(s), name_(kernel) {
@@ -116,21 +146,23 @@ LaunchTimer::LaunchTimer(const char *kernel, hipStream_t s) : s_(s), name_(kerne
         std::lock_guard<std::mutex> lk(g_time_mu);
         if (g_time_kernel.empty() || g_time_kernel != kernel) return;
     }
-    if (hipEventCreate(&a_) != hipSuccess || hipEventRecord(a_, s_) != hipSuccess) {
+    a_ = take_event();
+    if (a_ && hipEventRecord(a_, s_) != hipSuccess) {
         (void)hipGetLastError();
+        give_event(a_);
         a_ = nullptr;
     }
 }
 
 LaunchTimer::~LaunchTimer() {
     if (!a_) return;
-    hipEvent_t b = nullptr;
-    if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, s_) == hipSuccess) {
+    hipEvent_t b = take_event();
+    if (b && hipEventRecord(b, s_) == hipSuccess) {
         g_pending.push_back({name_, a_, b});
     } else {
         (void)hipGetLastError();
-        (void)hipEventDestroy(a_);
-        if (b) (void)hipEventDestroy(b);
+        give_event(a_);
+        give_event(b);
     }
 }
 
@@ -144,8 +176,8 @@ void timing_resolve() {
             acc.launches += 1;
         }
         (void)hipGetLastError();
-        (void)hipEventDestroy(p.a);
-        (void)hipEventDestroy(p.b);
+        give_event(p.a);
+        give_event(p.b);
     }
     g_pending.clear();
 }
