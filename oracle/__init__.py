@@ -71,6 +71,8 @@ def _load():
                                 C.c_uint32]
         lib.or_ranks.restype = None
         lib.or_ranks.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, P64]
+        lib.or_pair_ranks.restype = None
+        lib.or_pair_ranks.argtypes = [C.c_uint64, C.c_uint64, P64, P64]
         lib.or_live_batch.restype = None
         lib.or_live_batch.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, P32, P32, P32, P32,
                                       C.POINTER(C.c_uint8)]
@@ -80,6 +82,10 @@ def _load():
         lib.or_sketch_brute.restype = None
         lib.or_sketch_brute.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32,
                                         C.c_uint32, P32, C.c_uint64, P64, P32, P64]
+        lib.or_sketch_brute_budget.restype = None
+        lib.or_sketch_brute_budget.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32,
+                                               C.c_uint32, P32, C.c_uint64, C.c_uint64,
+                                               C.c_uint32, P64, P32, P64, C.POINTER(C.c_uint8)]
         lib.or_build_alg2.restype = C.c_int
         lib.or_build_alg2.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32,
                                       C.c_uint32, C.c_uint32, P64, P32, C.POINTER(BuildCounters)]
@@ -152,18 +158,40 @@ def influence(g, seed: int, ell: int, S, per_instance: bool = False):
     return (int(tot), per[:ell]) if per_instance else int(tot)
 
 
-def sketch_brute(g, seed: int, ell: int, k: int, nodes=None):
-    """Sketches by the plain definition, for the given nodes (default all)."""
+def pair_ranks(seed: int, pairs) -> np.ndarray:
+    """r(v, i) for pair ids p = 64 v + i (Section 3's ranks)."""
+    p = np.ascontiguousarray(pairs, dtype=np.uint64)
+    out = np.empty(p.size, dtype=np.uint64)
+    if p.size:
+        _load().or_pair_ranks(seed & ((1 << 64) - 1), p.size, _p(p, P64), _p(out, P64))
+    return out
+
+
+def sketch_brute(g, seed: int, ell: int, k: int, nodes=None, budget: int | None = None,
+                 threads: int | None = None):
+    """Sketches by the plain definition, for the given nodes (default all).
+
+    With `budget`, a node whose forward searches (over all l instances) would
+    scan more out-edges than that is left out; returns (ranks, size, reach,
+    ok) then, ok[j] = False for a node left out (its rows are undefined).
+    """
     rp, col, thr = _g(g)
     nodes = np.arange(g.n, dtype=np.uint32) if nodes is None else \
         np.ascontiguousarray(nodes, dtype=np.uint32)
     ranks = np.empty(nodes.size * k, dtype=np.uint64)
     size = np.empty(nodes.size, dtype=np.uint32)
     reach = np.empty(nodes.size, dtype=np.uint64)
-    _load().or_sketch_brute(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell, k,
-                            _p(nodes, P32), nodes.size, _p(ranks, P64), _p(size, P32),
-                            _p(reach, P64))
-    return ranks.reshape(nodes.size, k), size, reach
+    ok = np.ones(nodes.size, dtype=np.uint8)
+    nthreads = threads or min(16, os.cpu_count() or 1)
+    _load().or_sketch_brute_budget(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell, k,
+                                   _p(nodes, P32), nodes.size,
+                                   (1 << 64) - 1 if budget is None else int(budget),
+                                   nthreads if budget is not None or threads else 1,
+                                   _p(ranks, P64), _p(size, P32), _p(reach, P64),
+                                   ok.ctypes.data_as(C.POINTER(C.c_uint8)))
+    if budget is None:
+        return ranks.reshape(nodes.size, k), size, reach
+    return ranks.reshape(nodes.size, k), size, reach, ok.astype(bool)
 
 
 def build_alg2(g, seed: int, ell: int, k: int, threads: int | None = None):

@@ -83,6 +83,12 @@ void or_ranks(uint64_t seed, uint32_t n, uint32_t ell, uint64_t *out)
         for (uint32_t i = 0; i < ell; i++) out[(uint64_t)v * ell + i] = or_rank(seed, v, i);
 }
 
+/* Ranks of arbitrary pair ids p = 64 v + i: out[j] = r(v, i). */
+void or_pair_ranks(uint64_t seed, uint64_t cnt, const uint64_t *pairs, uint64_t *out)
+{
+    for (uint64_t j = 0; j < cnt; j++) out[j] = or_sm64(seed, pairs[j]);
+}
+
 /* Live-edge coins for a batch of (u, v, i, thr) tuples. */
 void or_live_batch(uint64_t seed, uint32_t n, uint64_t cnt, const uint32_t *u,
                    const uint32_t *v, const uint32_t *inst, const uint32_t *thr, uint8_t *out)
@@ -101,17 +107,24 @@ typedef struct {
 
 /* ------------------------------------------- influence by forward search */
 
-/* Nodes reached from the set S in instance i (Section 2: u in S counts). */
-static uint64_t reach_count(const or_graph *g, uint64_t seed, uint32_t i,
-                            const uint32_t *S, uint64_t ns, uint8_t *seen, uint32_t *queue)
+/* Nodes reached from the set S in instance i (Section 2: u in S counts),
+ * scanning at most *budget out-edges (the budget is decremented by the edges
+ * scanned).  Returns UINT64_MAX, with `seen` cleared, when the search would
+ * scan more; otherwise the reached nodes are in queue[0..returned). */
+static uint64_t reach_count_budget(const or_graph *g, uint64_t seed, uint32_t i,
+                                   const uint32_t *S, uint64_t ns, uint8_t *seen,
+                                   uint32_t *queue, uint64_t *budget)
 {
-    uint64_t head = 0, tail = 0;
+    uint64_t head = 0, tail = 0, aborted = 0;
     for (uint64_t j = 0; j < ns; j++) {
         uint32_t s = S[j];
         if (!seen[s]) { seen[s] = 1; queue[tail++] = s; }
     }
-    while (head < tail) {
+    while (head < tail && !aborted) {
         uint32_t u = queue[head++];
+        uint64_t deg = g->row_ptr[u + 1] - g->row_ptr[u];
+        if (deg > *budget) { aborted = 1; break; }
+        *budget -= deg;
         for (uint64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; e++) {
             uint32_t v = g->col[e];
             if (!seen[v] && or_live(seed, g->n, u, v, i, g->thr[e])) {
@@ -121,7 +134,14 @@ static uint64_t reach_count(const or_graph *g, uint64_t seed, uint32_t i,
         }
     }
     for (uint64_t j = 0; j < tail; j++) seen[queue[j]] = 0;
-    return tail;
+    return aborted ? UINT64_MAX : tail;
+}
+
+static uint64_t reach_count(const or_graph *g, uint64_t seed, uint32_t i,
+                            const uint32_t *S, uint64_t ns, uint8_t *seen, uint32_t *queue)
+{
+    uint64_t unlimited = UINT64_MAX;
+    return reach_count_budget(g, seed, i, S, ns, seen, queue, &unlimited);
 }
 
 /* sum over instances of |reach_i(S)|, i.e. l * Inf({G^(i)}, S); per-instance
@@ -156,38 +176,84 @@ static int cmp_u64(const void *a, const void *b)
 /* X_u = the k smallest ranks r(v,i) over all (v,i) with u ~>_i v
  * (eq. combinedrs), computed by a full forward search in every instance.
  * out_ranks[j*k .. j*k+k) ascending, padded with UINT64_MAX; out_size[j] =
- * min(k, |R_u|); out_reach[j] (may be NULL) = |R_u|. */
+ * min(k, |R_u|); out_reach[j] (may be NULL) = |R_u|.  With a finite
+ * `budget`, a node whose searches would scan more out-edges in total is
+ * left out: out_ok[j] = 0 and its outputs are not written (out_ok may be
+ * NULL when the budget is UINT64_MAX).  Nodes are split over `threads`
+ * POSIX threads. */
+typedef struct {
+    or_graph g;
+    uint64_t seed, budget;
+    uint32_t ell, k;
+    const uint32_t *nodes;
+    uint64_t nq, first, step;
+    uint64_t *out_ranks, *out_reach;
+    uint32_t *out_size;
+    uint8_t *out_ok;
+} brute_job;
+
+static void *brute_worker(void *arg)
+{
+    brute_job *J = arg;
+    uint8_t *seen = calloc(J->g.n ? J->g.n : 1, 1);
+    uint32_t *queue = malloc(sizeof(uint32_t) * (J->g.n ? J->g.n : 1));
+    uint64_t cap = 1024, cnt;
+    uint64_t *all = malloc(sizeof(uint64_t) * cap);
+    for (uint64_t j = J->first; j < J->nq; j += J->step) {
+        uint32_t u = J->nodes[j];
+        uint64_t budget = J->budget;
+        int ok = 1;
+        cnt = 0;
+        for (uint32_t i = 0; i < J->ell && ok; i++) {
+            uint64_t reached = reach_count_budget(&J->g, J->seed, i, &u, 1, seen, queue, &budget);
+            if (reached == UINT64_MAX) { ok = 0; break; }
+            if (cnt + reached > cap) {
+                while (cnt + reached > cap) cap *= 2;
+                all = realloc(all, sizeof(uint64_t) * cap);
+            }
+            for (uint64_t t = 0; t < reached; t++) all[cnt++] = or_rank(J->seed, queue[t], i);
+        }
+        if (J->out_ok) J->out_ok[j] = (uint8_t)ok;
+        if (!ok) continue;
+        qsort(all, cnt, sizeof(uint64_t), cmp_u64);
+        uint32_t s = (uint32_t)(cnt < J->k ? cnt : J->k);
+        for (uint32_t t = 0; t < J->k; t++) J->out_ranks[j * J->k + t] = t < s ? all[t] : OR_NONE;
+        J->out_size[j] = s;
+        if (J->out_reach) J->out_reach[j] = cnt;
+    }
+    free(seen);
+    free(queue);
+    free(all);
+    return NULL;
+}
+
+void or_sketch_brute_budget(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                            const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
+                            const uint32_t *nodes, uint64_t nq, uint64_t budget,
+                            uint32_t threads, uint64_t *out_ranks, uint32_t *out_size,
+                            uint64_t *out_reach, uint8_t *out_ok)
+{
+    if (threads < 1) threads = 1;
+    if (threads > 256) threads = 256;
+    brute_job jobs[256];
+    pthread_t tid[256];
+    for (uint32_t t = 0; t < threads; t++) {
+        brute_job J = {{n, row_ptr, col, thr}, seed, budget, ell, k, nodes, nq, t, threads,
+                       out_ranks, out_reach, out_size, out_ok};
+        jobs[t] = J;
+    }
+    for (uint32_t t = 1; t < threads; t++) pthread_create(&tid[t], NULL, brute_worker, &jobs[t]);
+    brute_worker(&jobs[0]);
+    for (uint32_t t = 1; t < threads; t++) pthread_join(tid[t], NULL);
+}
+
 void or_sketch_brute(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
                      const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
                      const uint32_t *nodes, uint64_t nq,
                      uint64_t *out_ranks, uint32_t *out_size, uint64_t *out_reach)
 {
-    or_graph g = {n, row_ptr, col, thr};
-    uint8_t *seen = calloc(n, 1);
-    uint32_t *queue = malloc(sizeof(uint32_t) * n);
-    uint64_t cap = 1024, cnt;
-    uint64_t *all = malloc(sizeof(uint64_t) * cap);
-    for (uint64_t j = 0; j < nq; j++) {
-        uint32_t u = nodes[j];
-        cnt = 0;
-        for (uint32_t i = 0; i < ell; i++) {
-            uint64_t reached = reach_count(&g, seed, i, &u, 1, seen, queue);
-            /* reach_count leaves the reached nodes in queue[0..reached) */
-            if (cnt + reached > cap) {
-                while (cnt + reached > cap) cap *= 2;
-                all = realloc(all, sizeof(uint64_t) * cap);
-            }
-            for (uint64_t t = 0; t < reached; t++) all[cnt++] = or_rank(seed, queue[t], i);
-        }
-        qsort(all, cnt, sizeof(uint64_t), cmp_u64);
-        uint32_t s = (uint32_t)(cnt < k ? cnt : k);
-        for (uint32_t t = 0; t < k; t++) out_ranks[j * k + t] = t < s ? all[t] : OR_NONE;
-        out_size[j] = s;
-        if (out_reach) out_reach[j] = cnt;
-    }
-    free(all);
-    free(seen);
-    free(queue);
+    or_sketch_brute_budget(n, row_ptr, col, thr, seed, ell, k, nodes, nq, UINT64_MAX, 1,
+                           out_ranks, out_size, out_reach, NULL);
 }
 
 /* --------------------------------------------------- Algorithm 2 (5.2) */

@@ -73,12 +73,12 @@ struct Ctl {
 
 // ------------------------------------------------------- 2. rank windows
 
-// Window of a rank: window 0 holds ranks of at most `b0` bits; window j >= 1
-// the ranks of b0 + 2(j-1) + 1 or b0 + 2j bits (each window four times the
-// previous one).
-__device__ __forceinline__ uint32_t window_of(uint64_t r, uint32_t b0) {
+// Rank bucket: bucket 0 holds the ranks of at most `b0` bits, bucket j >= 1
+// the ranks of exactly b0 + j bits (each bucket doubles the rank range seen
+// so far).  A window is a run of one or two consecutive buckets.
+__device__ __forceinline__ uint32_t bucket_of(uint64_t r, uint32_t b0) {
     const int bits = r ? 64 - __clzll((long long)r) : 0;
-    return bits <= (int)b0 ? 0u : 1u + (uint32_t)(bits - (int)b0 - 1) / 2u;
+    return bits <= (int)b0 ? 0u : (uint32_t)(bits - (int)b0);
 }
 
 constexpr int kRankPer = 8;  // pairs per thread in the bucketing kernels
@@ -94,7 +94,7 @@ __global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W,
         const uint64_t t = base + (uint64_t)j * kBlock + threadIdx.x;
         if (t < total) {
             const uint32_t v = (uint32_t)(t / ell), i = (uint32_t)(t % ell);
-            atomicAdd(&h[window_of(pair_rank(seed, v * kPairStride + i), b0)], 1u);
+            atomicAdd(&h[bucket_of(pair_rank(seed, v * kPairStride + i), b0)], 1u);
         }
     }
     __syncthreads();
@@ -117,7 +117,7 @@ __global__ void k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed, uint32_t
         if (t < total) {
             const uint32_t v = (uint32_t)(t / ell), i = (uint32_t)(t % ell);
             pid[j] = v * kPairStride + i;
-            win[j] = window_of(pair_rank(seed, pid[j]), b0);
+            win[j] = bucket_of(pair_rank(seed, pid[j]), b0);
             slot[j] = atomicAdd(&h[win[j]], 1u);
         }
     }
@@ -172,6 +172,16 @@ __device__ int hset_insert(uint64_t *T, uint32_t logcap, uint64_t key) {
         h = (h + 1) & mask;
     }
     return -1;
+}
+
+// Move every key of a hash set into a larger one.
+__global__ void k_rehash(const uint64_t *old, uint64_t old_size, uint64_t *T, uint32_t logcap,
+                         uint32_t *flags) {
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < old_size;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t key = old[j];
+        if (key != kNone && hset_insert(T, logcap, key) < 0) atomicOr(flags, kOvfHash);
+    }
 }
 
 struct WinArgs {
@@ -364,7 +374,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32
     }
     __syncthreads();
     uint32_t scans = 0, hashed = 0, visits = 0;
-    if (!s_flags) {  // after an overflow the windows are redone with more room
+    if (!s_flags && s_size) {  // after an overflow the windows are redone with more room
         expand_range(A, A.front[L & 1], A.front[(L + 1) & 1], &A.ctl->size[(L + 1) % 3], s_size,
                      chunk, X.F, X.R, scans, hashed, visits);
     }
@@ -373,10 +383,16 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32
     wave_add(&A.ctl->visits, visits);
 }
 
-// Start of a window: clear the per-window fields.
-__global__ void k_ctl_begin(Ctl *ctl) {
+// Start of a window (or of its redo): clear the per-window fields and set
+// the running counters to their values at the window start.
+__global__ void k_ctl_begin(Ctl *ctl, unsigned long long visits, unsigned long long scans,
+                            unsigned long long records) {
     ctl->size[0] = ctl->size[1] = ctl->size[2] = 0;
     ctl->hinserts = 0;
+    ctl->flags = 0;
+    ctl->visits = visits;
+    ctl->scans = scans;
+    ctl->records = records;
 }
 
 struct WinBases {
@@ -460,14 +476,14 @@ __global__ void __launch_bounds__(64) k_select(const uint64_t *goff, const uint6
     }
 }
 
-// Window 0 holds about k/2 sources per instance (ranks of at most b0 bits,
-// a fraction 2^(b0-64) of all); the windows after it grow fourfold.
-void choose_windows(uint32_t n, uint32_t k, uint32_t &W, uint32_t &b0) {
-    const double x = 2.0 * n / (double)k;  // 1 / (window-0 fraction)
+// Bucket 0 holds about k/2 sources per instance (ranks of at most b0 bits,
+// a fraction 2^(b0-64) of all); NB buckets in all.
+void choose_buckets(uint32_t n, uint32_t k, uint32_t &NB, uint32_t &b0) {
+    const double x = 2.0 * n / (double)k;  // 1 / (bucket-0 fraction)
     uint32_t lg = 0;
     while (lg < 63 && (double)(1ull << lg) < x) ++lg;
     b0 = 64 - lg;
-    W = 1 + (lg + 1) / 2;
+    NB = 1 + lg;
 }
 
 uint64_t next_pow2(uint64_t x) {
@@ -478,7 +494,7 @@ uint64_t next_pow2(uint64_t x) {
 
 struct Capacity {
     uint64_t rec, front, hash;
-    bool hash_full;  // use the whole hash table in every window
+    uint64_t hash_min;  // least hash-set size of a window (raised after an overflow)
 };
 
 }  // namespace
@@ -500,19 +516,49 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     fill_u32(xadd, 0, n + 1, s);
     Ctl *ctl = A.alloc<Ctl>(1);
     fill_u64((uint64_t *)ctl, 0, sizeof(Ctl) / 8, s);
-    uint64_t *rec = A.alloc<uint64_t>(cap.rec);
-    uint64_t *front0 = A.alloc<uint64_t>(cap.front);
-    uint64_t *front1 = A.alloc<uint64_t>(cap.front);
-    uint64_t *hset = A.alloc<uint64_t>(cap.hash);
+    uint64_t rec_cap = cap.rec, front_cap = cap.front;
+    uint64_t *rec = A.alloc<uint64_t>(rec_cap);
+    uint64_t *front[2] = {A.alloc<uint64_t>(front_cap), A.alloc<uint64_t>(front_cap)};
+    // The hash set is allocated once for up to 2^29 entries (4 GiB) and only
+    // reallocated by windows that need more.
+    uint64_t hset_size = std::min<uint64_t>(cap.hash, 1ull << 29);
+    uint64_t *hset = A.alloc<uint64_t>(hset_size);
+    uint64_t *snap = nullptr;  // pair states at the start of a guarded window
+    uint32_t levels_run = 0;
     uint64_t windows_done = 0, prev_hash = 0, prev_nw = 0;
-    constexpr uint64_t kSmall = 65536;  // frontiers handled in batches of 8 levels
+    const bool debug = std::getenv("SKIM_DEBUG") != nullptr;
+    const bool debug2 = debug && std::atoi(std::getenv("SKIM_DEBUG")) > 1;
+    // Buffers grow between levels when the next levels could outrun them
+    // (a level's new visits are assumed to be at most kGrow times its
+    // frontier; a level that breaks this overflows and the windows are
+    // redone with more room).
+    constexpr uint64_t kGrow = 3;
+    constexpr uint64_t kSmall = 65536;  // frontiers handled in batches of levels
+    auto grow_u64 = [&](uint64_t *&buf, uint64_t &capacity, uint64_t keep, uint64_t need) {
+        if (need <= capacity) return;
+        uint64_t nc = capacity;
+        while (nc < need) nc *= 2;
+        uint64_t *nb = A.alloc<uint64_t>(nc);
+        if (keep) SKIM_HIP(hipMemcpyAsync(nb, buf, keep * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        A.release(buf);
+        buf = nb;
+        capacity = nc;
+    };
     Ctl h;
-    for (uint32_t w = 0; w < W; ++w) {
-        const uint64_t ws = wb[w], we = wb[w + 1];
-        if (ws == we) continue;
+    // Window w covers buckets [bb, be): bucket 0 alone, then two buckets (a
+    // fourfold rank range) at a time, or one (twofold) after a window whose
+    // visited pairs took more than kHeavy visits each on average (large
+    // reach sets: a smaller step keeps the visits past k in check).
+    constexpr double kHeavy = 4.0;
+    uint64_t prev_visits = 0;
+    uint32_t span = 1, span_next = 2;
+    for (uint32_t w = 0, bb = 0; bb < W && w < 255; ++w, bb += span) {
+        span = std::min<uint32_t>(w == 0 ? 1u : span_next, W - bb);
+        const uint64_t ws = wb[bb], we = wb[bb + span];
         read_back(&h, ctl, sizeof h, s);
         if (h.flags) throw Retry{h.flags};
         if (h.full >= n) break;  // every sketch holds k ranks: later ranks cannot enter
+        if (ws == we) continue;
         const uint64_t nw = we - ws;
         // A pair is often visited by several sources of one window; every
         // visit after the first goes through the hash set.  Hashed visits
@@ -521,55 +567,142 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
         const double pred = w == 0 || prev_nw == 0
                                 ? 16.0 * (double)nw
                                 : 1.5 * (double)prev_hash * (double)nw / (double)prev_nw + (double)nw;
-        const uint64_t hsize =
-            cap.hash_full ? cap.hash
-                          : std::min<uint64_t>(cap.hash, next_pow2(std::max<uint64_t>(
-                                                             1ull << 16, (uint64_t)(2.5 * pred))));
-        uint32_t logcap = 0;
-        while ((1ull << logcap) < hsize) ++logcap;
-        fill_u64(hset, kNone, hsize, s);
-        k_ctl_begin<<<1, 1, 0, s>>>(ctl);
-        SKIM_LAUNCH_CHECK();
-        WinArgs WA{words, live.ptr, live.adj, hset, logcap, w, k, xcnt, xadd, rec, cap.rec,
-                   {front0, front1}, cap.front, ctl};
-        {
-            LaunchTimer t("k_seed_window", s);
-            k_seed_window<<<grid_for(nw, kChunk, 4096), kBlock, 0, s>>>(WA, sources, ws, we);
+        uint64_t hsize = std::min<uint64_t>(
+            cap.hash, next_pow2(std::max<uint64_t>(cap.hash_min, (uint64_t)(2.5 * pred))));
+        // Windows after a heavy one keep a copy of the pair states: an
+        // overflow there costs one redo of the window with more room instead
+        // of a restart of all windows.  (Redoing the first window costs about
+        // what a restart does.)
+        const bool guard = w > 0 && span_next == 1;
+        if (guard) {
+            if (!snap) snap = A.alloc<uint64_t>(npairs);
+            SKIM_HIP(hipMemcpyAsync(snap, words, npairs * sizeof(uint64_t),
+                                    hipMemcpyDeviceToDevice, s));
         }
-        SKIM_LAUNCH_CHECK();
-        uint32_t L = 0;
-        for (;;) {
-            read_back(&h, ctl, sizeof h, s);
-            if (h.flags) {
-                if (std::getenv("SKIM_DEBUG"))
-                    std::fprintf(stderr, "skim window %u overflow %u: hashed %llu table %llu\n", w,
-                                 h.flags, h.hinserts, (unsigned long long)hsize);
-                throw Retry{h.flags};
+        const Ctl base = h;  // counters at the window start
+        for (int redo = 0;; ++redo) {
+            uint32_t logcap = 0;
+            while ((1ull << logcap) < hsize) ++logcap;
+            if (hsize > hset_size) {
+                if (hset) A.release(hset);
+                hset = A.alloc<uint64_t>(hsize);
+                hset_size = hsize;
             }
-            const uint64_t f = h.size[L % 3];
-            if (f == 0) break;  // empty frontier: window done
-            // One frontier entry per thread while the frontier fits the grid,
-            // 1024-entry chunks per block beyond.  Small frontiers (the long
-            // tail of a window) go in batches of 8 levels; a level that finds
-            // an empty frontier does nothing.  Frontiers shrink level by level
-            // in the tail, so the batch keeps the first level's grid.
-            const bool small = f <= kSmall;
-            const int batch = small ? 8 : 3;
-            const uint32_t chunk = f <= (uint64_t)kBlock * 2048 ? kBlock : kChunk;
-            for (int j = 0; j < batch; ++j, ++L) {
-                const unsigned grid = j == 0 || small ? grid_for(f, chunk, 2048) : 2048;
-                LaunchTimer t("k_expand", s);
-                k_expand<<<grid, kBlock, 0, s>>>(WA, L, j == 0 || small ? chunk : kChunk);
-                SKIM_LAUNCH_CHECK();
+            fill_u64(hset, kNone, hsize, s);
+            k_ctl_begin<<<1, 1, 0, s>>>(ctl, base.visits, base.scans, base.records);
+            SKIM_LAUNCH_CHECK();
+            auto args = [&]() {
+                return WinArgs{words, live.ptr, live.adj, hset, logcap, w, k, xcnt, xadd, rec,
+                               rec_cap, {front[0], front[1]}, front_cap, ctl};
+            };
+            {
+                const WinArgs WA = args();
+                LaunchTimer t("k_seed_window", s);
+                k_seed_window<<<grid_for(nw, kChunk, 4096), kBlock, 0, s>>>(WA, sources, ws, we);
             }
+            SKIM_LAUNCH_CHECK();
+            uint32_t L = 0;
+            uint32_t overflow = 0;
+            uint64_t f_prev = 0;
+            for (;;) {
+                read_back(&h, ctl, sizeof h, s);
+                if (h.flags) {
+                    overflow = h.flags;
+                    if (debug)
+                        std::fprintf(stderr, "skim window %u overflow %u: hashed %llu table %llu\n",
+                                     w, h.flags, h.hinserts, (unsigned long long)hsize);
+                    break;
+                }
+                const uint64_t f = h.size[L % 3];
+                if (f == 0) break;  // empty frontier: window done
+                if (debug2)
+                    std::fprintf(stderr, "skim window %u level %u: frontier %llu hashed %llu\n", w,
+                                 L, (unsigned long long)f, h.hinserts);
+                // Room for the next level: the frontier and the records are grown
+                // to kGrow times the frontier, the hash set (rehashed) once it is
+                // 40% full.  A level that still overflows is redone with the
+                // window (guarded windows) or with all windows.
+                {
+                    uint64_t *cur = front[L & 1], *nxt = front[(L + 1) & 1];
+                    uint64_t c0 = front_cap, c1 = front_cap;
+                    grow_u64(cur, c0, f, kGrow * f);
+                    grow_u64(nxt, c1, 0, kGrow * f);
+                    front[L & 1] = cur;
+                    front[(L + 1) & 1] = nxt;
+                    front_cap = std::min(c0, c1);
+                }
+                grow_u64(rec, rec_cap, h.records, h.records + kGrow * f);
+                if (5 * h.hinserts > 2 * hsize) {
+                    const uint64_t ns = 2 * hsize;
+                    uint32_t nlog = 0;
+                    while ((1ull << nlog) < ns) ++nlog;
+                    uint64_t *nt = A.alloc<uint64_t>(ns);
+                    fill_u64(nt, kNone, ns, s);
+                    k_rehash<<<grid_for(hsize, kBlock, 65536), kBlock, 0, s>>>(hset, hsize, nt, nlog,
+                                                                               &ctl->flags);
+                    SKIM_LAUNCH_CHECK();
+                    A.release(hset);
+                    hset = nt;
+                    hset_size = hsize = ns;
+                    logcap = nlog;
+                    if (debug)
+                        std::fprintf(stderr, "skim window %u: hash set grown to %llu\n", w,
+                                     (unsigned long long)ns);
+                }
+                const int batch = f > kSmall ? 3 : 8;
+                // room for 64-fold growth at a window's first level and after a
+                // batch over which the frontier grew more than fourfold
+                const bool growing = f_prev == 0 || f > 4 * f_prev;
+                f_prev = f;
+                // Small frontiers go in batches of 8 levels (a level that finds an
+                // empty frontier does nothing) on a grid sized to the frontier,
+                // or with room for 64-fold growth while it grows fast; large
+                // ones in batches of 3.
+                const WinArgs WA = args();
+                const uint32_t chunk = f <= (uint64_t)kBlock * 2048 ? kBlock : kChunk;
+                for (int j = 0; j < batch; ++j, ++L) {
+                    const unsigned grid =
+                        f > kSmall ? (j == 0 ? grid_for(f, chunk, 2048) : 2048)
+                                   : grid_for((growing ? 64 : 1) * f, chunk, 2048);
+                    LaunchTimer t("k_expand", s);
+                    k_expand<<<grid, kBlock, 0, s>>>(WA, L, f > kSmall && j > 0 ? kChunk : chunk);
+                    SKIM_LAUNCH_CHECK();
+                }
+            }
+            if (!overflow) {
+                levels_run = L;
+                break;
+            }
+            if (!guard || redo >= 6) throw Retry{overflow};
+            // redo the window with more room
+            if (overflow & kOvfHash) hsize = std::max(16 * hsize, next_pow2(4 * h.hinserts));
+            if (overflow & kOvfSpill) {
+                const uint64_t nc = 2 * front_cap;
+                uint64_t c0 = front_cap, c1 = front_cap;
+                grow_u64(front[0], c0, 0, nc);
+                grow_u64(front[1], c1, 0, nc);
+                front_cap = std::min(c0, c1);
+            }
+            if (overflow & kOvfRecords) grow_u64(rec, rec_cap, base.records, 2 * rec_cap);
+            SKIM_HIP(hipMemcpyAsync(words, snap, npairs * sizeof(uint64_t),
+                                    hipMemcpyDeviceToDevice, s));
+            fill_u32(xadd, 0, n + 1, s);
+            if (debug) std::fprintf(stderr, "skim window %u: redo %d\n", w, redo + 1);
         }
         prev_hash = h.hinserts;
         prev_nw = nw;
-        if (std::getenv("SKIM_DEBUG"))
+        {   // the next window's step
+            const uint64_t v = h.visits - prev_visits;
+            const uint64_t distinct = v > h.hinserts ? v - h.hinserts : 1;
+            const uint32_t next = (double)v > kHeavy * (double)distinct ? 1u : 2u;
+            prev_visits = h.visits;
+            span_next = next;
+        }
+        if (debug)
             std::fprintf(stderr, "skim window %u: sources %llu visits-so-far %llu hashed %llu "
                                  "table %llu levels %u records %llu\n",
                          w, (unsigned long long)nw, h.visits, h.hinserts,
-                         (unsigned long long)hsize, L, h.records);
+                         (unsigned long long)hsize, levels_run, h.records);
         k_fold<<<grid_for(n, kBlock, 8192), kBlock, 0, s>>>(xcnt, xadd, n, k, ctl);
         SKIM_LAUNCH_CHECK();
         ++windows_done;
@@ -580,9 +713,9 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
 
     // ---- 5. merge: group records by node, keep the k smallest
     A.release(words);
-    A.release(front0);
-    A.release(front1);
-    A.release(hset);
+    A.release(front[0]);
+    A.release(front[1]);
+    if (hset) A.release(hset);
     uint64_t *goff = A.alloc<uint64_t>((uint64_t)n + 1);
     exclusive_scan_u32(xcnt, goff, n, A);
     uint64_t *seg = A.alloc<uint64_t>(nrec ? nrec : 1);
@@ -627,9 +760,9 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     LiveLists live = build_live_lists(g, ell, seed, esrc, /*forward=*/false, A);
     A.release(esrc);
 
-    // ---- 2. rank windows
-    uint32_t W = 1, b0 = 64;
-    choose_windows(n, k, W, b0);
+    // ---- 2. rank buckets
+    uint32_t W = 1, b0 = 64;  // W: number of buckets
+    choose_buckets(n, k, W, b0);
     unsigned long long *wbuf = A.alloc<unsigned long long>(2 * 64);
     fill_u64((uint64_t *)wbuf, 0, 128, s);
     const unsigned rblocks = (unsigned)((nsrc + (uint64_t)kBlock * kRankPer - 1) /
@@ -649,11 +782,14 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     SKIM_LAUNCH_CHECK();
 
     // ---- 3./4./5. windows and merge; restart with more room on overflow
-    uint64_t biggest = 0;
-    for (uint32_t w = 0; w < W; ++w) biggest = std::max<uint64_t>(biggest, hw[w]);
-    Capacity cap{std::max<uint64_t>(1ull << 20, 2 * (uint64_t)n * k),
-                 std::max<uint64_t>(1ull << 20, 2 * biggest),
-                 next_pow2(std::max<uint64_t>(1ull << 16, 8 * biggest)), false};
+    uint64_t biggest = 0, bucket_max = 0;  // largest possible window (two buckets), bucket
+    for (uint32_t w = 0; w < W; ++w) {
+        biggest = std::max<uint64_t>(biggest, hw[w] + (w + 1 < W ? hw[w + 1] : 0));
+        bucket_max = std::max<uint64_t>(bucket_max, hw[w]);
+    }
+    Capacity cap{std::max<uint64_t>(1ull << 20, 3 * (uint64_t)n * k),
+                 std::max<uint64_t>(1ull << 20, 3 * biggest),
+                 next_pow2(std::max<uint64_t>(1ull << 16, 8 * bucket_max)), 1ull << 16};
     uint32_t retry_flags = 0;
     int attempt = 0;
     for (;; ++attempt) {
@@ -663,6 +799,8 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
             break;
         } catch (const Retry &r) {
             retry_flags |= r.flags;
+            if (std::getenv("SKIM_DEBUG"))
+                std::fprintf(stderr, "skim restart %d: flags %u\n", attempt, r.flags);
             if (attempt >= 6) {
                 set_error("sketch build buffers did not fit after %d attempts (flags %u)", attempt,
                           r.flags);
@@ -671,8 +809,8 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
             if (r.flags & kOvfRecords) cap.rec *= 2;
             if (r.flags & kOvfSpill) cap.front *= 2;
             if (r.flags & kOvfHash) {
-                if (cap.hash_full) cap.hash *= 2;
-                cap.hash_full = true;
+                cap.hash_min *= 16;
+                cap.hash = std::max(cap.hash, cap.hash_min);
             }
         }
     }

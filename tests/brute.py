@@ -110,3 +110,35 @@ def random_small_graph(rng, n, m, thr_choices):
     dst = np.array([pairs[j][1] for j in idx], dtype=np.int64)
     thr = rng.choice(np.array(thr_choices, dtype=np.uint64), size=src.size).astype(np.uint32)
     return src, dst, thr
+
+
+# ------------------------------------------------------ inverting ranks
+# SplitMix64 is a bijection (Steele, Lea, Flood 2014): every step of its
+# finaliser is invertible (xorshifts by undoing the shifted bits, products by
+# the inverse of the odd multiplier mod 2^64), and the counter is recovered
+# from seed + (c + 1) * golden.  This turns a rank found in a sketch back into
+# its node-instance pair, so large outputs can be checked pair by pair.
+_M64 = (1 << 64) - 1
+_GOLDEN = 0x9E3779B97F4A7C15
+_MUL1 = 0xBF58476D1CE4E5B9
+_MUL2 = 0x94D049BB133111EB
+
+
+def _unxorshift(x, s):
+    y = x.copy()
+    for t in range(1, 64 // s + 1):
+        y = x ^ (y >> np.uint64(s))
+    return y
+
+
+def rank_to_pair(ranks, seed):
+    """Pair id 64 v + i of each rank (uint64 array in, uint64 array out)."""
+    x = np.asarray(ranks, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = _unxorshift(x, 31)
+        z = z * np.uint64(pow(_MUL2, -1, 1 << 64))
+        z = _unxorshift(z, 27)
+        z = z * np.uint64(pow(_MUL1, -1, 1 << 64))
+        z = _unxorshift(z, 30)
+        c1 = (z - np.uint64(seed & _M64)) * np.uint64(pow(_GOLDEN, -1, 1 << 64))
+        return c1 - np.uint64(1)

@@ -130,3 +130,16 @@ def test_live_instances_independent(oracle_lib):
     # the coin depends on the seed
     d = oracle_lib.live_batch(3, n, u, v, 2 * j, thr).astype(float)
     assert abs(np.corrcoef(a, d)[0, 1]) < 5 / np.sqrt(N)
+
+
+def test_rank_inversion_recovers_pairs(oracle_lib):
+    """The test helper that maps a rank back to its pair inverts the oracle's
+    rank function exactly (used to check full-size sketches pair by pair)."""
+    from brute import rank_to_pair
+    rng = np.random.default_rng(11)
+    for seed in (0, 1, 0xDEADBEEFCAFEF00D):
+        v = rng.integers(0, 1 << 25, 2000)
+        i = rng.integers(0, 64, 2000)
+        r = np.array([oracle_lib.rank(seed, int(a), int(b)) for a, b in zip(v, i)], dtype=np.uint64)
+        p = rank_to_pair(r, seed)
+        assert np.array_equal(p, (v * 64 + i).astype(np.uint64))

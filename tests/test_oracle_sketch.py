@@ -138,3 +138,22 @@ def test_estimator_unbiased_with_bounded_cv(oracle_lib):
     cv_bound = 1 / np.sqrt(k - 2)
     assert abs(vals.mean() - true) < 5 * cv_bound * true / np.sqrt(len(vals))
     assert vals.std() / true < cv_bound * 1.15
+
+
+def test_budgeted_brute_force_matches_and_aborts(oracle_lib):
+    """The budgeted, threaded form of the definition returns the same sketches
+    as the plain one, and leaves out exactly the nodes whose searches would
+    scan more out-edges than the budget."""
+    from brute import random_small_graph
+    from workloads import from_edges
+    rng = np.random.default_rng(77)
+    src, dst, thr = random_small_graph(rng, 120, 500, [0xFFFFFFFF, 0xFFFFFFFF // 3])
+    g = from_edges(120, src, dst, thr)
+    R0, S0, reach0 = oracle_lib.sketch_brute(g, 5, 8, 6)
+    R1, S1, reach1, ok = oracle_lib.sketch_brute(g, 5, 8, 6, budget=1 << 40, threads=3)
+    assert ok.all() and np.array_equal(R0, R1) and np.array_equal(S0, S1)
+    assert np.array_equal(reach0, reach1)
+    outdeg = np.diff(g.row_ptr.astype(np.int64))
+    R2, S2, _, ok2 = oracle_lib.sketch_brute(g, 5, 8, 6, budget=0, threads=2)
+    assert np.array_equal(ok2, outdeg == 0)  # zero budget: only nodes with nothing to scan
+    assert np.array_equal(R2[ok2], R0[ok2]) and np.array_equal(S2[ok2], S0[ok2])

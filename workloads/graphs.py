@@ -10,8 +10,9 @@ synthetic graphs stand in for them:
   source ~ out-weight, head ~ in-weight, self-loops and duplicates dropped,
   and a seeded subset of exactly m distinct edges kept.
 * R-MAT: 2^scale nodes, a fixed number of recursive quadrant samples with
-  probabilities (a, b, c, d), a seeded node permutation, then self-loops and
-  duplicates dropped (the final edge count is reported, not topped up).
+  probabilities (a, b, c, d) (float32 uniforms), a seeded node permutation,
+  then self-loops and duplicates dropped (the final edge count is reported,
+  not topped up).
 
 Every graph is returned as a forward CSR (out-edges): row_ptr uint64[n+1],
 col uint32[m] with strictly increasing heads inside each row, no self-loops,
@@ -165,30 +166,58 @@ def chung_lu_graph(n: int, m: int, gamma: float, seed: int) -> tuple[np.ndarray,
     return _csr_from_keys(n, keys)
 
 
+def _rmat_chunk(ss, cnt: int, scale: int, abcd, perm: np.ndarray, nb: int) -> list:
+    """One chunk of R-MAT samples from its own seed sequence: permuted, no
+    self-loops, deduplicated, split into `nb` buckets by the top bits of the
+    source (each bucket sorted)."""
+    a, b, c, _ = abcd
+    rng = np.random.Generator(np.random.PCG64(ss))
+    src = np.zeros(cnt, dtype=np.uint32)
+    dst = np.zeros(cnt, dtype=np.uint32)
+    f_ab, f_abc, f_a = np.float32(a + b), np.float32(a + b + c), np.float32(a)
+    for _ in range(scale):
+        u = rng.random(cnt, dtype=np.float32)
+        down = u >= f_ab                                   # quadrant c or d
+        right = np.where(down, u >= f_abc, u >= f_a)       # quadrant b or d
+        src = (src << np.uint32(1)) | down.astype(np.uint32)
+        dst = (dst << np.uint32(1)) | right.astype(np.uint32)
+    src = perm[src]
+    dst = perm[dst]
+    ok = src != dst
+    src = src[ok]
+    keys = (src.astype(np.uint64) << np.uint64(scale)) | dst[ok].astype(np.uint64)
+    shift = max(scale - (nb.bit_length() - 1), 0)
+    bucket = (src >> np.uint32(shift)).astype(np.int64)
+    order = np.argsort(bucket, kind="stable")
+    keys, bucket = keys[order], bucket[order]
+    bounds = np.searchsorted(bucket, np.arange(nb + 1))
+    return [np.unique(keys[bounds[j]:bounds[j + 1]]) for j in range(nb)]
+
+
 def rmat_graph(scale: int, samples: int, abcd, seed: int,
-               chunk: int = 1 << 24) -> tuple[np.ndarray, np.ndarray]:
-    """R-MAT with a seeded node permutation; self-loops/duplicates dropped."""
-    a, b, c, d = abcd
+               chunks: int = 64, threads: int | None = None) -> tuple[np.ndarray, np.ndarray]:
+    """R-MAT: `samples` recursive quadrant draws with probabilities (a, b, c,
+    d), a seeded node permutation, self-loops and duplicates dropped.
+
+    The samples come in `chunks` fixed chunks, chunk j drawn from the j-th
+    child of the seed sequence, so the graph does not depend on how many
+    threads generate it.  Threads work on chunks, then on source buckets
+    (numpy releases the interpreter lock in its bulk kernels).
+    """
+    import os
+    from concurrent.futures import ThreadPoolExecutor
     n = 1 << scale
-    rng = np.random.Generator(np.random.PCG64(seed))
-    perm = rng.permutation(n).astype(np.uint64)
-    parts = []
-    done = 0
-    t_ab = a + b
-    while done < samples:
-        cnt = min(chunk, samples - done)
-        src = np.zeros(cnt, dtype=np.uint64)
-        dst = np.zeros(cnt, dtype=np.uint64)
-        for _ in range(scale):
-            u = rng.random(cnt)
-            down = u >= t_ab                      # quadrants c, d
-            right = np.where(down, u >= t_ab + c, (u >= a))  # b or d
-            src = (src << np.uint64(1)) | down.astype(np.uint64)
-            dst = (dst << np.uint64(1)) | right.astype(np.uint64)
-        src = perm[src]
-        dst = perm[dst]
-        ok = src != dst
-        parts.append(np.unique(src[ok] * np.uint64(n) + dst[ok]))
-        done += cnt
-    keys = np.unique(np.concatenate(parts))
+    root = np.random.SeedSequence(seed)
+    perm_ss, *chunk_ss = root.spawn(chunks + 1)
+    perm = np.random.Generator(np.random.PCG64(perm_ss)).permutation(n).astype(np.uint32)
+    sizes = [samples // chunks + (1 if j < samples % chunks else 0) for j in range(chunks)]
+    nb = 16
+    threads = threads or max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda j: _rmat_chunk(chunk_ss[j], sizes[j], scale, abcd, perm, nb),
+                            range(chunks)))
+        merged = list(ex.map(lambda b: np.unique(np.concatenate([p[b] for p in parts])),
+                             range(nb)))
+    del parts
+    keys = np.concatenate(merged)
     return _csr_from_keys(n, keys)
