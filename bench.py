@@ -104,14 +104,26 @@ def calibrate_copy():
                       "write_bytes": CALIBRATION_BYTES, "launches": 3}), flush=True)
 
 
-def algorithmic_bytes_expand(cnt):
-    """Bytes the pruned reverse search must move (Algorithm 2's work).
+def algorithmic_bytes_search(cnt):
+    """HBM floor of the pruned reverse searches (the traversal terms of the
+    build's floor): every CSR edge read under perfect instance packing
+    (source id + threshold, 8 B, C_min of them) and the offsets and instance
+    mask of every packed expansion (16 B, N_exp of them)."""
+    return 8 * cnt["c_min"] + 16 * cnt["n_exp"]
 
-    Per rank insertion (an accepted node-instance-source visit): read the
-    visit (8 B) and its live-list bounds (16 B), write the pair state on
-    claim (8 B) and the new visit (8 B).  Per live-edge traversal: read the
-    live source id (4 B) and the visited pair's state word (8 B).
-    """
+
+def algorithmic_bytes_build(cnt, n, k):
+    """HBM floor of a whole build: the search floor plus the sketches (8 B per
+    entry, n * k) and the estimates (8 B per node)."""
+    return algorithmic_bytes_search(cnt) + 8 * n * k + 8 * n
+
+
+def visit_model_bytes(cnt):
+    """Bytes this design's search touches per unit of work when every access
+    is counted once: per rank insertion the frontier entry (8 B), the live-list
+    bounds (16 B), the claimed state word (8 B) and the new entry (8 B); per
+    live-edge traversal the live source id (4 B) and the visited state word
+    (8 B)."""
     return cnt["n_ins"] * (8 + 16 + 8 + 8) + cnt["w_live"] * (4 + 8)
 
 
@@ -313,19 +325,25 @@ def main():
 
     sec, work, kms, klaunch, sec_events = bench_build(args, torch, sk, g, cfg)
     value = cnt["w_live"] / sec
-    alg_bytes = algorithmic_bytes_expand(cnt)
+    alg_bytes = algorithmic_bytes_search(cnt)
+    floor = algorithmic_bytes_build(cnt, g.n, cfg["k"])
     roof = None
     if klaunch:
         per_launch_bytes = alg_bytes * args.steps / klaunch
         avg_s = kms / klaunch / 1e3
         achieved = per_launch_bytes / avg_s / 1e9
+        traffic = measured_traffic(args.workload)
         roof = {"bound": "hbm", "kernel": DOMINANT, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                "traffic": measured_traffic(args.workload),
+                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "launches_per_step": klaunch / args.steps, "avg_launch_us": avg_s * 1e6,
                 "kernel_ms_per_step": kms / args.steps,
                 "ms_per_step_with_kernel_events": sec_events * 1e3,
-                "algorithmic_bytes_per_step": alg_bytes}
+                "algorithmic_bytes_per_step": alg_bytes,
+                "traffic_over_algorithmic": None if traffic is None else traffic / per_launch_bytes,
+                "visit_model_bytes_per_step": visit_model_bytes(cnt),
+                "build_floor_bytes": floor,
+                "build_floor_ms": floor / (HBM_PEAK_GBS * 1e9) * 1e3,
+                "build_floor_over_measured": floor / (HBM_PEAK_GBS * 1e9) / sec}
     out = {
         "metric": METRIC, "value": value, "unit": "live-edge traversals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": sec * 1e3,
