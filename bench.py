@@ -153,6 +153,12 @@ def bench_build(args, torch, sk, g, cfg):
     size = torch.empty(n, dtype=torch.int32, device=dev)
     est = torch.empty(n, dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    tuning = None
+    if not args.no_tune:
+        best, best_ms, start_ms = sk.skim_tune_build(G, ell, k, seed, ranks, size, reps=2,
+                                                    stream=stream)
+        tuning = {"params": best, "best_ms": best_ms, "default_ms": start_ms}
+        log(f"autotuned {tuning}")
     for w in range(args.warmup):
         work = sk.skim_build_sketches(G, ell, k, seed, ranks, size, est, stream=stream)
         log(f"warmup {w}: {work}")
@@ -177,7 +183,7 @@ def bench_build(args, torch, sk, g, cfg):
     sk.skim_timing_enable(None)
     kms, klaunch = sk.skim_timing_read(DOMINANT)
     log(f"kernel pass {args.steps} steps: {(t3 - t2) * 1e3 / args.steps:.3f} ms/step")
-    return (t1 - t0) / args.steps, work, kms, klaunch, (t3 - t2) / args.steps
+    return (t1 - t0) / args.steps, work, kms, klaunch, (t3 - t2) / args.steps, tuning
 
 
 def bench_queries(torch, sk, reps=5, plain_q=20000):
@@ -205,6 +211,20 @@ def bench_queries(torch, sk, reps=5, plain_q=20000):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
     tb = float(np.median(times))
+    # the same batch as a captured HIP graph, replayed
+    gest = torch.empty(Q, dtype=torch.float64, device=dev)
+    plan = sk.QueryPlan(ranks, size, n, k, ell, qo, qn, gest)
+    plan.launch()
+    torch.cuda.synchronize()
+    gtimes = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        plan.launch()
+        torch.cuda.synchronize()
+        gtimes.append(time.perf_counter() - t)
+    tg = float(np.median(gtimes))
+    same_graph = bool(torch.equal(gest, est))
+    plan.free()
     # plain path: one launch per query, on the first plain_q queries
     po = qo[:plain_q + 1].clone()
     pest = torch.empty(plain_q, dtype=torch.float64, device=dev)
@@ -218,6 +238,7 @@ def bench_queries(torch, sk, reps=5, plain_q=20000):
     sizes = np.diff(off.astype(np.int64))
     return {"workload": "batched-query", "queries": Q, "mean_set_size": round(float(sizes.mean()), 3),
             "batched_queries_per_s": Q / tb, "batched_ms": tb * 1e3,
+            "graph_queries_per_s": Q / tg, "graph_ms": tg * 1e3, "graph_identical": same_graph,
             "plain_queries_per_s": plain_q / tp, "plain_sample": plain_q,
             "batched_over_plain": (Q / tb) / (plain_q / tp), "identical_estimates": same}
 
@@ -298,6 +319,8 @@ def main():
     ap.add_argument("--workload", default="chung-lu-1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="build only (no query/SKIM legs)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the build with the default launch shapes (no autotuning)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB copy (for PMC byte calibration)")
     args = ap.parse_args()
@@ -323,7 +346,7 @@ def main():
     cnt = oracle_counters(args.workload, g, cfg)
     log(f"oracle counters {cnt}")
 
-    sec, work, kms, klaunch, sec_events = bench_build(args, torch, sk, g, cfg)
+    sec, work, kms, klaunch, sec_events, tuning = bench_build(args, torch, sk, g, cfg)
     value = cnt["w_live"] / sec
     alg_bytes = algorithmic_bytes_search(cnt)
     floor = algorithmic_bytes_build(cnt, g.n, cfg["k"])
@@ -354,6 +377,7 @@ def main():
                    "probabilities": "weighted cascade 1/indeg(head)",
                    "parallelism": "single GPU"},
         "oracle_counters": cnt, "device_work": work, "roofline": roof,
+        "build_params": sk.skim_get_build_params(), "autotune": tuning,
     }
     if not args.no_extras:
         log("queries")

@@ -116,15 +116,42 @@ skim_status skim_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t
  *   qoff [q+1] (qoff[0] = 0, non-decreasing), qnodes [qoff[q]]: device.
  *   est [q] out, device.  qstatus [q] out, device, may be NULL: 0, or -1
  *   when the set names a node >= n, or -2 when it has more than 1024
- *   entries (that query's est is 0; the rest of the batch is unaffected).
- *   An empty set gives est 0, status 0.
+ *   entries, or -3 when its offsets are out of order (only a replayed plan
+ *   can see that; that query's est is 0, the rest of the batch is
+ *   unaffected).  An empty set gives est 0, status 0.
  *   mode 0: one persistent launch for the whole batch (default);
  *   mode 1: one launch per query (the plain path, for comparison).
+ * The call validates qoff, launches, and waits for the stream.
  */
 skim_status skim_query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
                              uint32_t k, uint32_t ell, uint64_t q, const uint64_t *qoff,
                              const uint32_t *qnodes, uint32_t estimator, uint32_t mode,
                              double *est, int32_t *qstatus, void *stream);
+
+/*
+ * Query plans: the batched launch of skim_query_batch (mode 0) for fixed
+ * buffers, captured once into a HIP graph.
+ *   skim_query_plan_create: validates qoff as skim_query_batch does, then
+ *     captures the launch (arguments as for skim_query_batch; q >= 1).  The
+ *     buffers must stay allocated while the plan lives; their contents may
+ *     change between launches (sets may be rewritten in place as long as
+ *     qoff[q] does not exceed qnodes' length: a set whose offsets are out of
+ *     order or beyond qoff[q] gets status -3).
+ *   skim_query_plan_launch: replays the graph on `stream` without waiting
+ *     (the caller synchronises); SKIM_EDEVICE on a launch failure.
+ *   skim_query_plan_free: releases the plan (NULL is ignored).
+ * For callers that answer batches of a fixed shape repeatedly (serving loops,
+ * benchmarks): a replay costs one graph launch instead of validation, two
+ * launches and a wait.
+ */
+typedef struct skim_query_plan skim_query_plan;
+
+skim_status skim_query_plan_create(const uint64_t *ranks, const uint32_t *size, uint32_t n,
+                                   uint32_t k, uint32_t ell, uint64_t q, const uint64_t *qoff,
+                                   const uint32_t *qnodes, uint32_t estimator, double *est,
+                                   int32_t *qstatus, void *stream, skim_query_plan **plan);
+skim_status skim_query_plan_launch(skim_query_plan *plan, void *stream);
+void skim_query_plan_free(skim_query_plan *plan);
 
 /*
  * skim_greedy -- SKIM seed selection (Section 4, Algorithm 1) for s seeds.
@@ -211,13 +238,58 @@ skim_status skim_server_poll_greedy(skim_server *server, uint64_t ticket, uint32
  * Open-loop replay, for measurement: submits set j (HOST offsets[q+1],
  * nodes) at arrival_s[j] seconds after the call starts (retrying on
  * SKIM_EBUSY; latency still counts from the scheduled arrival) and collects
- * every result into HOST arrays est[q], status[q] (-4 = rejected),
+ * every result into HOST arrays est[q], status[q] (-4 = rejected, -5 = the
+ * batch's launch failed),
  * latency_us[q] (may be NULL).  busy_retries (HOST, may be NULL) counts
  * admission refusals.
  */
 skim_status skim_server_replay(skim_server *server, uint64_t q, const uint64_t *offsets,
                                const uint32_t *nodes, const double *arrival_s, double *est,
                                int32_t *status, double *latency_us, uint64_t *busy_retries);
+
+/*
+ * Launch shapes of the sketch build's pruned search (process-wide; they
+ * change speed only, never results):
+ *   small_frontier   frontiers of at most this many entries go in batches of
+ *                    small_batch levels launched without reading back the
+ *                    frontier size (default 65536);
+ *   small_batch      levels per such batch (default 8, 1..64);
+ *   large_batch      levels per batch of larger frontiers (default 3, 1..64);
+ *   thread_frontier  frontiers of at most this many entries are expanded one
+ *                    entry per thread, larger ones 1024 entries per
+ *                    workgroup per round (default 524288);
+ *   heavy_visits     a rank window whose visited pairs took more than this
+ *                    many visits each on average is followed by a window of
+ *                    one rank bucket instead of two (default 4, >= 1).
+ * skim_set_build_params(NULL) restores the defaults; fields out of range give
+ * SKIM_EINVAL and change nothing.
+ */
+typedef struct {
+    uint32_t small_frontier;
+    uint32_t small_batch;
+    uint32_t large_batch;
+    uint32_t thread_frontier;
+    uint32_t heavy_visits;
+} skim_build_params;
+
+skim_status skim_set_build_params(const skim_build_params *params);
+void skim_get_build_params(skim_build_params *params);
+
+/*
+ * Autotuner for the build's launch shapes: builds the sketches of (g, l, k,
+ * seed) into ranks/size (device, as for skim_build_sketches) with the
+ * current parameters and then with candidate values of one parameter at a
+ * time (coordinate descent over small_frontier, small_batch, large_batch,
+ * thread_frontier), each timed as the best of `reps` builds with HIP events
+ * on `stream` after one warm-up build.  The fastest set becomes the current
+ * parameters and is written to *best (HOST); *best_ms and *start_ms (HOST,
+ * may be NULL) receive its time and that of the parameters in force at the
+ * call.  Results of every build are identical; ranks/size hold the last.
+ */
+skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+                            uint64_t *ranks, uint32_t *size, uint32_t reps,
+                            skim_build_params *best, double *best_ms, double *start_ms,
+                            void *stream);
 
 /*
  * Kernel timing, for measurement: while a kernel name is enabled, every

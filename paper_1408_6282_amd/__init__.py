@@ -24,7 +24,9 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_greedy_state_selected", "skim_timing_enable", "skim_timing_reset",
            "skim_timing_read", "skim_server_create", "skim_server_destroy", "skim_server_submit",
            "skim_server_poll", "skim_server_set_graph", "skim_server_submit_greedy",
-           "skim_server_poll_greedy", "skim_server_replay"]
+           "skim_server_poll_greedy", "skim_server_replay", "skim_set_build_params",
+           "skim_get_build_params", "skim_tune_build", "skim_query_plan_create",
+           "skim_query_plan_launch", "skim_query_plan_free"]
 
 
 class SkimError(RuntimeError):
@@ -36,6 +38,15 @@ class SkimError(RuntimeError):
 class skim_server_config(C.Structure):
     _fields_ = [("budget_bytes", C.c_uint64), ("max_batch", C.c_uint32), ("streams", C.c_uint32),
                 ("estimator", C.c_uint32)]
+
+
+class skim_build_params(C.Structure):
+    _fields_ = [("small_frontier", C.c_uint32), ("small_batch", C.c_uint32),
+                ("large_batch", C.c_uint32), ("thread_frontier", C.c_uint32),
+                ("heavy_visits", C.c_uint32)]
+
+    def as_dict(self):
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
 
 
 class skim_graph(C.Structure):
@@ -52,6 +63,9 @@ def load_library(path: str | None = None):
     if _lib is not None:
         return _lib
     path = path or LIB_PATH
+    # torch first: the library then binds to the HIP runtime torch already
+    # loaded (one runtime per process) rather than loading its own copy.
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run __graft_entry__.build() or python -m paper_1408_6282_amd.build)")
@@ -96,6 +110,20 @@ def load_library(path: str | None = None):
     lib.skim_server_poll_greedy.argtypes = [vp, C.c_uint64, vp, vp, PD]
     lib.skim_server_replay.restype = C.c_int
     lib.skim_server_replay.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, vp, vp, P64]
+    lib.skim_set_build_params.restype = C.c_int
+    lib.skim_set_build_params.argtypes = [C.POINTER(skim_build_params)]
+    lib.skim_get_build_params.restype = None
+    lib.skim_get_build_params.argtypes = [C.POINTER(skim_build_params)]
+    lib.skim_tune_build.restype = C.c_int
+    lib.skim_tune_build.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint32, C.c_uint64, vp,
+                                    vp, C.c_uint32, C.POINTER(skim_build_params), PD, PD, vp]
+    lib.skim_query_plan_create.restype = C.c_int
+    lib.skim_query_plan_create.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
+                                           vp, vp, C.c_uint32, vp, vp, vp, C.POINTER(vp)]
+    lib.skim_query_plan_launch.restype = C.c_int
+    lib.skim_query_plan_launch.argtypes = [vp, vp]
+    lib.skim_query_plan_free.restype = None
+    lib.skim_query_plan_free.argtypes = [vp]
     lib.skim_timing_enable.restype = None
     lib.skim_timing_enable.argtypes = [C.c_char_p]
     lib.skim_timing_reset.restype = None
@@ -182,6 +210,70 @@ def skim_query_batch(ranks, size, n: int, k: int, ell: int, qoff, qnodes, est, q
                               _ptr(qnodes) if qnodes is not None and qnodes.numel() else None,
                               estimator, mode, _ptr(est), _ptr(qstatus), _stream(stream))
     _check("skim_query_batch", st)
+
+
+class QueryPlan:
+    """skim_query_plan_*: a batched query launch captured once into a HIP graph;
+    launch() replays it on a stream without waiting."""
+
+    def __init__(self, ranks, size, n: int, k: int, ell: int, qoff, qnodes, est, qstatus=None,
+                 estimator: int = 0, stream=None):
+        lib = load_library()
+        self.handle = C.c_void_p(None)
+        q = int(qoff.numel()) - 1
+        self._keep = (ranks, size, qoff, qnodes, est, qstatus)  # buffers outlive the plan
+        st = lib.skim_query_plan_create(_ptr(ranks), _ptr(size), n, k, ell, max(q, 0), _ptr(qoff),
+                                        _ptr(qnodes) if qnodes is not None and qnodes.numel()
+                                        else None, estimator, _ptr(est), _ptr(qstatus),
+                                        _stream(stream), C.byref(self.handle))
+        _check("skim_query_plan_create", st)
+
+    def launch(self, stream=None):
+        _check("skim_query_plan_launch",
+               load_library().skim_query_plan_launch(self.handle, _stream(stream)))
+
+    def free(self):
+        if self.handle:
+            load_library().skim_query_plan_free(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def skim_set_build_params(params: dict | None):
+    """Launch shapes of the build's search (None restores the defaults)."""
+    lib = load_library()
+    if params is None:
+        _check("skim_set_build_params", lib.skim_set_build_params(None))
+        return
+    p = skim_get_build_params()
+    p.update(params)
+    _check("skim_set_build_params", lib.skim_set_build_params(C.byref(skim_build_params(**p))))
+
+
+def skim_get_build_params() -> dict:
+    p = skim_build_params()
+    load_library().skim_get_build_params(C.byref(p))
+    return p.as_dict()
+
+
+def skim_tune_build(graph: DeviceGraph, ell: int, k: int, seed: int, ranks, size, reps: int = 2,
+                    stream=None):
+    """Autotune the build's launch shapes on this graph; returns (params, best_ms, start_ms)
+    and leaves the best parameters in force."""
+    lib = load_library()
+    best = skim_build_params()
+    best_ms = C.c_double(0)
+    start_ms = C.c_double(0)
+    st = lib.skim_tune_build(C.byref(graph.struct), ell, k, seed & 0xFFFFFFFFFFFFFFFF, _ptr(ranks),
+                             _ptr(size), reps, C.byref(best), C.byref(best_ms),
+                             C.byref(start_ms), _stream(stream))
+    _check("skim_tune_build", st)
+    return best.as_dict(), float(best_ms.value), float(start_ms.value)
 
 
 class GreedyState:

@@ -38,6 +38,8 @@
 
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
+#include <string>
 #include <cstring>
 
 namespace skim {
@@ -492,6 +494,29 @@ uint64_t next_pow2(uint64_t x) {
     return p;
 }
 
+// Launch shapes of the search (see skim_build_params).
+struct Shapes {
+    uint64_t small_frontier = 65536;
+    int small_batch = 8;
+    int large_batch = 3;
+    uint64_t thread_frontier = (uint64_t)kBlock * 2048;
+    double heavy = 4.0;
+};
+
+std::mutex g_shapes_mu;
+skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4};
+
+Shapes current_shapes() {
+    std::lock_guard<std::mutex> lk(g_shapes_mu);
+    Shapes sh;
+    sh.small_frontier = g_params.small_frontier;
+    sh.small_batch = (int)g_params.small_batch;
+    sh.large_batch = (int)g_params.large_batch;
+    sh.thread_frontier = g_params.thread_frontier;
+    sh.heavy = (double)g_params.heavy_visits;
+    return sh;
+}
+
 struct Capacity {
     uint64_t rec, front, hash;
     uint64_t hash_min;  // least hash-set size of a window (raised after an overflow)
@@ -503,8 +528,8 @@ struct Capacity {
 // too small (the caller's outputs are written only by the merge).
 static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const LiveLists &live,
                         const uint32_t *sources, const unsigned long long *wb, uint32_t W,
-                        const Capacity &cap, uint64_t *ranks_out, uint32_t *size_out,
-                        uint64_t *work, Arena &A) {
+                        const Capacity &cap, const Shapes &sh, uint64_t *ranks_out,
+                        uint32_t *size_out, uint64_t *work, Arena &A) {
     hipStream_t s = A.stream();
     const uint32_t n = g->n;
     const uint64_t npairs = (uint64_t)n * kPairStride;
@@ -533,7 +558,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     // frontier; a level that breaks this overflows and the windows are
     // redone with more room).
     constexpr uint64_t kGrow = 3;
-    constexpr uint64_t kSmall = 65536;  // frontiers handled in batches of levels
+    const uint64_t kSmall = sh.small_frontier;  // frontiers handled in blind batches of levels
     auto grow_u64 = [&](uint64_t *&buf, uint64_t &capacity, uint64_t keep, uint64_t need) {
         if (need <= capacity) return;
         uint64_t nc = capacity;
@@ -549,7 +574,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     // fourfold rank range) at a time, or one (twofold) after a window whose
     // visited pairs took more than kHeavy visits each on average (large
     // reach sets: a smaller step keeps the visits past k in check).
-    constexpr double kHeavy = 4.0;
+    const double kHeavy = sh.heavy;
     uint64_t prev_visits = 0;
     uint32_t span = 1, span_next = 2;
     for (uint32_t w = 0, bb = 0; bb < W && w < 255; ++w, bb += span) {
@@ -649,7 +674,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                         std::fprintf(stderr, "skim window %u: hash set grown to %llu\n", w,
                                      (unsigned long long)ns);
                 }
-                const int batch = f > kSmall ? 3 : 8;
+                const int batch = f > kSmall ? sh.large_batch : sh.small_batch;
                 // room for 64-fold growth at a window's first level and after a
                 // batch over which the frontier grew more than fourfold
                 const bool growing = f_prev == 0 || f > 4 * f_prev;
@@ -659,7 +684,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                 // or with room for 64-fold growth while it grows fast; large
                 // ones in batches of 3.
                 const WinArgs WA = args();
-                const uint32_t chunk = f <= (uint64_t)kBlock * 2048 ? kBlock : kChunk;
+                const uint32_t chunk = f <= sh.thread_frontier ? kBlock : kChunk;
                 for (int j = 0; j < batch; ++j, ++L) {
                     const unsigned grid =
                         f > kSmall ? (j == 0 ? grid_for(f, chunk, 2048) : 2048)
@@ -746,6 +771,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
 static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
                            uint64_t *ranks_out, uint32_t *size_out, double *est_out,
                            uint64_t *work, hipStream_t s) {
+    const Shapes shapes = current_shapes();
     SKIM_REQUIRE(ell >= 1 && ell <= 64, "l must be in [1, 64]");
     SKIM_REQUIRE(k >= 2 && k <= 256, "k must be in [2, 256]");
     SKIM_REQUIRE(ranks_out && size_out, "ranks/size output is NULL");
@@ -795,7 +821,8 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     for (;; ++attempt) {
         try {
             Arena B(s);
-            run_windows(g, k, seed, live, sources, wb, W, cap, ranks_out, size_out, work, B);
+            run_windows(g, k, seed, live, sources, wb, W, cap, shapes, ranks_out, size_out, work,
+                        B);
             break;
         } catch (const Retry &r) {
             retry_flags |= r.flags;
@@ -835,4 +862,104 @@ extern "C" skim_status skim_build_sketches(const skim_graph *g, uint32_t ell, ui
     } catch (const skim::Fail &f) {
         return f.st;
     }
+}
+
+extern "C" skim_status skim_set_build_params(const skim_build_params *p) {
+    skim::clear_error();
+    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4};
+    if (p) {
+        if (p->small_frontier < 1 || p->small_batch < 1 || p->small_batch > 64 ||
+            p->large_batch < 1 || p->large_batch > 64 || p->thread_frontier < 1 ||
+            p->heavy_visits < 1) {
+            skim::set_error("build parameters out of range");
+            return SKIM_EINVAL;
+        }
+        v = *p;
+    }
+    std::lock_guard<std::mutex> lk(skim::g_shapes_mu);
+    skim::g_params = v;
+    return SKIM_OK;
+}
+
+extern "C" void skim_get_build_params(skim_build_params *p) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(skim::g_shapes_mu);
+    *p = skim::g_params;
+}
+
+extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32_t k,
+                                       uint64_t seed, uint64_t *ranks, uint32_t *size,
+                                       uint32_t reps, skim_build_params *best, double *best_ms,
+                                       double *start_ms, void *stream) {
+    skim::clear_error();
+    hipStream_t s = (hipStream_t)stream;
+    if (reps < 1) reps = 1;
+    skim_build_params cur;
+    skim_get_build_params(&cur);
+    const skim_build_params at_start = cur;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        skim::set_error("hipEventCreate failed");
+        if (a) (void)hipEventDestroy(a);
+        return SKIM_EDEVICE;
+    }
+    // best of `reps` builds with the given parameters, in ms (< 0 on error)
+    auto time_with = [&](const skim_build_params &p, skim_status &st) -> double {
+        st = skim_set_build_params(&p);
+        if (st != SKIM_OK) return -1.0;
+        double t_best = 1e300;
+        for (uint32_t r = 0; r < reps; ++r) {
+            if (hipEventRecord(a, s) != hipSuccess) { st = SKIM_EDEVICE; return -1.0; }
+            st = skim_build_sketches(g, ell, k, seed, ranks, size, nullptr, nullptr, stream);
+            if (st != SKIM_OK) return -1.0;
+            float ms = 0;
+            if (hipEventRecord(b, s) != hipSuccess || hipEventSynchronize(b) != hipSuccess ||
+                hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+                st = SKIM_EDEVICE;
+                return -1.0;
+            }
+            t_best = std::min(t_best, (double)ms);
+        }
+        return t_best;
+    };
+    skim_status st = skim_build_sketches(g, ell, k, seed, ranks, size, nullptr, nullptr, stream);
+    double t_cur = st == SKIM_OK ? time_with(cur, st) : -1.0;
+    const double t_start = t_cur;
+    if (st == SKIM_OK) {
+        const uint32_t sf[] = {16384, 65536, 262144};
+        const uint32_t sb[] = {4, 8, 16};
+        const uint32_t lb[] = {2, 3, 4};
+        const uint32_t tf[] = {131072, 524288, 2097152};
+        for (int field = 0; field < 4 && st == SKIM_OK; ++field) {
+            for (int c = 0; c < 3 && st == SKIM_OK; ++c) {
+                skim_build_params p = cur;
+                uint32_t *slot = field == 0 ? &p.small_frontier
+                                 : field == 1 ? &p.small_batch
+                                 : field == 2 ? &p.large_batch
+                                              : &p.thread_frontier;
+                const uint32_t v = field == 0 ? sf[c] : field == 1 ? sb[c] : field == 2 ? lb[c] : tf[c];
+                if (*slot == v) continue;
+                *slot = v;
+                const double t = time_with(p, st);
+                if (st == SKIM_OK && t < t_cur) {
+                    t_cur = t;
+                    cur = p;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != SKIM_OK) {
+        const std::string msg = skim_last_error();
+        (void)skim_set_build_params(&at_start);
+        skim::set_error("%s", msg.c_str());
+        return st;
+    }
+    st = skim_set_build_params(&cur);
+    if (st != SKIM_OK) return st;
+    if (best) *best = cur;
+    if (best_ms) *best_ms = t_cur;
+    if (start_ms) *start_ms = t_start;
+    return SKIM_OK;
 }

@@ -1,5 +1,5 @@
 // skim_common.hip -- host plumbing shared by every entry point: errors,
-// stream-ordered scratch, fills, exclusive scan, graph validation, and the
+// cached scratch allocation, fills, exclusive scan, graph validation, and the
 // per-node estimate entry point.
 #include "skim_internal.h"
 
@@ -12,8 +12,7 @@ namespace skim {
 
 namespace {
 thread_local char g_err[512] = "";
-std::mutex g_pool_mu;
-bool g_pool_ready[64] = {};
+
 }  // namespace
 
 void set_error(const char *fmt, ...) {
@@ -25,52 +24,153 @@ void set_error(const char *fmt, ...) {
 
 void clear_error() { g_err[0] = 0; }
 
-static void ensure_pool() {
-    int dev = 0;
-    SKIM_HIP(hipGetDevice(&dev));
-    if (dev < 0 || dev >= 64) return;
-    std::lock_guard<std::mutex> lk(g_pool_mu);
-    if (g_pool_ready[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t keep = ~0ull;  // keep freed scratch cached between calls
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-    }
-    (void)hipGetLastError();
-    g_pool_ready[dev] = true;
+// ----------------------------------------------------- scratch allocation
+// Calls take their scratch from a per-device cache of device blocks: a block
+// is allocated once (hipMalloc) and reused by later calls, so a build does
+// not map ~20 GB afresh.  (The runtime's stream-ordered pool was measured to
+// get slower with every call in a long-running process.)  Every non-persistent
+// arena synchronises its stream before its blocks go back to the cache, so a
+// cached block is never still in use by a queued kernel; blocks released in
+// the middle of a call are reused only by the same arena (same stream).
+namespace {
+struct DeviceCache {
+    std::multimap<size_t, void *> free;  // block size -> block
+    size_t cached = 0;                   // bytes held in `free`
+    size_t limit = 0;                    // most bytes to keep cached
+};
+std::mutex g_cache_mu;
+DeviceCache g_cache[64];
+
+// Size class: at most 1/8 above the request (256-byte granularity below 2 KiB).
+size_t size_class(size_t bytes) {
+    if (bytes < 2048) return (bytes + 255) & ~(size_t)255;
+    int lg = 63 - __builtin_clzll((unsigned long long)bytes);
+    const size_t step = (size_t)1 << (lg - 3);
+    return (bytes + step - 1) & ~(step - 1);
 }
 
-Arena::Arena(hipStream_t s, bool persistent) : s_(s), persistent_(persistent) { ensure_pool(); }
+int current_device() {
+    int dev = 0;
+    SKIM_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device index %d out of range", dev);
+        throw Fail{SKIM_EUNSUPPORTED};
+    }
+    return dev;
+}
+
+// Free cached blocks of `dev` (largest first) until at most `keep` bytes stay.
+void trim_cache(int dev, size_t keep) {
+    DeviceCache &C = g_cache[dev];
+    while (C.cached > keep && !C.free.empty()) {
+        auto it = std::prev(C.free.end());
+        C.cached -= it->first;
+        (void)hipFree(it->second);
+        C.free.erase(it);
+    }
+    (void)hipGetLastError();
+}
+}  // namespace
+
+Arena::Arena(hipStream_t s, bool persistent) : s_(s), persistent_(persistent) {
+    dev_ = current_device();
+}
 
 Arena::~Arena() {
-    for (void *p : bufs_)
-        if (p) (void)(persistent_ ? hipFree(p) : hipFreeAsync(p, s_));
+    if (persistent_) {
+        for (auto &b : bufs_)
+            if (b.p) (void)hipFree(b.p);
+        (void)hipGetLastError();
+        return;
+    }
+    bool any = false;
+    for (auto &b : bufs_) any |= b.p != nullptr;
+    for (auto &b : spare_) any |= b.p != nullptr;
+    if (!any) return;
+    (void)hipStreamSynchronize(s_);  // nothing queued may still use the blocks
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    DeviceCache &C = g_cache[dev_];
+    if (!C.limit) {
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && tot) C.limit = tot / 10 * 7;
+        else C.limit = (size_t)64 << 30;
+        (void)hipGetLastError();
+    }
+    for (auto *list : {&bufs_, &spare_})
+        for (auto &b : *list)
+            if (b.p) {
+                C.free.emplace(b.bytes, b.p);
+                C.cached += b.bytes;
+                b.p = nullptr;
+            }
+    if (C.cached > C.limit) trim_cache(dev_, C.limit);
 }
 
 void *Arena::get(size_t bytes) {
-    void *p = nullptr;
     if (bytes == 0) bytes = 8;
-    bytes = (bytes + 255) & ~(size_t)255;
-    hipError_t e = persistent_ ? hipMalloc(&p, bytes) : hipMallocAsync(&p, bytes, s_);
-    if (e != hipSuccess || !p) {
-        (void)hipGetLastError();
-        set_error("device allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
-        throw Fail{SKIM_ENOMEM};
+    const size_t cls = size_class(bytes);
+    void *p = nullptr;
+    size_t got = cls;
+    if (persistent_) {
+        hipError_t e = hipMalloc(&p, cls);
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error("device allocation of %zu bytes failed: %s", cls, hipGetErrorString(e));
+            throw Fail{SKIM_ENOMEM};
+        }
+        bufs_.push_back({p, cls});
+        return p;
     }
-    bufs_.push_back(p);
+    // a block this arena released earlier (same stream: ordered)
+    for (auto &b : spare_)
+        if (b.p && b.bytes >= cls && b.bytes <= cls + cls / 4) {
+            bufs_.push_back(b);
+            b.p = nullptr;
+            return bufs_.back().p;
+        }
+    {   // a cached block of this size class (or at most a quarter larger)
+        std::lock_guard<std::mutex> lk(g_cache_mu);
+        DeviceCache &C = g_cache[dev_];
+        auto it = C.free.lower_bound(cls);
+        if (it != C.free.end() && it->first <= cls + cls / 4) {
+            p = it->second;
+            got = it->first;
+            C.cached -= it->first;
+            C.free.erase(it);
+        }
+    }
+    if (!p) {
+        hipError_t e = hipMalloc(&p, cls);
+        if (e != hipSuccess || !p) {  // give the cache back to the device and try once more
+            (void)hipGetLastError();
+            {
+                std::lock_guard<std::mutex> lk(g_cache_mu);
+                trim_cache(dev_, 0);
+            }
+            p = nullptr;
+            e = hipMalloc(&p, cls);
+        }
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            set_error("device allocation of %zu bytes failed: %s", cls, hipGetErrorString(e));
+            throw Fail{SKIM_ENOMEM};
+        }
+    }
+    bufs_.push_back({p, got});
     return p;
 }
 
 void Arena::release(void *p) {
     for (auto &b : bufs_)
-        if (b == p) {
+        if (b.p == p) {
             if (persistent_) {
                 (void)hipStreamSynchronize(s_);
-                (void)hipFree(b);
+                (void)hipFree(b.p);
             } else {
-                (void)hipFreeAsync(b, s_);
+                spare_.push_back(b);  // reusable by this arena's later allocations
             }
-            b = nullptr;
+            b.p = nullptr;
         }
 }
 

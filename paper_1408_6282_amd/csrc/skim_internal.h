@@ -130,21 +130,28 @@ struct Fail {
         }                                 \
     } while (0)
 
-// Stream-ordered scratch: every buffer comes from hipMallocAsync on the
-// call's stream and is released with hipFreeAsync when the arena dies.
+// Scratch of one call on one stream.  Blocks come from a per-device cache
+// (hipMalloc on a miss) and return to it when the arena dies, after a
+// synchronisation of the stream; a persistent arena owns its blocks outright
+// (hipMalloc / hipFree) for state that outlives a call.
 class Arena {
   public:
     explicit Arena(hipStream_t s, bool persistent = false);
     ~Arena();
     void *get(size_t bytes);
     template <class T> T *alloc(size_t count) { return (T *)get(count * sizeof(T)); }
-    void release(void *p);  // give one buffer back early
+    void release(void *p);  // give one buffer back early (reused by this arena)
     hipStream_t stream() const { return s_; }
 
   private:
+    struct Block {
+        void *p;
+        size_t bytes;
+    };
     hipStream_t s_;
     bool persistent_;
-    std::vector<void *> bufs_;
+    int dev_ = 0;
+    std::vector<Block> bufs_, spare_;
 };
 
 // Small pinned host buffer per thread, for reading device counters.
@@ -198,6 +205,7 @@ struct QueryArgs {
     const uint64_t *ranks;
     const uint32_t *size;
     uint32_t n, k, ell;
+    uint64_t q;  // sets in the batch (qoff has q + 1 entries)
     const uint64_t *qoff;
     const uint32_t *qnodes;
     double *est;

@@ -15,6 +15,8 @@
 // query.
 #include "skim_internal.h"
 
+#include <memory>
+
 namespace skim {
 
 namespace {
@@ -49,8 +51,17 @@ __device__ void answer_query(const QArgs &Q, uint64_t j, uint32_t *mnode, uint16
                              uint16_t *mlim) {
     const uint32_t lane = lane_id();
     const uint64_t a = Q.qoff[j], b = Q.qoff[j + 1];
-    const uint64_t S = b - a;
     const uint32_t k = Q.k;
+    // Offsets are validated before a batch; a replayed plan re-checks its
+    // own set here (non-decreasing, within qoff[q]) and never reads outside.
+    if (b < a || b > Q.qoff[Q.q] || (j == 0 && a != 0)) {
+        if (lane == 0) {
+            Q.est[j] = 0.0;
+            if (Q.qstatus) Q.qstatus[j] = -3;
+        }
+        return;
+    }
+    const uint64_t S = b - a;
     // membership checks (node ids are validated per query)
     bool bad = false;
     for (uint64_t t = a + lane; t < b; t += 64) bad |= Q.qnodes[t] >= Q.n;
@@ -210,7 +221,7 @@ static void query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
     uint64_t total = 0;
     read_back(&total, qoff + q, sizeof total, s);
     SKIM_REQUIRE(total == 0 || qnodes, "qnodes is NULL");
-    QArgs Q{ranks, size, n, k, ell, qoff, qnodes, est, qstatus, estimator};
+    QArgs Q{ranks, size, n, k, ell, q, qoff, qnodes, est, qstatus, estimator};
     if (mode == 0) {
         unsigned long long *next = A.alloc<unsigned long long>(1);
         LaunchTimer t("k_query_persistent", s);
@@ -240,3 +251,119 @@ extern "C" skim_status skim_query_batch(const uint64_t *ranks, const uint32_t *s
         return f.st;
     }
 }
+
+// ------------------------------------------------------------ query plans
+// A plan is the batched launch (counter reset by a fill kernel, then the
+// persistent query kernel) captured once into a HIP graph; launching the plan
+// replays the graph on the caller's stream.
+struct skim_query_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    unsigned long long *next = nullptr;
+    uint64_t q = 0;
+    int device = 0;
+};
+
+namespace skim {
+
+static void plan_free(skim_query_plan *p) {
+    if (!p) return;
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    if (have) (void)hipSetDevice(p->device);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->next) (void)hipFree(p->next);
+    if (have) (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+    delete p;
+}
+
+static skim_query_plan *plan_create(const uint64_t *ranks, const uint32_t *size, uint32_t n,
+                                    uint32_t k, uint32_t ell, uint64_t q, const uint64_t *qoff,
+                                    const uint32_t *qnodes, uint32_t estimator, double *est,
+                                    int32_t *qstatus, hipStream_t s) {
+    SKIM_REQUIRE(ranks && size, "sketches are NULL");
+    SKIM_REQUIRE(n >= 1 && k >= 2 && k <= 256 && ell >= 1 && ell <= 64,
+                 "need n >= 1, 2 <= k <= 256, 1 <= l <= 64");
+    SKIM_REQUIRE(estimator <= 1, "estimator must be 0 (bottom-k) or 1 (Cohen-Kaplan)");
+    SKIM_REQUIRE(q >= 1, "a plan needs q >= 1 sets");
+    SKIM_REQUIRE(qoff && est, "qoff/est is NULL");
+    {   // the offsets as they are now
+        Arena A(s);
+        uint32_t *err = A.alloc<uint32_t>(1);
+        fill_u32(err, 0, 1, s);
+        k_check_offsets<<<grid_for(q + 1, 256, 4096), 256, 0, s>>>(qoff, q, err);
+        SKIM_LAUNCH_CHECK();
+        uint32_t herr = 0;
+        read_back(&herr, err, sizeof herr, s);
+        SKIM_REQUIRE(herr == 0, "qoff must start at 0 and be non-decreasing");
+        uint64_t total = 0;
+        read_back(&total, qoff + q, sizeof total, s);
+        SKIM_REQUIRE(total == 0 || qnodes, "qnodes is NULL");
+    }
+    std::unique_ptr<skim_query_plan, void (*)(skim_query_plan *)> p(new skim_query_plan,
+                                                                   plan_free);
+    SKIM_HIP(hipGetDevice(&p->device));
+    p->q = q;
+    SKIM_HIP(hipMalloc(&p->next, sizeof(unsigned long long)));
+    hipStream_t cs = nullptr;
+    SKIM_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    QArgs Q{ranks, size, n, k, ell, q, qoff, qnodes, est, qstatus, estimator};
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        try {
+            launch_queries_async(Q, q, p->next, cs);
+        } catch (const Fail &) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            (void)hipStreamDestroy(cs);
+            throw;
+        }
+        e = hipStreamEndCapture(cs, &p->graph);
+    }
+    (void)hipStreamDestroy(cs);
+    SKIM_HIP(e);
+    SKIM_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
+    return p.release();
+}
+
+}  // namespace skim
+
+extern "C" skim_status skim_query_plan_create(const uint64_t *ranks, const uint32_t *size,
+                                              uint32_t n, uint32_t k, uint32_t ell, uint64_t q,
+                                              const uint64_t *qoff, const uint32_t *qnodes,
+                                              uint32_t estimator, double *est, int32_t *qstatus,
+                                              void *stream, skim_query_plan **plan) {
+    skim::clear_error();
+    if (!plan) {
+        skim::set_error("plan is NULL");
+        return SKIM_EINVAL;
+    }
+    *plan = nullptr;
+    try {
+        *plan = skim::plan_create(ranks, size, n, k, ell, q, qoff, qnodes, estimator, est, qstatus,
+                                  (hipStream_t)stream);
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
+extern "C" skim_status skim_query_plan_launch(skim_query_plan *plan, void *stream) {
+    skim::clear_error();
+    if (!plan) {
+        skim::set_error("plan is NULL");
+        return SKIM_EINVAL;
+    }
+    try {
+        skim::LaunchTimer t("k_query_persistent", (hipStream_t)stream);
+        SKIM_HIP(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
+extern "C" void skim_query_plan_free(skim_query_plan *plan) { skim::plan_free(plan); }

@@ -148,6 +148,7 @@ bool skim_server::launch_batch(Slot &sl) {
     (void)hipMemcpyAsync(sl.d_off, sl.h_off, (q + 1) * 8, hipMemcpyHostToDevice, s);
     if (o) (void)hipMemcpyAsync(sl.d_nodes, sl.h_nodes, o * 4, hipMemcpyHostToDevice, s);
     skim::QueryArgs Q = base;
+    Q.q = q;
     Q.qoff = sl.d_off;
     Q.qnodes = sl.d_nodes;
     Q.est = sl.d_est;
@@ -155,10 +156,10 @@ bool skim_server::launch_batch(Slot &sl) {
     try {
         skim::launch_queries_async(Q, q, sl.d_next, s);
     } catch (const skim::Fail &) {
-        // mark the batch failed; its requests complete with status -3
+        // mark the batch failed; its requests complete with status -5
         for (uint64_t j = 0; j < q; ++j) {
             sl.h_est[j] = 0.0;
-            sl.h_st[j] = -3;
+            sl.h_st[j] = -5;
         }
         (void)hipStreamSynchronize(s);
         retire(sl);
@@ -283,7 +284,7 @@ extern "C" skim_status skim_server_create(const uint64_t *ranks, const uint32_t 
         auto sv = std::make_unique<skim_server>();
         SKIM_HIP(hipGetDevice(&sv->device));
         sv->cfg = *cfg;
-        sv->base = skim::QueryArgs{ranks, size, n, k, ell, nullptr, nullptr, nullptr, nullptr,
+        sv->base = skim::QueryArgs{ranks, size, n, k, ell, 0, nullptr, nullptr, nullptr, nullptr,
                                    cfg->estimator};
         const uint64_t cap_nodes = std::max<uint64_t>(1024, cfg->budget_bytes / 4 / cfg->streams);
         sv->slots.resize(cfg->streams);

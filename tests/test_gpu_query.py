@@ -95,3 +95,63 @@ def test_bad_offsets_rejected(tiny):
     with pytest.raises(sk.SkimError) as ei:
         gpu_query(rt, st, g.n, cfg["k"], cfg["ell"], off, nodes)
     assert ei.value.status == sk.SKIM_EINVAL
+
+
+def test_graph_plan_replays_match_batches(oracle_lib, tiny):
+    """A captured plan, replayed several times with eager work and
+    synchronisations in between, equals the batch call every time; sets
+    rewritten in place are answered as rewritten; out-of-order offsets get
+    status -3 without touching the sets that do not share them."""
+    import torch
+    import paper_1408_6282_amd as sk
+    from gpu_util import to_dev_u64, to_dev_u32
+    cfg, g, R, S, rt, st = tiny
+    k, ell = cfg["k"], cfg["ell"]
+    off, nodes = uniform_query_sets(500, g.n, 23, 1, 300)
+    qo, qn = to_dev_u64(off), to_dev_u32(nodes)
+    q = len(off) - 1
+    for estimator, fn in [(0, oracle_lib.union_query), (1, oracle_lib.ck_query)]:
+        est = torch.empty(q, dtype=torch.float64, device="cuda:0")
+        status = torch.empty(q, dtype=torch.int32, device="cuda:0")
+        plan = sk.QueryPlan(rt, st, g.n, k, ell, qo, qn, est, status, estimator=estimator)
+        want, _ = fn(R, S, k, ell, off, nodes)
+        for rep in range(4):
+            est.fill_(-1.0)
+            plan.launch()
+            torch.cuda.synchronize()
+            assert np.array_equal(est.cpu().numpy(), want), f"replay {rep}"
+            assert (status.cpu().numpy() == 0).all()
+            x = torch.arange(1 << 16, device="cuda:0").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            assert int(x) == (1 << 16) * ((1 << 16) - 1) // 2
+        # rewrite the sets in place (same offsets, other nodes)
+        rng = np.random.default_rng(estimator)
+        nodes2 = nodes.copy()
+        for j in range(q):
+            a, b = int(off[j]), int(off[j + 1])
+            nodes2[a:b] = rng.choice(g.n, b - a, replace=False)
+        qn.copy_(to_dev_u32(nodes2))
+        plan.launch()
+        torch.cuda.synchronize()
+        want2, _ = fn(R, S, k, ell, off, nodes2)
+        assert np.array_equal(est.cpu().numpy(), want2)
+        # break the order of one offset in place
+        bad = off.copy()
+        bad[7] = bad[8] + 1
+        qo.copy_(to_dev_u64(bad))
+        plan.launch()
+        torch.cuda.synchronize()
+        stat = status.cpu().numpy()
+        got = est.cpu().numpy()
+        assert stat[7] == -3 and got[7] == 0.0  # its end now lies before its start
+        # set 6 ends at the moved offset: a valid, longer set
+        s6 = nodes2[int(off[6]):int(bad[7])]
+        w6, _ = fn(R, S, k, ell, np.array([0, s6.size], dtype=np.uint64), s6)
+        assert stat[6] == 0 and got[6] == w6[0]
+        good = np.ones(q, dtype=bool)
+        good[[6, 7]] = False
+        assert (stat[good] == 0).all()
+        assert np.array_equal(got[good], want2[good])
+        qo.copy_(to_dev_u64(off))
+        qn.copy_(to_dev_u32(nodes))
+        plan.free()

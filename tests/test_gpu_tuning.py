@@ -1,0 +1,73 @@
+"""Launch shapes of the sketch build (skim_build_params) and their autotuner:
+any valid shape gives the oracle's sketches bit for bit, the tuner leaves the
+fastest shape in force, and out-of-range shapes are refused."""
+import numpy as np
+import pytest
+
+from workloads import from_edges
+from brute import random_small_graph
+from gpu_util import gpu_build, log
+
+pytestmark = pytest.mark.gpu
+
+EXTREME = dict(small_frontier=1, small_batch=1, large_batch=1, thread_frontier=1, heavy_visits=1)
+WIDE = dict(small_frontier=1 << 24, small_batch=64, large_batch=64, thread_frontier=1 << 30,
+            heavy_visits=1000)
+
+
+@pytest.fixture
+def restore_params():
+    import paper_1408_6282_amd as sk
+    yield
+    sk.skim_set_build_params(None)
+
+
+def _powerlaw(n=20000, m=320000):
+    from workloads.graphs import Graph, chung_lu_graph, wc_thresholds
+    rp, col = chung_lu_graph(n, m, 2.1, 55)
+    return Graph(n, rp, col, wc_thresholds(rp, col, n))
+
+
+@pytest.mark.parametrize("shape", ["extreme", "wide"])
+def test_any_shape_gives_oracle_sketches(oracle_lib, restore_params, shape):
+    import paper_1408_6282_amd as sk
+    sk.skim_set_build_params(EXTREME if shape == "extreme" else WIDE)
+    rng = np.random.default_rng(5)
+    graphs = [_powerlaw()]
+    for _ in range(3):
+        src, dst, thr = random_small_graph(rng, 50, 200, [0xFFFFFFFF, 0xFFFFFFFF // 3])
+        graphs.append(from_edges(50, src, dst, thr))
+    for g in graphs:
+        log(f"shape {shape}: n={g.n} m={g.m}")
+        R, S, E, work, _ = gpu_build(g, 32, 16, 3)
+        R0, S0, _ = oracle_lib.build_alg2(g, 3, 32, 16)
+        assert np.array_equal(R, R0) and np.array_equal(S, S0)
+        assert np.array_equal(E, oracle_lib.estimates(R0, S0, 16, 32))
+
+
+def test_tuner_keeps_results_and_sets_params(oracle_lib, restore_params):
+    import torch
+    import paper_1408_6282_amd as sk
+    g = _powerlaw()
+    G = sk.DeviceGraph.from_host(g, "cuda:0")
+    ranks = torch.empty(g.n * 16, dtype=torch.int64, device="cuda:0")
+    size = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    best, best_ms, start_ms = sk.skim_tune_build(G, 32, 16, 3, ranks, size, reps=1)
+    log(f"tuned {best} {best_ms:.3f} ms (start {start_ms:.3f} ms)")
+    assert best_ms <= start_ms
+    assert sk.skim_get_build_params() == best
+    R0, S0, _ = oracle_lib.build_alg2(g, 3, 32, 16)
+    R = ranks.cpu().numpy().view(np.uint64).reshape(g.n, 16)
+    assert np.array_equal(R, R0) and np.array_equal(size.cpu().numpy().view(np.uint32), S0)
+
+
+@pytest.mark.parametrize("field,value", [("small_frontier", 0), ("small_batch", 0),
+                                         ("small_batch", 65), ("large_batch", 0),
+                                         ("thread_frontier", 0), ("heavy_visits", 0)])
+def test_out_of_range_params_refused(restore_params, field, value):
+    import paper_1408_6282_amd as sk
+    before = sk.skim_get_build_params()
+    with pytest.raises(sk.SkimError) as ei:
+        sk.skim_set_build_params({field: value})
+    assert ei.value.status == sk.SKIM_EINVAL
+    assert sk.skim_get_build_params() == before
