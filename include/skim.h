@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SKIM_ABI_VERSION 1u
+#define SKIM_ABI_VERSION 2u
 
 typedef enum {
     SKIM_OK = 0,
@@ -260,7 +260,10 @@ skim_status skim_server_replay(skim_server *server, uint64_t q, const uint64_t *
  *                    workgroup per round (default 524288);
  *   heavy_visits     a rank window whose visited pairs took more than this
  *                    many visits each on average is followed by a window of
- *                    one rank bucket instead of two (default 4, >= 1).
+ *                    one rank bucket instead of two (default 4, >= 1);
+ *   sort_frontier    frontiers of more than this many entries are sorted by
+ *                    pair before they are expanded, so that live lists are
+ *                    read in order (0 = never, the default).
  * skim_set_build_params(NULL) restores the defaults; fields out of range give
  * SKIM_EINVAL and change nothing.
  */
@@ -270,6 +273,7 @@ typedef struct {
     uint32_t large_batch;
     uint32_t thread_frontier;
     uint32_t heavy_visits;
+    uint32_t sort_frontier;
 } skim_build_params;
 
 skim_status skim_set_build_params(const skim_build_params *params);
@@ -280,8 +284,8 @@ void skim_get_build_params(skim_build_params *params);
  * seed) into ranks/size (device, as for skim_build_sketches) with the
  * current parameters and then with candidate values of one parameter at a
  * time (coordinate descent over small_frontier, small_batch, large_batch,
- * thread_frontier), each timed as the best of `reps` builds with HIP events
- * on `stream` after one warm-up build.  The fastest set becomes the current
+ * thread_frontier, sort_frontier), each timed as the best of `reps` builds
+ * with HIP events on `stream` after one warm-up build.  The fastest set becomes the current
  * parameters and is written to *best (HOST); *best_ms and *start_ms (HOST,
  * may be NULL) receive its time and that of the parameters in force at the
  * call.  Results of every build are identical; ranks/size hold the last.

@@ -194,8 +194,7 @@ struct WinArgs {
     uint32_t logcap;
     uint32_t win;          // window id (tag)
     uint32_t k;
-    const uint32_t *xcnt;  // records per node before this window
-    uint32_t *xadd;        // records per node in this window
+    const uint8_t *want;   // node records its visits in this window (fewer than k so far)
     uint64_t *rec;         // records: (node << 32) | source pair
     uint64_t rec_cap;
     uint64_t *front[2];    // current / next level: (pair << 32) | source pair
@@ -236,7 +235,7 @@ __device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
 
 // Record a visit of node v when v held fewer than k ranks at the window start.
 __device__ __forceinline__ bool wants_record(const WinArgs &A, uint32_t v) {
-    return A.xcnt[v] < A.k;
+    return A.want[v] != 0;
 }
 
 // ------------------------------------ 3. level-synchronous window search
@@ -312,7 +311,6 @@ __device__ __forceinline__ void expand_range(const WinArgs &A, const uint64_t *c
                     stage_push(F, ((uint64_t)q << 32) | src, next, A.front_cap, next_count,
                                &A.ctl->flags, kOvfSpill);
                     if (wants_record(A, w)) {
-                        atomicAdd(A.xadd + w, 1u);
                         stage_push(R, ((uint64_t)w << 32) | src, A.rec, A.rec_cap,
                                    &A.ctl->records, &A.ctl->flags, kOvfRecords);
                     }
@@ -351,7 +349,6 @@ __global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_
                        &A.ctl->flags, kOvfSpill);
             const uint32_t v = p / kPairStride;
             if (wants_record(A, v)) {
-                atomicAdd(A.xadd + v, 1u);
                 stage_push(X.R, ((uint64_t)v << 32) | p, A.rec, A.rec_cap, &A.ctl->records,
                            &A.ctl->flags, kOvfRecords);
             }
@@ -407,19 +404,40 @@ __global__ void k_set_bases(unsigned long long *dst, WinBases wb) {
 
 // ---------------------------------------------------------- 4. records
 
-__global__ void k_fold(uint32_t *xcnt, uint32_t *xadd, uint32_t n, uint32_t k, Ctl *ctl) {
-    uint32_t crossed = 0;
-    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
-         v += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t add = xadd[v];
-        if (add) {
-            const uint32_t old = xcnt[v];
-            xcnt[v] = old + add;
-            xadd[v] = 0;
-            crossed += (old < k && old + add >= k);
+// After a window: want[v] = 1 while node v has received fewer than k ranks
+// in all, summed over its 64 pairs (each pair's count undercounts at worst,
+// so a node never stops recording too early); ctl->full counts the others.
+// Eight lanes per node, each summing eight consecutive state words.
+__global__ void k_want(const uint64_t *words, uint32_t n, uint32_t k, uint8_t *want, Ctl *ctl) {
+    uint32_t full = 0;
+    const uint64_t lanes = (uint64_t)n * 8;
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ((lanes + 63) & ~63ull);
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        uint32_t c = 0;
+        if (t < lanes) {
+            const uint64_t *wv = words + t * 8;
+            for (int j = 0; j < 8; ++j) c += prior_count(wv[j], 0xFEu);
+        }
+        c += __shfl_xor(c, 1);
+        c += __shfl_xor(c, 2);
+        c += __shfl_xor(c, 4);
+        if (t < lanes && (t & 7) == 0) {
+            const bool w = c < k;
+            want[t >> 3] = w;
+            full += !w;
         }
     }
-    wave_add(&ctl->full, crossed);
+    wave_add(&ctl->full, full);
+}
+
+// Segment [start[v], end[v]) of node v in the records sorted by node.
+__global__ void k_bounds(const uint64_t *seg, uint64_t nrec, uint64_t *start, uint64_t *end) {
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nrec;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)(seg[t] >> 32);
+        if (t == 0 || (uint32_t)(seg[t - 1] >> 32) != v) start[v] = t;
+        if (t + 1 == nrec || (uint32_t)(seg[t + 1] >> 32) != v) end[v] = t + 1;
+    }
 }
 
 // ------------------------------------------------------------- 5. merge
@@ -444,13 +462,13 @@ __device__ void lds_bitonic(uint64_t *x, uint32_t P) {
 }
 
 // One block (one wave) per node: keep the k smallest ranks of the node's
-// records seg[goff[v], goff[v+1]) (records sorted by node).
-__global__ void __launch_bounds__(64) k_select(const uint64_t *goff, const uint64_t *seg,
-                                               uint32_t n, uint32_t k, uint64_t seed,
-                                               uint64_t *ranks, uint32_t *size) {
+// records seg[start[v], end[v]) (records sorted by node).
+__global__ void __launch_bounds__(64) k_select(const uint64_t *start, const uint64_t *end,
+                                               const uint64_t *seg, uint32_t n, uint32_t k,
+                                               uint64_t seed, uint64_t *ranks, uint32_t *size) {
     __shared__ uint64_t buf[512];
     for (uint32_t v = blockIdx.x; v < n; v += gridDim.x) {
-        const uint64_t a = goff[v], b = goff[v + 1];
+        const uint64_t a = start[v], b = end[v];
         const uint64_t S = b - a;
         uint32_t keep;
         if (S <= 512) {
@@ -501,10 +519,11 @@ struct Shapes {
     int large_batch = 3;
     uint64_t thread_frontier = (uint64_t)kBlock * 2048;
     double heavy = 4.0;
+    uint64_t sort_frontier = 0;  // 0: never sort
 };
 
 std::mutex g_shapes_mu;
-skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4};
+skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0};
 
 Shapes current_shapes() {
     std::lock_guard<std::mutex> lk(g_shapes_mu);
@@ -514,6 +533,7 @@ Shapes current_shapes() {
     sh.large_batch = (int)g_params.large_batch;
     sh.thread_frontier = g_params.thread_frontier;
     sh.heavy = (double)g_params.heavy_visits;
+    sh.sort_frontier = g_params.sort_frontier;
     return sh;
 }
 
@@ -535,10 +555,8 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     const uint64_t npairs = (uint64_t)n * kPairStride;
     uint64_t *words = A.alloc<uint64_t>(npairs);
     fill_u64(words, kWordInit, npairs, s);
-    uint32_t *xcnt = A.alloc<uint32_t>(n + 1);
-    uint32_t *xadd = A.alloc<uint32_t>(n + 1);
-    fill_u32(xcnt, 0, n + 1, s);
-    fill_u32(xadd, 0, n + 1, s);
+    uint8_t *want = A.alloc<uint8_t>((uint64_t)n + 4);
+    fill_u32((uint32_t *)want, 0x01010101u, (n + 3) / 4, s);  // no records yet: all record
     Ctl *ctl = A.alloc<Ctl>(1);
     fill_u64((uint64_t *)ctl, 0, sizeof(Ctl) / 8, s);
     uint64_t rec_cap = cap.rec, front_cap = cap.front;
@@ -549,6 +567,11 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     uint64_t hset_size = std::min<uint64_t>(cap.hash, 1ull << 29);
     uint64_t *hset = A.alloc<uint64_t>(hset_size);
     uint64_t *snap = nullptr;  // pair states at the start of a guarded window
+    uint64_t *sort_buf = nullptr, sort_cap = 0;  // frontier sorting (sort_frontier)
+    uint8_t *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
+    int pair_bits = 1;
+    while (pair_bits < 32 && (1ull << pair_bits) < npairs) ++pair_bits;
     uint32_t levels_run = 0;
     uint64_t windows_done = 0, prev_hash = 0, prev_nw = 0;
     const bool debug = std::getenv("SKIM_DEBUG") != nullptr;
@@ -560,12 +583,12 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     constexpr uint64_t kGrow = 3;
     const uint64_t kSmall = sh.small_frontier;  // frontiers handled in blind batches of levels
     auto grow_u64 = [&](uint64_t *&buf, uint64_t &capacity, uint64_t keep, uint64_t need) {
-        if (need <= capacity) return;
-        uint64_t nc = capacity;
+        if (need <= capacity && buf) return;
+        uint64_t nc = std::max<uint64_t>(capacity, 1024);
         while (nc < need) nc *= 2;
         uint64_t *nb = A.alloc<uint64_t>(nc);
         if (keep) SKIM_HIP(hipMemcpyAsync(nb, buf, keep * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-        A.release(buf);
+        if (buf) A.release(buf);
         buf = nb;
         capacity = nc;
     };
@@ -617,7 +640,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
             k_ctl_begin<<<1, 1, 0, s>>>(ctl, base.visits, base.scans, base.records);
             SKIM_LAUNCH_CHECK();
             auto args = [&]() {
-                return WinArgs{words, live.ptr, live.adj, hset, logcap, w, k, xcnt, xadd, rec,
+                return WinArgs{words, live.ptr, live.adj, hset, logcap, w, k, want, rec,
                                rec_cap, {front[0], front[1]}, front_cap, ctl};
             };
             {
@@ -674,7 +697,27 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                         std::fprintf(stderr, "skim window %u: hash set grown to %llu\n", w,
                                      (unsigned long long)ns);
                 }
-                const int batch = f > kSmall ? sh.large_batch : sh.small_batch;
+                int batch = f > kSmall ? sh.large_batch : sh.small_batch;
+                if (sh.sort_frontier && f > sh.sort_frontier) {
+                    // the frontier in pair order: live-list bounds and entries
+                    // are then read nearly sequentially
+                    uint64_t *cur = front[L & 1];
+                    grow_u64(sort_buf, sort_cap, 0, front_cap);
+                    size_t tb = 0;
+                    SKIM_HIP(rocprim::radix_sort_keys(nullptr, tb, cur, sort_buf, (size_t)f, 32,
+                                                      32 + pair_bits, s));
+                    if (tb > sort_tmp_bytes) {
+                        if (sort_tmp) A.release(sort_tmp);
+                        sort_tmp = A.alloc<uint8_t>(tb);
+                        sort_tmp_bytes = tb;
+                    }
+                    SKIM_HIP(rocprim::radix_sort_keys(sort_tmp, tb, cur, sort_buf, (size_t)f, 32,
+                                                      32 + pair_bits, s));
+                    front[L & 1] = sort_buf;  // capacity >= front_cap
+                    sort_buf = cur;
+                    sort_cap = front_cap;
+                    batch = 1;
+                }
                 // room for 64-fold growth at a window's first level and after a
                 // batch over which the frontier grew more than fourfold
                 const bool growing = f_prev == 0 || f > 4 * f_prev;
@@ -711,7 +754,6 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
             if (overflow & kOvfRecords) grow_u64(rec, rec_cap, base.records, 2 * rec_cap);
             SKIM_HIP(hipMemcpyAsync(words, snap, npairs * sizeof(uint64_t),
                                     hipMemcpyDeviceToDevice, s));
-            fill_u32(xadd, 0, n + 1, s);
             if (debug) std::fprintf(stderr, "skim window %u: redo %d\n", w, redo + 1);
         }
         prev_hash = h.hinserts;
@@ -728,7 +770,8 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                                  "table %llu levels %u records %llu\n",
                          w, (unsigned long long)nw, h.visits, h.hinserts,
                          (unsigned long long)hsize, levels_run, h.records);
-        k_fold<<<grid_for(n, kBlock, 8192), kBlock, 0, s>>>(xcnt, xadd, n, k, ctl);
+        fill_u64((uint64_t *)&ctl->full, 0, 1, s);
+        k_want<<<grid_for((uint64_t)n * 8, kBlock, 8192), kBlock, 0, s>>>(words, n, k, want, ctl);
         SKIM_LAUNCH_CHECK();
         ++windows_done;
     }
@@ -741,9 +784,10 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     A.release(front[0]);
     A.release(front[1]);
     if (hset) A.release(hset);
-    uint64_t *goff = A.alloc<uint64_t>((uint64_t)n + 1);
-    exclusive_scan_u32(xcnt, goff, n, A);
     uint64_t *seg = A.alloc<uint64_t>(nrec ? nrec : 1);
+    uint64_t *gstart = A.alloc<uint64_t>(n), *gend = A.alloc<uint64_t>(n);
+    fill_u64(gstart, 0, n, s);
+    fill_u64(gend, 0, n, s);
     if (nrec) {
         // stable radix sort of the records on their node bits
         int nb = 1;
@@ -754,9 +798,14 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
         LaunchTimer t("sort_records", s);
         SKIM_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, rec, seg, (size_t)nrec, 32, 32 + nb, s));
     }
+    if (nrec) {
+        k_bounds<<<grid_for(nrec, kBlock, 65536), kBlock, 0, s>>>(seg, nrec, gstart, gend);
+        SKIM_LAUNCH_CHECK();
+    }
     {
         LaunchTimer t("k_select", s);
-        k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(goff, seg, n, k, seed, ranks_out, size_out);
+        k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(gstart, gend, seg, n, k, seed, ranks_out,
+                                                      size_out);
     }
     SKIM_LAUNCH_CHECK();
     if (work) {
@@ -866,7 +915,7 @@ extern "C" skim_status skim_build_sketches(const skim_graph *g, uint32_t ell, ui
 
 extern "C" skim_status skim_set_build_params(const skim_build_params *p) {
     skim::clear_error();
-    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4};
+    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4, 0};
     if (p) {
         if (p->small_frontier < 1 || p->small_batch < 1 || p->small_batch > 64 ||
             p->large_batch < 1 || p->large_batch > 64 || p->thread_frontier < 1 ||
@@ -930,14 +979,20 @@ extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32
         const uint32_t sb[] = {4, 8, 16};
         const uint32_t lb[] = {2, 3, 4};
         const uint32_t tf[] = {131072, 524288, 2097152};
-        for (int field = 0; field < 4 && st == SKIM_OK; ++field) {
+        const uint32_t so[] = {0, 1u << 20, 1u << 22};
+        for (int field = 0; field < 5 && st == SKIM_OK; ++field) {
             for (int c = 0; c < 3 && st == SKIM_OK; ++c) {
                 skim_build_params p = cur;
-                uint32_t *slot = field == 0 ? &p.small_frontier
+                uint32_t *slot = field == 0   ? &p.small_frontier
                                  : field == 1 ? &p.small_batch
                                  : field == 2 ? &p.large_batch
-                                              : &p.thread_frontier;
-                const uint32_t v = field == 0 ? sf[c] : field == 1 ? sb[c] : field == 2 ? lb[c] : tf[c];
+                                 : field == 3 ? &p.thread_frontier
+                                              : &p.sort_frontier;
+                const uint32_t v = field == 0   ? sf[c]
+                                   : field == 1 ? sb[c]
+                                   : field == 2 ? lb[c]
+                                   : field == 3 ? tf[c]
+                                                : so[c];
                 if (*slot == v) continue;
                 *slot = v;
                 const double t = time_with(p, st);

@@ -162,6 +162,7 @@ void *Arena::get(size_t bytes) {
 }
 
 void Arena::release(void *p) {
+    if (!p) return;
     for (auto &b : bufs_)
         if (b.p == p) {
             if (persistent_) {

@@ -29,7 +29,10 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert sorted(_declared()) == sorted(sk.EXPORTS)
     lib.skim_abi_version.restype = ctypes.c_uint32
-    assert lib.skim_abi_version() == 1
+    import re
+    with open(os.path.join(ROOT, "include", "skim.h")) as f:
+        want = int(re.search(r"#define SKIM_ABI_VERSION (\d+)u", f.read()).group(1))
+    assert lib.skim_abi_version() == want
 
 
 def test_binding_fails_loudly_without_library(tmp_path):

@@ -10,9 +10,10 @@ from gpu_util import gpu_build, log
 
 pytestmark = pytest.mark.gpu
 
-EXTREME = dict(small_frontier=1, small_batch=1, large_batch=1, thread_frontier=1, heavy_visits=1)
+EXTREME = dict(small_frontier=1, small_batch=1, large_batch=1, thread_frontier=1, heavy_visits=1,
+               sort_frontier=1)
 WIDE = dict(small_frontier=1 << 24, small_batch=64, large_batch=64, thread_frontier=1 << 30,
-            heavy_visits=1000)
+            heavy_visits=1000, sort_frontier=0)
 
 
 @pytest.fixture
