@@ -7,8 +7,11 @@
 //  1. Live lists.  One coalesced pass over the edges evaluates every
 //     instance's coin of each edge (a 64-bit instance mask per edge), and
 //     the live in-lists of every node-instance pair p = 64 v + i are
-//     materialised as one CSR (lptr / lsrc).  Every expansion later reads
-//     only live in-edges of its own instance.
+//     materialised as one CSR; each pair's 16-byte record holds its search
+//     state word next to its list (the source itself when the list has one
+//     entry), so a claim reads both in one cache line.  Every expansion
+//     later reads only live in-edges of its own instance, and pairs without
+//     any are never put on a frontier.
 //  2. Rank windows.  All pairs are bucketed by rank into W windows: window 0
 //     holds about k/2 sources per instance, each later window four times as
 //     many ranks as the one before.  Windows are processed in increasing
@@ -49,7 +52,7 @@ void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, u
 
 namespace {
 
-constexpr uint32_t kOvfHash = 2u, kOvfRecords = 4u, kOvfSpill = 8u;
+constexpr uint32_t kOvfHash = 2u, kOvfRecords = 4u, kOvfSpill = 8u, kOvfLiveList = 16u;
 constexpr int kBlock = 256;
 
 // Thrown inside the build when a buffer was too small; the windows restart
@@ -186,10 +189,16 @@ __global__ void k_rehash(const uint64_t *old, uint64_t old_size, uint64_t *T, ui
     }
 }
 
+// Per-pair record, 16 bytes, in one array: the state word (above) and the
+// pair's live in-list, read by the claim in the same cache line.  The list
+// word is 0 for no live in-edge, bit 63 | u for the single source u, else
+// begin << 24 | count into the live-source array.
+constexpr uint64_t kLiveOne = 1ull << 63;
+constexpr uint32_t kLiveCountBits = 24;
+
 struct WinArgs {
-    uint64_t *words;       // [64 n] pair state words
-    const uint64_t *lptr;  // live in-lists
-    const uint32_t *lsrc;
+    uint64_t *prec;        // [2 * 64 n] state word, live-list word per pair
+    const uint32_t *lsrc;  // live sources of lists with two or more entries
     uint64_t *hset;
     uint32_t logcap;
     uint32_t win;          // window id (tag)
@@ -197,22 +206,26 @@ struct WinArgs {
     const uint8_t *want;   // node records its visits in this window (fewer than k so far)
     uint64_t *rec;         // records: (node << 32) | source pair
     uint64_t rec_cap;
-    uint64_t *front[2];    // current / next level: (pair << 32) | source pair
+    uint64_t *fkey[2];     // current / next level: (pair << 32) | source pair
+    uint64_t *flive[2];    // the pair's live-list word
     uint64_t front_cap;
     Ctl *ctl;
 };
 
 // Visit of pair q by the search of source pair src: 1 if it is a new visit
 // (and counts as one more rank received by q), 0 if pruned or repeated.
+// `live` receives q's live-list word.
 __device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
-                                     uint32_t &hashed) {
-    uint64_t old = load_relaxed(A.words + q);
+                                     uint32_t &hashed, uint64_t &live) {
+    uint64_t *rq = A.prec + 2 * (uint64_t)q;
+    uint64_t old = load_relaxed(rq);
+    live = rq[1];  // read-only during the searches
     for (;;) {
         if (prior_count(old, A.win) >= A.k) return 0;  // instance-local sketch full: prune
         if (w_tag(old) != A.win) {
             const uint64_t nw = (uint64_t)src | ((uint64_t)A.win << 32) | (1ull << 40) |
                                 ((uint64_t)prior_count(old, A.win) << 52);
-            const uint64_t prev = atomicCAS((unsigned long long *)(A.words + q), old, nw);
+            const uint64_t prev = atomicCAS((unsigned long long *)rq, old, nw);
             if (prev == old) return 1;
             old = prev;
             continue;
@@ -227,7 +240,7 @@ __device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
         // 12-bit arrival field (4096 arrivals) turns into +1 on cnt, and cnt
         // itself can wrap: both only ever undercount, which can only weaken
         // pruning, never make it wrong.
-        atomicAdd((unsigned long long *)(A.words + q), 1ull << 40);
+        atomicAdd((unsigned long long *)rq, 1ull << 40);
         ++hashed;
         return 1;
     }
@@ -240,46 +253,77 @@ __device__ __forceinline__ bool wants_record(const WinArgs &A, uint32_t v) {
 
 // ------------------------------------ 3. level-synchronous window search
 // Block-aggregated appends: threads stage new entries in LDS; one global
-// reservation per flush moves them to the output array (coalesced).
-constexpr uint32_t kChunk = 1024;  // frontier entries per block per round
-constexpr uint32_t kStage = 2040;  // staged outputs per round (5 workgroups fit in 160 KiB of LDS)
+// reservation per flush moves them to the output arrays (coalesced).
+constexpr uint32_t kChunk = 1024;   // frontier entries per block per round
+constexpr uint32_t kStageF = 1024;  // staged frontier entries per round (16 bytes each)
+constexpr uint32_t kStageR = 2040;  // staged records per round (5 workgroups fit in LDS)
 
-struct Stage {
-    uint64_t buf[kStage];
+struct StageF {
+    uint64_t key[kStageF];
+    uint64_t live[kStageF];
     uint32_t n;
     unsigned long long base;
 };
 
-__device__ __forceinline__ void stage_push(Stage &S, uint64_t v, uint64_t *out, uint64_t cap,
-                                           unsigned long long *count, uint32_t *flags,
-                                           uint32_t ovf_bit) {
+struct StageR {
+    uint64_t buf[kStageR];
+    uint32_t n;
+    unsigned long long base;
+};
+
+// Frontier entries carry the pair's live-list word; pairs without live
+// in-edges have nothing to expand and are not appended.
+__device__ __forceinline__ void push_front(StageF &S, uint64_t key, uint64_t live, uint64_t *okey,
+                                           uint64_t *olive, uint64_t cap,
+                                           unsigned long long *count, uint32_t *flags) {
     const uint32_t pos = atomicAdd(&S.n, 1u);
-    if (pos < kStage) {
+    if (pos < kStageF) {
+        S.key[pos] = key;
+        S.live[pos] = live;
+        return;
+    }
+    const unsigned long long g = atomicAdd(count, 1ull);  // rare: stage full
+    if (g < cap) {
+        okey[g] = key;
+        olive[g] = live;
+    } else {
+        atomicOr(flags, kOvfSpill);
+    }
+}
+
+__device__ __forceinline__ void push_record(StageR &S, uint64_t v, uint64_t *out, uint64_t cap,
+                                            unsigned long long *count, uint32_t *flags) {
+    const uint32_t pos = atomicAdd(&S.n, 1u);
+    if (pos < kStageR) {
         S.buf[pos] = v;
         return;
     }
     const unsigned long long g = atomicAdd(count, 1ull);  // rare: stage full
     if (g < cap) out[g] = v;
-    else atomicOr(flags, ovf_bit);
+    else atomicOr(flags, kOvfRecords);
 }
 
 // Flush both stages; the two reservations are issued by different waves so
 // they are in flight together.  Called by every thread of the block.
-__device__ __forceinline__ void stage_flush2(Stage &F, uint64_t *fout, uint64_t fcap,
-                                             unsigned long long *fcount, Stage &R, uint64_t *rout,
-                                             uint64_t rcap, unsigned long long *rcount,
-                                             uint32_t *flags) {
+__device__ __forceinline__ void stage_flush2(StageF &F, uint64_t *okey, uint64_t *olive,
+                                             uint64_t fcap, unsigned long long *fcount, StageR &R,
+                                             uint64_t *rout, uint64_t rcap,
+                                             unsigned long long *rcount, uint32_t *flags) {
     __syncthreads();
-    const uint32_t mf = F.n < kStage ? F.n : kStage;
-    const uint32_t mr = R.n < kStage ? R.n : kStage;
+    const uint32_t mf = F.n < kStageF ? F.n : kStageF;
+    const uint32_t mr = R.n < kStageR ? R.n : kStageR;
     if (threadIdx.x == 0) F.base = mf ? atomicAdd(fcount, (unsigned long long)mf) : 0;
     if (threadIdx.x == 64) R.base = mr ? atomicAdd(rcount, (unsigned long long)mr) : 0;
     __syncthreads();
     const unsigned long long fb = F.base, rb = R.base;
     if (threadIdx.x == 0 && mf && fb + mf > fcap) atomicOr(flags, kOvfSpill);
     if (threadIdx.x == 64 && mr && rb + mr > rcap) atomicOr(flags, kOvfRecords);
-    for (uint32_t j = threadIdx.x; j < mf; j += blockDim.x)
-        if (fb + j < fcap) fout[fb + j] = F.buf[j];
+    for (uint32_t j = threadIdx.x; j < mf; j += blockDim.x) {
+        if (fb + j < fcap) {
+            okey[fb + j] = F.key[j];
+            olive[fb + j] = F.live[j];
+        }
+    }
     for (uint32_t j = threadIdx.x; j < mr; j += blockDim.x)
         if (rb + j < rcap) rout[rb + j] = R.buf[j];
     __syncthreads();
@@ -287,44 +331,62 @@ __device__ __forceinline__ void stage_flush2(Stage &F, uint64_t *fout, uint64_t 
     __syncthreads();
 }
 
-// Expand cur[0, b) (already claimed and recorded) over live in-edges; new
-// visits are recorded and appended to next (counted in *next_count).
-__device__ __forceinline__ void expand_range(const WinArgs &A, const uint64_t *cur, uint64_t *next,
+struct ExpandShared {
+    StageF F;
+    StageR R;
+};
+
+// One live in-edge w -> v of the expanded pair (v, i), taken by the search
+// of source pair src.
+__device__ __forceinline__ void visit_edge(const WinArgs &A, uint32_t w, uint32_t i, uint32_t src,
+                                           uint64_t *nkey, uint64_t *nlive,
+                                           unsigned long long *next_count, ExpandShared &X,
+                                           uint32_t &scans, uint32_t &hashed, uint32_t &visits) {
+    const uint32_t q = w * kPairStride + i;
+    ++scans;
+    uint64_t live;
+    if (claim(A, q, src, hashed, live) == 1) {
+        ++visits;
+        if (live)
+            push_front(X.F, ((uint64_t)q << 32) | src, live, nkey, nlive, A.front_cap, next_count,
+                       &A.ctl->flags);
+        if (wants_record(A, w))
+            push_record(X.R, ((uint64_t)w << 32) | src, A.rec, A.rec_cap, &A.ctl->records,
+                        &A.ctl->flags);
+    }
+}
+
+// Expand the current level's entries [0, b) (already claimed and recorded)
+// over their live in-edges; new visits are recorded and appended to the
+// next level (counted in *next_count).
+__device__ __forceinline__ void expand_range(const WinArgs &A, uint32_t L,
                                              unsigned long long *next_count, uint64_t b,
-                                             uint32_t chunk, Stage &F, Stage &R, uint32_t &scans,
+                                             uint32_t chunk, ExpandShared &X, uint32_t &scans,
                                              uint32_t &hashed, uint32_t &visits) {
+    const uint64_t *ckey = A.fkey[L & 1], *clive = A.flive[L & 1];
+    uint64_t *nkey = A.fkey[(L + 1) & 1], *nlive = A.flive[(L + 1) & 1];
     const uint64_t stride = (uint64_t)gridDim.x * chunk;
     for (uint64_t c = (uint64_t)blockIdx.x * chunk; c < b; c += stride) {
         const uint64_t end = c + chunk < b ? c + chunk : b;
         for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
-            const uint64_t it = cur[t];
-            const uint32_t p = (uint32_t)(it >> 32);
+            const uint64_t it = ckey[t], live = clive[t];
+            const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
             const uint32_t src = (uint32_t)it;
-            const uint32_t i = p % kPairStride;
-            const uint64_t e1 = A.lptr[p + 1];
-            for (uint64_t e = A.lptr[p]; e < e1; ++e) {
-                const uint32_t w = A.lsrc[e];
-                const uint32_t q = w * kPairStride + i;
-                ++scans;
-                if (claim(A, q, src, hashed) == 1) {
-                    ++visits;
-                    stage_push(F, ((uint64_t)q << 32) | src, next, A.front_cap, next_count,
-                               &A.ctl->flags, kOvfSpill);
-                    if (wants_record(A, w)) {
-                        stage_push(R, ((uint64_t)w << 32) | src, A.rec, A.rec_cap,
-                                   &A.ctl->records, &A.ctl->flags, kOvfRecords);
-                    }
-                }
+            if (live & kLiveOne) {
+                visit_edge(A, (uint32_t)live, i, src, nkey, nlive, next_count, X, scans, hashed,
+                           visits);
+            } else {
+                const uint64_t e0 = live >> kLiveCountBits;
+                const uint64_t e1 = e0 + (live & ((1u << kLiveCountBits) - 1));
+                for (uint64_t e = e0; e < e1; ++e)
+                    visit_edge(A, A.lsrc[e], i, src, nkey, nlive, next_count, X, scans, hashed,
+                               visits);
             }
         }
-        stage_flush2(F, next, A.front_cap, next_count, R, A.rec, A.rec_cap, &A.ctl->records,
-                     &A.ctl->flags);
+        stage_flush2(X.F, nkey, nlive, A.front_cap, next_count, X.R, A.rec, A.rec_cap,
+                     &A.ctl->records, &A.ctl->flags);
     }
 }
-
-struct ExpandShared {
-    Stage F, R;
-};
 
 // Level 0: the window's sources visit their own pairs.  Each source pair is
 // reached only by its own source at this point, so the claim is a store.
@@ -339,22 +401,22 @@ __global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_
         const uint64_t end = c + kChunk < we ? c + kChunk : we;
         for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
             const uint32_t p = sources[t];
-            const uint64_t old = A.words[p];
+            uint64_t *rp = A.prec + 2 * (uint64_t)p;
+            const uint64_t old = rp[0], live = rp[1];
             const uint32_t prior = prior_count(old, A.win);
             if (prior >= A.k) continue;  // pruned
-            A.words[p] = (uint64_t)p | ((uint64_t)A.win << 32) | (1ull << 40) |
-                         ((uint64_t)prior << 52);
+            rp[0] = (uint64_t)p | ((uint64_t)A.win << 32) | (1ull << 40) | ((uint64_t)prior << 52);
             ++visits;
-            stage_push(X.F, ((uint64_t)p << 32) | p, A.front[0], A.front_cap, &A.ctl->size[0],
-                       &A.ctl->flags, kOvfSpill);
+            if (live)
+                push_front(X.F, ((uint64_t)p << 32) | p, live, A.fkey[0], A.flive[0], A.front_cap,
+                           &A.ctl->size[0], &A.ctl->flags);
             const uint32_t v = p / kPairStride;
-            if (wants_record(A, v)) {
-                stage_push(X.R, ((uint64_t)v << 32) | p, A.rec, A.rec_cap, &A.ctl->records,
-                           &A.ctl->flags, kOvfRecords);
-            }
+            if (wants_record(A, v))
+                push_record(X.R, ((uint64_t)v << 32) | p, A.rec, A.rec_cap, &A.ctl->records,
+                            &A.ctl->flags);
         }
-        stage_flush2(X.F, A.front[0], A.front_cap, &A.ctl->size[0], X.R, A.rec, A.rec_cap,
-                     &A.ctl->records, &A.ctl->flags);
+        stage_flush2(X.F, A.fkey[0], A.flive[0], A.front_cap, &A.ctl->size[0], X.R, A.rec,
+                     A.rec_cap, &A.ctl->records, &A.ctl->flags);
     }
     wave_add(&A.ctl->visits, visits);
 }
@@ -374,12 +436,30 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32
     __syncthreads();
     uint32_t scans = 0, hashed = 0, visits = 0;
     if (!s_flags && s_size) {  // after an overflow the windows are redone with more room
-        expand_range(A, A.front[L & 1], A.front[(L + 1) & 1], &A.ctl->size[(L + 1) % 3], s_size,
-                     chunk, X.F, X.R, scans, hashed, visits);
+        expand_range(A, L, &A.ctl->size[(L + 1) % 3], s_size, chunk, X, scans, hashed, visits);
     }
     wave_add(&A.ctl->scans, scans);
     wave_add(&A.ctl->hinserts, hashed);
     wave_add(&A.ctl->visits, visits);
+}
+
+// Pair records at the start of a build: the initial state word and the
+// live-list word of every pair (from the CSR of live in-lists).
+__global__ void k_pair_init(const uint64_t *lptr, const uint32_t *lsrc, uint64_t npairs,
+                            uint64_t *prec, uint32_t *flags) {
+    for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < npairs;
+         q += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t b = lptr[q], c = lptr[q + 1] - b;
+        uint64_t live = 0;
+        if (c == 1) {
+            live = kLiveOne | lsrc[b];
+        } else if (c > 1) {
+            if (c >> kLiveCountBits) atomicOr(flags, kOvfLiveList);
+            live = (b << kLiveCountBits) | c;
+        }
+        prec[2 * q] = kWordInit;
+        prec[2 * q + 1] = live;
+    }
 }
 
 // Start of a window (or of its redo): clear the per-window fields and set
@@ -407,16 +487,17 @@ __global__ void k_set_bases(unsigned long long *dst, WinBases wb) {
 // After a window: want[v] = 1 while node v has received fewer than k ranks
 // in all, summed over its 64 pairs (each pair's count undercounts at worst,
 // so a node never stops recording too early); ctl->full counts the others.
-// Eight lanes per node, each summing eight consecutive state words.
-__global__ void k_want(const uint64_t *words, uint32_t n, uint32_t k, uint8_t *want, Ctl *ctl) {
+// Eight lanes per node, each summing the state words of eight consecutive
+// pairs.
+__global__ void k_want(const uint64_t *prec, uint32_t n, uint32_t k, uint8_t *want, Ctl *ctl) {
     uint32_t full = 0;
     const uint64_t lanes = (uint64_t)n * 8;
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ((lanes + 63) & ~63ull);
          t += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t c = 0;
         if (t < lanes) {
-            const uint64_t *wv = words + t * 8;
-            for (int j = 0; j < 8; ++j) c += prior_count(wv[j], 0xFEu);
+            const uint64_t *wv = prec + t * 16;
+            for (int j = 0; j < 8; ++j) c += prior_count(wv[2 * j], 0xFEu);
         }
         c += __shfl_xor(c, 1);
         c += __shfl_xor(c, 2);
@@ -553,21 +634,24 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     hipStream_t s = A.stream();
     const uint32_t n = g->n;
     const uint64_t npairs = (uint64_t)n * kPairStride;
-    uint64_t *words = A.alloc<uint64_t>(npairs);
-    fill_u64(words, kWordInit, npairs, s);
-    uint8_t *want = A.alloc<uint8_t>((uint64_t)n + 4);
-    fill_u32((uint32_t *)want, 0x01010101u, (n + 3) / 4, s);  // no records yet: all record
     Ctl *ctl = A.alloc<Ctl>(1);
     fill_u64((uint64_t *)ctl, 0, sizeof(Ctl) / 8, s);
+    uint64_t *prec = A.alloc<uint64_t>(2 * npairs);
+    k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(live.ptr, live.adj, npairs, prec,
+                                                                  &ctl->flags);
+    SKIM_LAUNCH_CHECK();
+    uint8_t *want = A.alloc<uint8_t>((uint64_t)n + 4);
+    fill_u32((uint32_t *)want, 0x01010101u, (n + 3) / 4, s);  // no records yet: all record
     uint64_t rec_cap = cap.rec, front_cap = cap.front;
     uint64_t *rec = A.alloc<uint64_t>(rec_cap);
-    uint64_t *front[2] = {A.alloc<uint64_t>(front_cap), A.alloc<uint64_t>(front_cap)};
+    uint64_t *fkey[2] = {A.alloc<uint64_t>(front_cap), A.alloc<uint64_t>(front_cap)};
+    uint64_t *flive[2] = {A.alloc<uint64_t>(front_cap), A.alloc<uint64_t>(front_cap)};
     // The hash set is allocated once for up to 2^29 entries (4 GiB) and only
     // reallocated by windows that need more.
     uint64_t hset_size = std::min<uint64_t>(cap.hash, 1ull << 29);
     uint64_t *hset = A.alloc<uint64_t>(hset_size);
-    uint64_t *snap = nullptr;  // pair states at the start of a guarded window
-    uint64_t *sort_buf = nullptr, sort_cap = 0;  // frontier sorting (sort_frontier)
+    uint64_t *snap = nullptr;  // pair records at the start of a guarded window
+    uint64_t *sort_key = nullptr, *sort_live = nullptr, sort_cap = 0;  // sort_frontier
     uint8_t *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
     int pair_bits = 1;
@@ -623,8 +707,8 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
         // what a restart does.)
         const bool guard = w > 0 && span_next == 1;
         if (guard) {
-            if (!snap) snap = A.alloc<uint64_t>(npairs);
-            SKIM_HIP(hipMemcpyAsync(snap, words, npairs * sizeof(uint64_t),
+            if (!snap) snap = A.alloc<uint64_t>(2 * npairs);
+            SKIM_HIP(hipMemcpyAsync(snap, prec, 2 * npairs * sizeof(uint64_t),
                                     hipMemcpyDeviceToDevice, s));
         }
         const Ctl base = h;  // counters at the window start
@@ -640,8 +724,11 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
             k_ctl_begin<<<1, 1, 0, s>>>(ctl, base.visits, base.scans, base.records);
             SKIM_LAUNCH_CHECK();
             auto args = [&]() {
-                return WinArgs{words, live.ptr, live.adj, hset, logcap, w, k, want, rec,
-                               rec_cap, {front[0], front[1]}, front_cap, ctl};
+                return WinArgs{prec,    live.adj, hset,
+                               logcap,  w,        k,
+                               want,    rec,      rec_cap,
+                               {fkey[0], fkey[1]}, {flive[0], flive[1]}, front_cap,
+                               ctl};
             };
             {
                 const WinArgs WA = args();
@@ -671,13 +758,12 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                 // 40% full.  A level that still overflows is redone with the
                 // window (guarded windows) or with all windows.
                 {
-                    uint64_t *cur = front[L & 1], *nxt = front[(L + 1) & 1];
-                    uint64_t c0 = front_cap, c1 = front_cap;
-                    grow_u64(cur, c0, f, kGrow * f);
-                    grow_u64(nxt, c1, 0, kGrow * f);
-                    front[L & 1] = cur;
-                    front[(L + 1) & 1] = nxt;
-                    front_cap = std::min(c0, c1);
+                    uint64_t c[4] = {front_cap, front_cap, front_cap, front_cap};
+                    grow_u64(fkey[L & 1], c[0], f, kGrow * f);
+                    grow_u64(flive[L & 1], c[1], f, kGrow * f);
+                    grow_u64(fkey[(L + 1) & 1], c[2], 0, kGrow * f);
+                    grow_u64(flive[(L + 1) & 1], c[3], 0, kGrow * f);
+                    front_cap = std::min(std::min(c[0], c[1]), std::min(c[2], c[3]));
                 }
                 grow_u64(rec, rec_cap, h.records, h.records + kGrow * f);
                 if (5 * h.hinserts > 2 * hsize) {
@@ -701,20 +787,23 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                 if (sh.sort_frontier && f > sh.sort_frontier) {
                     // the frontier in pair order: live-list bounds and entries
                     // are then read nearly sequentially
-                    uint64_t *cur = front[L & 1];
-                    grow_u64(sort_buf, sort_cap, 0, front_cap);
+                    uint64_t sc0 = sort_cap, sc1 = sort_cap;
+                    grow_u64(sort_key, sc0, 0, front_cap);
+                    grow_u64(sort_live, sc1, 0, front_cap);
                     size_t tb = 0;
-                    SKIM_HIP(rocprim::radix_sort_keys(nullptr, tb, cur, sort_buf, (size_t)f, 32,
-                                                      32 + pair_bits, s));
+                    SKIM_HIP(rocprim::radix_sort_pairs(nullptr, tb, fkey[L & 1], sort_key,
+                                                       flive[L & 1], sort_live, (size_t)f, 32,
+                                                       32 + pair_bits, s));
                     if (tb > sort_tmp_bytes) {
                         if (sort_tmp) A.release(sort_tmp);
                         sort_tmp = A.alloc<uint8_t>(tb);
                         sort_tmp_bytes = tb;
                     }
-                    SKIM_HIP(rocprim::radix_sort_keys(sort_tmp, tb, cur, sort_buf, (size_t)f, 32,
-                                                      32 + pair_bits, s));
-                    front[L & 1] = sort_buf;  // capacity >= front_cap
-                    sort_buf = cur;
+                    SKIM_HIP(rocprim::radix_sort_pairs(sort_tmp, tb, fkey[L & 1], sort_key,
+                                                       flive[L & 1], sort_live, (size_t)f, 32,
+                                                       32 + pair_bits, s));
+                    std::swap(fkey[L & 1], sort_key);  // capacities >= front_cap
+                    std::swap(flive[L & 1], sort_live);
                     sort_cap = front_cap;
                     batch = 1;
                 }
@@ -746,13 +835,15 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
             if (overflow & kOvfHash) hsize = std::max(16 * hsize, next_pow2(4 * h.hinserts));
             if (overflow & kOvfSpill) {
                 const uint64_t nc = 2 * front_cap;
-                uint64_t c0 = front_cap, c1 = front_cap;
-                grow_u64(front[0], c0, 0, nc);
-                grow_u64(front[1], c1, 0, nc);
-                front_cap = std::min(c0, c1);
+                uint64_t c[4] = {front_cap, front_cap, front_cap, front_cap};
+                grow_u64(fkey[0], c[0], 0, nc);
+                grow_u64(fkey[1], c[1], 0, nc);
+                grow_u64(flive[0], c[2], 0, nc);
+                grow_u64(flive[1], c[3], 0, nc);
+                front_cap = std::min(std::min(c[0], c[1]), std::min(c[2], c[3]));
             }
             if (overflow & kOvfRecords) grow_u64(rec, rec_cap, base.records, 2 * rec_cap);
-            SKIM_HIP(hipMemcpyAsync(words, snap, npairs * sizeof(uint64_t),
+            SKIM_HIP(hipMemcpyAsync(prec, snap, 2 * npairs * sizeof(uint64_t),
                                     hipMemcpyDeviceToDevice, s));
             if (debug) std::fprintf(stderr, "skim window %u: redo %d\n", w, redo + 1);
         }
@@ -771,7 +862,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                          w, (unsigned long long)nw, h.visits, h.hinserts,
                          (unsigned long long)hsize, levels_run, h.records);
         fill_u64((uint64_t *)&ctl->full, 0, 1, s);
-        k_want<<<grid_for((uint64_t)n * 8, kBlock, 8192), kBlock, 0, s>>>(words, n, k, want, ctl);
+        k_want<<<grid_for((uint64_t)n * 8, kBlock, 8192), kBlock, 0, s>>>(prec, n, k, want, ctl);
         SKIM_LAUNCH_CHECK();
         ++windows_done;
     }
@@ -780,9 +871,11 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     const uint64_t nrec = h.records;
 
     // ---- 5. merge: group records by node, keep the k smallest
-    A.release(words);
-    A.release(front[0]);
-    A.release(front[1]);
+    A.release(prec);
+    for (int j = 0; j < 2; ++j) {
+        A.release(fkey[j]);
+        A.release(flive[j]);
+    }
     if (hset) A.release(hset);
     uint64_t *seg = A.alloc<uint64_t>(nrec ? nrec : 1);
     uint64_t *gstart = A.alloc<uint64_t>(n), *gend = A.alloc<uint64_t>(n);
@@ -834,6 +927,11 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     // ---- 1. live lists (reverse: in-edges of every pair)
     LiveLists live = build_live_lists(g, ell, seed, esrc, /*forward=*/false, A);
     A.release(esrc);
+    if (live.nlive >> (64 - 1 - kLiveCountBits)) {
+        set_error("%llu live edges exceed the pair records' list offsets",
+                  (unsigned long long)live.nlive);
+        throw Fail{SKIM_EUNSUPPORTED};
+    }
 
     // ---- 2. rank buckets
     uint32_t W = 1, b0 = 64;  // W: number of buckets
@@ -875,6 +973,10 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
             break;
         } catch (const Retry &r) {
             retry_flags |= r.flags;
+            if (r.flags & kOvfLiveList) {
+                set_error("a pair has 2^%u or more live in-edges", kLiveCountBits);
+                throw Fail{SKIM_EUNSUPPORTED};
+            }
             if (std::getenv("SKIM_DEBUG"))
                 std::fprintf(stderr, "skim restart %d: flags %u\n", attempt, r.flags);
             if (attempt >= 6) {
