@@ -12,10 +12,14 @@
 //     entry), so a claim reads both in one cache line.  Every expansion
 //     later reads only live in-edges of its own instance, and pairs without
 //     any are never put on a frontier.
-//  2. Rank windows.  All pairs are bucketed by rank into W windows: window 0
-//     holds about k/2 sources per instance, each later window four times as
-//     many ranks as the one before.  Windows are processed in increasing
-//     order.
+//  2. Rank windows.  All pairs are bucketed by the bit length of their
+//     rank: bucket 0 holds about k/2 ranks per instance and each later
+//     bucket doubles the rank range.  A window is a run of buckets: the
+//     first one several (a pair is pruned only once it has received k
+//     ranks, so merging the early windows costs few extra visits and saves
+//     their search levels), later ones
+//     two at a time, or one after a window with many visits per pair.
+//     Windows are processed in increasing order.
 //  3. Pruned reverse searches, window by window.  Every source pair (u, i)
 //     of the window runs a reverse search in G^(i).  A visited pair (w, i)
 //     is pruned when it received k ranks in earlier windows (the paper's
@@ -23,12 +27,12 @@
 //     path to an unpruned pair reaches a subset of what it reaches, an
 //     unpruned pair receives every rank of its instance in the window, so
 //     the rule is exact whatever order the window's searches run in.  All
-//     searches of a window advance together, level by level (whole-grid
-//     launches for large frontiers, one workgroup looping over levels for
-//     small ones).  Visits are deduplicated per source exactly: the first
-//     visitor of a pair in the window claims the pair's state word; later
-//     visitors go through a hash set keyed by (pair, source).  The same word
-//     counts the pair's arrivals.
+//     searches of a window advance together, level by level, one whole-grid
+//     launch per level (levels of small frontiers are launched in batches
+//     without reading their sizes back).  Visits are deduplicated per source
+//     exactly: the first visitor of a pair in the window claims the pair's
+//     state word; later visitors go through a hash set keyed by (pair,
+//     source).  The same word counts the pair's arrivals.
 //  4. Records.  A visit of node v is recorded while v held fewer than k
 //     ranks at the window start; windows go up in rank, so the k smallest
 //     records of v are its sketch.
@@ -601,10 +605,11 @@ struct Shapes {
     uint64_t thread_frontier = (uint64_t)kBlock * 2048;
     double heavy = 4.0;
     uint64_t sort_frontier = 0;  // 0: never sort
+    uint32_t first_window = 5;   // buckets in window 0
 };
 
 std::mutex g_shapes_mu;
-skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0};
+skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0, 5};
 
 Shapes current_shapes() {
     std::lock_guard<std::mutex> lk(g_shapes_mu);
@@ -615,6 +620,7 @@ Shapes current_shapes() {
     sh.thread_frontier = g_params.thread_frontier;
     sh.heavy = (double)g_params.heavy_visits;
     sh.sort_frontier = g_params.sort_frontier;
+    sh.first_window = g_params.first_window;
     return sh;
 }
 
@@ -677,15 +683,16 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
         capacity = nc;
     };
     Ctl h;
-    // Window w covers buckets [bb, be): bucket 0 alone, then two buckets (a
-    // fourfold rank range) at a time, or one (twofold) after a window whose
-    // visited pairs took more than kHeavy visits each on average (large
-    // reach sets: a smaller step keeps the visits past k in check).
+    // Window w covers buckets [bb, be): the first sh.first_window buckets,
+    // then two buckets (a fourfold rank range) at a time, or one (twofold)
+    // after a window whose visited pairs took more than kHeavy visits each
+    // on average (large reach sets: a smaller step keeps the visits past k
+    // in check).
     const double kHeavy = sh.heavy;
     uint64_t prev_visits = 0;
     uint32_t span = 1, span_next = 2;
     for (uint32_t w = 0, bb = 0; bb < W && w < 255; ++w, bb += span) {
-        span = std::min<uint32_t>(w == 0 ? 1u : span_next, W - bb);
+        span = std::min<uint32_t>(w == 0 ? sh.first_window : span_next, W - bb);
         const uint64_t ws = wb[bb], we = wb[bb + span];
         read_back(&h, ctl, sizeof h, s);
         if (h.flags) throw Retry{h.flags};
@@ -1017,11 +1024,11 @@ extern "C" skim_status skim_build_sketches(const skim_graph *g, uint32_t ell, ui
 
 extern "C" skim_status skim_set_build_params(const skim_build_params *p) {
     skim::clear_error();
-    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4, 0};
+    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4, 0, 5};
     if (p) {
         if (p->small_frontier < 1 || p->small_batch < 1 || p->small_batch > 64 ||
             p->large_batch < 1 || p->large_batch > 64 || p->thread_frontier < 1 ||
-            p->heavy_visits < 1) {
+            p->heavy_visits < 1 || p->first_window < 1 || p->first_window > 16) {
             skim::set_error("build parameters out of range");
             return SKIM_EINVAL;
         }
@@ -1082,19 +1089,22 @@ extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32
         const uint32_t lb[] = {2, 3, 4};
         const uint32_t tf[] = {131072, 524288, 2097152};
         const uint32_t so[] = {0, 1u << 20, 1u << 22};
-        for (int field = 0; field < 5 && st == SKIM_OK; ++field) {
+        const uint32_t fw[] = {3, 5, 7};
+        for (int field = 0; field < 6 && st == SKIM_OK; ++field) {
             for (int c = 0; c < 3 && st == SKIM_OK; ++c) {
                 skim_build_params p = cur;
                 uint32_t *slot = field == 0   ? &p.small_frontier
                                  : field == 1 ? &p.small_batch
                                  : field == 2 ? &p.large_batch
                                  : field == 3 ? &p.thread_frontier
-                                              : &p.sort_frontier;
+                                 : field == 4 ? &p.sort_frontier
+                                              : &p.first_window;
                 const uint32_t v = field == 0   ? sf[c]
                                    : field == 1 ? sb[c]
                                    : field == 2 ? lb[c]
                                    : field == 3 ? tf[c]
-                                                : so[c];
+                                   : field == 4 ? so[c]
+                                                : fw[c];
                 if (*slot == v) continue;
                 *slot = v;
                 const double t = time_with(p, st);
