@@ -264,13 +264,11 @@ skim_status skim_server_replay(skim_server *server, uint64_t q, const uint64_t *
  *   sort_frontier    frontiers of more than this many entries are sorted by
  *                    pair before they are expanded, so that live lists are
  *                    read in order (0 = never, the default);
- *   first_window     rank buckets in the first window (default 5, 1..16):
- *                    bucket 0 holds about k/2 ranks per instance and each
- *                    later bucket doubles the rank range, so the default
- *                    first window holds about 8k ranks per instance.  While
- *                    no pair can have received k ranks yet, one wide window
- *                    does the same visits as several narrow ones in fewer
- *                    search levels.
+ *   window_span      rank buckets per window after a window with few visits
+ *                    per pair (default 2, 1..8); bucket 0 holds about k/2
+ *                    ranks per instance and each later bucket doubles the
+ *                    rank range.  Wider windows mean fewer search levels and
+ *                    more visits past k.
  * skim_set_build_params(NULL) restores the defaults; fields out of range give
  * SKIM_EINVAL and change nothing.
  */
@@ -281,7 +279,7 @@ typedef struct {
     uint32_t thread_frontier;
     uint32_t heavy_visits;
     uint32_t sort_frontier;
-    uint32_t first_window;
+    uint32_t window_span;
 } skim_build_params;
 
 skim_status skim_set_build_params(const skim_build_params *params);
@@ -292,7 +290,7 @@ void skim_get_build_params(skim_build_params *params);
  * seed) into ranks/size (device, as for skim_build_sketches) with the
  * current parameters and then with candidate values of one parameter at a
  * time (coordinate descent over small_frontier, small_batch, large_batch,
- * thread_frontier, sort_frontier, first_window), each timed as the best of `reps` builds
+ * thread_frontier, sort_frontier, window_span), each timed as the best of `reps` builds
  * with HIP events on `stream` after one warm-up build.  The fastest set becomes the current
  * parameters and is written to *best (HOST); *best_ms and *start_ms (HOST,
  * may be NULL) receive its time and that of the parameters in force at the

@@ -14,11 +14,12 @@
 //     any are never put on a frontier.
 //  2. Rank windows.  All pairs are bucketed by the bit length of their
 //     rank: bucket 0 holds about k/2 ranks per instance and each later
-//     bucket doubles the rank range.  A window is a run of buckets: the
-//     first one several (a pair is pruned only once it has received k
-//     ranks, so merging the early windows costs few extra visits and saves
-//     their search levels), later ones
-//     two at a time, or one after a window with many visits per pair.
+//     bucket doubles the rank range.  A window is a run of buckets: bucket
+//     0 alone, then as many as keep the arrivals per pair (measured on
+//     bucket 0) below k (a pair is pruned only once it has received k
+//     ranks, so merging those buckets costs few extra visits and saves
+//     search levels), later ones two at a time, or one after a window with
+//     many visits per pair.
 //     Windows are processed in increasing order.
 //  3. Pruned reverse searches, window by window.  Every source pair (u, i)
 //     of the window runs a reverse search in G^(i).  A visited pair (w, i)
@@ -44,6 +45,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
+#include <chrono>
 #include <cstdlib>
 #include <mutex>
 #include <string>
@@ -207,6 +209,7 @@ struct WinArgs {
     uint32_t logcap;
     uint32_t win;          // window id (tag)
     uint32_t k;
+    uint32_t last;         // last window: its arrivals are never read
     const uint8_t *want;   // node records its visits in this window (fewer than k so far)
     uint64_t *rec;         // records: (node << 32) | source pair
     uint64_t rec_cap;
@@ -243,8 +246,8 @@ __device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
         // One more source reached q in this window.  A carry out of the
         // 12-bit arrival field (4096 arrivals) turns into +1 on cnt, and cnt
         // itself can wrap: both only ever undercount, which can only weaken
-        // pruning, never make it wrong.
-        atomicAdd((unsigned long long *)rq, 1ull << 40);
+        // pruning, never make it wrong.  Arrivals only serve later windows.
+        if (!A.last) atomicAdd((unsigned long long *)rq, 1ull << 40);
         ++hashed;
         return 1;
     }
@@ -260,7 +263,9 @@ __device__ __forceinline__ bool wants_record(const WinArgs &A, uint32_t v) {
 // reservation per flush moves them to the output arrays (coalesced).
 constexpr uint32_t kChunk = 1024;   // frontier entries per block per round
 constexpr uint32_t kStageF = 1024;  // staged frontier entries per round (16 bytes each)
-constexpr uint32_t kStageR = 2040;  // staged records per round (5 workgroups fit in LDS)
+constexpr uint32_t kStageR = 1912;  // staged records per round (5 workgroups fit in LDS)
+constexpr uint32_t kHeavyCap = 256;  // long live lists per round expanded by the whole block
+constexpr uint32_t kSerialEdges = 16;  // longer lists go to the block
 
 struct StageF {
     uint64_t key[kStageF];
@@ -275,18 +280,31 @@ struct StageR {
     unsigned long long base;
 };
 
+// Stage slots are handed out per wave (one LDS atomic for all lanes that
+// push at once); when a stage is full the overflowing lanes reserve their
+// output slots per wave as well, so a burst of outputs (a hub's in-edges)
+// does not serialise on one global counter.
+__device__ __forceinline__ uint32_t stage_slots(uint32_t *n) {
+    const unsigned long long act = __ballot(1);
+    const int leader = __ffsll((long long)act) - 1;
+    const uint32_t lane = lane_id();
+    uint32_t pos0 = 0;
+    if ((int)lane == leader) pos0 = atomicAdd(n, (uint32_t)__popcll(act));
+    return __shfl(pos0, leader) + (uint32_t)__popcll(act & ((1ull << lane) - 1ull));
+}
+
 // Frontier entries carry the pair's live-list word; pairs without live
 // in-edges have nothing to expand and are not appended.
 __device__ __forceinline__ void push_front(StageF &S, uint64_t key, uint64_t live, uint64_t *okey,
                                            uint64_t *olive, uint64_t cap,
                                            unsigned long long *count, uint32_t *flags) {
-    const uint32_t pos = atomicAdd(&S.n, 1u);
+    const uint32_t pos = stage_slots(&S.n);
     if (pos < kStageF) {
         S.key[pos] = key;
         S.live[pos] = live;
         return;
     }
-    const unsigned long long g = atomicAdd(count, 1ull);  // rare: stage full
+    const uint64_t g = wave_reserve(count, true);  // stage full
     if (g < cap) {
         okey[g] = key;
         olive[g] = live;
@@ -297,12 +315,12 @@ __device__ __forceinline__ void push_front(StageF &S, uint64_t key, uint64_t liv
 
 __device__ __forceinline__ void push_record(StageR &S, uint64_t v, uint64_t *out, uint64_t cap,
                                             unsigned long long *count, uint32_t *flags) {
-    const uint32_t pos = atomicAdd(&S.n, 1u);
+    const uint32_t pos = stage_slots(&S.n);
     if (pos < kStageR) {
         S.buf[pos] = v;
         return;
     }
-    const unsigned long long g = atomicAdd(count, 1ull);  // rare: stage full
+    const uint64_t g = wave_reserve(count, true);  // stage full
     if (g < cap) out[g] = v;
     else atomicOr(flags, kOvfRecords);
 }
@@ -312,7 +330,8 @@ __device__ __forceinline__ void push_record(StageR &S, uint64_t v, uint64_t *out
 __device__ __forceinline__ void stage_flush2(StageF &F, uint64_t *okey, uint64_t *olive,
                                              uint64_t fcap, unsigned long long *fcount, StageR &R,
                                              uint64_t *rout, uint64_t rcap,
-                                             unsigned long long *rcount, uint32_t *flags) {
+                                             unsigned long long *rcount, uint32_t *flags,
+                                             uint32_t *heavy_n = nullptr) {
     __syncthreads();
     const uint32_t mf = F.n < kStageF ? F.n : kStageF;
     const uint32_t mr = R.n < kStageR ? R.n : kStageR;
@@ -331,13 +350,22 @@ __device__ __forceinline__ void stage_flush2(StageF &F, uint64_t *okey, uint64_t
     for (uint32_t j = threadIdx.x; j < mr; j += blockDim.x)
         if (rb + j < rcap) rout[rb + j] = R.buf[j];
     __syncthreads();
-    if (threadIdx.x == 0) F.n = R.n = 0;
+    if (threadIdx.x == 0) {
+        F.n = R.n = 0;
+        if (heavy_n) *heavy_n = 0;
+    }
     __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t live_count(uint64_t live) {
+    return (uint32_t)(live & ((1u << kLiveCountBits) - 1));
 }
 
 struct ExpandShared {
     StageF F;
     StageR R;
+    uint32_t heavy[kHeavyCap];  // frontier positions of this round's long lists
+    uint32_t nheavy;
 };
 
 // One live in-edge w -> v of the expanded pair (v, i), taken by the search
@@ -379,16 +407,37 @@ __device__ __forceinline__ void expand_range(const WinArgs &A, uint32_t L,
             if (live & kLiveOne) {
                 visit_edge(A, (uint32_t)live, i, src, nkey, nlive, next_count, X, scans, hashed,
                            visits);
-            } else {
-                const uint64_t e0 = live >> kLiveCountBits;
-                const uint64_t e1 = e0 + (live & ((1u << kLiveCountBits) - 1));
-                for (uint64_t e = e0; e < e1; ++e)
-                    visit_edge(A, A.lsrc[e], i, src, nkey, nlive, next_count, X, scans, hashed,
-                               visits);
+                continue;
             }
+            const uint32_t cnt = live_count(live);
+            if (cnt > kSerialEdges) {  // a long list: the whole block takes it below
+                const uint32_t slot = stage_slots(&X.nheavy);
+                if (slot < kHeavyCap) {
+                    X.heavy[slot] = (uint32_t)(t - c);
+                    continue;
+                }
+            }
+            const uint64_t e0 = live >> kLiveCountBits;
+            for (uint64_t e = e0; e < e0 + cnt; ++e)
+                visit_edge(A, A.lsrc[e], i, src, nkey, nlive, next_count, X, scans, hashed,
+                           visits);
+        }
+        __syncthreads();
+        // Long live lists (hubs) spread over all threads of the block, one
+        // list after the other, instead of one thread walking each.
+        const uint32_t nh = X.nheavy < kHeavyCap ? X.nheavy : kHeavyCap;
+        for (uint32_t h = 0; h < nh; ++h) {
+            const uint64_t t = c + X.heavy[h];
+            const uint64_t it = ckey[t], live = clive[t];
+            const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
+            const uint32_t src = (uint32_t)it;
+            const uint64_t e0 = live >> kLiveCountBits, e1 = e0 + live_count(live);
+            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
+                visit_edge(A, A.lsrc[e], i, src, nkey, nlive, next_count, X, scans, hashed,
+                           visits);
         }
         stage_flush2(X.F, nkey, nlive, A.front_cap, next_count, X.R, A.rec, A.rec_cap,
-                     &A.ctl->records, &A.ctl->flags);
+                     &A.ctl->records, &A.ctl->flags, &X.nheavy);
     }
 }
 
@@ -432,7 +481,7 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32
     __shared__ uint32_t s_flags;
     __shared__ unsigned long long s_size;
     if (threadIdx.x == 0) {
-        X.F.n = X.R.n = 0;
+        X.F.n = X.R.n = X.nheavy = 0;
         s_flags = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_size = A.ctl->size[L % 3];
         if (blockIdx.x == 0) A.ctl->size[(L + 2) % 3] = 0;  // counter of level L + 2
@@ -605,11 +654,11 @@ struct Shapes {
     uint64_t thread_frontier = (uint64_t)kBlock * 2048;
     double heavy = 4.0;
     uint64_t sort_frontier = 0;  // 0: never sort
-    uint32_t first_window = 5;   // buckets in window 0
+    uint32_t window_span = 2;    // buckets per window after a light one
 };
 
 std::mutex g_shapes_mu;
-skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0, 5};
+skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0, 2};
 
 Shapes current_shapes() {
     std::lock_guard<std::mutex> lk(g_shapes_mu);
@@ -620,7 +669,7 @@ Shapes current_shapes() {
     sh.thread_frontier = g_params.thread_frontier;
     sh.heavy = (double)g_params.heavy_visits;
     sh.sort_frontier = g_params.sort_frontier;
-    sh.first_window = g_params.first_window;
+    sh.window_span = g_params.window_span;
     return sh;
 }
 
@@ -666,6 +715,11 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     uint64_t windows_done = 0, prev_hash = 0, prev_nw = 0;
     const bool debug = std::getenv("SKIM_DEBUG") != nullptr;
     const bool debug2 = debug && std::atoi(std::getenv("SKIM_DEBUG")) > 1;
+    const auto t_start = std::chrono::steady_clock::now();
+    auto elapsed_ms = [&]() {
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start)
+            .count();
+    };
     // Buffers grow between levels when the next levels could outrun them
     // (a level's new visits are assumed to be at most kGrow times its
     // frontier; a level that breaks this overflows and the windows are
@@ -683,17 +737,20 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
         capacity = nc;
     };
     Ctl h;
-    // Window w covers buckets [bb, be): the first sh.first_window buckets,
-    // then two buckets (a fourfold rank range) at a time, or one (twofold)
-    // after a window whose visited pairs took more than kHeavy visits each
-    // on average (large reach sets: a smaller step keeps the visits past k
-    // in check).
+    // Window w covers buckets [bb, be): bucket 0 alone; then, unless that
+    // was heavy, as many buckets as keep the arrivals per pair below k; then
+    // sh.window_span buckets at a time, or one (twofold) after a window whose
+    // visited pairs took more than kHeavy visits each on average (large
+    // reach sets: a smaller step keeps the visits past k in check).
     const double kHeavy = sh.heavy;
     uint64_t prev_visits = 0;
     uint32_t span = 1, span_next = 2;
+    bool merged = false;  // the current window was merged by the bucket-0 rule
     for (uint32_t w = 0, bb = 0; bb < W && w < 255; ++w, bb += span) {
-        span = std::min<uint32_t>(w == 0 ? sh.first_window : span_next, W - bb);
+        span = std::min<uint32_t>(w == 0 ? 1u : span_next, W - bb);
+        if (bb + span == W && span > 1) --span;  // the last bucket (half the ranks) alone
         const uint64_t ws = wb[bb], we = wb[bb + span];
+        const uint32_t last = bb + span >= W;
         read_back(&h, ctl, sizeof h, s);
         if (h.flags) throw Retry{h.flags};
         if (h.full >= n) break;  // every sketch holds k ranks: later ranks cannot enter
@@ -708,12 +765,12 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                                 : 1.5 * (double)prev_hash * (double)nw / (double)prev_nw + (double)nw;
         uint64_t hsize = std::min<uint64_t>(
             cap.hash, next_pow2(std::max<uint64_t>(cap.hash_min, (uint64_t)(2.5 * pred))));
-        // Windows after a heavy one keep a copy of the pair states: an
+        // The first window and windows after a heavy one can be redone: an
         // overflow there costs one redo of the window with more room instead
-        // of a restart of all windows.  (Redoing the first window costs about
-        // what a restart does.)
-        const bool guard = w > 0 && span_next == 1;
-        if (guard) {
+        // of a restart of all windows.  The first window restores the pair
+        // records from scratch, the others from a copy taken here.
+        const bool guard = w == 0 || span_next == 1;
+        if (guard && w > 0) {
             if (!snap) snap = A.alloc<uint64_t>(2 * npairs);
             SKIM_HIP(hipMemcpyAsync(snap, prec, 2 * npairs * sizeof(uint64_t),
                                     hipMemcpyDeviceToDevice, s));
@@ -733,7 +790,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
             auto args = [&]() {
                 return WinArgs{prec,    live.adj, hset,
                                logcap,  w,        k,
-                               want,    rec,      rec_cap,
+                               last,    want,     rec,      rec_cap,
                                {fkey[0], fkey[1]}, {flive[0], flive[1]}, front_cap,
                                ctl};
             };
@@ -850,8 +907,14 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
                 front_cap = std::min(std::min(c[0], c[1]), std::min(c[2], c[3]));
             }
             if (overflow & kOvfRecords) grow_u64(rec, rec_cap, base.records, 2 * rec_cap);
-            SKIM_HIP(hipMemcpyAsync(prec, snap, 2 * npairs * sizeof(uint64_t),
-                                    hipMemcpyDeviceToDevice, s));
+            if (w == 0) {
+                k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(
+                    live.ptr, live.adj, npairs, prec, &ctl->flags);
+                SKIM_LAUNCH_CHECK();
+            } else {
+                SKIM_HIP(hipMemcpyAsync(prec, snap, 2 * npairs * sizeof(uint64_t),
+                                        hipMemcpyDeviceToDevice, s));
+            }
             if (debug) std::fprintf(stderr, "skim window %u: redo %d\n", w, redo + 1);
         }
         prev_hash = h.hinserts;
@@ -859,18 +922,42 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
         {   // the next window's step
             const uint64_t v = h.visits - prev_visits;
             const uint64_t distinct = v > h.hinserts ? v - h.hinserts : 1;
-            const uint32_t next = (double)v > kHeavy * (double)distinct ? 1u : 2u;
+            const double per_pair = (double)v / (double)distinct;
+            // heavy: more than kHeavy visits per visited pair (per two
+            // buckets for the merged window, which gathers arrivals by design)
+            const bool heavy =
+                per_pair > kHeavy * (merged ? std::max(1.0, span / 2.0) : 1.0);
+            uint32_t next = heavy ? 1u : sh.window_span;
+            merged = false;
+            if (w == 0 && !heavy) {
+                // Bucket 0 gave each visited pair per_pair arrivals; with no
+                // pruning yet they grow with the source count, which doubles
+                // with every bucket.  While they stay below k nothing can be
+                // pruned, so the buckets up to there form one window, cut so
+                // that the windows after it end on the last bucket alone.
+                uint32_t j = 0;
+                while (j < 16 && per_pair * (double)(2u << j) <= (double)k) ++j;
+                if (j > next) {
+                    const uint32_t rest = W > 2 + j ? W - 2 - j : 0;
+                    const uint32_t cut = rest % sh.window_span;
+                    next = std::max(next, j - std::min(cut, j - 1));
+                    merged = true;
+                }
+            }
             prev_visits = h.visits;
             span_next = next;
         }
         if (debug)
             std::fprintf(stderr, "skim window %u: sources %llu visits-so-far %llu hashed %llu "
-                                 "table %llu levels %u records %llu\n",
+                                 "table %llu levels %u records %llu at %.1f ms\n",
                          w, (unsigned long long)nw, h.visits, h.hinserts,
-                         (unsigned long long)hsize, levels_run, h.records);
-        fill_u64((uint64_t *)&ctl->full, 0, 1, s);
-        k_want<<<grid_for((uint64_t)n * 8, kBlock, 8192), kBlock, 0, s>>>(prec, n, k, want, ctl);
-        SKIM_LAUNCH_CHECK();
+                         (unsigned long long)hsize, levels_run, h.records, elapsed_ms());
+        if (!last) {
+            fill_u64((uint64_t *)&ctl->full, 0, 1, s);
+            k_want<<<grid_for((uint64_t)n * 8, kBlock, 8192), kBlock, 0, s>>>(prec, n, k, want,
+                                                                              ctl);
+            SKIM_LAUNCH_CHECK();
+        }
         ++windows_done;
     }
     read_back(&h, ctl, sizeof h, s);
@@ -1024,11 +1111,11 @@ extern "C" skim_status skim_build_sketches(const skim_graph *g, uint32_t ell, ui
 
 extern "C" skim_status skim_set_build_params(const skim_build_params *p) {
     skim::clear_error();
-    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4, 0, 5};
+    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4, 0, 2};
     if (p) {
         if (p->small_frontier < 1 || p->small_batch < 1 || p->small_batch > 64 ||
             p->large_batch < 1 || p->large_batch > 64 || p->thread_frontier < 1 ||
-            p->heavy_visits < 1 || p->first_window < 1 || p->first_window > 16) {
+            p->heavy_visits < 1 || p->window_span < 1 || p->window_span > 8) {
             skim::set_error("build parameters out of range");
             return SKIM_EINVAL;
         }
@@ -1089,7 +1176,7 @@ extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32
         const uint32_t lb[] = {2, 3, 4};
         const uint32_t tf[] = {131072, 524288, 2097152};
         const uint32_t so[] = {0, 1u << 20, 1u << 22};
-        const uint32_t fw[] = {3, 5, 7};
+        const uint32_t fw[] = {2, 3, 4};
         for (int field = 0; field < 6 && st == SKIM_OK; ++field) {
             for (int c = 0; c < 3 && st == SKIM_OK; ++c) {
                 skim_build_params p = cur;
@@ -1098,7 +1185,7 @@ extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32
                                  : field == 2 ? &p.large_batch
                                  : field == 3 ? &p.thread_frontier
                                  : field == 4 ? &p.sort_frontier
-                                              : &p.first_window;
+                                              : &p.window_span;
                 const uint32_t v = field == 0   ? sf[c]
                                    : field == 1 ? sb[c]
                                    : field == 2 ? lb[c]

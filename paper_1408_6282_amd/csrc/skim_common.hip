@@ -3,6 +3,9 @@
 // per-node estimate entry point.
 #include "skim_internal.h"
 
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -141,6 +144,8 @@ void *Arena::get(size_t bytes) {
         }
     }
     if (!p) {
+        static const bool trace = std::getenv("SKIM_TRACE_ALLOC") != nullptr;
+        const auto t0 = std::chrono::steady_clock::now();
         hipError_t e = hipMalloc(&p, cls);
         if (e != hipSuccess || !p) {  // give the cache back to the device and try once more
             (void)hipGetLastError();
@@ -155,6 +160,16 @@ void *Arena::get(size_t bytes) {
             (void)hipGetLastError();
             set_error("device allocation of %zu bytes failed: %s", cls, hipGetErrorString(e));
             throw Fail{SKIM_ENOMEM};
+        }
+        if (trace) {
+            size_t held = 0, spare = 0;
+            for (auto &b : bufs_) held += b.p ? b.bytes : 0;
+            for (auto &b : spare_) spare += b.p ? b.bytes : 0;
+            std::fprintf(stderr, "skim alloc %.3f GB in %.1f ms (arena holds %.3f GB, %.3f GB spare)\n",
+                         cls / 1e9,
+                         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0)
+                             .count(),
+                         held / 1e9, spare / 1e9);
         }
     }
     bufs_.push_back({p, got});

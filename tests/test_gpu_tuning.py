@@ -11,9 +11,9 @@ from gpu_util import gpu_build, log
 pytestmark = pytest.mark.gpu
 
 EXTREME = dict(small_frontier=1, small_batch=1, large_batch=1, thread_frontier=1, heavy_visits=1,
-               sort_frontier=1, first_window=1)
+               sort_frontier=1, window_span=1)
 WIDE = dict(small_frontier=1 << 24, small_batch=64, large_batch=64, thread_frontier=1 << 30,
-            heavy_visits=1000, sort_frontier=0, first_window=16)
+            heavy_visits=1000, sort_frontier=0, window_span=8)
 
 
 @pytest.fixture
@@ -65,7 +65,7 @@ def test_tuner_keeps_results_and_sets_params(oracle_lib, restore_params):
 @pytest.mark.parametrize("field,value", [("small_frontier", 0), ("small_batch", 0),
                                          ("small_batch", 65), ("large_batch", 0),
                                          ("thread_frontier", 0), ("heavy_visits", 0),
-                                         ("first_window", 0), ("first_window", 17)])
+                                         ("window_span", 0), ("window_span", 9)])
 def test_out_of_range_params_refused(restore_params, field, value):
     import paper_1408_6282_amd as sk
     before = sk.skim_get_build_params()
