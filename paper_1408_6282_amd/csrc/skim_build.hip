@@ -5,9 +5,11 @@
 // How (Section 5.2, Algorithm 2, re-organised for the GPU):
 //
 //  1. Live lists.  One coalesced pass over the edges evaluates every
-//     instance's coin of each edge (a 64-bit instance mask per edge), and
-//     the live in-lists of every node-instance pair p = 64 v + i are
-//     materialised as one CSR; each pair's 16-byte record holds its search
+//     instance's coin of each edge (a 64-bit instance mask per edge); the
+//     live (pair, source) entries are written at per-edge prefix offsets
+//     and radix-sorted by pair, so the live in-list of every node-instance
+//     pair p = 64 v + i is one run, built without atomics; each pair's
+//     16-byte record holds its search
 //     state word next to its list (the source itself when the list has one
 //     entry), so a claim reads both in one cache line.  Every expansion
 //     later reads only live in-edges of its own instance, and pairs without
@@ -497,12 +499,12 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32
 }
 
 // Pair records at the start of a build: the initial state word and the
-// live-list word of every pair (from the CSR of live in-lists).
-__global__ void k_pair_init(const uint64_t *lptr, const uint32_t *lsrc, uint64_t npairs,
-                            uint64_t *prec, uint32_t *flags) {
+// live-list word of every pair (from the runs of live in-lists).
+__global__ void k_pair_init(const uint64_t *lbeg, const uint64_t *lend, const uint32_t *lsrc,
+                            uint64_t npairs, uint64_t *prec, uint32_t *flags) {
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < npairs;
          q += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t b = lptr[q], c = lptr[q + 1] - b;
+        const uint64_t b = lbeg[q], c = lend[q] - b;
         uint64_t live = 0;
         if (c == 1) {
             live = kLiveOne | lsrc[b];
@@ -548,7 +550,9 @@ __global__ void k_want(const uint64_t *prec, uint32_t n, uint32_t k, uint8_t *wa
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ((lanes + 63) & ~63ull);
          t += (uint64_t)gridDim.x * blockDim.x) {
         uint32_t c = 0;
-        if (t < lanes) {
+        // a node that stopped recording never records again: skip its words
+        const bool open = t < lanes && want[t >> 3];
+        if (open) {
             const uint64_t *wv = prec + t * 16;
             for (int j = 0; j < 8; ++j) c += prior_count(wv[2 * j], 0xFEu);
         }
@@ -556,8 +560,8 @@ __global__ void k_want(const uint64_t *prec, uint32_t n, uint32_t k, uint8_t *wa
         c += __shfl_xor(c, 2);
         c += __shfl_xor(c, 4);
         if (t < lanes && (t & 7) == 0) {
-            const bool w = c < k;
-            want[t >> 3] = w;
+            const bool w = open && c < k;
+            if (open) want[t >> 3] = w;
             full += !w;
         }
     }
@@ -682,7 +686,7 @@ struct Capacity {
 
 // One attempt at the windows and the merge; throws Retry when a buffer was
 // too small (the caller's outputs are written only by the merge).
-static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const LiveLists &live,
+static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const PairLists &live,
                         const uint32_t *sources, const unsigned long long *wb, uint32_t W,
                         const Capacity &cap, const Shapes &sh, uint64_t *ranks_out,
                         uint32_t *size_out, uint64_t *work, Arena &A) {
@@ -692,8 +696,8 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
     Ctl *ctl = A.alloc<Ctl>(1);
     fill_u64((uint64_t *)ctl, 0, sizeof(Ctl) / 8, s);
     uint64_t *prec = A.alloc<uint64_t>(2 * npairs);
-    k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(live.ptr, live.adj, npairs, prec,
-                                                                  &ctl->flags);
+    k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(live.beg, live.end, live.adj,
+                                                                  npairs, prec, &ctl->flags);
     SKIM_LAUNCH_CHECK();
     uint8_t *want = A.alloc<uint8_t>((uint64_t)n + 4);
     fill_u32((uint32_t *)want, 0x01010101u, (n + 3) / 4, s);  // no records yet: all record
@@ -909,7 +913,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Li
             if (overflow & kOvfRecords) grow_u64(rec, rec_cap, base.records, 2 * rec_cap);
             if (w == 0) {
                 k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(
-                    live.ptr, live.adj, npairs, prec, &ctl->flags);
+                    live.beg, live.end, live.adj, npairs, prec, &ctl->flags);
                 SKIM_LAUNCH_CHECK();
             } else {
                 SKIM_HIP(hipMemcpyAsync(prec, snap, 2 * npairs * sizeof(uint64_t),
@@ -1019,7 +1023,7 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     const uint64_t nsrc = (uint64_t)n * ell;  // actual pairs
 
     // ---- 1. live lists (reverse: in-edges of every pair)
-    LiveLists live = build_live_lists(g, ell, seed, esrc, /*forward=*/false, A);
+    PairLists live = build_pair_lists(g, ell, seed, esrc, A);
     A.release(esrc);
     if (live.nlive >> (64 - 1 - kLiveCountBits)) {
         set_error("%llu live edges exceed the pair records' list offsets",

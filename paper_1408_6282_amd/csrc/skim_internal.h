@@ -185,6 +185,18 @@ struct LiveLists {
 LiveLists build_live_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
                            bool forward, Arena &a, LiveLists *also_other = nullptr);
 
+// Live in-lists of every pair as runs of one array: adj[beg[p] .. end[p])
+// = sources u of edges (u -> v) live in instance i, p = 64 v + i, in edge
+// order (beg = end = 0 for a pair without live in-edges).  Built with no
+// atomics: per-edge prefix offsets and a radix sort by pair.
+struct PairLists {
+    uint64_t *beg = nullptr, *end = nullptr;  // [64 n]
+    uint32_t *adj = nullptr;
+    uint64_t nlive = 0;
+};
+PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
+                           Arena &a);
+
 // Optional per-kernel timing: while a kernel name is enabled, each launch of
 // that kernel is bracketed by HIP events on its stream; durations are folded
 // into the totals when the owning call resolves them after its final sync.
