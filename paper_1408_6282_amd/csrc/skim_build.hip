@@ -81,7 +81,7 @@ struct Ctl {
     unsigned long long full;      // nodes holding k records
     unsigned long long visits;    // accepted visits (work counter)
     uint32_t flags;               // overflow bits
-    uint32_t pad;
+    uint32_t level;               // level reached by the tail kernel
 };
 
 // ------------------------------------------------------- 2. rank windows
@@ -96,8 +96,13 @@ __device__ __forceinline__ uint32_t bucket_of(uint64_t r, uint32_t b0) {
 
 constexpr int kRankPer = 8;  // pairs per thread in the bucketing kernels
 
+// Bucketing is a stable counting sort: each block counts its pairs per
+// bucket (bcount is bucket-major, so one exclusive scan gives every block
+// its place inside every bucket), then writes its pairs in pair order.
+// Every bucket of the sources array is therefore in increasing pair order,
+// and a window's pair records are visited in memory order.
 __global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W, uint32_t b0,
-                            unsigned long long *whist) {
+                            unsigned long long *whist, uint32_t *bcount, uint32_t nblocks) {
     __shared__ uint32_t h[64];
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
     __syncthreads();
@@ -111,35 +116,61 @@ __global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W,
         }
     }
     __syncthreads();
-    if (threadIdx.x < W && h[threadIdx.x]) atomicAdd(&whist[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < W) {
+        bcount[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+        if (h[threadIdx.x]) atomicAdd(&whist[threadIdx.x], h[threadIdx.x]);
+    }
 }
 
-__global__ void k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W, uint32_t b0,
-                               const unsigned long long *wbase, unsigned long long *wfill,
-                               uint32_t *sources) {
-    __shared__ uint32_t h[64];
-    __shared__ unsigned long long off[64];
-    if (threadIdx.x < 64) h[threadIdx.x] = 0;
-    __syncthreads();
+// Pairs base + j * kBlock + tid, in that order (j outer): within each round
+// j every wave ranks its lanes per bucket by ballots, and the waves of the
+// block and the earlier rounds are added in order.
+__global__ void __launch_bounds__(kBlock) k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed,
+                                                         uint32_t W, uint32_t b0,
+                                                         const uint64_t *boff, uint32_t nblocks,
+                                                         uint32_t *sources) {
+    constexpr int kWaves = kBlock / 64;
+    __shared__ uint32_t wcnt[kWaves][64];  // lanes per bucket of every wave, this round
+    __shared__ uint32_t run[64];           // pairs per bucket of the earlier rounds
+    const uint32_t tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    if (tid < 64) run[tid] = 0;
     const uint64_t total = (uint64_t)n * ell;
     const uint64_t base = (uint64_t)blockIdx.x * kBlock * kRankPer;
-    uint32_t pid[kRankPer], win[kRankPer], slot[kRankPer];
     for (int j = 0; j < kRankPer; ++j) {
-        const uint64_t t = base + (uint64_t)j * kBlock + threadIdx.x;
-        win[j] = 0xFFFFFFFFu;
+        wcnt[wave][lane] = 0;
+        __syncthreads();
+        const uint64_t t = base + (uint64_t)j * kBlock + tid;
+        uint32_t b = 0xFFFFFFFFu, pid = 0, rank = 0;
         if (t < total) {
             const uint32_t v = (uint32_t)(t / ell), i = (uint32_t)(t % ell);
-            pid[j] = v * kPairStride + i;
-            win[j] = bucket_of(pair_rank(seed, pid[j]), b0);
-            slot[j] = atomicAdd(&h[win[j]], 1u);
+            pid = v * kPairStride + i;
+            b = bucket_of(pair_rank(seed, pid), b0);
         }
+        bool todo = b != 0xFFFFFFFFu;
+        for (;;) {  // one bucket of this wave per pass (wave-uniform loop)
+            const unsigned long long act = __ballot(todo);
+            if (!act) break;
+            const int leader = __ffsll((long long)act) - 1;
+            const uint32_t bb = __shfl(b, leader);
+            const bool mine = todo && b == bb;
+            const unsigned long long m = __ballot(mine);
+            if (mine) {
+                rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                todo = false;
+            }
+            if ((int)lane == leader) wcnt[wave][bb] = (uint32_t)__popcll(m);
+        }
+        __syncthreads();
+        if (b != 0xFFFFFFFFu) {
+            uint32_t before = run[b] + rank;
+            for (uint32_t w2 = 0; w2 < wave; ++w2) before += wcnt[w2][b];
+            sources[boff[(uint64_t)b * nblocks + blockIdx.x] + before] = pid;
+        }
+        __syncthreads();
+        if (tid < 64)
+            for (int w2 = 0; w2 < kWaves; ++w2) run[tid] += wcnt[w2][tid];
+        __syncthreads();
     }
-    __syncthreads();
-    if (threadIdx.x < W && h[threadIdx.x])
-        off[threadIdx.x] = wbase[threadIdx.x] + atomicAdd(&wfill[threadIdx.x], h[threadIdx.x]);
-    __syncthreads();
-    for (int j = 0; j < kRankPer; ++j)
-        if (win[j] != 0xFFFFFFFFu) sources[off[win[j]] + slot[j]] = pid[j];
 }
 
 // --------------------------------------------------- pair state words
@@ -517,6 +548,216 @@ __global__ void k_pair_init(const uint64_t *lbeg, const uint64_t *lend, const ui
     }
 }
 
+// ------------------------------------------- tail levels in one workgroup
+// Once a window's frontier is small, its remaining levels run inside one
+// workgroup: the frontier stays in LDS from level to level and levels are
+// separated by workgroup barriers, so no launch and no host round trip
+// stands between them.  The kernel hands the search back to the host (the
+// frontier in global memory, ctl->level = the level reached) when the
+// frontier outgrows LDS, the next level could outgrow the records, the hash
+// set (40% load) or the frontier arrays, a claim overflowed, or after
+// max_levels levels.
+constexpr uint32_t kTailCap = 1024;  // frontier entries held in LDS
+constexpr int kTailBlock = 1024;
+constexpr uint32_t kTailLevels = 4096;         // levels per launch at most
+constexpr uint64_t kTailRecords = 1ull << 20;  // record room the host adds before a launch
+
+struct TailShared {
+    uint64_t key[2][kTailCap];
+    uint64_t live[2][kTailCap];
+    uint32_t n[2];  // entries of each level (beyond kTailCap: in global memory)
+    StageR R;
+    uint32_t heavy[kHeavyCap];
+    uint32_t nheavy;
+    uint32_t hashed;  // hash inserts of the current level
+    uint32_t spilled;  // records of the current level that bypassed the stage
+    unsigned long long work;  // live in-edges the current level scans
+    unsigned long long recs, hins;  // running totals of records and hash inserts
+    uint32_t stop;    // 1: leave the loop
+    uint32_t give;    // 1: the frontier goes back to global memory
+};
+
+// A new frontier entry: in LDS while it fits, past that at the same index in
+// the next level's global array.
+__device__ __forceinline__ void tail_push(TailShared &T, uint32_t nxt, uint64_t key, uint64_t live,
+                                          uint64_t *gkey, uint64_t *glive, uint64_t cap,
+                                          uint32_t *flags) {
+    const uint32_t pos = stage_slots(&T.n[nxt]);
+    if (pos < kTailCap) {
+        T.key[nxt][pos] = key;
+        T.live[nxt][pos] = live;
+    } else if (pos < cap) {
+        gkey[pos] = key;
+        glive[pos] = live;
+    } else {
+        atomicOr(flags, kOvfSpill);
+    }
+}
+
+__device__ __forceinline__ void tail_visit(const WinArgs &A, TailShared &T, uint32_t nxt, uint32_t w,
+                                           uint32_t i, uint32_t src, uint64_t *gkey,
+                                           uint64_t *glive, uint32_t &scans, uint32_t &hashed,
+                                           uint32_t &visits) {
+    const uint32_t q = w * kPairStride + i;
+    ++scans;
+    uint64_t live;
+    if (claim(A, q, src, hashed, live) == 1) {
+        ++visits;
+        if (live) tail_push(T, nxt, ((uint64_t)q << 32) | src, live, gkey, glive, A.front_cap,
+                            &A.ctl->flags);
+        if (wants_record(A, w)) {
+            const uint32_t pos = stage_slots(&T.R.n);
+            if (pos < kStageR) {
+                T.R.buf[pos] = ((uint64_t)w << 32) | src;
+            } else {  // stage full: straight to global memory
+                atomicAdd(&T.spilled, 1u);
+                const uint64_t g = wave_reserve(&A.ctl->records, true);
+                if (g < A.rec_cap) A.rec[g] = ((uint64_t)w << 32) | src;
+                else atomicOr(&A.ctl->flags, kOvfRecords);
+            }
+        }
+    }
+}
+
+// Levels L0, L0 + 1, ... of the current window; the frontier of level L0
+// (at most kTailCap entries; a larger one is left untouched) is in global
+// memory.
+__global__ void __launch_bounds__(kTailBlock) k_tail(WinArgs A, uint32_t L0, uint32_t max_levels) {
+    __shared__ TailShared T;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
+        const unsigned long long f = A.ctl->size[L0 % 3];
+        const uint32_t fl =
+            __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        T.stop = f == 0 || f > kTailCap || fl != 0;
+        T.n[0] = T.stop ? 0 : (uint32_t)f;
+        T.R.n = 0;
+        T.give = 0;
+        T.recs = A.ctl->records;  // the kernel is the only writer while it runs
+        T.hins = A.ctl->hinserts;
+        if (T.stop) A.ctl->level = L0;  // not taken: everything stays as it is
+    }
+    __syncthreads();
+    if (T.stop) return;
+    for (uint32_t t = tid; t < T.n[0]; t += blockDim.x) {
+        T.key[0][t] = A.fkey[L0 & 1][t];
+        T.live[0][t] = A.flive[L0 & 1][t];
+    }
+    uint32_t scans = 0, visits = 0, L = L0, cur = 0;
+    unsigned long long recs = T.recs;  // records count, kept alike by every thread
+    for (uint32_t lv = 0;; ++lv) {
+        if (tid == 0) {
+            T.n[cur ^ 1] = 0;
+            T.nheavy = 0;
+            T.hashed = 0;
+            T.spilled = 0;
+            T.work = 0;
+        }
+        __syncthreads();
+        const uint32_t nc = T.n[cur];
+        if (T.stop || nc == 0) break;  // uniform: read after the barrier
+        {   // the level's live in-edges bound its visits, records and inserts
+            unsigned long long wk = 0;
+            for (uint32_t t = tid; t < nc; t += blockDim.x) {
+                const uint64_t live = T.live[cur][t];
+                wk += (live & kLiveOne) ? 1u : live_count(live);
+            }
+            if (wk) atomicAdd(&T.work, wk);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const unsigned long long W = T.work;
+            if (lv >= max_levels || recs + W > A.rec_cap ||
+                5 * (T.hins + W) > 2 * (1ull << A.logcap) || W > A.front_cap) {
+                T.stop = 1;
+                T.give = 1;
+            }
+        }
+        __syncthreads();
+        if (T.stop) break;
+        const uint32_t nxt = cur ^ 1;
+        uint64_t *gkey = A.fkey[(L + 1) & 1], *glive = A.flive[(L + 1) & 1];
+        uint32_t hashed = 0;
+        for (uint32_t t = tid; t < nc; t += blockDim.x) {
+            const uint64_t it = T.key[cur][t], live = T.live[cur][t];
+            const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
+            const uint32_t src = (uint32_t)it;
+            if (live & kLiveOne) {
+                tail_visit(A, T, nxt, (uint32_t)live, i, src, gkey, glive, scans, hashed, visits);
+                continue;
+            }
+            const uint32_t cnt = live_count(live);
+            if (cnt > kSerialEdges) {
+                const uint32_t slot = stage_slots(&T.nheavy);
+                if (slot < kHeavyCap) {
+                    T.heavy[slot] = t;
+                    continue;
+                }
+            }
+            const uint64_t e0 = live >> kLiveCountBits;
+            for (uint64_t e = e0; e < e0 + cnt; ++e)
+                tail_visit(A, T, nxt, A.lsrc[e], i, src, gkey, glive, scans, hashed, visits);
+        }
+        __syncthreads();
+        const uint32_t nh = T.nheavy < kHeavyCap ? T.nheavy : kHeavyCap;
+        for (uint32_t h = 0; h < nh; ++h) {
+            const uint32_t t = T.heavy[h];
+            const uint64_t it = T.key[cur][t], live = T.live[cur][t];
+            const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
+            const uint32_t src = (uint32_t)it;
+            const uint64_t e0 = live >> kLiveCountBits, e1 = e0 + live_count(live);
+            for (uint64_t e = e0 + tid; e < e1; e += blockDim.x)
+                tail_visit(A, T, nxt, A.lsrc[e], i, src, gkey, glive, scans, hashed, visits);
+        }
+        if (hashed) atomicAdd(&T.hashed, hashed);
+        // records of this level to global memory; the flags are read while
+        // they are written
+        uint32_t fl = 0;
+        if (tid == 0) fl = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const uint32_t mr = T.R.n < kStageR ? T.R.n : kStageR;
+        const uint32_t sp = T.spilled, hs = T.hashed, nn = T.n[nxt];
+        __syncthreads();  // every thread has read the level's counters
+        // The kernel is the only writer of the records count, so the stage
+        // goes right after the records this level spilled past it.
+        const unsigned long long rb = recs + sp;
+        for (uint32_t j = tid; j < mr; j += blockDim.x)
+            if (rb + j < A.rec_cap) A.rec[rb + j] = T.R.buf[j];
+        recs += mr + sp;
+        if (tid == 0) {
+            if (mr) atomicAdd(&A.ctl->records, (unsigned long long)mr);
+            if (mr && rb + mr > A.rec_cap) atomicOr(&A.ctl->flags, kOvfRecords);
+            T.R.n = 0;
+            // the level is done: decide whether to go on
+            if (hs) atomicAdd(&A.ctl->hinserts, (unsigned long long)hs);
+            T.hins += hs;
+            if (fl || nn == 0) {
+                T.stop = 1;
+                T.give = 0;
+            } else if (nn > kTailCap) {
+                T.stop = 1;
+                T.give = 1;
+            }
+        }
+        L += 1;
+        cur ^= 1;
+    }
+    // hand the frontier of level L back (its entries past kTailCap are there already)
+    const uint32_t nn = T.n[cur];
+    if (T.give)
+        for (uint32_t t = tid; t < nn && t < kTailCap; t += blockDim.x) {
+            A.fkey[L & 1][t] = T.key[cur][t];
+            A.flive[L & 1][t] = T.live[cur][t];
+        }
+    if (tid == 0) {
+        A.ctl->size[L % 3] = T.give ? nn : 0;
+        A.ctl->size[(L + 1) % 3] = 0;
+        A.ctl->level = L;
+    }
+    wave_add(&A.ctl->scans, scans);
+    wave_add(&A.ctl->visits, visits);
+}
+
 // Start of a window (or of its redo): clear the per-window fields and set
 // the running counters to their values at the window start.
 __global__ void k_ctl_begin(Ctl *ctl, unsigned long long visits, unsigned long long scans,
@@ -527,14 +768,6 @@ __global__ void k_ctl_begin(Ctl *ctl, unsigned long long visits, unsigned long l
     ctl->visits = visits;
     ctl->scans = scans;
     ctl->records = records;
-}
-
-struct WinBases {
-    unsigned long long b[64];
-};
-
-__global__ void k_set_bases(unsigned long long *dst, WinBases wb) {
-    if (threadIdx.x < 64) dst[threadIdx.x] = wb.b[threadIdx.x];
 }
 
 // ---------------------------------------------------------- 4. records
@@ -807,8 +1040,14 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
             uint32_t L = 0;
             uint32_t overflow = 0;
             uint64_t f_prev = 0;
+            uint32_t tail_from = ~0u, tail_stuck = ~0u;  // level the tail kernel started at
             for (;;) {
                 read_back(&h, ctl, sizeof h, s);
+                if (tail_from != ~0u) {
+                    if (h.level == tail_from) tail_stuck = tail_from;  // it made no progress
+                    L = h.level;
+                    tail_from = ~0u;
+                }
                 if (h.flags) {
                     overflow = h.flags;
                     if (debug)
@@ -850,6 +1089,18 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
                     if (debug)
                         std::fprintf(stderr, "skim window %u: hash set grown to %llu\n", w,
                                      (unsigned long long)ns);
+                }
+                if (f <= kTailCap && L != tail_stuck) {
+                    // the rest of the window in one workgroup, with room for
+                    // the records of many levels
+                    grow_u64(rec, rec_cap, h.records, h.records + kTailRecords);
+                    const WinArgs WA = args();
+                    LaunchTimer t("k_tail", s);
+                    k_tail<<<1, kTailBlock, 0, s>>>(WA, L, kTailLevels);
+                    SKIM_LAUNCH_CHECK();
+                    tail_from = L;
+                    f_prev = 0;
+                    continue;
                 }
                 int batch = f > kSmall ? sh.large_batch : sh.small_batch;
                 if (sh.sort_frontier && f > sh.sort_frontier) {
@@ -1034,23 +1285,24 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     // ---- 2. rank buckets
     uint32_t W = 1, b0 = 64;  // W: number of buckets
     choose_buckets(n, k, W, b0);
-    unsigned long long *wbuf = A.alloc<unsigned long long>(2 * 64);
-    fill_u64((uint64_t *)wbuf, 0, 128, s);
+    unsigned long long *wbuf = A.alloc<unsigned long long>(64);
+    fill_u64((uint64_t *)wbuf, 0, 64, s);
     const unsigned rblocks = (unsigned)((nsrc + (uint64_t)kBlock * kRankPer - 1) /
                                         ((uint64_t)kBlock * kRankPer));
-    k_rank_hist<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, wbuf);
+    uint32_t *bcount = A.alloc<uint32_t>((uint64_t)W * rblocks);
+    k_rank_hist<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, wbuf, bcount, rblocks);
     SKIM_LAUNCH_CHECK();
+    uint64_t *boff = A.alloc<uint64_t>((uint64_t)W * rblocks + 1);
+    exclusive_scan_u32(bcount, boff, (uint64_t)W * rblocks, A);
+    A.release(bcount);
     unsigned long long hw[64] = {};
     read_back(hw, wbuf, sizeof(unsigned long long) * 64, s);
     unsigned long long wb[65] = {};
     for (uint32_t w = 0; w < W; ++w) wb[w + 1] = wb[w] + hw[w];
-    WinBases bases;
-    std::memcpy(bases.b, wb, sizeof bases.b);
-    k_set_bases<<<1, 64, 0, s>>>(wbuf, bases);
-    SKIM_LAUNCH_CHECK();
     uint32_t *sources = A.alloc<uint32_t>(nsrc);
-    k_rank_scatter<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, wbuf, wbuf + 64, sources);
+    k_rank_scatter<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, boff, rblocks, sources);
     SKIM_LAUNCH_CHECK();
+    A.release(boff);
 
     // ---- 3./4./5. windows and merge; restart with more room on overflow
     uint64_t biggest = 0, bucket_max = 0;  // largest possible window (two buckets), bucket
