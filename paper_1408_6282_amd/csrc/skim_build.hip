@@ -279,8 +279,10 @@ __device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
         // One more source reached q in this window.  A carry out of the
         // 12-bit arrival field (4096 arrivals) turns into +1 on cnt, and cnt
         // itself can wrap: both only ever undercount, which can only weaken
-        // pruning, never make it wrong.  Arrivals only serve later windows.
-        if (!A.last) atomicAdd((unsigned long long *)rq, 1ull << 40);
+        // pruning, never make it wrong.  Arrivals only serve later windows,
+        // and only until the pair holds k (the word read above may be older
+        // than the pair's count, never newer).
+        if (!A.last && w_cnt(old) + w_arr(old) < A.k) atomicAdd((unsigned long long *)rq, 1ull << 40);
         ++hashed;
         return 1;
     }
