@@ -254,12 +254,16 @@ struct WinArgs {
 
 // Visit of pair q by the search of source pair src: 1 if it is a new visit
 // (and counts as one more rank received by q), 0 if pruned or repeated.
-// `live` receives q's live-list word.
-__device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
+// `live` receives q's live-list word.  A pair without live in-edges whose
+// node records nothing more (`want` false) is skipped outright: the visit
+// would neither expand nor record, and its count serves nothing (such a
+// pair never expands, and its node's recording never resumes).
+__device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src, bool want,
                                      uint32_t &hashed, uint64_t &live) {
     uint64_t *rq = A.prec + 2 * (uint64_t)q;
     uint64_t old = load_relaxed(rq);
     live = rq[1];  // read-only during the searches
+    if (!live && !want) return 0;
     for (;;) {
         if (prior_count(old, A.win) >= A.k) return 0;  // instance-local sketch full: prune
         if (w_tag(old) != A.win) {
@@ -411,13 +415,14 @@ __device__ __forceinline__ void visit_edge(const WinArgs &A, uint32_t w, uint32_
                                            uint32_t &scans, uint32_t &hashed, uint32_t &visits) {
     const uint32_t q = w * kPairStride + i;
     ++scans;
+    const bool want = wants_record(A, w);
     uint64_t live;
-    if (claim(A, q, src, hashed, live) == 1) {
+    if (claim(A, q, src, want, hashed, live) == 1) {
         ++visits;
         if (live)
             push_front(X.F, ((uint64_t)q << 32) | src, live, nkey, nlive, A.front_cap, next_count,
                        &A.ctl->flags);
-        if (wants_record(A, w))
+        if (want)
             push_record(X.R, ((uint64_t)w << 32) | src, A.rec, A.rec_cap, &A.ctl->records,
                         &A.ctl->flags);
     }
@@ -493,13 +498,15 @@ __global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_
             const uint64_t old = rp[0], live = rp[1];
             const uint32_t prior = prior_count(old, A.win);
             if (prior >= A.k) continue;  // pruned
+            const uint32_t v = p / kPairStride;
+            const bool want = wants_record(A, v);
+            if (!live && !want) continue;  // would neither expand nor record (see claim)
             rp[0] = (uint64_t)p | ((uint64_t)A.win << 32) | (1ull << 40) | ((uint64_t)prior << 52);
             ++visits;
             if (live)
                 push_front(X.F, ((uint64_t)p << 32) | p, live, A.fkey[0], A.flive[0], A.front_cap,
                            &A.ctl->size[0], &A.ctl->flags);
-            const uint32_t v = p / kPairStride;
-            if (wants_record(A, v))
+            if (want)
                 push_record(X.R, ((uint64_t)v << 32) | p, A.rec, A.rec_cap, &A.ctl->records,
                             &A.ctl->flags);
         }
@@ -602,12 +609,13 @@ __device__ __forceinline__ void tail_visit(const WinArgs &A, TailShared &T, uint
                                            uint32_t &visits) {
     const uint32_t q = w * kPairStride + i;
     ++scans;
+    const bool want = wants_record(A, w);
     uint64_t live;
-    if (claim(A, q, src, hashed, live) == 1) {
+    if (claim(A, q, src, want, hashed, live) == 1) {
         ++visits;
         if (live) tail_push(T, nxt, ((uint64_t)q << 32) | src, live, gkey, glive, A.front_cap,
                             &A.ctl->flags);
-        if (wants_record(A, w)) {
+        if (want) {
             const uint32_t pos = stage_slots(&T.R.n);
             if (pos < kStageR) {
                 T.R.buf[pos] = ((uint64_t)w << 32) | src;
