@@ -73,15 +73,23 @@ struct Retry {
 // Level L of a window's search reads front[L % 2] (size[L % 3] entries) and
 // appends level L + 1 to front[(L + 1) % 2], counting in size[(L + 1) % 3];
 // it also clears size[(L + 2) % 3] for the level after.
-struct Ctl {
-    unsigned long long size[3];   // frontier sizes, ring over levels
-    unsigned long long scans;     // live in-edges scanned (work counter)
-    unsigned long long hinserts;  // hash-set insertions in this window
-    unsigned long long records;   // records appended (all windows)
-    unsigned long long full;      // nodes holding k records
-    unsigned long long visits;    // accepted visits (work counter)
-    uint32_t flags;               // overflow bits
-    uint32_t level;               // level reached by the tail kernel
+// Every counter has a 128-byte line of its own: device atomics on one line
+// are serialised (about 12 ns each on the MI355X, whichever word of the
+// line they hit), so counters sharing a line would queue behind each other.
+struct alignas(128) Ctl {
+    unsigned long long size[3 * 16];  // frontier sizes, ring over levels: size[16 j]
+    unsigned long long scans;         // live in-edges scanned (work counter)
+    char pad0[120];
+    unsigned long long hinserts;      // hash-set insertions in this window
+    char pad1[120];
+    unsigned long long records;       // records appended (all windows)
+    char pad2[120];
+    unsigned long long full;          // nodes holding k records
+    char pad3[120];
+    unsigned long long visits;        // accepted visits (work counter)
+    char pad4[120];
+    uint32_t flags;                   // overflow bits
+    uint32_t level;                   // level reached by the tail kernel
 };
 
 // ------------------------------------------------------- 2. rank windows
@@ -407,6 +415,36 @@ struct ExpandShared {
     uint32_t nheavy;
 };
 
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
+    const uint32_t lo = __shfl_xor((uint32_t)x, m), hi = __shfl_xor((uint32_t)(x >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Adds this workgroup's sums of up to three counters with one device atomic
+// each (per-wave atomics at the end of a launch would all queue on the
+// counters' lines).  Called by every thread; `scratch` holds 3 words per
+// wave of LDS that is free at this point.
+__device__ __forceinline__ void block_add3(uint64_t *scratch, unsigned long long *c0, uint32_t x0,
+                                           unsigned long long *c1, uint32_t x1,
+                                           unsigned long long *c2, uint32_t x2) {
+    unsigned long long v[3] = {x0, x1, x2};
+    for (int j = 0; j < 3; ++j)
+        for (int off = 32; off > 0; off >>= 1) v[j] += shfl_xor_u64(v[j], off);
+    const uint32_t wave = threadIdx.x / 64, waves = (blockDim.x + 63) / 64;
+    __syncthreads();
+    if (lane_id() == 0)
+        for (int j = 0; j < 3; ++j) scratch[3 * wave + j] = v[j];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long *c[3] = {c0, c1, c2};
+        for (int j = 0; j < 3; ++j) {
+            unsigned long long t = 0;
+            for (uint32_t w = 0; w < waves; ++w) t += scratch[3 * w + j];
+            if (t && c[j]) atomicAdd(c[j], t);
+        }
+    }
+}
+
 // One live in-edge w -> v of the expanded pair (v, i), taken by the search
 // of source pair src.
 __device__ __forceinline__ void visit_edge(const WinArgs &A, uint32_t w, uint32_t i, uint32_t src,
@@ -505,15 +543,15 @@ __global__ void __launch_bounds__(kBlock) k_seed_window(WinArgs A, const uint32_
             ++visits;
             if (live)
                 push_front(X.F, ((uint64_t)p << 32) | p, live, A.fkey[0], A.flive[0], A.front_cap,
-                           &A.ctl->size[0], &A.ctl->flags);
+                           &A.ctl->size[16 * (0)], &A.ctl->flags);
             if (want)
                 push_record(X.R, ((uint64_t)v << 32) | p, A.rec, A.rec_cap, &A.ctl->records,
                             &A.ctl->flags);
         }
-        stage_flush2(X.F, A.fkey[0], A.flive[0], A.front_cap, &A.ctl->size[0], X.R, A.rec,
+        stage_flush2(X.F, A.fkey[0], A.flive[0], A.front_cap, &A.ctl->size[16 * (0)], X.R, A.rec,
                      A.rec_cap, &A.ctl->records, &A.ctl->flags);
     }
-    wave_add(&A.ctl->visits, visits);
+    block_add3(X.R.buf, &A.ctl->visits, visits, nullptr, 0, nullptr, 0);
 }
 
 // Level L of the window's search, on the whole grid; each block takes
@@ -525,17 +563,15 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32
     if (threadIdx.x == 0) {
         X.F.n = X.R.n = X.nheavy = 0;
         s_flags = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s_size = A.ctl->size[L % 3];
-        if (blockIdx.x == 0) A.ctl->size[(L + 2) % 3] = 0;  // counter of level L + 2
+        s_size = A.ctl->size[16 * (L % 3)];
+        if (blockIdx.x == 0) A.ctl->size[16 * ((L + 2) % 3)] = 0;  // counter of level L + 2
     }
     __syncthreads();
     uint32_t scans = 0, hashed = 0, visits = 0;
     if (!s_flags && s_size) {  // after an overflow the windows are redone with more room
-        expand_range(A, L, &A.ctl->size[(L + 1) % 3], s_size, chunk, X, scans, hashed, visits);
+        expand_range(A, L, &A.ctl->size[16 * ((L + 1) % 3)], s_size, chunk, X, scans, hashed, visits);
     }
-    wave_add(&A.ctl->scans, scans);
-    wave_add(&A.ctl->hinserts, hashed);
-    wave_add(&A.ctl->visits, visits);
+    block_add3(X.R.buf, &A.ctl->scans, scans, &A.ctl->hinserts, hashed, &A.ctl->visits, visits);
 }
 
 // Pair records at the start of a build: the initial state word and the
@@ -636,7 +672,7 @@ __global__ void __launch_bounds__(kTailBlock) k_tail(WinArgs A, uint32_t L0, uin
     __shared__ TailShared T;
     const uint32_t tid = threadIdx.x;
     if (tid == 0) {
-        const unsigned long long f = A.ctl->size[L0 % 3];
+        const unsigned long long f = A.ctl->size[16 * (L0 % 3)];
         const uint32_t fl =
             __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         T.stop = f == 0 || f > kTailCap || fl != 0;
@@ -760,19 +796,18 @@ __global__ void __launch_bounds__(kTailBlock) k_tail(WinArgs A, uint32_t L0, uin
             A.flive[L & 1][t] = T.live[cur][t];
         }
     if (tid == 0) {
-        A.ctl->size[L % 3] = T.give ? nn : 0;
-        A.ctl->size[(L + 1) % 3] = 0;
+        A.ctl->size[16 * (L % 3)] = T.give ? nn : 0;
+        A.ctl->size[16 * ((L + 1) % 3)] = 0;
         A.ctl->level = L;
     }
-    wave_add(&A.ctl->scans, scans);
-    wave_add(&A.ctl->visits, visits);
+    block_add3(T.R.buf, &A.ctl->scans, scans, &A.ctl->visits, visits, nullptr, 0);
 }
 
 // Start of a window (or of its redo): clear the per-window fields and set
 // the running counters to their values at the window start.
 __global__ void k_ctl_begin(Ctl *ctl, unsigned long long visits, unsigned long long scans,
                             unsigned long long records) {
-    ctl->size[0] = ctl->size[1] = ctl->size[2] = 0;
+    ctl->size[16 * (0)] = ctl->size[16 * (1)] = ctl->size[16 * (2)] = 0;
     ctl->hinserts = 0;
     ctl->flags = 0;
     ctl->visits = visits;
@@ -788,6 +823,7 @@ __global__ void k_ctl_begin(Ctl *ctl, unsigned long long visits, unsigned long l
 // Eight lanes per node, each summing the state words of eight consecutive
 // pairs.
 __global__ void k_want(const uint64_t *prec, uint32_t n, uint32_t k, uint8_t *want, Ctl *ctl) {
+    __shared__ uint64_t scratch[3 * (kBlock / 64)];
     uint32_t full = 0;
     const uint64_t lanes = (uint64_t)n * 8;
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < ((lanes + 63) & ~63ull);
@@ -808,7 +844,7 @@ __global__ void k_want(const uint64_t *prec, uint32_t n, uint32_t k, uint8_t *wa
             full += !w;
         }
     }
-    wave_add(&ctl->full, full);
+    block_add3(scratch, &ctl->full, full, nullptr, 0, nullptr, 0);
 }
 
 // Segment [start[v], end[v]) of node v in the records sorted by node.
@@ -1065,7 +1101,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
                                      w, h.flags, h.hinserts, (unsigned long long)hsize);
                     break;
                 }
-                const uint64_t f = h.size[L % 3];
+                const uint64_t f = h.size[16 * (L % 3)];
                 if (f == 0) break;  // empty frontier: window done
                 if (debug2)
                     std::fprintf(stderr, "skim window %u level %u: frontier %llu hashed %llu\n", w,
