@@ -153,13 +153,23 @@ __global__ void __launch_bounds__(kQBlock) k_query_persistent(QArgs Q, uint64_t 
     __shared__ uint16_t mpos[kMaxMembers];
     __shared__ uint16_t mlim[kMaxMembers];
     __shared__ unsigned long long jcur;
+    // Queries are taken in runs that shrink as the batch drains (at most 32,
+    // about a quarter of an even share of what is left): takes from
+    // different waves on the one counter are serialised by the hardware, so
+    // one query per take would cap the batch at the counter's rate.
+    const uint64_t share = 4ull * gridDim.x;
+    uint64_t g = q / share;
+    g = g < 1 ? 1 : g > 32 ? 32 : g;
     for (;;) {
-        if (threadIdx.x == 0) jcur = atomicAdd(next, 1ull);
+        if (threadIdx.x == 0) jcur = atomicAdd(next, (unsigned long long)g);
         __syncthreads();
-        const uint64_t j = jcur;
+        const uint64_t j0 = jcur;
         __syncthreads();
-        if (j >= q) break;
-        answer_query(Q, j, mnode, mpos, mlim);
+        if (j0 >= q) break;
+        const uint64_t j1 = j0 + g < q ? j0 + g : q;
+        for (uint64_t j = j0; j < j1; ++j) answer_query(Q, j, mnode, mpos, mlim);
+        g = (q - j1) / share;
+        g = g < 1 ? 1 : g > 32 ? 32 : g;
     }
 }
 
