@@ -60,7 +60,7 @@ void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, u
 
 namespace {
 
-constexpr uint32_t kOvfHash = 2u, kOvfRecords = 4u, kOvfSpill = 8u, kOvfLiveList = 16u;
+constexpr uint32_t kOvfHash = 2u, kOvfRecords = 4u, kOvfSpill = 8u;
 constexpr int kBlock = 256;
 
 // Thrown inside the build when a buffer was too small; the windows restart
@@ -240,8 +240,6 @@ __global__ void k_rehash(const uint64_t *old, uint64_t old_size, uint64_t *T, ui
 // pair's live in-list, read by the claim in the same cache line.  The list
 // word is 0 for no live in-edge, bit 63 | u for the single source u, else
 // begin << 24 | count into the live-source array.
-constexpr uint64_t kLiveOne = 1ull << 63;
-constexpr uint32_t kLiveCountBits = 24;
 
 struct WinArgs {
     uint64_t *prec;        // [2 * 64 n] state word, live-list word per pair
@@ -575,21 +573,12 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32
 }
 
 // Pair records at the start of a build: the initial state word and the
-// live-list word of every pair (from the runs of live in-lists).
-__global__ void k_pair_init(const uint64_t *lbeg, const uint64_t *lend, const uint32_t *lsrc,
-                            uint64_t npairs, uint64_t *prec, uint32_t *flags) {
+// pair's live-list word.
+__global__ void k_pair_init(const uint64_t *live, uint64_t npairs, uint64_t *prec) {
     for (uint64_t q = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; q < npairs;
          q += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t b = lbeg[q], c = lend[q] - b;
-        uint64_t live = 0;
-        if (c == 1) {
-            live = kLiveOne | lsrc[b];
-        } else if (c > 1) {
-            if (c >> kLiveCountBits) atomicOr(flags, kOvfLiveList);
-            live = (b << kLiveCountBits) | c;
-        }
         prec[2 * q] = kWordInit;
-        prec[2 * q + 1] = live;
+        prec[2 * q + 1] = live[q];
     }
 }
 
@@ -975,8 +964,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
     Ctl *ctl = A.alloc<Ctl>(1);
     fill_u64((uint64_t *)ctl, 0, sizeof(Ctl) / 8, s);
     uint64_t *prec = A.alloc<uint64_t>(2 * npairs);
-    k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(live.beg, live.end, live.adj,
-                                                                  npairs, prec, &ctl->flags);
+    k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(live.live, npairs, prec);
     SKIM_LAUNCH_CHECK();
     uint8_t *want = A.alloc<uint8_t>((uint64_t)n + 4);
     fill_u32((uint32_t *)want, 0x01010101u, (n + 3) / 4, s);  // no records yet: all record
@@ -1209,8 +1197,8 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
             }
             if (overflow & kOvfRecords) grow_u64(rec, rec_cap, base.records, 2 * rec_cap);
             if (w == 0) {
-                k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(
-                    live.beg, live.end, live.adj, npairs, prec, &ctl->flags);
+                k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(live.live, npairs,
+                                                                              prec);
                 SKIM_LAUNCH_CHECK();
             } else {
                 SKIM_HIP(hipMemcpyAsync(prec, snap, 2 * npairs * sizeof(uint64_t),
@@ -1369,10 +1357,6 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
             break;
         } catch (const Retry &r) {
             retry_flags |= r.flags;
-            if (r.flags & kOvfLiveList) {
-                set_error("a pair has 2^%u or more live in-edges", kLiveCountBits);
-                throw Fail{SKIM_EUNSUPPORTED};
-            }
             if (std::getenv("SKIM_DEBUG"))
                 std::fprintf(stderr, "skim restart %d: flags %u\n", attempt, r.flags);
             if (attempt >= 6) {

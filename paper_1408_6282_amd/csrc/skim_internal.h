@@ -185,12 +185,18 @@ struct LiveLists {
 LiveLists build_live_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
                            bool forward, Arena &a, LiveLists *also_other = nullptr);
 
-// Live in-lists of every pair as runs of one array: adj[beg[p] .. end[p])
-// = sources u of edges (u -> v) live in instance i, p = 64 v + i, in edge
-// order (beg = end = 0 for a pair without live in-edges).  Built with no
-// atomics: per-edge prefix offsets and a radix sort by pair.
+// Live-list word of a pair: 0 for no live in-edge, kLiveOne | u for the
+// single source u, else begin << kLiveCountBits | count into the sources.
+constexpr uint64_t kLiveOne = 1ull << 63;
+constexpr uint32_t kLiveCountBits = 24;
+
+// Live in-lists of every pair as runs of one array: the sources u of edges
+// (u -> v) live in instance i, p = 64 v + i, in edge order, located by the
+// pair's live-list word live[p].  Built with no atomics: per-edge prefix
+// offsets and a radix sort by pair.  A list of 2^kLiveCountBits entries or
+// more gives SKIM_EUNSUPPORTED.
 struct PairLists {
-    uint64_t *beg = nullptr, *end = nullptr;  // [64 n]
+    uint64_t *live = nullptr;  // [64 n]
     uint32_t *adj = nullptr;
     uint64_t nlive = 0;
 };

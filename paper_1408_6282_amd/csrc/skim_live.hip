@@ -94,15 +94,28 @@ __global__ void k_live_emit(const uint32_t *esrc, const uint32_t *col, const uin
     }
 }
 
-__global__ void k_live_runs(const uint64_t *ent, uint64_t nlive, uint64_t *beg, uint64_t *end,
-                            uint32_t *adj) {
+// Runs of the sorted entries: the first entry of a pair's run leaves its
+// index in live[p], the last one turns it into the pair's live-list word.
+__global__ void k_live_run_starts(const uint64_t *ent, uint64_t nlive, uint64_t *live,
+                                  uint32_t *adj) {
     for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nlive;
          t += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t x = ent[t];
         const uint32_t p = (uint32_t)(x >> 32);
         adj[t] = (uint32_t)x;
-        if (t == 0 || (uint32_t)(ent[t - 1] >> 32) != p) beg[p] = t;
-        if (t + 1 == nlive || (uint32_t)(ent[t + 1] >> 32) != p) end[p] = t + 1;
+        if (t == 0 || (uint32_t)(ent[t - 1] >> 32) != p) live[p] = t;
+    }
+}
+
+__global__ void k_live_run_ends(const uint64_t *ent, uint64_t nlive, uint64_t *live,
+                                uint32_t *too_long) {
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nlive;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t p = (uint32_t)(ent[t] >> 32);
+        if (t + 1 < nlive && (uint32_t)(ent[t + 1] >> 32) == p) continue;
+        const uint64_t b = live[p], c = t + 1 - b;
+        if (c >> kLiveCountBits) atomicOr(too_long, 1u);
+        live[p] = c == 1 ? kLiveOne | (uint32_t)ent[t] : (b << kLiveCountBits) | c;
     }
 }
 
@@ -115,10 +128,8 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     const uint64_t m = g->m;
     const uint64_t npairs = (uint64_t)n * kPairStride;
     PairLists L;
-    L.beg = a.alloc<uint64_t>(npairs);
-    L.end = a.alloc<uint64_t>(npairs);
-    fill_u64(L.beg, 0, npairs, s);
-    fill_u64(L.end, 0, npairs, s);
+    L.live = a.alloc<uint64_t>(npairs);
+    fill_u64(L.live, 0, npairs, s);
     if (!m) {
         L.adj = a.alloc<uint32_t>(1);
         return L;
@@ -157,9 +168,19 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     SKIM_HIP(rocprim::radix_sort_keys(tmp, tb, ent, sorted, (size_t)tot, 32, 32 + pair_bits, s));
     a.release(tmp);
     a.release(ent);
-    k_live_runs<<<grid_for(tot, 256, 65536), 256, 0, s>>>(sorted, tot, L.beg, L.end, L.adj);
+    uint32_t *too_long = a.alloc<uint32_t>(1);
+    fill_u32(too_long, 0, 1, s);
+    k_live_run_starts<<<grid_for(tot, 256, 65536), 256, 0, s>>>(sorted, tot, L.live, L.adj);
+    SKIM_LAUNCH_CHECK();
+    k_live_run_ends<<<grid_for(tot, 256, 65536), 256, 0, s>>>(sorted, tot, L.live, too_long);
     SKIM_LAUNCH_CHECK();
     a.release(sorted);
+    uint32_t bad = 0;
+    read_back(&bad, too_long, sizeof bad, s);
+    if (bad) {
+        set_error("a pair has 2^%u or more live in-edges", kLiveCountBits);
+        throw Fail{SKIM_EUNSUPPORTED};
+    }
     return L;
 }
 
