@@ -60,13 +60,14 @@ struct GreedyDone {
     skim_status status;
 };
 
+// A batch of q queries moves in one copy each way: in = q + 1 offsets
+// (8 B) followed by the member nodes (4 B), out = q estimates (8 B)
+// followed by q statuses (4 B).
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t ev = nullptr;
-    uint64_t *h_off = nullptr, *d_off = nullptr;
-    uint32_t *h_nodes = nullptr, *d_nodes = nullptr;
-    double *h_est = nullptr, *d_est = nullptr;
-    int32_t *h_st = nullptr, *d_st = nullptr;
+    uint8_t *h_in = nullptr, *d_in = nullptr;    // pinned / device
+    uint8_t *h_out = nullptr, *d_out = nullptr;  // pinned / device
     unsigned long long *d_next = nullptr;
     uint32_t cap_q = 0;
     uint64_t cap_nodes = 0;
@@ -113,9 +114,12 @@ struct skim_server {
 void skim_server::retire(Slot &sl) {
     const auto now = Clock::now();
     std::lock_guard<std::mutex> lk(mu);
-    for (size_t j = 0; j < sl.reqs.size(); ++j) {
+    const size_t q = sl.reqs.size();
+    const double *est = (const double *)sl.h_out;
+    const int32_t *st = (const int32_t *)(sl.h_out + q * 8);
+    for (size_t j = 0; j < q; ++j) {
         auto &r = sl.reqs[j];
-        done[r.ticket] = {sl.h_est[j], sl.h_st[j],
+        done[r.ticket] = {est[j], st[j],
                           std::chrono::duration<double, std::micro>(now - r.t0).count()};
         inflight_bytes -= r.bytes;
     }
@@ -136,37 +140,37 @@ bool skim_server::launch_batch(Slot &sl) {
     }
     if (sl.reqs.empty()) return false;
     const uint64_t q = sl.reqs.size();
+    uint64_t *h_off = (uint64_t *)sl.h_in;
+    uint32_t *h_nodes = (uint32_t *)(sl.h_in + (q + 1) * 8);
     uint64_t o = 0;
     for (uint64_t j = 0; j < q; ++j) {
-        sl.h_off[j] = o;
+        h_off[j] = o;
         const auto &nd = sl.reqs[j].nodes;
-        if (!nd.empty()) std::memcpy(sl.h_nodes + o, nd.data(), nd.size() * 4);
+        if (!nd.empty()) std::memcpy(h_nodes + o, nd.data(), nd.size() * 4);
         o += nd.size();
     }
-    sl.h_off[q] = o;
+    h_off[q] = o;
     hipStream_t s = sl.stream;
-    (void)hipMemcpyAsync(sl.d_off, sl.h_off, (q + 1) * 8, hipMemcpyHostToDevice, s);
-    if (o) (void)hipMemcpyAsync(sl.d_nodes, sl.h_nodes, o * 4, hipMemcpyHostToDevice, s);
+    (void)hipMemcpyAsync(sl.d_in, sl.h_in, (q + 1) * 8 + o * 4, hipMemcpyHostToDevice, s);
     skim::QueryArgs Q = base;
     Q.q = q;
-    Q.qoff = sl.d_off;
-    Q.qnodes = sl.d_nodes;
-    Q.est = sl.d_est;
-    Q.qstatus = sl.d_st;
+    Q.qoff = (const uint64_t *)sl.d_in;
+    Q.qnodes = (const uint32_t *)(sl.d_in + (q + 1) * 8);
+    Q.est = (double *)sl.d_out;
+    Q.qstatus = (int32_t *)(sl.d_out + q * 8);
     try {
         skim::launch_queries_async(Q, q, sl.d_next, s);
     } catch (const skim::Fail &) {
         // mark the batch failed; its requests complete with status -5
         for (uint64_t j = 0; j < q; ++j) {
-            sl.h_est[j] = 0.0;
-            sl.h_st[j] = -5;
+            ((double *)sl.h_out)[j] = 0.0;
+            ((int32_t *)(sl.h_out + q * 8))[j] = -5;
         }
         (void)hipStreamSynchronize(s);
         retire(sl);
         return true;
     }
-    (void)hipMemcpyAsync(sl.h_est, sl.d_est, q * 8, hipMemcpyDeviceToHost, s);
-    (void)hipMemcpyAsync(sl.h_st, sl.d_st, q * 4, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(sl.h_out, sl.d_out, q * 12, hipMemcpyDeviceToHost, s);
     (void)hipEventRecord(sl.ev, s);
     sl.busy = true;
     return true;
@@ -293,14 +297,12 @@ extern "C" skim_status skim_server_create(const uint64_t *ranks, const uint32_t 
             sl.cap_nodes = cap_nodes;
             SKIM_HIP(hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking));
             SKIM_HIP(hipEventCreateWithFlags(&sl.ev, hipEventDisableTiming));
-            SKIM_HIP(hipHostMalloc((void **)&sl.h_off, (sl.cap_q + 1) * 8, hipHostMallocDefault));
-            SKIM_HIP(hipHostMalloc((void **)&sl.h_nodes, cap_nodes * 4, hipHostMallocDefault));
-            SKIM_HIP(hipHostMalloc((void **)&sl.h_est, sl.cap_q * 8, hipHostMallocDefault));
-            SKIM_HIP(hipHostMalloc((void **)&sl.h_st, sl.cap_q * 4, hipHostMallocDefault));
-            SKIM_HIP(hipMalloc((void **)&sl.d_off, (sl.cap_q + 1) * 8));
-            SKIM_HIP(hipMalloc((void **)&sl.d_nodes, cap_nodes * 4));
-            SKIM_HIP(hipMalloc((void **)&sl.d_est, sl.cap_q * 8));
-            SKIM_HIP(hipMalloc((void **)&sl.d_st, sl.cap_q * 4));
+            const size_t in_bytes = ((size_t)sl.cap_q + 1) * 8 + cap_nodes * 4;
+            const size_t out_bytes = (size_t)sl.cap_q * 12;
+            SKIM_HIP(hipHostMalloc((void **)&sl.h_in, in_bytes, hipHostMallocDefault));
+            SKIM_HIP(hipHostMalloc((void **)&sl.h_out, out_bytes, hipHostMallocDefault));
+            SKIM_HIP(hipMalloc((void **)&sl.d_in, in_bytes));
+            SKIM_HIP(hipMalloc((void **)&sl.d_out, out_bytes));
             SKIM_HIP(hipMalloc((void **)&sl.d_next, 8));
         }
         SKIM_HIP(hipStreamCreateWithFlags(&sv->gstream, hipStreamNonBlocking));
@@ -322,15 +324,11 @@ extern "C" void skim_server_destroy(skim_server *sv) {
     if (sv->gworker.joinable()) sv->gworker.join();
     for (auto &sl : sv->slots) {
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-        (void)hipFree(sl.d_off);
-        (void)hipFree(sl.d_nodes);
-        (void)hipFree(sl.d_est);
-        (void)hipFree(sl.d_st);
+        (void)hipFree(sl.d_in);
+        (void)hipFree(sl.d_out);
         (void)hipFree(sl.d_next);
-        (void)hipHostFree(sl.h_off);
-        (void)hipHostFree(sl.h_nodes);
-        (void)hipHostFree(sl.h_est);
-        (void)hipHostFree(sl.h_st);
+        (void)hipHostFree(sl.h_in);
+        (void)hipHostFree(sl.h_out);
         if (sl.ev) (void)hipEventDestroy(sl.ev);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
     }
