@@ -32,6 +32,7 @@ namespace skim {
 namespace {
 
 constexpr int kSkimBlock = 1024;
+constexpr uint32_t kSkimLdsNodes = 8192;  // graphs up to this size keep size[] in LDS
 constexpr uint32_t kFlagPool = 1u;
 
 struct SkCtl {
@@ -82,8 +83,20 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
     __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_total;
     __shared__ int s_x;
     __shared__ uint32_t s_found, s_stop;
+    // size[] and the batch counters live in LDS when the graph is small
+    // enough: every pair's search adds to them, and device atomics from
+    // different waves on one cache line are serialised.
+    __shared__ uint32_t s_size[kSkimLdsNodes], s_bcnt[kSkimLdsNodes];
     const uint32_t tid = threadIdx.x;
     const uint32_t n = A.n, k = A.k;
+    const bool in_lds = n <= kSkimLdsNodes;
+    uint32_t *SZ = in_lds ? s_size : A.size;
+    uint32_t *BC = in_lds ? s_bcnt : A.bcnt;
+    if (in_lds)
+        for (uint32_t v = tid; v < n; v += kSkimBlock) {
+            s_size[v] = ld(A.size + v);
+            s_bcnt[v] = 0;
+        }
     uint32_t *Q = A.queues + (uint64_t)tid * n;
     if (tid == 0) {
         s_cursor = A.ctl->cursor;
@@ -124,16 +137,16 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             uint32_t lo = 0, hi = B, T = B;
             for (;;) {
                 if (tid < T)
-                    for (uint32_t j = 0; j < cnt; ++j) atomicAdd(A.bcnt + Q[j], 1u);
+                    for (uint32_t j = 0; j < cnt; ++j) atomicAdd(BC + Q[j], 1u);
                 __syncthreads();
                 bool cand = false;
                 if (tid < T)
-                    for (uint32_t j = 0; j < cnt; ++j) cand |= ld(A.size + Q[j]) + ld(A.bcnt + Q[j]) >= k;
+                    for (uint32_t j = 0; j < cnt; ++j) cand |= ld(SZ + Q[j]) + ld(BC + Q[j]) >= k;
                 if (cand) atomicOr(&s_found, 1u);
                 __syncthreads();
                 const bool f = s_found != 0;
                 if (tid < T)
-                    for (uint32_t j = 0; j < cnt; ++j) st(A.bcnt + Q[j], 0u);
+                    for (uint32_t j = 0; j < cnt; ++j) st(BC + Q[j], 0u);
                 __syncthreads();
                 if (tid == 0) s_found = 0;
                 __syncthreads();
@@ -167,7 +180,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 const unsigned long long off = atomicAdd(&s_pool, (unsigned long long)cnt);
                 for (uint32_t j = 0; j < cnt; ++j) {
                     st(A.pool + off + j, Q[j]);
-                    atomicAdd(A.size + Q[j], 1u);
+                    atomicAdd(SZ + Q[j], 1u);
                 }
                 st(A.idx_off + p, (uint32_t)off);
                 st(A.idx_cnt + p, cnt);
@@ -177,7 +190,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 // the nodes that just reached k are in this pair's search
                 int x = -1;
                 for (uint32_t j = 0; j < cnt; ++j)
-                    if (ld(A.size + Q[j]) >= k && (x < 0 || Q[j] < (uint32_t)x)) x = (int)Q[j];
+                    if (ld(SZ + Q[j]) >= k && (x < 0 || Q[j] < (uint32_t)x)) x = (int)Q[j];
                 s_x = x;
             }
             if (tid == 0) s_cursor = cursor + T;
@@ -192,7 +205,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             for (uint32_t v = tid; v < n; v += kSkimBlock)
                 if (!ld(A.sel + v)) {
                     const unsigned long long key =
-                        ((unsigned long long)ld(A.size + v) << 32) | (0xFFFFFFFFu - v);
+                        ((unsigned long long)ld(SZ + v) << 32) | (0xFFFFFFFFu - v);
                     best = key > best ? key : best;
                 }
             atomicMax(&s_best, best);
@@ -222,7 +235,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                     const uint32_t c = ld(A.idx_cnt + q);
                     if (c) {
                         const uint32_t o = ld(A.idx_off + q);
-                        for (uint32_t j = 0; j < c; ++j) atomicSub(A.size + ld(A.pool + o + j), 1u);
+                        for (uint32_t j = 0; j < c; ++j) atomicSub(SZ + ld(A.pool + o + j), 1u);
                         st(A.idx_cnt + q, 0u);
                     }
                     for (uint64_t e = A.fptr[q]; e < A.fptr[q + 1]; ++e) {
@@ -246,6 +259,10 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         }
         ++done;
         __syncthreads();
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (uint32_t v = tid; v < n; v += kSkimBlock) st(A.size + v, s_size[v]);
     }
     if (tid == 0) {
         A.ctl->cursor = s_cursor;
