@@ -110,7 +110,7 @@ constexpr int kRankPer = 8;  // pairs per thread in the bucketing kernels
 // Every bucket of the sources array is therefore in increasing pair order,
 // and a window's pair records are visited in memory order.
 __global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W, uint32_t b0,
-                            unsigned long long *whist, uint32_t *bcount, uint32_t nblocks) {
+                            uint32_t *bcount, uint32_t nblocks) {
     __shared__ uint32_t h[64];
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
     __syncthreads();
@@ -124,10 +124,13 @@ __global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W,
         }
     }
     __syncthreads();
-    if (threadIdx.x < W) {
-        bcount[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-        if (h[threadIdx.x]) atomicAdd(&whist[threadIdx.x], h[threadIdx.x]);
-    }
+    if (threadIdx.x < W) bcount[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Bucket b starts at boff[b * nblocks] (b = W: the total).
+__global__ void k_bucket_bases(const uint64_t *boff, uint32_t nblocks, uint32_t W,
+                               unsigned long long *wb) {
+    if (threadIdx.x <= W) wb[threadIdx.x] = boff[(uint64_t)threadIdx.x * nblocks];
 }
 
 // Pairs base + j * kBlock + tid, in that order (j outer): within each round
@@ -1319,20 +1322,20 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     // ---- 2. rank buckets
     uint32_t W = 1, b0 = 64;  // W: number of buckets
     choose_buckets(n, k, W, b0);
-    unsigned long long *wbuf = A.alloc<unsigned long long>(64);
-    fill_u64((uint64_t *)wbuf, 0, 64, s);
+    unsigned long long *wbuf = A.alloc<unsigned long long>(65);
     const unsigned rblocks = (unsigned)((nsrc + (uint64_t)kBlock * kRankPer - 1) /
                                         ((uint64_t)kBlock * kRankPer));
     uint32_t *bcount = A.alloc<uint32_t>((uint64_t)W * rblocks);
-    k_rank_hist<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, wbuf, bcount, rblocks);
+    k_rank_hist<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, bcount, rblocks);
     SKIM_LAUNCH_CHECK();
     uint64_t *boff = A.alloc<uint64_t>((uint64_t)W * rblocks + 1);
     exclusive_scan_u32(bcount, boff, (uint64_t)W * rblocks, A);
     A.release(bcount);
-    unsigned long long hw[64] = {};
-    read_back(hw, wbuf, sizeof(unsigned long long) * 64, s);
-    unsigned long long wb[65] = {};
-    for (uint32_t w = 0; w < W; ++w) wb[w + 1] = wb[w] + hw[w];
+    k_bucket_bases<<<1, 128, 0, s>>>(boff, rblocks, W, wbuf);
+    SKIM_LAUNCH_CHECK();
+    unsigned long long wb[65] = {}, hw[64] = {};
+    read_back(wb, wbuf, sizeof(unsigned long long) * (W + 1), s);
+    for (uint32_t w = 0; w < W; ++w) hw[w] = wb[w + 1] - wb[w];
     uint32_t *sources = A.alloc<uint32_t>(nsrc);
     k_rank_scatter<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, boff, rblocks, sources);
     SKIM_LAUNCH_CHECK();
