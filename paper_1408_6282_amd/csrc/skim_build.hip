@@ -8,20 +8,21 @@
 //     instance's coin of each edge (a 64-bit instance mask per edge); the
 //     live (pair, source) entries are written at per-edge prefix offsets
 //     and radix-sorted by pair, so the live in-list of every node-instance
-//     pair p = 64 v + i is one run, built without atomics; each pair's
-//     16-byte record holds its search
-//     state word next to its list (the source itself when the list has one
-//     entry), so a claim reads both in one cache line.  Every expansion
-//     later reads only live in-edges of its own instance, and pairs without
-//     any are never put on a frontier.
+//     pair p = 64 v + i is one run, built without atomics.  Each pair's
+//     16-byte record holds its search state word next to its list word
+//     (the source itself when the list has one entry), so a claim reads
+//     both in one cache line.  Every expansion later reads only live
+//     in-edges of its own instance, and pairs without any are never put on
+//     a frontier.
 //  2. Rank windows.  All pairs are bucketed by the bit length of their
-//     rank: bucket 0 holds about k/2 ranks per instance and each later
-//     bucket doubles the rank range.  A window is a run of buckets: bucket
-//     0 alone, then as many as keep the arrivals per pair (measured on
+//     rank (a stable counting sort, so every bucket is in pair order):
+//     bucket 0 holds about k/2 ranks per instance and each later bucket
+//     doubles the rank range.  A window is a run of buckets: bucket 0
+//     alone, then as many as keep the arrivals per pair (measured on
 //     bucket 0) below k (a pair is pruned only once it has received k
 //     ranks, so merging those buckets costs few extra visits and saves
-//     search levels), later ones two at a time, or one after a window with
-//     many visits per pair.
+//     search levels), later ones window_span at a time, or one after a
+//     window with many visits per pair, and the last bucket alone.
 //     Windows are processed in increasing order.
 //  3. Pruned reverse searches, window by window.  Every source pair (u, i)
 //     of the window runs a reverse search in G^(i).  A visited pair (w, i)
@@ -30,18 +31,26 @@
 //     path to an unpruned pair reaches a subset of what it reaches, an
 //     unpruned pair receives every rank of its instance in the window, so
 //     the rule is exact whatever order the window's searches run in.  All
-//     searches of a window advance together, level by level, one whole-grid
-//     launch per level (levels of small frontiers are launched in batches
-//     without reading their sizes back).  Visits are deduplicated per source
-//     exactly: the first visitor of a pair in the window claims the pair's
-//     state word; later visitors go through a hash set keyed by (pair,
-//     source).  The same word counts the pair's arrivals.
+//     searches of a window advance together, level by level: one
+//     whole-grid launch per level (small frontiers in batches of levels
+//     launched without reading their sizes back), and once the frontier
+//     fits in LDS the remaining levels inside one workgroup.  Visits are
+//     deduplicated per source exactly: the first visitor of a pair in the
+//     window claims the pair's state word; later visitors go through a
+//     hash set keyed by (pair, source).  The same word counts the pair's
+//     arrivals (up to k, all pruning needs).  A visit that could neither
+//     expand nor record (no live in-edge, node no longer recording) is
+//     skipped.
 //  4. Records.  A visit of node v is recorded while v held fewer than k
 //     ranks at the window start; windows go up in rank, so the k smallest
 //     records of v are its sketch.
 //  5. Merge.  Records are sorted by node (radix sort on the node bits) and
 //     each node keeps its k smallest ranks in LDS (bitonic sort), written
 //     ascending.
+//
+// Device atomics from different waves on one 128-byte line are serialised
+// by the hardware, so shared counters sit on lines of their own and are
+// added to once per workgroup.
 #include "skim_internal.h"
 
 #include <rocprim/device/device_radix_sort.hpp>
