@@ -120,11 +120,11 @@ def algorithmic_bytes_build(cnt, n, k):
 
 def visit_model_bytes(cnt):
     """Bytes this design's search touches per unit of work when every access
-    is counted once: per rank insertion the frontier entry (8 B), the live-list
-    bounds (16 B), the claimed state word (8 B) and the new entry (8 B); per
-    live-edge traversal the live source id (4 B) and the visited state word
-    (8 B)."""
-    return cnt["n_ins"] * (8 + 16 + 8 + 8) + cnt["w_live"] * (4 + 8)
+    is counted once: per rank insertion the frontier entry (16 B: pair and
+    source, live-list word) written and read back, the claimed pair record
+    (16 B) and the record (8 B); per live-edge traversal the live source id
+    (4 B) and the visited pair record (16 B)."""
+    return cnt["n_ins"] * (16 + 16 + 16 + 8) + cnt["w_live"] * (4 + 16)
 
 
 def cpu_baseline(g, cfg, max_threads=16):
