@@ -74,9 +74,11 @@ def dominant_source_digest():
 
 
 def measured_traffic(workload):
-    """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None
-    when the summary is missing or was taken on other kernel sources."""
+    """HBM bytes per build of the dominant kernel from the committed
+    rocprofv3 PMC summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated, summed
+    over its launches in one build), or None when the summary is missing or
+    was taken on other kernel sources.  (Launches per build depend on the
+    launch shapes the tuner picks; the bytes per build do not.)"""
     path = os.path.join(ROOT, "profiles", f"{DOMINANT}_{workload.replace('-', '_')}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -86,9 +88,10 @@ def measured_traffic(workload):
             if ":" in line and not line.startswith("#"):
                 key, val = line.split(":", 1)
                 d[key.strip()] = val.strip()
-    if d.get("kernel_source_sha256") != dominant_source_digest():
+    if d.get("kernel_source_sha256") != dominant_source_digest() or \
+            "traffic_bytes_per_build" not in d:
         return None
-    return float(d["traffic_bytes_per_launch"])
+    return float(d["traffic_bytes_per_build"])
 
 
 def calibrate_copy():
@@ -355,7 +358,9 @@ def main():
         per_launch_bytes = alg_bytes * args.steps / klaunch
         avg_s = kms / klaunch / 1e3
         achieved = per_launch_bytes / avg_s / 1e9
-        traffic = measured_traffic(args.workload)
+        per_build = measured_traffic(args.workload)
+        # per launch like `achieved`: this run's launches share the build's bytes
+        traffic = None if per_build is None else per_build * args.steps / klaunch
         roof = {"bound": "hbm", "kernel": DOMINANT, "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "launches_per_step": klaunch / args.steps, "avg_launch_us": avg_s * 1e6,
