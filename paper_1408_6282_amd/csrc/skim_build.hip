@@ -221,30 +221,46 @@ __device__ __forceinline__ uint64_t hmix(uint64_t x) {
     return x;
 }
 
-// 1 = inserted, 0 = already present, -1 = table full.
-__device__ int hset_insert(uint64_t *T, uint32_t logcap, uint64_t key) {
+// Hash-set keys (pair, source).  When pair ids fit in 28 bits, a window
+// tag (1..239) rides in the top nibbles of both halves; keys of earlier
+// windows then count as empty slots and the set needs no clearing between
+// windows.  Tag 0: untagged keys, every non-empty slot is live.
+__device__ __forceinline__ uint64_t hkey(uint32_t q, uint32_t src, uint32_t tag) {
+    return ((uint64_t)(q | ((tag >> 4) << 28)) << 32) | (src | ((tag & 0xFu) << 28));
+}
+__device__ __forceinline__ uint32_t hkey_tag(uint64_t key) {
+    return (uint32_t)(key >> 60) << 4 | ((uint32_t)(key >> 28) & 0xFu);
+}
+__device__ __forceinline__ bool hslot_free(uint64_t cur, uint32_t tag) {
+    return cur == kNone || (tag && hkey_tag(cur) != tag);
+}
+
+// 1 = inserted, 0 = already present, -1 = table full.  Slots only go from
+// free to live within a window, so a probe chain never loses a key.
+__device__ int hset_insert(uint64_t *T, uint32_t logcap, uint64_t key, uint32_t tag) {
     const uint64_t mask = (1ull << logcap) - 1;
     uint64_t h = hmix(key) & mask;
     for (int probe = 0; probe < 256; ++probe) {
         uint64_t cur = load_relaxed(T + h);
         if (cur == key) return 0;
-        if (cur == kNone) {
-            const uint64_t prev = atomicCAS((unsigned long long *)(T + h), kNone, key);
-            if (prev == kNone) return 1;
-            if (prev == key) return 0;
+        if (hslot_free(cur, tag)) {
+            const uint64_t prev = atomicCAS((unsigned long long *)(T + h), cur, key);
+            if (prev == cur) return 1;
+            if (prev == key) return 0;  // else a live key of this window took it
         }
         h = (h + 1) & mask;
     }
     return -1;
 }
 
-// Move every key of a hash set into a larger one.
+// Move every live key of a hash set into a larger, cleared one.
 __global__ void k_rehash(const uint64_t *old, uint64_t old_size, uint64_t *T, uint32_t logcap,
-                         uint32_t *flags) {
+                         uint32_t tag, uint32_t *flags) {
     for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < old_size;
          j += (uint64_t)gridDim.x * blockDim.x) {
         const uint64_t key = old[j];
-        if (key != kNone && hset_insert(T, logcap, key) < 0) atomicOr(flags, kOvfHash);
+        if (!hslot_free(key, tag) && hset_insert(T, logcap, key, tag) < 0)
+            atomicOr(flags, kOvfHash);
     }
 }
 
@@ -258,6 +274,7 @@ struct WinArgs {
     const uint32_t *lsrc;  // live sources of lists with two or more entries
     uint64_t *hset;
     uint32_t logcap;
+    uint32_t htag;         // hash-key tag of this window (0: untagged)
     uint32_t win;          // window id (tag)
     uint32_t k;
     uint32_t last;         // last window: its arrivals are never read
@@ -293,7 +310,7 @@ __device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
             continue;
         }
         if ((uint32_t)old == src) return 0;
-        const int r = hset_insert(A.hset, A.logcap, ((uint64_t)q << 32) | src);
+        const int r = hset_insert(A.hset, A.logcap, hkey(q, src, A.htag), A.htag);
         if (r <= 0) {
             if (r < 0) atomicOr(&A.ctl->flags, kOvfHash);
             return 0;
@@ -988,6 +1005,8 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
     // reallocated by windows that need more.
     uint64_t hset_size = std::min<uint64_t>(cap.hash, 1ull << 29);
     uint64_t *hset = A.alloc<uint64_t>(hset_size);
+    bool hset_clean = false;  // every slot kNone or a tagged key
+    const bool tagged = npairs <= (1ull << 28);  // pair ids leave room for a window tag
     uint64_t *snap = nullptr;  // pair records at the start of a guarded window
     uint64_t *sort_key = nullptr, *sort_live = nullptr, sort_cap = 0;  // sort_frontier
     uint8_t *sort_tmp = nullptr;
@@ -1033,6 +1052,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
         span = std::min<uint32_t>(w == 0 ? 1u : span_next, W - bb);
         if (bb + span == W && span > 1) --span;  // the last bucket (half the ranks) alone
         const uint64_t ws = wb[bb], we = wb[bb + span];
+        const uint32_t htag = tagged ? w + 1 : 0;
         const uint32_t last = bb + span >= W;
         read_back(&h, ctl, sizeof h, s);
         if (h.flags) throw Retry{h.flags};
@@ -1066,13 +1086,21 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
                 if (hset) A.release(hset);
                 hset = A.alloc<uint64_t>(hsize);
                 hset_size = hsize;
+                hset_clean = false;
             }
-            fill_u64(hset, kNone, hsize, s);
+            // tagged keys of earlier windows are free slots: clear only a
+            // set that never was (or a window being redone)
+            if (!tagged) {
+                fill_u64(hset, kNone, hsize, s);
+            } else if (!hset_clean || redo > 0) {
+                fill_u64(hset, kNone, hset_size, s);
+                hset_clean = true;
+            }
             k_ctl_begin<<<1, 1, 0, s>>>(ctl, base.visits, base.scans, base.records);
             SKIM_LAUNCH_CHECK();
             auto args = [&]() {
                 return WinArgs{prec,    live.adj, hset,
-                               logcap,  w,        k,
+                               logcap,  htag,     w,        k,
                                last,    want,     rec,      rec_cap,
                                {fkey[0], fkey[1]}, {flive[0], flive[1]}, front_cap,
                                ctl};
@@ -1126,10 +1154,10 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
                     uint64_t *nt = A.alloc<uint64_t>(ns);
                     fill_u64(nt, kNone, ns, s);
                     k_rehash<<<grid_for(hsize, kBlock, 65536), kBlock, 0, s>>>(hset, hsize, nt, nlog,
-                                                                               &ctl->flags);
+                                                                               htag, &ctl->flags);
                     SKIM_LAUNCH_CHECK();
                     A.release(hset);
-                    hset = nt;
+                    hset = nt;  // cleared, then only this window's keys
                     hset_size = hsize = ns;
                     logcap = nlog;
                     if (debug)
