@@ -17,12 +17,13 @@
 //  2. Rank windows.  All pairs are bucketed by the bit length of their
 //     rank (a stable counting sort, so every bucket is in pair order):
 //     bucket 0 holds about k/2 ranks per instance and each later bucket
-//     doubles the rank range.  A window is a run of buckets: bucket 0
-//     alone, then as many as keep the arrivals per pair (measured on
-//     bucket 0) below k (a pair is pruned only once it has received k
-//     ranks, so merging those buckets costs few extra visits and saves
-//     search levels), later ones window_span at a time, or one after a
-//     window with many visits per pair, and the last bucket alone.
+//     doubles the rank range.  A window is a run of buckets: the first
+//     five (a pair is pruned only once it has received k ranks, so merging
+//     early buckets costs few extra visits and saves search levels); if
+//     that window overflows, the build restarts with bucket 0 alone and
+//     then as many buckets as keep the arrivals per pair (measured on
+//     bucket 0) below k.  Later windows take window_span buckets, or one
+//     after a window with many visits per pair, and the last bucket alone.
 //     Windows are processed in increasing order.
 //  3. Pruned reverse searches, window by window.  Every source pair (u, i)
 //     of the window runs a reverse search in G^(i).  A visited pair (w, i)
@@ -70,6 +71,11 @@ void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, u
 namespace {
 
 constexpr uint32_t kOvfHash = 2u, kOvfRecords = 4u, kOvfSpill = 8u;
+constexpr uint32_t kOvfFirst = 16u;  // the optimistic first window overflowed
+// Buckets of the first window: about 8k ranks per instance, which on graphs
+// with modest reach sets is still below where pruning starts; graphs where
+// it overflows restart with bucket 0 alone.
+constexpr uint32_t kFirstSpan = 5;
 constexpr int kBlock = 256;
 
 // Thrown inside the build when a buffer was too small; the windows restart
@@ -976,7 +982,8 @@ Shapes current_shapes() {
 
 struct Capacity {
     uint64_t rec, front, hash;
-    uint64_t hash_min;  // least hash-set size of a window (raised after an overflow)
+    uint64_t hash_min;    // least hash-set size of a window (raised after an overflow)
+    uint32_t first_span;  // buckets of window 0 (1 after an optimistic one overflowed)
 };
 
 }  // namespace
@@ -1047,9 +1054,9 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
     const double kHeavy = sh.heavy;
     uint64_t prev_visits = 0;
     uint32_t span = 1, span_next = 2;
-    bool merged = false;  // the current window was merged by the bucket-0 rule
+    bool merged = cap.first_span > 1;  // the current window gathers arrivals by design
     for (uint32_t w = 0, bb = 0; bb < W && w < 255; ++w, bb += span) {
-        span = std::min<uint32_t>(w == 0 ? 1u : span_next, W - bb);
+        span = std::min<uint32_t>(w == 0 ? cap.first_span : span_next, W - bb);
         if (bb + span == W && span > 1) --span;  // the last bucket (half the ranks) alone
         const uint64_t ws = wb[bb], we = wb[bb + span];
         const uint32_t htag = tagged ? w + 1 : 0;
@@ -1223,6 +1230,9 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
                 levels_run = L;
                 break;
             }
+            // An optimistic wide first window that overflows is given up:
+            // the build restarts with bucket 0 alone and the measured merge.
+            if (w == 0 && span > 1) throw Retry{overflow | kOvfFirst};
             if (!guard || redo >= 6) throw Retry{overflow};
             // redo the window with more room
             if (overflow & kOvfHash) hsize = std::max(16 * hsize, next_pow2(4 * h.hinserts));
@@ -1258,7 +1268,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
                 per_pair > kHeavy * (merged ? std::max(1.0, span / 2.0) : 1.0);
             uint32_t next = heavy ? 1u : sh.window_span;
             merged = false;
-            if (w == 0 && !heavy) {
+            if (w == 0 && span == 1 && !heavy) {
                 // Bucket 0 gave each visited pair per_pair arrivals; with no
                 // pruning yet they grow with the source count, which doubles
                 // with every bucket.  While they stay below k nothing can be
@@ -1386,7 +1396,8 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     }
     Capacity cap{std::max<uint64_t>(1ull << 20, 3 * (uint64_t)n * k),
                  std::max<uint64_t>(1ull << 20, 3 * biggest),
-                 next_pow2(std::max<uint64_t>(1ull << 16, 8 * bucket_max)), 1ull << 16};
+                 next_pow2(std::max<uint64_t>(1ull << 16, 8 * bucket_max)), 1ull << 16,
+                 kFirstSpan};
     uint32_t retry_flags = 0;
     int attempt = 0;
     for (;; ++attempt) {
@@ -1404,11 +1415,15 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
                           r.flags);
                 throw Fail{SKIM_ENOMEM};
             }
-            if (r.flags & kOvfRecords) cap.rec *= 2;
-            if (r.flags & kOvfSpill) cap.front *= 2;
-            if (r.flags & kOvfHash) {
-                cap.hash_min *= 16;
-                cap.hash = std::max(cap.hash, cap.hash_min);
+            if (r.flags & kOvfFirst) {
+                cap.first_span = 1;  // the wide first window was too much for this graph
+            } else {
+                if (r.flags & kOvfRecords) cap.rec *= 2;
+                if (r.flags & kOvfSpill) cap.front *= 2;
+                if (r.flags & kOvfHash) {
+                    cap.hash_min *= 16;
+                    cap.hash = std::max(cap.hash, cap.hash_min);
+                }
             }
         }
     }
