@@ -97,7 +97,7 @@ def _load():
                            PD, PI32]
         lib.or_skim.restype = C.c_int
         lib.or_skim.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32, C.c_uint32,
-                                C.c_uint32, P32, P64, C.POINTER(SkimCounters)]
+                                C.c_uint32, P32, P64, P64, P32, C.POINTER(SkimCounters)]
         _lib = lib
     return _lib
 
@@ -244,16 +244,26 @@ def ck_query(ranks, size, k, ell, offsets, nodes):
     return _query(_load().or_ck_query, ranks, size, k, ell, offsets, nodes)
 
 
-def skim(g, seed: int, ell: int, k: int, s: int):
-    """SKIM seeds, exact newly-covered pair counts, counters."""
+def skim(g, seed: int, ell: int, k: int, s: int, records: bool = False):
+    """SKIM seeds, exact newly-covered pair counts, counters.
+
+    With ``records`` also the per-seed tau (uint64 rank of the pair that filled
+    the seed's sketch; 2^64-1 for an exhaustion seed) and second largest sketch
+    k' of the adaptive error estimate: (seeds, gains, tau, second, counters).
+    """
     rp, col, thr = _g(g)
     seeds = np.zeros(max(s, 1), dtype=np.uint32)
     gain = np.zeros(max(s, 1), dtype=np.uint64)
+    tau = np.zeros(max(s, 1), dtype=np.uint64)
+    second = np.zeros(max(s, 1), dtype=np.uint32)
     cnt = SkimCounters()
     rc = _load().or_skim(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell, k, s,
-                         _p(seeds, P32), _p(gain, P64), C.byref(cnt))
+                         _p(seeds, P32), _p(gain, P64), _p(tau, P64), _p(second, P32),
+                         C.byref(cnt))
     if rc == -1:
         raise ValueError("or_skim: bad arguments")
     if rc == -2:
         raise AssertionError("or_skim: reverse search met a covered pair")
+    if records:
+        return seeds[:s], gain[:s], tau[:s], second[:s], cnt.as_dict()
     return seeds[:s], gain[:s], cnt.as_dict()

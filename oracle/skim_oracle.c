@@ -36,7 +36,11 @@
  *                                          (divide by l)
  *   or_union_query ........................ Section 5.1, bottom-k of the union
  *   or_ck_query ........................... Section 5.1, eq. (unionest)
- *   or_skim ............................... Section 4, Algorithm 1
+ *   or_skim ............................... Section 4, Algorithm 1; per-seed
+ *                                          records for the adaptive error
+ *                                          estimate (Section 4, adaptive error
+ *                                          estimation: tau and the second
+ *                                          largest sketch k')
  *
  * Parameter limits: 1 <= l <= 64, k >= 1, n < 2^27.
  */
@@ -612,12 +616,23 @@ static void build_live(const or_graph *g, uint64_t seed, uint32_t i, live_inst *
  * k during the reverse search of one pair, the smallest id is selected; the
  * exhaustion fallback takes the largest size among unselected nodes,
  * smallest id on ties.  out_seeds[s], out_gain[s] = newly covered pairs
- * (l times the marginal influence).  Returns 0, or -1 on bad arguments,
- * or -2 if the reverse search of an uncovered pair met a covered pair (an
- * internal invariant; cannot happen). */
+ * (l times the marginal influence).
+ *
+ * Records for the adaptive error estimate (may be NULL), taken at the moment
+ * the seed is chosen, before its residual update:
+ *   out_tau[s]    the rank of the pair whose reverse search filled the seed's
+ *                 sketch; OR_NONE for a seed of the exhaustion rule;
+ *   out_second[s] the second largest sketch: the largest size among the other
+ *                 unselected nodes, not counting the pair of rank tau (a node
+ *                 that pair's search reached counts one less), so it is at
+ *                 most k-1; for an exhaustion seed, the largest size among
+ *                 the other unselected nodes.
+ * Returns 0, or -1 on bad arguments, or -2 if the reverse search of an
+ * uncovered pair met a covered pair (an internal invariant; cannot happen). */
 int or_skim(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, const uint32_t *thr,
             uint64_t seed, uint32_t ell, uint32_t k, uint32_t s,
-            uint32_t *out_seeds, uint64_t *out_gain, or_skim_counters *counters)
+            uint32_t *out_seeds, uint64_t *out_gain, uint64_t *out_tau, uint32_t *out_second,
+            or_skim_counters *counters)
 {
     if (ell < 1 || ell > 64 || k < 1 || s > n || n == 0) return -1;
     or_graph g = {n, row_ptr, col, thr};
@@ -651,6 +666,7 @@ int or_skim(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, const uint
 
     for (uint32_t it = 0; it < s; it++) {
         int64_t x = -1;
+        uint64_t tau = OR_NONE, last_tag = 0;
         /* Build sketches: pairs by increasing rank, skipping covered ones. */
         while (x < 0 && cursor < npairs) {
             uint32_t packed = pairs[cursor].v;
@@ -682,6 +698,7 @@ int or_skim(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, const uint
                 idx[pid][t] = v;
                 if (size[v] == k && (x < 0 || v < (uint32_t)x)) x = v;
             }
+            if (x >= 0) { tau = pairs[cursor - 1].r; last_tag = tag; }
         }
         if (x < 0) {
             /* every rank processed: largest partial sketch, unselected */
@@ -692,6 +709,16 @@ int or_skim(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, const uint
             }
             cc.fallback++;
         }
+        /* second largest sketch, without the pair of rank tau (whose search
+         * carries the stamp last_tag; 0 when the seed came from exhaustion) */
+        uint32_t second = 0;
+        for (uint32_t v = 0; v < n; v++) {
+            if (selected[v] || v == (uint32_t)x) continue;
+            uint32_t sz = size[v] - (last_tag && stamp[v] == last_tag ? 1u : 0u);
+            if (sz > second) second = sz;
+        }
+        if (out_tau) out_tau[it] = tau;
+        if (out_second) out_second[it] = second;
         /* Residual problem: cover what x reaches in every instance. */
         uint64_t gain = 0;
         for (uint32_t i = 0; i < ell; i++) {
