@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SKIM_ABI_VERSION 3u
+#define SKIM_ABI_VERSION 4u
 
 typedef enum {
     SKIM_OK = 0,
@@ -185,6 +185,54 @@ void skim_greedy_state_free(skim_greedy_state *state);
 
 /* Seeds selected so far by a state (0 for NULL). */
 uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
+
+/*
+ * skim_greedy_records -- per-seed records of a SKIM run for its adaptive
+ * error estimate (Section 4, adaptive error estimation), taken when the seed
+ * is chosen, before its residual update.  For seeds first .. first+count-1
+ * of the run (in selection order):
+ *   tau    [count] out, device, may be NULL: the rank r(v, i) of the pair
+ *          whose reverse search filled the seed's sketch (the seed's
+ *          threshold rank); 2^64 - 1 for a seed chosen by the exhaustion rule.
+ *   second [count] out, device, may be NULL: the second largest sketch k',
+ *          the largest size among the other unselected nodes, where a node
+ *          reached by the search of the pair of rank tau counts one less (so
+ *          k' <= k - 1); for an exhaustion seed, the largest size among the
+ *          other unselected nodes.
+ * first + count must not exceed skim_greedy_state_selected(state)
+ * (SKIM_EINVAL otherwise); tau and second may not both be NULL when count > 0.
+ */
+skim_status skim_greedy_records(const skim_greedy_state *state, uint32_t first, uint32_t count,
+                                uint64_t *tau, uint32_t *second, void *stream);
+
+/*
+ * skim_discrepancy_tail -- confidence distribution of the total discrepancy
+ * of a SKIM seed sequence (Section 4, adaptive error estimation,
+ * eq. (chernoff)).  The discrepancy of seed j is the largest marginal gain of
+ * any node minus the seed's exact gain Delta_j (node-instance pairs).  For a
+ * filled-sketch seed, P[D_j > eps Delta_j] <= (e^-nu / (1-nu)^(1-nu))^mu with
+ * mu = rho(tau_j) Delta_j (1 + eps), nu = 1 - k'_j / mu, rho(T) =
+ * ((T >> 11) + 1) 2^-53 (1 where mu <= k'_j); an exhaustion seed has D_j = 0;
+ * a filled-sketch record with Delta_j = 0 gives no bound.  Each D_j is
+ * rounded up to the grid of step h = max_rel_error * I / bins pairs,
+ * I = sum_j Delta_j, with everything at or beyond bins * h kept in the last
+ * cell, and the per-seed distributions are convolved (treated as
+ * independent, as in the paper).
+ *   s                 number of seeds (records); 0 gives tail = (1, 0, ..., 0).
+ *   tau, second       [s] device: as returned by skim_greedy_records.
+ *   gain_pairs        [s] device: the seeds' gains as returned by skim_greedy.
+ *   bins              1 .. 65536; s * (bins + 1) <= 2^30 (else
+ *                     SKIM_EUNSUPPORTED).
+ *   max_rel_error     > 0, finite: the grid covers total discrepancies of
+ *                     0 .. max_rel_error * I.
+ *   tail              [bins + 1] out, device (double): tail[t] is an upper
+ *                     bound on P[D_1 + ... + D_s >= t h]; tail[0] = 1.
+ *                     With I = 0 the result is (1, 0, ..., 0).
+ * Scratch: 12 * s * (bins + 1) bytes of device memory for the call.
+ */
+skim_status skim_discrepancy_tail(uint32_t s, const uint64_t *tau, const uint32_t *second,
+                                  const uint64_t *gain_pairs, uint32_t bins,
+                                  double max_rel_error, double *tail, void *stream);
 
 /*
  * Serving: a request loop over resident sketches.  Union queries are

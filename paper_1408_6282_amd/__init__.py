@@ -26,7 +26,8 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_server_poll", "skim_server_set_graph", "skim_server_submit_greedy",
            "skim_server_poll_greedy", "skim_server_replay", "skim_set_build_params",
            "skim_get_build_params", "skim_tune_build", "skim_query_plan_create",
-           "skim_query_plan_launch", "skim_query_plan_free"]
+           "skim_query_plan_launch", "skim_query_plan_free", "skim_greedy_records",
+           "skim_discrepancy_tail"]
 
 
 class SkimError(RuntimeError):
@@ -91,6 +92,10 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_free.argtypes = [vp]
     lib.skim_greedy_state_selected.restype = C.c_uint32
     lib.skim_greedy_state_selected.argtypes = [vp]
+    lib.skim_greedy_records.restype = C.c_int
+    lib.skim_greedy_records.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, vp]
+    lib.skim_discrepancy_tail.restype = C.c_int
+    lib.skim_discrepancy_tail.argtypes = [C.c_uint32, vp, vp, vp, C.c_uint32, C.c_double, vp, vp]
     P64 = C.POINTER(C.c_uint64)
     PD = C.POINTER(C.c_double)
     lib.skim_server_create.restype = C.c_int
@@ -311,6 +316,25 @@ def skim_greedy(graph: DeviceGraph, ell: int, k: int, seed: int, s: int, seeds, 
 
 def skim_greedy_state_free(state: GreedyState):
     state.free()
+
+
+def skim_greedy_records(state: GreedyState, first: int, count: int, tau=None, second=None,
+                        stream=None):
+    """Per-seed tau (uint64) and second largest sketch (uint32) of seeds
+    first .. first+count-1 of a SKIM run, into device tensors."""
+    st = load_library().skim_greedy_records(state.handle, first, count, _ptr(tau), _ptr(second),
+                                            _stream(stream))
+    _check("skim_greedy_records", st)
+
+
+def skim_discrepancy_tail(tau, second, gain_pairs, bins: int, max_rel_error: float, tail,
+                          stream=None):
+    """Upper bounds on P[total discrepancy >= t * max_rel_error * I / bins],
+    t = 0..bins, into the float64 device tensor ``tail``; s = len(tau)."""
+    s = 0 if tau is None else int(tau.numel())
+    st = load_library().skim_discrepancy_tail(s, _ptr(tau), _ptr(second), _ptr(gain_pairs), bins,
+                                              float(max_rel_error), _ptr(tail), _stream(stream))
+    _check("skim_discrepancy_tail", st)
 
 
 def skim_timing_enable(kernel: str | None):

@@ -17,15 +17,24 @@
 //    smallest id among them is the seed.
 //  * exhaustion: with every rank processed, the unselected node with the
 //    largest size (smallest id on ties) is the seed.
+//  * records: before the residual update, the rank tau of the pair that filled
+//    the seed's sketch and the second largest sketch k' (largest size among
+//    the other unselected nodes, one less for nodes in that pair's search)
+//    are stored per seed for the adaptive error estimate (Section 4).
 //  * residual: one thread per instance runs the forward search from the seed
 //    over live out-edges, not entering covered pairs; every newly covered
 //    pair counts towards the seed's gain and decrements the size of every
 //    node in its index entry, which is then erased.
+//
+// The adaptive error estimate itself (skim_discrepancy_tail) bounds each
+// seed's discrepancy with eq. (chernoff) on a grid of discrepancy values and
+// convolves the per-seed distributions pairwise in a tree of launches.
 #include "skim_internal.h"
 
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include <memory>
+#include <utility>
 
 namespace skim {
 
@@ -61,6 +70,9 @@ struct SkArgs {
     uint32_t *bcnt;         // [n] per-batch increment counters
     uint32_t *queues;       // [kSkimBlock * n]
     SkCtl *ctl;
+    uint64_t seed;
+    uint64_t *rec_tau;      // [n] per selected seed: rank that filled its sketch
+    uint32_t *rec_second;   // [n] per selected seed: second largest sketch
 };
 
 __device__ __forceinline__ bool in_queue(const uint32_t *Q, uint32_t cnt, uint32_t w) {
@@ -79,10 +91,11 @@ template <class T> __device__ __forceinline__ void st(T *p, T v) {
 }
 
 __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, uint32_t *seeds,
-                                                     uint64_t *gains, double *gain_d) {
-    __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_total;
-    __shared__ int s_x;
-    __shared__ uint32_t s_found, s_stop;
+                                                     uint64_t *gains, double *gain_d,
+                                                     uint64_t *rec_tau, uint32_t *rec_second) {
+    __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_total, s_tau;
+    __shared__ int s_x, s_filler;
+    __shared__ uint32_t s_found, s_stop, s_fill_cnt, s_second;
     // size[] and the batch counters live in LDS when the graph is small
     // enough: every pair's search adds to them, and device atomics from
     // different waves on one cache line are serialised.
@@ -107,7 +120,10 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
     __syncthreads();
     uint32_t done = 0;
     for (uint32_t it = 0; it < goal; ++it) {
-        if (tid == 0) s_x = -1;
+        if (tid == 0) {
+            s_x = -1;
+            s_filler = -1;
+        }
         __syncthreads();
         // ------------------------------------------------ scan pairs by rank
         while (s_x < 0 && s_cursor < A.nsrc) {
@@ -192,6 +208,9 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 for (uint32_t j = 0; j < cnt; ++j)
                     if (ld(SZ + Q[j]) >= k && (x < 0 || Q[j] < (uint32_t)x)) x = (int)Q[j];
                 s_x = x;
+                s_filler = (int)tid;
+                s_fill_cnt = cnt;
+                s_tau = pair_rank(A.seed, p);
             }
             if (tid == 0) s_cursor = cursor + T;
             __syncthreads();
@@ -218,8 +237,32 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             }
             __syncthreads();
         }
-        // ------------------------------------------------- residual problem
         const uint32_t x = (uint32_t)s_x;
+        // ------------------------------------ records for the error estimate
+        // The filling pair's search is still in its thread's queue; the batch
+        // counters are all zero here and mark it while the sizes are scanned.
+        const bool filler = (int)tid == s_filler;
+        if (filler)
+            for (uint32_t j = 0; j < s_fill_cnt; ++j) st(BC + Q[j], 1u);
+        if (tid == 0) s_second = 0;
+        __syncthreads();
+        {
+            uint32_t best2 = 0;
+            for (uint32_t v = tid; v < n; v += kSkimBlock)
+                if (v != x && !ld(A.sel + v)) {
+                    const uint32_t sz = ld(SZ + v) - ld(BC + v);
+                    best2 = sz > best2 ? sz : best2;
+                }
+            if (best2) atomicMax(&s_second, best2);
+        }
+        __syncthreads();
+        if (filler)
+            for (uint32_t j = 0; j < s_fill_cnt; ++j) st(BC + Q[j], 0u);
+        if (tid == 0) {
+            rec_tau[it] = s_filler >= 0 ? (uint64_t)s_tau : ~0ull;
+            rec_second[it] = s_second;
+        }
+        // ------------------------------------------------- residual problem
         if (tid == 0) s_gain = 0;
         __syncthreads();
         if (tid < A.ell) {
@@ -279,6 +322,97 @@ __global__ void k_pair_keys(uint32_t n, uint32_t ell, uint64_t seed, uint64_t *k
         const uint32_t p = (uint32_t)(t / ell) * kPairStride + (uint32_t)(t % ell);
         keys[t] = pair_rank(seed, p);
         vals[t] = p;
+    }
+}
+
+// ------------------------------------------------ adaptive error estimate
+// Section 4 (adaptive error estimation), eq. (chernoff).  Discrepancies are
+// counted on a grid of step h = max_rel_error * I / bins pairs, I the sum of
+// the gains; every distribution is held as its survival function
+// S[j] = P[D >= j h], j = 0..bins, with everything at or beyond bins * h kept
+// in the last cell.
+
+constexpr uint32_t kTailMaxBins = 1u << 16;
+constexpr uint64_t kTailMaxCells = 1ull << 30;  // seeds * (bins + 1)
+constexpr int kTailBlock = 256;
+
+__global__ void __launch_bounds__(kTailBlock) k_tail_total(uint32_t s, const uint64_t *gain,
+                                                           uint64_t *total) {
+    __shared__ unsigned long long acc;
+    if (threadIdx.x == 0) acc = 0;
+    __syncthreads();
+    unsigned long long t = 0;
+    for (uint32_t r = threadIdx.x; r < s; r += kTailBlock) t += gain[r];
+    atomicAdd(&acc, t);
+    __syncthreads();
+    if (threadIdx.x == 0) *total = acc;
+}
+
+// eq. (chernoff) with Z = z and nu = 1 - z / mu, in logarithms:
+// (e^-nu / (1 - nu)^(1 - nu))^mu = exp(z - mu + z ln(mu / z)); 1 when z >= mu.
+__device__ __forceinline__ double chernoff_bound(double mu, double z) {
+    if (z >= mu) return 1.0;
+    if (z == 0.0) return exp(-mu);
+    return exp(z - mu + z * log(mu / z));
+}
+
+// S_r[j] >= P[D_r > (j-1) h] for record r: a seed whose sketch filled at rank
+// tau with second largest sketch k' and gain Delta has
+// P[D > eps Delta] <= bound(mu = rho(tau) Delta (1 + eps), k').  An exhaustion
+// seed (tau = all ones) is exact (D = 0); a filled record with no gain gives
+// no bound (S = 1).
+__global__ void __launch_bounds__(kTailBlock) k_tail_survival(
+    uint32_t s, const uint64_t *tau, const uint32_t *second, const uint64_t *gain,
+    const uint64_t *total, uint32_t bins, double max_rel, double *S) {
+    const uint64_t W = (uint64_t)bins + 1, work = (uint64_t)s * W;
+    const uint64_t I = *total;
+    const double h = max_rel * (double)I / (double)bins;
+    for (uint64_t t = blockIdx.x * (uint64_t)kTailBlock + threadIdx.x; t < work;
+         t += (uint64_t)gridDim.x * kTailBlock) {
+        const uint64_t r = t / W;
+        const uint32_t j = (uint32_t)(t - r * W);
+        double v;
+        if (j == 0) {
+            v = 1.0;
+        } else if (I == 0 || tau[r] == ~0ull) {
+            v = 0.0;
+        } else if (gain[r] == 0) {
+            v = 1.0;
+        } else {
+            const double d = (double)gain[r];
+            const double rho = (double)((tau[r] >> 11) + 1) * 0x1p-53;
+            const double eps = (double)(j - 1) * h / d;
+            const double mu = rho * d * (1.0 + eps);
+            v = fmin(1.0, chernoff_bound(mu, (double)second[r]));
+        }
+        S[t] = v;
+    }
+}
+
+// One level of the pairwise tree: out[p] = the capped sum of rows 2p and
+// 2p+1 of in (an odd last row is copied).  With a[i] = Sa[i] - Sa[i+1],
+//   Sc[j] = P[A + B >= j] = Sa[j+1] + sum_{i <= j} a[i] Sb[j-i],  Sa[bins+1] = 0.
+__global__ void __launch_bounds__(kTailBlock) k_tail_pair(const double *in, double *out,
+                                                          uint32_t rows, uint32_t bins) {
+    const uint64_t W = (uint64_t)bins + 1;
+    const uint64_t outs = ((uint64_t)rows + 1) / 2, work = outs * W;
+    for (uint64_t t = blockIdx.x * (uint64_t)kTailBlock + threadIdx.x; t < work;
+         t += (uint64_t)gridDim.x * kTailBlock) {
+        const uint64_t p = t / W;
+        const uint32_t j = (uint32_t)(t - p * W);
+        const double *a = in + 2 * p * W;
+        double v;
+        if (2 * p + 1 >= rows) {
+            v = a[j];
+        } else {
+            const double *b = a + W;
+            v = j < bins ? a[j + 1] : 0.0;
+            for (uint32_t i = 0; i <= j; ++i) {
+                const double ai = a[i] - (i < bins ? a[i + 1] : 0.0);
+                v += ai * b[j - i];
+            }
+        }
+        out[t] = v;
     }
 }
 
@@ -357,6 +491,9 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
     A.pool_cap = std::max<uint64_t>(1ull << 16, 2 * A.nsrc);
     A.pool = M.alloc<uint32_t>(A.pool_cap);
     A.ctl = M.alloc<SkCtl>(1);
+    A.seed = seed;
+    A.rec_tau = M.alloc<uint64_t>(n);
+    A.rec_second = M.alloc<uint32_t>(n);
     fill_u32(A.covered, 0, npairs, s);
     fill_u32(A.size, 0, n, s);
     fill_u32(A.sel, 0, n, s);
@@ -382,7 +519,8 @@ void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_
     for (int attempt = 0; done < s_goal; ++attempt) {
         SKIM_REQUIRE(attempt < 40, "SKIM index pool did not converge");
         k_skim<<<1, kSkimBlock, 0, s>>>(A, s_goal - done, seeds + done, gains + done,
-                                        gain_d ? gain_d + done : nullptr);
+                                        gain_d ? gain_d + done : nullptr,
+                                        A.rec_tau + st->selected, A.rec_second + st->selected);
         SKIM_LAUNCH_CHECK();
         SkCtl c;
         read_back(&c, A.ctl, sizeof c, s);
@@ -441,4 +579,76 @@ extern "C" void skim_greedy_state_free(skim_greedy_state *state) { delete state;
 
 extern "C" uint32_t skim_greedy_state_selected(const skim_greedy_state *state) {
     return state ? state->selected : 0;
+}
+
+extern "C" skim_status skim_greedy_records(const skim_greedy_state *state, uint32_t first,
+                                           uint32_t count, uint64_t *tau, uint32_t *second,
+                                           void *stream) {
+    skim::clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    try {
+        SKIM_REQUIRE(state != nullptr, "state is NULL");
+        SKIM_REQUIRE(first <= state->selected && count <= state->selected - first,
+                     "records [%u, %u) outside the %u selected seeds", first, first + count,
+                     state->selected);
+        SKIM_REQUIRE(count == 0 || tau || second, "tau and second are both NULL");
+        if (count && tau)
+            SKIM_HIP(hipMemcpyAsync(tau, state->args.rec_tau + first, count * sizeof(uint64_t),
+                                    hipMemcpyDeviceToDevice, hs));
+        if (count && second)
+            SKIM_HIP(hipMemcpyAsync(second, state->args.rec_second + first,
+                                    count * sizeof(uint32_t), hipMemcpyDeviceToDevice, hs));
+        SKIM_HIP(hipStreamSynchronize(hs));
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
+extern "C" skim_status skim_discrepancy_tail(uint32_t s, const uint64_t *tau,
+                                             const uint32_t *second, const uint64_t *gain_pairs,
+                                             uint32_t bins, double max_rel_error, double *tail,
+                                             void *stream) {
+    using namespace skim;
+    clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    try {
+        SKIM_REQUIRE(bins >= 1 && bins <= kTailMaxBins, "bins must be in [1, %u]", kTailMaxBins);
+        SKIM_REQUIRE(max_rel_error > 0.0 && max_rel_error <= 1e300,
+                     "max_rel_error must be positive and finite");
+        SKIM_REQUIRE(tail != nullptr, "tail is NULL");
+        SKIM_REQUIRE(s == 0 || (tau && second && gain_pairs), "tau/second/gain_pairs is NULL");
+        const uint64_t W = (uint64_t)bins + 1;
+        if ((uint64_t)s * W > kTailMaxCells) {
+            set_error("seeds * (bins + 1) exceeds %llu", (unsigned long long)kTailMaxCells);
+            throw Fail{SKIM_EUNSUPPORTED};
+        }
+        if (s == 0) {  // the empty sum is 0 with certainty
+            fill_u64((uint64_t *)tail, 0, W, hs);
+            fill_u64((uint64_t *)tail, 0x3FF0000000000000ull, 1, hs);  // 1.0
+            SKIM_HIP(hipStreamSynchronize(hs));
+            return SKIM_OK;
+        }
+        Arena T(hs);
+        uint64_t *total = T.alloc<uint64_t>(1);
+        double *bufA = T.alloc<double>((uint64_t)s * W);
+        double *bufB = T.alloc<double>(((uint64_t)s + 1) / 2 * W);
+        k_tail_total<<<1, kTailBlock, 0, hs>>>(s, gain_pairs, total);
+        SKIM_LAUNCH_CHECK();
+        k_tail_survival<<<grid_for((uint64_t)s * W, kTailBlock), kTailBlock, 0, hs>>>(
+            s, tau, second, gain_pairs, total, bins, max_rel_error, bufA);
+        SKIM_LAUNCH_CHECK();
+        double *in = bufA, *out = bufB;
+        for (uint32_t rows = s; rows > 1; rows = (rows + 1) / 2) {
+            k_tail_pair<<<grid_for(((uint64_t)rows + 1) / 2 * W, kTailBlock), kTailBlock, 0,
+                          hs>>>(in, out, rows, bins);
+            SKIM_LAUNCH_CHECK();
+            std::swap(in, out);
+        }
+        SKIM_HIP(hipMemcpyAsync(tail, in, W * sizeof(double), hipMemcpyDeviceToDevice, hs));
+        SKIM_HIP(hipStreamSynchronize(hs));
+        return SKIM_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    }
 }

@@ -54,8 +54,9 @@ def gpu_query(ranks_t, size_t, n, k, ell, off, nodes, estimator=0, mode=0):
     return est.cpu().numpy()[:q], st.cpu().numpy()[:q]
 
 
-def gpu_greedy(g, ell, k, seed, chunks, G=None):
-    """Run SKIM in the given chunk sizes with one resumed state; concatenated outputs."""
+def gpu_greedy(g, ell, k, seed, chunks, G=None, records=False):
+    """Run SKIM in the given chunk sizes with one resumed state; concatenated
+    outputs (plus the per-seed tau and second largest sketch with records)."""
     import torch
     import paper_1408_6282_amd as sk
     d = dev()
@@ -73,6 +74,13 @@ def gpu_greedy(g, ell, k, seed, chunks, G=None):
             gains.append(b.cpu().numpy().view(np.uint64)[:s])
             gd.append(c.cpu().numpy()[:s])
         sel = state.selected
+        if records:
+            tau = torch.empty(max(sel, 1), dtype=torch.int64, device=d)
+            sec = torch.empty(max(sel, 1), dtype=torch.int32, device=d)
+            sk.skim_greedy_records(state, 0, sel, tau, sec)
+            torch.cuda.synchronize()
+            rec = (tau.cpu().numpy().view(np.uint64)[:sel], sec.cpu().numpy().view(np.uint32)[:sel])
     finally:
         state.free()
-    return np.concatenate(seeds), np.concatenate(gains), np.concatenate(gd), sel
+    out = (np.concatenate(seeds), np.concatenate(gains), np.concatenate(gd), sel)
+    return out + rec if records else out

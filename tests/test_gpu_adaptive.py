@@ -1,0 +1,156 @@
+"""GPU parity of SKIM's adaptive error estimate (Section 4, adaptive error
+estimation, eq. (chernoff)) against the oracle.
+
+* skim_greedy_records: the per-seed tau and second largest sketch k' equal the
+  oracle's bit for bit (served-SKIM configuration, random graphs into the
+  exhaustion rule, resumed runs, sub-ranges).
+* skim_discrepancy_tail: equal to the oracle's sequential convolution within
+  a tolerance derived from the arithmetic.  The kernel convolves pairwise in
+  a tree and in survival form, the oracle one seed after another in
+  probability-mass form, so the two differ by rounding only: each output is a
+  sum of at most bins + 2 products of numbers in [0, 1] per convolution, with
+  s - 1 convolutions on each side, and the bound itself goes through exp/log
+  (device vs host libm, a few ulps of a value <= 1, relative error about
+  mu * 2^-52 with mu < 10^3 here).  Hence |gpu - oracle| <=
+  s * (bins + 2) * (8 * 2^-53 + 1e-14).
+"""
+import numpy as np
+import pytest
+
+from oracle import adaptive as ad
+from workloads import from_edges
+from workloads.configs import make_config, make_graph
+from brute import random_small_graph
+from gpu_util import dev, gpu_greedy, log, to_dev_u32, to_dev_u64
+
+pytestmark = pytest.mark.gpu
+
+
+def _tol(s, bins):
+    return max(s, 1) * (bins + 2) * (8 * 2.0 ** -53 + 1e-14)
+
+
+def gpu_tail(tau, second, gain, bins, rel):
+    import torch
+    import paper_1408_6282_amd as sk
+    s = len(tau)
+    out = torch.full((bins + 1,), -7.0, dtype=torch.float64, device=dev())
+    if s:
+        sk.skim_discrepancy_tail(to_dev_u64(tau), to_dev_u32(second), to_dev_u64(gain), bins, rel,
+                                 out)
+    else:
+        sk.skim_discrepancy_tail(None, None, None, bins, rel, out)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_records_served_skim_config(oracle_lib):
+    cfg = make_config("served-skim")
+    g = make_graph(cfg)
+    log("records: served-skim 200 seeds in 3 resumed steps")
+    seeds, gains, _, sel, tau, sec = gpu_greedy(g, cfg["ell"], cfg["k"], cfg["seed"],
+                                                [70, 1, 129], records=True)
+    ws, wg, wt, wsec, _ = oracle_lib.skim(g, cfg["seed"], cfg["ell"], cfg["k"], 200, records=True)
+    assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+    assert np.array_equal(tau, wt) and np.array_equal(sec, wsec)
+    for bins, rel in ((1, 0.5), (256, 0.5), (1000, 0.05), (4096, 2.0)):
+        log(f"tail: served-skim 200 seeds bins={bins} rel={rel}")
+        got = gpu_tail(tau, sec, gains, bins, rel)
+        want = ad.discrepancy_tail(wt, wsec, wg, bins, rel)
+        assert np.max(np.abs(got - want)) <= _tol(200, bins)
+        assert got[0] == pytest.approx(1.0, abs=1e-12)
+
+
+@pytest.mark.parametrize("ell,k", [(1, 2), (4, 3), (16, 8), (64, 64)])
+def test_records_random_graphs(oracle_lib, ell, k):
+    rng = np.random.default_rng(ell * 13 + k)
+    for trial in range(4):
+        n = int(rng.integers(2, 80))
+        src, dst, thr = random_small_graph(rng, n, int(rng.integers(0, 3 * n)),
+                                           [0xFFFFFFFF, 0xFFFFFFFF // 2, 0xFFFFFFFF // 10])
+        g = from_edges(n, src, dst, thr)
+        seed = int(rng.integers(0, 2 ** 62))
+        s = n if trial % 2 else int(rng.integers(1, n + 1))  # half run into exhaustion
+        log(f"records ell={ell} k={k} n={n} m={g.m} s={s} seed={seed}")
+        seeds, gains, _, _, tau, sec = gpu_greedy(g, ell, k, seed, [s], records=True)
+        ws, wg, wt, wsec, _ = oracle_lib.skim(g, seed, ell, k, s, records=True)
+        assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+        assert np.array_equal(tau, wt) and np.array_equal(sec, wsec)
+        bins = int(rng.integers(1, 300))
+        got = gpu_tail(tau, sec, gains, bins, 0.3)
+        want = ad.discrepancy_tail(wt, wsec, wg, bins, 0.3)
+        assert np.max(np.abs(got - want)) <= _tol(s, bins)
+
+
+def test_records_sub_range_and_errors():
+    import torch
+    import paper_1408_6282_amd as sk
+    cfg = make_config("tiny-ic")
+    g = make_graph(cfg)
+    G = sk.DeviceGraph.from_host(g, dev())
+    state = sk.GreedyState()
+    try:
+        a = torch.empty(12, dtype=torch.int32, device=dev())
+        b = torch.empty(12, dtype=torch.int64, device=dev())
+        sk.skim_greedy(G, 8, 4, 3, 12, a, b, state=state)
+        full = torch.empty(12, dtype=torch.int64, device=dev())
+        sk.skim_greedy_records(state, 0, 12, full, None)
+        part = torch.empty(5, dtype=torch.int64, device=dev())
+        sec = torch.empty(5, dtype=torch.int32, device=dev())
+        sk.skim_greedy_records(state, 4, 5, part, sec)
+        torch.cuda.synchronize()
+        assert torch.equal(part.cpu(), full.cpu()[4:9])
+        sk.skim_greedy_records(state, 12, 0, None, None)  # empty range is fine
+        for first, count in ((0, 13), (12, 1), (13, 0)):
+            with pytest.raises(sk.SkimError) as ei:
+                sk.skim_greedy_records(state, first, count, full, None)
+            assert ei.value.status == sk.SKIM_EINVAL
+        with pytest.raises(sk.SkimError) as ei:
+            sk.skim_greedy_records(state, 0, 3, None, None)
+        assert ei.value.status == sk.SKIM_EINVAL
+    finally:
+        state.free()
+
+
+def _synthetic(rng, s):
+    tau = rng.integers(1 << 50, 1 << 63, size=s, dtype=np.uint64)
+    tau[rng.random(s) < 0.15] = np.uint64(ad.NONE)
+    gain = rng.integers(1, 3000, size=s).astype(np.uint64)
+    gain[rng.random(s) < 0.05] = 0
+    second = rng.integers(0, 300, size=s).astype(np.uint32)
+    second[rng.random(s) < 0.1] = 0
+    return tau, second, gain
+
+
+@pytest.mark.parametrize("s,bins", [(1, 1), (2, 7), (3, 255), (37, 256), (37, 257), (200, 2048),
+                                    (513, 100), (3, 65536)])
+def test_tail_synthetic_records(s, bins):
+    rng = np.random.default_rng(s * 1009 + bins)
+    tau, second, gain = _synthetic(rng, s)
+    log(f"tail synthetic s={s} bins={bins}")
+    got = gpu_tail(tau, second, gain, bins, 0.25)
+    want = ad.discrepancy_tail(tau, second, gain, bins, 0.25)
+    assert np.max(np.abs(got - want)) <= _tol(s, bins)
+
+
+def test_tail_edge_cases():
+    import torch
+    import paper_1408_6282_amd as sk
+    e = np.eye(1, 17)[0]
+    assert np.array_equal(gpu_tail([], [], [], 16, 0.1), e)                     # no seeds
+    assert np.array_equal(gpu_tail([ad.NONE] * 4, [3, 0, 1, 2], [5, 0, 9, 1], 16, 0.1), e)
+    assert np.array_equal(gpu_tail([1 << 60, 1 << 61], [2, 2], [0, 0], 16, 0.1), e)  # I = 0
+    got = gpu_tail([1 << 60, ad.NONE], [3, 0], [0, 5], 16, 0.1)                # no bound
+    assert np.all(got == 1.0)
+    t = torch.empty(9, dtype=torch.float64, device=dev())
+    one = to_dev_u64([1 << 60])
+    for bins, rel in ((0, 0.1), (1 << 17, 0.1), (8, 0.0), (8, -1.0), (8, float("nan")),
+                      (8, float("inf"))):
+        with pytest.raises(sk.SkimError) as ei:
+            sk.skim_discrepancy_tail(one, to_dev_u32([1]), to_dev_u64([5]), bins, rel, t)
+        assert ei.value.status == sk.SKIM_EINVAL
+    with pytest.raises(sk.SkimError) as ei:  # seeds * (bins + 1) over the limit
+        big = torch.zeros(20000, dtype=torch.int64, device=dev())
+        sk.skim_discrepancy_tail(big, big.to(torch.int32), big, 65536, 0.1,
+                                 torch.empty(65537, dtype=torch.float64, device=dev()))
+    assert ei.value.status == sk.SKIM_EUNSUPPORTED
