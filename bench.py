@@ -264,8 +264,54 @@ def bench_skim(torch, sk, reps=3):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t)
     t = float(np.median(times))
-    return {"workload": "served-skim", "seeds": s, "ms": t * 1e3, "seeds_per_s": s / t,
-            "influence_pairs": int(gains.sum().item())}
+    out = {"workload": "served-skim", "seeds": s, "ms": t * 1e3, "seeds_per_s": s / t,
+           "influence_pairs": int(gains.sum().item())}
+    out["adaptive_error"] = bench_adaptive(torch, sk, G, cfg, s, reps)
+    return out
+
+
+def tail_convolution_flops(s, bins):
+    """Multiply-adds of the pairwise tree of capped convolutions, 2 flops each:
+    every pair of rows costs sum_{j=0..bins} (j + 1)."""
+    per_pair = (bins + 1) * (bins + 2) // 2
+    rows, pairs = s, 0
+    while rows > 1:
+        pairs += rows // 2
+        rows = (rows + 1) // 2
+    return 2 * pairs * per_pair
+
+
+def bench_adaptive(torch, sk, G, cfg, s, reps, bins=4096, rel=0.25):
+    """The adaptive error estimate of the same 200-seed run: records from a
+    resumable state, then the confidence distribution of the total
+    discrepancy (Section 4), timed per call."""
+    dev = torch.device("cuda:0")
+    state = sk.GreedyState()
+    try:
+        seeds = torch.empty(s, dtype=torch.int32, device=dev)
+        gains = torch.empty(s, dtype=torch.int64, device=dev)
+        sk.skim_greedy(G, cfg["ell"], cfg["k"], cfg["seed"], s, seeds, gains, state=state)
+        tau = torch.empty(s, dtype=torch.int64, device=dev)
+        second = torch.empty(s, dtype=torch.int32, device=dev)
+        sk.skim_greedy_records(state, 0, s, tau, second)
+    finally:
+        state.free()
+    tail = torch.empty(bins + 1, dtype=torch.float64, device=dev)
+    sk.skim_discrepancy_tail(tau, second, gains, bins, rel, tail)
+    times = []
+    for _ in range(max(reps, 5)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sk.skim_discrepancy_tail(tau, second, gains, bins, rel, tail)
+        times.append(time.perf_counter() - t)
+    t = float(np.median(times))
+    T = tail.cpu().numpy()
+    flops = tail_convolution_flops(s, bins)
+    at = {f"{x:g}": float(T[int(round(x / rel * bins))]) for x in (0.01, 0.02, 0.05, 0.1, 0.25)}
+    return {"bins": bins, "max_rel_error": rel, "ms": t * 1e3,
+            "conv_tflops": flops / t / 1e12, "fp64_peak_tflops": 78.6,
+            "filled_seeds": int((tau != -1).sum().item()),
+            "p_total_discrepancy_at_least": at}
 
 
 def bench_serving(torch, sk, duration=2.0):

@@ -33,6 +33,7 @@
 
 #include <rocprim/device/device_radix_sort.hpp>
 
+#include <algorithm>
 #include <memory>
 #include <utility>
 
@@ -88,6 +89,17 @@ template <class T> __device__ __forceinline__ T ld(const T *p) {
 }
 template <class T> __device__ __forceinline__ void st(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Inclusive prefix sum of v over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t t = __shfl_up(v, off);
+        if (lane >= off) v += t;
+    }
+    return v;
 }
 
 __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, uint32_t *seeds,
@@ -158,7 +170,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 bool cand = false;
                 if (tid < T)
                     for (uint32_t j = 0; j < cnt; ++j) cand |= ld(SZ + Q[j]) + ld(BC + Q[j]) >= k;
-                if (cand) atomicOr(&s_found, 1u);
+                if (__any(cand) && (tid & 63u) == 0) atomicOr(&s_found, 1u);
                 __syncthreads();
                 const bool f = s_found != 0;
                 if (tid < T)
@@ -179,9 +191,14 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             }
             T = hi;  // B when nothing fills; else the first filling prefix
             // does the committed prefix fit in the index pool?
+            // (LDS atomics: one per wave, lanes on one address are serialised)
+            const uint32_t mine = tid < T ? cnt : 0u;
+            const uint32_t incl = wave_incl_sum(mine);
+            const uint32_t wave_total = __shfl(incl, 63);
             if (tid == 0) s_total = 0;
             __syncthreads();
-            if (tid < T && cnt) atomicAdd(&s_total, (unsigned long long)cnt);
+            if ((tid & 63u) == 63u && wave_total)
+                atomicAdd(&s_total, (unsigned long long)wave_total);
             __syncthreads();
             if (s_pool + s_total > A.pool_cap) {
                 if (tid == 0) {
@@ -192,8 +209,13 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 __syncthreads();
                 break;
             }
+            unsigned long long wave_base = 0;
+            if ((tid & 63u) == 63u && wave_total)
+                wave_base = atomicAdd(&s_pool, (unsigned long long)wave_total);
+            wave_base = ((unsigned long long)__shfl((uint32_t)(wave_base >> 32), 63) << 32) |
+                        __shfl((uint32_t)wave_base, 63);
             if (tid < T && cnt) {
-                const unsigned long long off = atomicAdd(&s_pool, (unsigned long long)cnt);
+                const unsigned long long off = wave_base + (incl - mine);
                 for (uint32_t j = 0; j < cnt; ++j) {
                     st(A.pool + off + j, Q[j]);
                     atomicAdd(SZ + Q[j], 1u);
@@ -241,23 +263,30 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         // ------------------------------------ records for the error estimate
         // The filling pair's search is still in its thread's queue; the batch
         // counters are all zero here and mark it while the sizes are scanned.
-        const bool filler = (int)tid == s_filler;
-        if (filler)
-            for (uint32_t j = 0; j < s_fill_cnt; ++j) st(BC + Q[j], 1u);
+        const uint32_t *Qf = s_filler >= 0 ? A.queues + (uint64_t)s_filler * n : nullptr;
+        const uint32_t fcnt = s_filler >= 0 ? s_fill_cnt : 0u;
+        for (uint32_t j = tid; j < fcnt; j += kSkimBlock) st(BC + ld(Qf + j), 1u);
         if (tid == 0) s_second = 0;
         __syncthreads();
         {
+            // Selected nodes need no test: every pair a seed reaches is
+            // covered, so its size is 0 from then on and no later search
+            // reaches it.
             uint32_t best2 = 0;
             for (uint32_t v = tid; v < n; v += kSkimBlock)
-                if (v != x && !ld(A.sel + v)) {
+                if (v != x) {
                     const uint32_t sz = ld(SZ + v) - ld(BC + v);
                     best2 = sz > best2 ? sz : best2;
                 }
-            if (best2) atomicMax(&s_second, best2);
+            // one LDS atomic per wave: lanes on one address are serialised
+            for (int off = 32; off > 0; off >>= 1) {
+                const uint32_t o = (uint32_t)__shfl_xor((int)best2, off);
+                best2 = o > best2 ? o : best2;
+            }
+            if ((tid & 63) == 0 && best2) atomicMax(&s_second, best2);
         }
         __syncthreads();
-        if (filler)
-            for (uint32_t j = 0; j < s_fill_cnt; ++j) st(BC + Q[j], 0u);
+        for (uint32_t j = tid; j < fcnt; j += kSkimBlock) st(BC + ld(Qf + j), 0u);
         if (tid == 0) {
             rec_tau[it] = s_filler >= 0 ? (uint64_t)s_tau : ~0ull;
             rec_second[it] = s_second;
@@ -392,27 +421,96 @@ __global__ void __launch_bounds__(kTailBlock) k_tail_survival(
 // One level of the pairwise tree: out[p] = the capped sum of rows 2p and
 // 2p+1 of in (an odd last row is copied).  With a[i] = Sa[i] - Sa[i+1],
 //   Sc[j] = P[A + B >= j] = Sa[j+1] + sum_{i <= j} a[i] Sb[j-i],  Sa[bins+1] = 0.
-__global__ void __launch_bounds__(kTailBlock) k_tail_pair(const double *in, double *out,
-                                                          uint32_t rows, uint32_t bins) {
+// A workgroup owns kTailOut consecutive outputs j0.. of one pair; each of its
+// kTailGroups waves takes the i tiles g, g + kTailGroups, ... of kTailI
+// values, and lane l of a wave keeps the partial sums of the kTailPer
+// consecutive outputs j0 + kTailPer l + c.  As i steps by one, the Sb values
+// those outputs need slide by one place, so a lane holds them in registers
+// and reads one new value per step.  A tile's a[i] and the Sb values it
+// meets, Sb[j0 - i0 - kTailI + u] for u = 0 .. kTailOut + kTailI - 1 (zero
+// outside 0 .. bins: below 0 this drops the terms with i > j), sit in the
+// wave's LDS with u interleaved by u mod kTailPer, so the lanes of a wave
+// read consecutive words.  The waves' partial sums are added in a fixed order
+// at the end, so the result does not depend on scheduling.
+constexpr int kTailGroups = 8, kTailPairBlock = 64 * kTailGroups;
+constexpr int kTailPer = 4, kTailOut = 64 * kTailPer, kTailI = 256;
+constexpr int kTailSpan = kTailOut + kTailI, kTailStride = kTailSpan / kTailPer;
+
+__device__ __forceinline__ int tail_pos(int u) { return (u % kTailPer) * kTailStride + u / kTailPer; }
+
+__global__ void __launch_bounds__(kTailPairBlock) k_tail_pair(const double *in, double *out,
+                                                              uint32_t rows, uint32_t bins) {
+    __shared__ double s_a[kTailGroups][kTailI];
+    __shared__ double s_b[kTailGroups][kTailSpan];
     const uint64_t W = (uint64_t)bins + 1;
-    const uint64_t outs = ((uint64_t)rows + 1) / 2, work = outs * W;
-    for (uint64_t t = blockIdx.x * (uint64_t)kTailBlock + threadIdx.x; t < work;
-         t += (uint64_t)gridDim.x * kTailBlock) {
-        const uint64_t p = t / W;
-        const uint32_t j = (uint32_t)(t - p * W);
+    const uint64_t outs = ((uint64_t)rows + 1) / 2;
+    const uint64_t chunks = (W + kTailOut - 1) / kTailOut, nblk = outs * chunks;
+    const int g = (int)threadIdx.x / 64, lane = (int)threadIdx.x % 64;
+    for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const uint64_t p = blk / chunks;
+        const int64_t j0 = (int64_t)(blk - p * chunks) * kTailOut;
+        const int64_t j1 = j0 + kTailOut < (int64_t)W ? j0 + kTailOut : (int64_t)W;
         const double *a = in + 2 * p * W;
-        double v;
+        double *o = out + p * W;
         if (2 * p + 1 >= rows) {
-            v = a[j];
-        } else {
-            const double *b = a + W;
-            v = j < bins ? a[j + 1] : 0.0;
-            for (uint32_t i = 0; i <= j; ++i) {
-                const double ai = a[i] - (i < bins ? a[i + 1] : 0.0);
-                v += ai * b[j - i];
+            for (int64_t j = j0 + threadIdx.x; j < j1; j += kTailPairBlock) o[j] = a[j];
+            continue;
+        }
+        const double *b = a + W;
+        double acc[kTailPer];
+#pragma unroll
+        for (int c = 0; c < kTailPer; ++c) acc[c] = 0.0;
+        const int64_t tiles = (j1 + kTailI - 1) / kTailI;  // tiles with i0 < j1
+        for (int64_t round = 0; round * kTailGroups < tiles; ++round) {
+            const int64_t i0 = (round * kTailGroups + g) * kTailI;
+            const bool active = i0 < j1;
+            __syncthreads();  // the previous tiles are consumed
+            if (active) {
+                for (int t = lane; t < kTailI; t += 64) {
+                    const int64_t i = i0 + t;
+                    s_a[g][t] =
+                        i < (int64_t)W ? a[i] - (i + 1 < (int64_t)W ? a[i + 1] : 0.0) : 0.0;
+                }
+                const int64_t base = j0 - i0 - kTailI;
+                for (int u = lane; u < kTailSpan; u += 64) {
+                    const int64_t q = base + u;
+                    s_b[g][tail_pos(u)] = q >= 0 && q < (int64_t)W ? b[q] : 0.0;
+                }
+            }
+            __syncthreads();
+            if (active) {
+                // output j0 + kTailPer lane + c at step t needs u = kTailPer lane + c + kTailI - t
+                const double *sa = s_a[g];
+                const double *sb = s_b[g];
+                double w[kTailPer];
+#pragma unroll
+                for (int c = 0; c < kTailPer; ++c) w[c] = sb[tail_pos(kTailPer * lane + c + kTailI)];
+#pragma unroll 8
+                for (int t = 0; t < kTailI; ++t) {
+                    const double at = sa[t];
+#pragma unroll
+                    for (int c = 0; c < kTailPer; ++c) acc[c] += at * w[c];
+#pragma unroll
+                    for (int c = kTailPer - 1; c > 0; --c) w[c] = w[c - 1];
+                    w[0] = sb[tail_pos(kTailPer * lane + kTailI - 1 - t)];
+                }
             }
         }
-        out[t] = v;
+        // fixed-order reduction over the waves, through the staging LDS
+        __syncthreads();
+        double *red = &s_b[0][0];
+#pragma unroll
+        for (int c = 0; c < kTailPer; ++c) red[g * kTailOut + kTailPer * lane + c] = acc[c];
+        __syncthreads();
+        for (int jj = threadIdx.x; jj < kTailOut; jj += kTailPairBlock) {
+            const int64_t j = j0 + jj;
+            if (j < j1) {
+                double v = j + 1 < (int64_t)W ? a[j + 1] : 0.0;
+                for (int q = 0; q < kTailGroups; ++q) v += red[q * kTailOut + jj];
+                o[j] = v;
+            }
+        }
+        __syncthreads();  // LDS is reused by the next block of the stride
     }
 }
 
@@ -640,8 +738,9 @@ extern "C" skim_status skim_discrepancy_tail(uint32_t s, const uint64_t *tau,
         SKIM_LAUNCH_CHECK();
         double *in = bufA, *out = bufB;
         for (uint32_t rows = s; rows > 1; rows = (rows + 1) / 2) {
-            k_tail_pair<<<grid_for(((uint64_t)rows + 1) / 2 * W, kTailBlock), kTailBlock, 0,
-                          hs>>>(in, out, rows, bins);
+            const uint64_t blocks = ((uint64_t)rows + 1) / 2 * ((W + kTailOut - 1) / kTailOut);
+            k_tail_pair<<<(unsigned)std::min<uint64_t>(blocks, 65536), kTailPairBlock, 0, hs>>>(
+                in, out, rows, bins);
             SKIM_LAUNCH_CHECK();
             std::swap(in, out);
         }

@@ -127,3 +127,7 @@ def test_bench_algorithmic_bytes():
     assert bench.algorithmic_bytes_search(cnt) == 8 * 1000 + 16 * 100
     assert bench.algorithmic_bytes_build(cnt, n=10, k=4) == 8 * 1000 + 16 * 100 + 8 * 40 + 8 * 10
     assert bench.visit_model_bytes(cnt) == 500 * 56 + 700 * 20
+    # the discrepancy-tail tree: 5 rows pair up as 5 -> 3 -> 2 -> 1 (4 pairs),
+    # each pair sum_{j=0..bins} (j + 1) multiply-adds
+    assert bench.tail_convolution_flops(5, 3) == 2 * 4 * (1 + 2 + 3 + 4)
+    assert bench.tail_convolution_flops(1, 100) == 0
