@@ -187,6 +187,29 @@ void skim_greedy_state_free(skim_greedy_state *state);
 uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
 
 /*
+ * skim_influence_batch -- exact influence of q seed sets over the l
+ * instances of `seed` (Section 2, eqs. (Inf) and (timedinf)):
+ * reach_pairs[j] = sum_i |reach_i(S_j)| = l Inf({G^(i)}, S_j), the number of
+ * node-instance pairs reachable from S_j over live edges.  For a quality
+ * harness: with a seed other than the one the sketches or SKIM used, it
+ * scores their seed sets on fresh instances (call it with several seeds for
+ * more than 64 instances).  Same graph conventions and validation as
+ * skim_build_sketches; l in [1, 64].
+ *   qoff        [q+1] device: set j is qnodes[qoff[j] .. qoff[j+1]); qoff[0]
+ *               must be 0 and qoff non-decreasing (SKIM_EINVAL otherwise).
+ *   qnodes      [qoff[q]] device (may be NULL when every set is empty).
+ *               Duplicate nodes act once; an empty set reaches 0 pairs.
+ *   reach_pairs [q] out, device.
+ *   qstatus     [q] out, device, may be NULL: 0, or -1 when the set holds a
+ *               node >= n (its reach_pairs is then 0).
+ * Scratch: the live out-lists of the graph (8 (64 n + 1) bytes plus 4 bytes
+ * per live edge-instance) and up to 2 GiB of per-query search state.
+ */
+skim_status skim_influence_batch(const skim_graph *g, uint32_t ell, uint64_t seed, uint64_t q,
+                                 const uint64_t *qoff, const uint32_t *qnodes,
+                                 uint64_t *reach_pairs, int32_t *qstatus, void *stream);
+
+/*
  * skim_greedy_records -- per-seed records of a SKIM run for its adaptive
  * error estimate (Section 4, adaptive error estimation), taken when the seed
  * is chosen, before its residual update.  For seeds first .. first+count-1

@@ -27,7 +27,7 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_server_poll_greedy", "skim_server_replay", "skim_set_build_params",
            "skim_get_build_params", "skim_tune_build", "skim_query_plan_create",
            "skim_query_plan_launch", "skim_query_plan_free", "skim_greedy_records",
-           "skim_discrepancy_tail"]
+           "skim_discrepancy_tail", "skim_influence_batch"]
 
 
 class SkimError(RuntimeError):
@@ -94,6 +94,9 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_selected.argtypes = [vp]
     lib.skim_greedy_records.restype = C.c_int
     lib.skim_greedy_records.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, vp]
+    lib.skim_influence_batch.restype = C.c_int
+    lib.skim_influence_batch.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint64,
+                                         C.c_uint64, vp, vp, vp, vp, vp]
     lib.skim_discrepancy_tail.restype = C.c_int
     lib.skim_discrepancy_tail.argtypes = [C.c_uint32, vp, vp, vp, C.c_uint32, C.c_double, vp, vp]
     P64 = C.POINTER(C.c_uint64)
@@ -316,6 +319,18 @@ def skim_greedy(graph: DeviceGraph, ell: int, k: int, seed: int, s: int, seeds, 
 
 def skim_greedy_state_free(state: GreedyState):
     state.free()
+
+
+def skim_influence_batch(graph: DeviceGraph, ell: int, seed: int, qoff, qnodes, reach_pairs,
+                         qstatus=None, stream=None):
+    """Exact sum_i |reach_i(S_j)| over the l instances of `seed` for every set
+    S_j = qnodes[qoff[j]:qoff[j+1]], into the uint64 device tensor reach_pairs."""
+    q = int(qoff.numel()) - 1
+    st = load_library().skim_influence_batch(
+        C.byref(graph.struct), ell, seed & 0xFFFFFFFFFFFFFFFF, q, _ptr(qoff),
+        _ptr(qnodes) if qnodes is not None and qnodes.numel() else None, _ptr(reach_pairs),
+        _ptr(qstatus), _stream(stream))
+    _check("skim_influence_batch", st)
 
 
 def skim_greedy_records(state: GreedyState, first: int, count: int, tau=None, second=None,
