@@ -267,7 +267,43 @@ def bench_skim(torch, sk, reps=3):
     out = {"workload": "served-skim", "seeds": s, "ms": t * 1e3, "seeds_per_s": s / t,
            "influence_pairs": int(gains.sum().item())}
     out["adaptive_error"] = bench_adaptive(torch, sk, G, cfg, s, reps)
+    out["fresh_instances"] = bench_fresh(torch, sk, G, cfg, seeds, gains)
     return out
+
+
+def bench_fresh(torch, sk, G, cfg, seeds, gains, groups=8):
+    """Quality harness: the influence of every prefix of the SKIM seed sequence
+    on 64 * groups fresh instances (seeds the sketches never used), by the
+    exact evaluator, against SKIM's own in-sample gains."""
+    dev = torch.device("cuda:0")
+    ell = cfg["ell"]
+    S = seeds.cpu().numpy().view(np.uint32)
+    s = S.size
+    off = np.zeros(s + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(np.arange(1, s + 1, dtype=np.uint64))
+    nodes = np.concatenate([S[:j] for j in range(1, s + 1)])
+    qo = torch.from_numpy(off.view(np.int64)).to(dev)
+    qn = torch.from_numpy(nodes.view(np.int32)).to(dev)
+    reach = torch.empty(s, dtype=torch.int64, device=dev)
+    total = np.zeros(s)
+    times, visits = [], 0
+    for gix in range(groups):
+        fresh_seed = cfg["seed"] + 7919 * (gix + 1)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sk.skim_influence_batch(G, 64, fresh_seed, qo, qn, reach)
+        times.append(time.perf_counter() - t)
+        r = reach.cpu().numpy().view(np.uint64).astype(np.float64)
+        total += r
+        visits += int(r.sum())
+    fresh = total / (64 * groups)
+    insample = np.cumsum(gains.cpu().numpy().astype(np.float64)) / ell
+    t = float(np.median(times))
+    return {"instances": 64 * groups, "sets": s, "member_nodes": int(nodes.size),
+            "ms_per_call": t * 1e3, "pair_visits_per_s": visits / groups / t,
+            "influence_200_fresh": float(fresh[-1]), "influence_200_in_sample": float(insample[-1]),
+            "influence_50_fresh": float(fresh[49]), "influence_50_in_sample": float(insample[49]),
+            "max_rel_gap_prefixes": float(np.max(np.abs(fresh - insample) / fresh))}
 
 
 def tail_convolution_flops(s, bins):
