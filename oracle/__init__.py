@@ -98,6 +98,14 @@ def _load():
         lib.or_skim.restype = C.c_int
         lib.or_skim.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32, C.c_uint32,
                                 C.c_uint32, P32, P64, P64, P32, C.POINTER(SkimCounters)]
+        lib.or_ic_live.restype = C.c_int
+        lib.or_ic_live.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
+                                   C.c_uint32]
+        lib.or_ic_order.restype = None
+        lib.or_ic_order.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, P32]
+        lib.or_ic_sketches.restype = C.c_int
+        lib.or_ic_sketches.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint32, C.c_uint64, P32,
+                                       PD, P64]
         _lib = lib
     return _lib
 
@@ -267,3 +275,32 @@ def skim(g, seed: int, ell: int, k: int, s: int, records: bool = False):
     if records:
         return seeds[:s], gain[:s], tau[:s], second[:s], cnt.as_dict()
     return seeds[:s], gain[:s], cnt.as_dict()
+
+
+def ic_live(seed: int, n: int, u: int, w: int, t: int, thr: int) -> bool:
+    """Is edge (u -> w) live in the IC-model instance of position t (>= 1)?"""
+    return bool(_load().or_ic_live(seed & 0xFFFFFFFFFFFFFFFF, n, u, w, t, thr))
+
+
+def ic_order(seed: int, n: int, k: int) -> np.ndarray:
+    """node_at[t - 1]: the node at structured permutation position t, t = 1..k n."""
+    out = np.zeros(max(k * n, 1), dtype=np.uint32)
+    _load().or_ic_order(seed & 0xFFFFFFFFFFFFFFFF, n, k, _p(out, P32))
+    return out[:k * n]
+
+
+def ic_sketches(g, k: int, seed: int):
+    """IC-model sketches: positions [n, k] (uint32, ascending), estimates
+    n (k - 1) / (T - 1) [n], and the number of (position, node) visits."""
+    rp, col, thr = _g(g)
+    pos = np.zeros(max(g.n * k, 1), dtype=np.uint32)
+    est = np.zeros(max(g.n, 1))
+    visits = np.zeros(1, dtype=np.uint64)
+    rc = _load().or_ic_sketches(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), k,
+                                seed & 0xFFFFFFFFFFFFFFFF, _p(pos, P32), _p(est, PD),
+                                _p(visits, P64))
+    if rc == -1:
+        raise ValueError("or_ic_sketches: bad arguments")
+    if rc == -2:
+        raise AssertionError("or_ic_sketches: a node holds fewer than k positions")
+    return pos[:g.n * k].reshape(g.n, k), est[:g.n], int(visits[0])

@@ -36,6 +36,9 @@
  *                                          (divide by l)
  *   or_union_query ........................ Section 5.1, bottom-k of the union
  *   or_ck_query ........................... Section 5.1, eq. (unionest)
+ *   or_ic_live, or_ic_order, or_ic_sketches  Section 3, structured permutation
+ *                                          ranks and sketches for an IC model
+ *                                          (the l -> infinity limit)
  *   or_skim ............................... Section 4, Algorithm 1; per-seed
  *                                          records for the adaptive error
  *                                          estimate (Section 4, adaptive error
@@ -754,5 +757,114 @@ done:
     free(covered); free(size); free(selected); free(pairs);
     for (uint32_t i = 0; i < ell; i++) { free(L[i].fptr); free(L[i].rptr); free(L[i].fadj); free(L[i].radj); }
     free(L);
+    return rc;
+}
+
+/* ------------------------------------- IC-model sketches (Section 3, 4) */
+/* Sketches for the IC model itself (Section 3, "Sketches for an IC model"),
+ * with structured permutation ranks (Section 3, "Structured permutation
+ * ranks") in the limit l -> infinity, where every rank position is a node in
+ * an instance of its own.  Conventions fixed here:
+ *  - chunk c (0 <= c < k) holds positions c n + 1 .. (c + 1) n, each node
+ *    once: node v takes position c n + 1 + |{w : h_c(w) < h_c(v)}| with
+ *    h_c(v) = SM(seed, 2^63 + c n + v) (distinct: SM is a bijection);
+ *  - position t has instance t; the coin of edge (u -> w) in instance t is
+ *    the high (t - 1 even) or low (t - 1 odd) half of
+ *    SM(SM(seed, 2^63 + 2^62 + u n + w), floor((t - 1) / 2)), live iff
+ *    coin <= thr, so P[live] = (thr + 1) / 2^32 independently per instance;
+ *  - X_u = the k smallest positions t such that u reaches v_t (the node at
+ *    position t) in instance t.  Only positions up to k n matter: u holds one
+ *    position of its own in every chunk;
+ *  - the influence estimate is n (k - 1) / (T - 1), T the k-th smallest
+ *    position (the limit of the permutation-rank estimator divided by l). */
+#define OR_IC_CHUNK (1ULL << 63)
+#define OR_IC_EDGE ((1ULL << 63) | (1ULL << 62))
+
+int or_ic_live(uint64_t seed, uint32_t n, uint32_t u, uint32_t w, uint64_t t, uint32_t thr)
+{
+    uint64_t edge_seed = or_sm64(seed, OR_IC_EDGE + (uint64_t)u * n + w);
+    uint64_t h = or_sm64(edge_seed, (t - 1) / 2);
+    uint32_t coin = ((t - 1) % 2 == 0) ? (uint32_t)(h >> 32) : (uint32_t)h;
+    return coin <= thr;
+}
+
+/* node_at[t - 1] = the node at position t, for t = 1 .. k n */
+void or_ic_order(uint64_t seed, uint32_t n, uint32_t k, uint32_t *node_at)
+{
+    rank_node *tmp = malloc(sizeof(rank_node) * (n ? n : 1));
+    for (uint32_t c = 0; c < k; c++) {
+        for (uint32_t v = 0; v < n; v++) {
+            tmp[v].r = or_sm64(seed, OR_IC_CHUNK + (uint64_t)c * n + v);
+            tmp[v].v = v;
+        }
+        qsort(tmp, n, sizeof(rank_node), cmp_rank_node);
+        for (uint32_t j = 0; j < n; j++) node_at[(uint64_t)c * n + j] = tmp[j].v;
+    }
+    free(tmp);
+}
+
+/* out_pos[n k]: X_u ascending (1-based positions); out_est[n] (may be NULL);
+ * *out_visits (may be NULL) = sum over positions of the nodes reached.
+ * Returns 0, -1 on bad arguments, -2 if a node ended with fewer than k
+ * positions (cannot happen: every node reaches itself in every chunk). */
+int or_ic_sketches(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, const uint32_t *thr,
+                   uint32_t k, uint64_t seed, uint32_t *out_pos, double *out_est,
+                   uint64_t *out_visits)
+{
+    if (n == 0 || k < 2 || (uint64_t)k * n >= (1ULL << 32)) return -1;
+    uint64_t m = row_ptr[n];
+    /* reverse graph: in-edges of every node with their source and threshold */
+    uint64_t *rptr = calloc((size_t)n + 1, sizeof(uint64_t));
+    uint32_t *rsrc = malloc(sizeof(uint32_t) * (m ? m : 1));
+    uint32_t *rthr = malloc(sizeof(uint32_t) * (m ? m : 1));
+    uint64_t *fill = calloc(n, sizeof(uint64_t));
+    for (uint64_t e = 0; e < m; e++) rptr[col[e] + 1]++;
+    for (uint32_t v = 0; v < n; v++) rptr[v + 1] += rptr[v];
+    for (uint32_t u = 0; u < n; u++)
+        for (uint64_t e = row_ptr[u]; e < row_ptr[u + 1]; e++) {
+            uint32_t w = col[e];
+            uint64_t at = rptr[w] + fill[w]++;
+            rsrc[at] = u;
+            rthr[at] = thr[e];
+        }
+    uint64_t total = (uint64_t)k * n;
+    uint32_t *node_at = malloc(sizeof(uint32_t) * total);
+    or_ic_order(seed, n, k, node_at);
+    uint32_t *cnt = calloc(n, sizeof(uint32_t));
+    uint32_t *stamp = calloc(n, sizeof(uint32_t));
+    uint32_t *queue = malloc(sizeof(uint32_t) * n);
+    uint64_t visits = 0;
+    for (uint64_t t = 1; t <= total; t++) {
+        /* reverse search from v_t in instance t: every node that reaches v_t */
+        uint32_t v = node_at[t - 1];
+        uint64_t head = 0, tail = 0;
+        stamp[v] = (uint32_t)t;
+        queue[tail++] = v;
+        while (head < tail) {
+            uint32_t x = queue[head++];
+            for (uint64_t e = rptr[x]; e < rptr[x + 1]; e++) {
+                uint32_t u = rsrc[e];
+                if (stamp[u] != (uint32_t)t && or_ic_live(seed, n, u, x, t, rthr[e])) {
+                    stamp[u] = (uint32_t)t;
+                    queue[tail++] = u;
+                }
+            }
+        }
+        visits += tail;
+        for (uint64_t j = 0; j < tail; j++) {
+            uint32_t y = queue[j];
+            if (cnt[y] < k) out_pos[(uint64_t)y * k + cnt[y]++] = (uint32_t)t;
+        }
+    }
+    int rc = 0;
+    for (uint32_t y = 0; y < n; y++) {
+        if (cnt[y] != k) { rc = -2; break; }
+        if (out_est)
+            out_est[y] = ((double)n * (double)(k - 1)) /
+                         (double)(out_pos[(uint64_t)y * k + k - 1] - 1);
+    }
+    if (out_visits) *out_visits = visits;
+    free(rptr); free(rsrc); free(rthr); free(fill); free(node_at);
+    free(cnt); free(stamp); free(queue);
     return rc;
 }
