@@ -187,6 +187,31 @@ void skim_greedy_state_free(skim_greedy_state *state);
 uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
 
 /*
+ * skim_build_ic_sketches -- sketches for the IC model itself (Section 3,
+ * "Sketches for an IC model"), with structured permutation ranks (Section 3,
+ * "Structured permutation ranks") in the limit of infinitely many instances,
+ * so that nothing depends on l.
+ *   Positions t = 1 .. k n form k chunks of n; chunk c holds every node once,
+ *   node v at position c n + 1 + |{w : h_c(w) < h_c(v)}| with
+ *   h_c(v) = SM(2^63 + c n + v).  Every position has an instance of its own:
+ *   edge (u -> w) is live in the instance of position t iff the high
+ *   (t - 1 even) or low (t - 1 odd) 32 bits of output floor((t - 1) / 2) of
+ *   the SplitMix64 stream seeded with SM(2^63 + 2^62 + u n + w) are <= thr.
+ *   The sketch of u is the k smallest positions t whose node u reaches in the
+ *   instance of t; the influence estimate is n (k - 1) / (T - 1), T the k-th
+ *   smallest (every node reaches itself in every chunk, so T <= k n).
+ *   positions [n k] out, device (uint32): row u ascending.
+ *   est       [n] out, device, may be NULL.
+ * k in [2, 256], k n < 2^32; same graph conventions and validation as
+ * skim_build_sketches.  Every position runs a complete reverse search (an
+ * instance has one source, so nothing prunes): the work is about k times
+ * the sum of all nodes' influence, and the per-thread search state (n / 8 +
+ * 4 n bytes) is budgeted at 2 GiB, which suits graphs up to about 2^18 nodes.
+ */
+skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, uint64_t seed,
+                                   uint32_t *positions, double *est, void *stream);
+
+/*
  * skim_influence_batch -- exact influence of q seed sets over the l
  * instances of `seed` (Section 2, eqs. (Inf) and (timedinf)):
  * reach_pairs[j] = sum_i |reach_i(S_j)| = l Inf({G^(i)}, S_j), the number of

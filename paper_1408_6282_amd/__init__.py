@@ -27,7 +27,7 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_server_poll_greedy", "skim_server_replay", "skim_set_build_params",
            "skim_get_build_params", "skim_tune_build", "skim_query_plan_create",
            "skim_query_plan_launch", "skim_query_plan_free", "skim_greedy_records",
-           "skim_discrepancy_tail", "skim_influence_batch"]
+           "skim_discrepancy_tail", "skim_influence_batch", "skim_build_ic_sketches"]
 
 
 class SkimError(RuntimeError):
@@ -94,6 +94,9 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_selected.argtypes = [vp]
     lib.skim_greedy_records.restype = C.c_int
     lib.skim_greedy_records.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, vp]
+    lib.skim_build_ic_sketches.restype = C.c_int
+    lib.skim_build_ic_sketches.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint64, vp, vp,
+                                           vp]
     lib.skim_influence_batch.restype = C.c_int
     lib.skim_influence_batch.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint64,
                                          C.c_uint64, vp, vp, vp, vp, vp]
@@ -319,6 +322,16 @@ def skim_greedy(graph: DeviceGraph, ell: int, k: int, seed: int, s: int, seeds, 
 
 def skim_greedy_state_free(state: GreedyState):
     state.free()
+
+
+def skim_build_ic_sketches(graph: DeviceGraph, k: int, seed: int, positions, est=None,
+                           stream=None):
+    """IC-model sketches (structured permutation positions, uint32 [n, k]) and
+    their influence estimates n (k - 1) / (T - 1) into device tensors."""
+    st = load_library().skim_build_ic_sketches(C.byref(graph.struct), k,
+                                               seed & 0xFFFFFFFFFFFFFFFF, _ptr(positions),
+                                               _ptr(est), _stream(stream))
+    _check("skim_build_ic_sketches", st)
 
 
 def skim_influence_batch(graph: DeviceGraph, ell: int, seed: int, qoff, qnodes, reach_pairs,

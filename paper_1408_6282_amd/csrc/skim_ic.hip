@@ -1,0 +1,261 @@
+// skim_ic.hip -- sketches for the IC model itself (Section 3, "Sketches for
+// an IC model"), with structured permutation ranks (Section 3, "Structured
+// permutation ranks") in the limit of infinitely many instances.
+//
+// Positions t = 1 .. k n come in k chunks of n; each chunk holds every node
+// once, in the order of a SplitMix64 hash (a rocPRIM segmented radix sort per
+// chunk).  Every position has an instance of its own, so the sketch of u is
+// the k smallest positions t whose node v_t u reaches in instance t, and the
+// influence estimate is n (k - 1) / (T - 1) with T the k-th smallest.  Nothing
+// prunes a search here (an instance has one source), so:
+//  * one thread per position runs the complete reverse search from v_t over
+//    the in-edges whose coin in instance t is live (coins on the fly from a
+//    per-edge SplitMix64 stream), deduplicating with a visited bitmap of its
+//    own and clearing only the bits it set;
+//  * a first pass counts the nodes each search reaches, a scan gives every
+//    position its record range, and a second pass writes the records
+//    (node << 32 | t) there, so no record needs an atomic;
+//  * the records are radix-sorted; every node holds at least k of them (it
+//    reaches itself in every chunk) and keeps its first k.
+#include "skim_internal.h"
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_segmented_radix_sort.hpp>
+
+#include <algorithm>
+
+namespace skim {
+
+namespace {
+
+constexpr uint64_t kIcChunk = 1ull << 63;                  // counters of the chunk hashes
+constexpr uint64_t kIcEdge = (1ull << 63) | (1ull << 62);  // counters of the per-edge streams
+constexpr int kIcBlock = 256;
+constexpr uint64_t kIcStateBudget = 2ull << 30;            // bytes of per-thread search state
+
+// Coin of edge (u -> w) in the instance of position t (>= 1): the high
+// (t - 1 even) or low (t - 1 odd) half of output floor((t - 1) / 2) of the
+// stream seeded with SM(seed, kIcEdge + u n + w).
+__device__ __forceinline__ bool ic_live(uint64_t seed, uint32_t n, uint32_t u, uint32_t w,
+                                        uint32_t t, uint32_t thr) {
+    const uint64_t edge_seed = sm_at(seed, kIcEdge + (uint64_t)u * n + w);
+    const uint64_t h = sm_at(edge_seed, (t - 1) / 2);
+    const uint32_t coin = ((t - 1) & 1u) == 0 ? (uint32_t)(h >> 32) : (uint32_t)h;
+    return coin <= thr;
+}
+
+__global__ void k_ic_indeg(const uint32_t *col, uint64_t m, uint32_t *indeg) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x)
+        atomicAdd(indeg + col[e], 1u);
+}
+
+// In-edges grouped by head: source and threshold (order within a head is
+// immaterial: a search's reached set does not depend on it).
+__global__ void k_ic_rfill(const uint32_t *esrc, const uint32_t *col, const uint32_t *thr,
+                           uint64_t m, const uint64_t *rptr, uint32_t *cursor, uint32_t *rsrc,
+                           uint32_t *rthr) {
+    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t w = col[e];
+        const uint64_t at = rptr[w] + atomicAdd(cursor + w, 1u);
+        rsrc[at] = esrc[e];
+        rthr[at] = thr[e];
+    }
+}
+
+__global__ void k_ic_hash(uint32_t n, uint32_t k, uint64_t seed, uint64_t *keys, uint32_t *vals,
+                          uint32_t *offs) {
+    const uint64_t total = (uint64_t)n * k;
+    for (uint64_t x = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; x < total;
+         x += (uint64_t)gridDim.x * blockDim.x) {
+        keys[x] = sm_at(seed, kIcChunk + x);  // x = c n + v
+        vals[x] = (uint32_t)(x % n);
+        if (x % n == 0) offs[x / n] = (uint32_t)x;
+        if (x == 0) offs[k] = (uint32_t)total;
+    }
+}
+
+struct IcArgs {
+    uint32_t n, k;
+    uint64_t seed;
+    const uint64_t *rptr;
+    const uint32_t *rsrc, *rthr;
+    const uint32_t *node_at;  // [k n] node at position t = index + 1
+    uint32_t *counts;         // [k n] pass 0 out
+    const uint64_t *offsets;  // [k n + 1] pass 1 in
+    uint64_t *records;        // pass 1 out
+    uint32_t *bitmaps;        // [threads][(n + 31) / 32]
+    uint32_t *queues;         // [threads][n]
+};
+
+template <int kPass>
+__global__ void __launch_bounds__(kIcBlock) k_ic_search(IcArgs A) {
+    const uint64_t tid = blockIdx.x * (uint64_t)kIcBlock + threadIdx.x;
+    const uint64_t threads = (uint64_t)gridDim.x * kIcBlock;
+    const uint32_t words = (A.n + 31) / 32;
+    uint32_t *bm = A.bitmaps + tid * words;
+    uint32_t *Q = A.queues + tid * A.n;
+    const uint64_t total = (uint64_t)A.n * A.k;
+    for (uint64_t x = tid; x < total; x += threads) {
+        const uint32_t t = (uint32_t)(x + 1);
+        const uint32_t v = A.node_at[x];
+        Q[0] = v;
+        bm[v >> 5] |= 1u << (v & 31);
+        uint32_t cnt = 1;
+        for (uint32_t head = 0; head < cnt; ++head) {
+            const uint32_t y = Q[head];
+            for (uint64_t e = A.rptr[y]; e < A.rptr[y + 1]; ++e) {
+                const uint32_t u = A.rsrc[e];
+                const uint32_t bit = 1u << (u & 31);
+                if ((bm[u >> 5] & bit) == 0 && ic_live(A.seed, A.n, u, y, t, A.rthr[e])) {
+                    bm[u >> 5] |= bit;
+                    Q[cnt++] = u;
+                }
+            }
+        }
+        if (kPass == 0) {
+            A.counts[x] = cnt;
+        } else {
+            uint64_t *out = A.records + A.offsets[x];
+            for (uint32_t j = 0; j < cnt; ++j) out[j] = ((uint64_t)Q[j] << 32) | t;
+        }
+        for (uint32_t j = 0; j < cnt; ++j) bm[Q[j] >> 5] = 0;
+    }
+}
+
+// start[u] = index of u's first record (every node has records).
+__global__ void k_ic_starts(const uint64_t *rec, uint64_t R, uint64_t *start) {
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j < R;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t node = (uint32_t)(rec[j] >> 32);
+        if (j == 0 || (uint32_t)(rec[j - 1] >> 32) != node) start[node] = j;
+    }
+}
+
+__global__ void k_ic_select(const uint64_t *rec, const uint64_t *start, uint32_t n, uint32_t k,
+                            uint32_t *pos, double *est) {
+    for (uint64_t u = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; u < n;
+         u += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t s = start[u];
+        for (uint32_t j = 0; j < k; ++j) pos[u * k + j] = (uint32_t)rec[s + j];
+        if (est) {
+            const uint32_t T = (uint32_t)rec[s + k - 1];
+            est[u] = ((double)n * (double)(k - 1)) / (double)(T - 1);
+        }
+    }
+}
+
+}  // namespace
+
+}  // namespace skim
+
+extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, uint64_t seed,
+                                              uint32_t *positions, double *est, void *stream) {
+    using namespace skim;
+    clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    try {
+        SKIM_REQUIRE(g != nullptr, "graph is NULL");
+        SKIM_REQUIRE(k >= 2 && k <= 256, "k must be in [2, 256]");
+        SKIM_REQUIRE(positions != nullptr, "positions is NULL");
+        SKIM_REQUIRE((uint64_t)g->n * k < (1ull << 32), "k n must be below 2^32");
+        Arena T(hs);
+        const uint32_t n = g->n;
+        const uint64_t m = g->m;
+        uint32_t *esrc = T.alloc<uint32_t>(m ? m : 1);
+        validate_graph(g, esrc, T);
+        // reverse graph with thresholds
+        uint32_t *indeg = T.alloc<uint32_t>(n);
+        fill_u32(indeg, 0, n, hs);
+        if (m) {
+            k_ic_indeg<<<grid_for(m, 256, 16384), 256, 0, hs>>>(g->col, m, indeg);
+            SKIM_LAUNCH_CHECK();
+        }
+        uint64_t *rptr = T.alloc<uint64_t>((uint64_t)n + 1);
+        exclusive_scan_u32(indeg, rptr, n, T);
+        uint32_t *rsrc = T.alloc<uint32_t>(m ? m : 1);
+        uint32_t *rthr = T.alloc<uint32_t>(m ? m : 1);
+        fill_u32(indeg, 0, n, hs);  // reused as per-head cursors
+        if (m) {
+            k_ic_rfill<<<grid_for(m, 256, 16384), 256, 0, hs>>>(esrc, g->col, g->thr, m, rptr,
+                                                               indeg, rsrc, rthr);
+            SKIM_LAUNCH_CHECK();
+        }
+        // the structured permutation: chunk c orders the nodes by their hash
+        const uint64_t total = (uint64_t)n * k;
+        uint64_t *hkeys = T.alloc<uint64_t>(total);
+        uint64_t *hkeys2 = T.alloc<uint64_t>(total);
+        uint32_t *hvals = T.alloc<uint32_t>(total);
+        uint32_t *node_at = T.alloc<uint32_t>(total);
+        uint32_t *offs = T.alloc<uint32_t>((uint64_t)k + 1);
+        k_ic_hash<<<grid_for(total, 256, 16384), 256, 0, hs>>>(n, k, seed, hkeys, hvals, offs);
+        SKIM_LAUNCH_CHECK();
+        size_t tmp_bytes = 0;
+        SKIM_HIP(rocprim::segmented_radix_sort_pairs(nullptr, tmp_bytes, hkeys, hkeys2, hvals,
+                                                     node_at, (unsigned)total, k, offs, offs + 1,
+                                                     0, 64, hs));
+        void *tmp = T.get(tmp_bytes);
+        SKIM_HIP(rocprim::segmented_radix_sort_pairs(tmp, tmp_bytes, hkeys, hkeys2, hvals,
+                                                     node_at, (unsigned)total, k, offs, offs + 1,
+                                                     0, 64, hs));
+        T.release(tmp);
+        T.release(hkeys);
+        T.release(hkeys2);
+        T.release(hvals);
+        // per-thread search state within the budget
+        const uint32_t words = (n + 31) / 32;
+        const uint64_t per_thread = ((uint64_t)words + n) * sizeof(uint32_t);
+        uint64_t threads = std::max<uint64_t>(kIcBlock, kIcStateBudget / per_thread);
+        threads = std::min<uint64_t>(threads, (total + kIcBlock - 1) / kIcBlock * kIcBlock);
+        threads = std::min<uint64_t>(threads, 65536ull * kIcBlock);
+        threads = threads / kIcBlock * kIcBlock;
+        IcArgs A{};
+        A.n = n;
+        A.k = k;
+        A.seed = seed;
+        A.rptr = rptr;
+        A.rsrc = rsrc;
+        A.rthr = rthr;
+        A.node_at = node_at;
+        A.bitmaps = T.alloc<uint32_t>(threads * words);
+        A.queues = T.alloc<uint32_t>(threads * n);
+        fill_u32(A.bitmaps, 0, threads * words, hs);
+        A.counts = T.alloc<uint32_t>(total);
+        const unsigned grid = (unsigned)(threads / kIcBlock);
+        {
+            LaunchTimer t("k_ic_search", hs);
+            k_ic_search<0><<<grid, kIcBlock, 0, hs>>>(A);
+            SKIM_LAUNCH_CHECK();
+        }
+        uint64_t *offsets = T.alloc<uint64_t>(total + 1);
+        exclusive_scan_u32(A.counts, offsets, total, T);
+        uint64_t R = 0;
+        read_back(&R, offsets + total, sizeof R, hs);
+        A.offsets = offsets;
+        A.records = T.alloc<uint64_t>(R);
+        {
+            LaunchTimer t("k_ic_search", hs);
+            k_ic_search<1><<<grid, kIcBlock, 0, hs>>>(A);
+            SKIM_LAUNCH_CHECK();
+        }
+        T.release(A.bitmaps);
+        T.release(A.queues);
+        // records by (node, position); every node keeps its first k
+        uint64_t *sorted = T.alloc<uint64_t>(R);
+        tmp_bytes = 0;
+        SKIM_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, A.records, sorted, (size_t)R, 0, 64,
+                                          hs));
+        tmp = T.get(tmp_bytes);
+        SKIM_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, A.records, sorted, (size_t)R, 0, 64, hs));
+        uint64_t *start = T.alloc<uint64_t>(n);
+        k_ic_starts<<<grid_for(R, 256, 16384), 256, 0, hs>>>(sorted, R, start);
+        SKIM_LAUNCH_CHECK();
+        k_ic_select<<<grid_for(n, 256, 4096), 256, 0, hs>>>(sorted, start, n, k, positions, est);
+        SKIM_LAUNCH_CHECK();
+        SKIM_HIP(hipStreamSynchronize(hs));
+        return SKIM_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    }
+}
