@@ -350,6 +350,36 @@ def bench_adaptive(torch, sk, G, cfg, s, reps, bins=4096, rel=0.25):
             "p_total_discrepancy_at_least": at}
 
 
+def bench_ic(torch, sk, reps=3):
+    """IC-model sketches (structured permutation ranks, Section 3) on served-skim
+    and on a 20,000-node weighted-cascade Chung-Lu graph, k = 64."""
+    from workloads.configs import make_config, make_graph
+    from workloads.graphs import Graph, chung_lu_graph, wc_thresholds
+    dev = torch.device("cuda:0")
+    cfg = make_config("served-skim")
+    rp, col = chung_lu_graph(20000, 320000, 2.1, 56)
+    graphs = [("served-skim", make_graph(cfg)),
+              ("chung-lu-20k-wc", Graph(20000, rp, col, wc_thresholds(rp, col, 20000)))]
+    out = {}
+    k = 64
+    for name, g in graphs:
+        G = sk.DeviceGraph.from_host(g, dev)
+        pos = torch.empty(g.n * k, dtype=torch.int32, device=dev)
+        est = torch.empty(g.n, dtype=torch.float64, device=dev)
+        sk.skim_build_ic_sketches(G, k, cfg["seed"], pos, est)
+        times = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            sk.skim_build_ic_sketches(G, k, cfg["seed"], pos, est)
+            times.append(time.perf_counter() - t)
+        t = float(np.median(times))
+        out[name] = {"n": g.n, "m": g.m, "k": k, "ms": t * 1e3,
+                     "positions_per_s": g.n * k / t,
+                     "mean_estimate": float(est.mean().item())}
+    return out
+
+
 def bench_serving(torch, sk, duration=2.0):
     """Open-loop Poisson stream of union queries against resident sketches,
     with incremental SKIM requests overlapping on the device."""
@@ -471,6 +501,8 @@ def main():
         out["queries"] = bench_queries(torch, sk)
         log("skim")
         out["skim"] = bench_skim(torch, sk)
+        log("ic-model sketches")
+        out["ic_sketches"] = bench_ic(torch, sk)
         log("serving")
         out["serving"] = bench_serving(torch, sk)
     if not args.no_cpu_baseline:

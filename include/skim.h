@@ -206,7 +206,7 @@ uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
  * skim_build_sketches.  Every position runs a complete reverse search (an
  * instance has one source, so nothing prunes): the work is about k times
  * the sum of all nodes' influence, and the per-thread search state (n / 8 +
- * 4 n bytes) is budgeted at 2 GiB, which suits graphs up to about 2^18 nodes.
+ * 4 n bytes) is budgeted at 8 GiB, which suits graphs up to about 2^18 nodes.
  */
 skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, uint64_t seed,
                                    uint32_t *positions, double *est, void *stream);

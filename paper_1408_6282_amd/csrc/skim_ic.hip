@@ -31,7 +31,7 @@ namespace {
 constexpr uint64_t kIcChunk = 1ull << 63;                  // counters of the chunk hashes
 constexpr uint64_t kIcEdge = (1ull << 63) | (1ull << 62);  // counters of the per-edge streams
 constexpr int kIcBlock = 256;
-constexpr uint64_t kIcStateBudget = 2ull << 30;            // bytes of per-thread search state
+constexpr uint64_t kIcStateBudget = 8ull << 30;            // bytes of per-thread search state
 
 // Coin of edge (u -> w) in the instance of position t (>= 1): the high
 // (t - 1 even) or low (t - 1 odd) half of output floor((t - 1) / 2) of the
