@@ -235,6 +235,20 @@ skim_status skim_influence_batch(const skim_graph *g, uint32_t ell, uint64_t see
                                  uint64_t *reach_pairs, int32_t *qstatus, void *stream);
 
 /*
+ * skim_greedy_exact -- exact greedy on the l instances of `seed`, for
+ * graphs small enough to score every node at every step (a reference for a
+ * quality harness; Section 4 compares SKIM against it).  Step j selects the
+ * unselected node of largest exact marginal gain (newly covered
+ * node-instance pairs; smallest id on ties) and covers the pairs it reaches.
+ *   seeds      [s] out, device.
+ *   gain_pairs [s] out, device: l times each seed's exact marginal influence.
+ * s <= n; same graph conventions and validation as skim_build_sketches;
+ * l in [1, 64].  Each step runs n searches (pruned at covered pairs).
+ */
+skim_status skim_greedy_exact(const skim_graph *g, uint32_t ell, uint64_t seed, uint32_t s,
+                              uint32_t *seeds, uint64_t *gain_pairs, void *stream);
+
+/*
  * skim_greedy_records -- per-seed records of a SKIM run for its adaptive
  * error estimate (Section 4, adaptive error estimation), taken when the seed
  * is chosen, before its residual update.  For seeds first .. first+count-1

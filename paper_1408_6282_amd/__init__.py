@@ -27,7 +27,8 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_server_poll_greedy", "skim_server_replay", "skim_set_build_params",
            "skim_get_build_params", "skim_tune_build", "skim_query_plan_create",
            "skim_query_plan_launch", "skim_query_plan_free", "skim_greedy_records",
-           "skim_discrepancy_tail", "skim_influence_batch", "skim_build_ic_sketches"]
+           "skim_discrepancy_tail", "skim_influence_batch", "skim_build_ic_sketches",
+           "skim_greedy_exact"]
 
 
 class SkimError(RuntimeError):
@@ -94,6 +95,9 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_selected.argtypes = [vp]
     lib.skim_greedy_records.restype = C.c_int
     lib.skim_greedy_records.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, vp]
+    lib.skim_greedy_exact.restype = C.c_int
+    lib.skim_greedy_exact.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint64, C.c_uint32,
+                                      vp, vp, vp]
     lib.skim_build_ic_sketches.restype = C.c_int
     lib.skim_build_ic_sketches.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint64, vp, vp,
                                            vp]
@@ -322,6 +326,14 @@ def skim_greedy(graph: DeviceGraph, ell: int, k: int, seed: int, s: int, seeds, 
 
 def skim_greedy_state_free(state: GreedyState):
     state.free()
+
+
+def skim_greedy_exact(graph: DeviceGraph, ell: int, seed: int, s: int, seeds, gain_pairs,
+                      stream=None):
+    """Exact greedy (largest marginal gain, smallest id on ties) for s seeds."""
+    st = load_library().skim_greedy_exact(C.byref(graph.struct), ell, seed & 0xFFFFFFFFFFFFFFFF,
+                                          s, _ptr(seeds), _ptr(gain_pairs), _stream(stream))
+    _check("skim_greedy_exact", st)
 
 
 def skim_build_ic_sketches(graph: DeviceGraph, k: int, seed: int, positions, est=None,

@@ -122,3 +122,47 @@ def test_errors_and_empty_batches():
     with pytest.raises(sk.SkimError) as ei:  # sets hold nodes but no node array
         sk.skim_influence_batch(G, 4, 1, to_dev_u64([0, 1, 2]), None, r)
     assert ei.value.status == sk.SKIM_EINVAL
+
+
+def gpu_greedy_exact(g, ell, seed, s):
+    import torch
+    import paper_1408_6282_amd as sk
+    G = sk.DeviceGraph.from_host(g, dev())
+    a = torch.full((max(s, 1),), -1, dtype=torch.int32, device=dev())
+    b = torch.full((max(s, 1),), -1, dtype=torch.int64, device=dev())
+    sk.skim_greedy_exact(G, ell, seed, s, a, b)
+    torch.cuda.synchronize()
+    return a.cpu().numpy().view(np.uint32)[:s], b.cpu().numpy().view(np.uint64)[:s]
+
+
+@pytest.mark.parametrize("ell", [1, 8, 64])
+def test_greedy_exact_matches_oracle(oracle_lib, ell):
+    # the oracle's SKIM with k above every |R_u| is exact greedy (pinned
+    # against brute force): every seed from the exhaustion rule
+    rng = np.random.default_rng(ell + 70)
+    for trial in range(3):
+        n = int(rng.integers(2, 60))
+        src, dst, thr = random_small_graph(rng, n, int(rng.integers(0, 3 * n)),
+                                           [0xFFFFFFFF, 0xFFFFFFFF // 2, 0xFFFFFFFF // 10])
+        g = from_edges(n, src, dst, thr)
+        seed = int(rng.integers(0, 2 ** 62))
+        s = n if trial == 0 else int(rng.integers(1, n + 1))
+        log(f"greedy exact ell={ell} n={n} m={g.m} s={s}")
+        seeds, gains = gpu_greedy_exact(g, ell, seed, s)
+        ws, wg, cnt = oracle_lib.skim(g, seed, ell, n * ell + 1, s)
+        assert cnt["fallback"] == s
+        assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+
+
+def test_greedy_exact_served_config(oracle_lib):
+    cfg = make_config("served-skim")
+    g = make_graph(cfg)
+    log("greedy exact served-skim 50 seeds")
+    seeds, gains = gpu_greedy_exact(g, cfg["ell"], cfg["seed"], 50)
+    ws, wg, _ = oracle_lib.skim(g, cfg["seed"], cfg["ell"], g.n * cfg["ell"] + 1, 50)
+    assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+    # the prefixes' influence on the same instances is the running sum of gains
+    got = gpu_influence(g, cfg["ell"], cfg["seed"], [seeds[:j].tolist() for j in (1, 10, 50)],
+                        status=False)
+    cum = np.cumsum(gains)
+    assert [int(v) for v in got] == [int(cum[0]), int(cum[9]), int(cum[49])]
