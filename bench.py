@@ -268,7 +268,27 @@ def bench_skim(torch, sk, reps=3):
            "influence_pairs": int(gains.sum().item())}
     out["adaptive_error"] = bench_adaptive(torch, sk, G, cfg, s, reps)
     out["fresh_instances"] = bench_fresh(torch, sk, G, cfg, seeds, gains)
+    out["vs_exact_greedy"] = bench_exact_greedy(torch, sk, G, cfg, gains)
     return out
+
+
+def bench_exact_greedy(torch, sk, G, cfg, skim_gains, s=50):
+    """SKIM against exact greedy on the same 64 instances (Section 4's
+    comparison): the influence of the first s seeds of each, and the time of
+    the exact greedy that scores every node at every step."""
+    dev = torch.device("cuda:0")
+    seeds = torch.empty(s, dtype=torch.int32, device=dev)
+    gains = torch.empty(s, dtype=torch.int64, device=dev)
+    sk.skim_greedy_exact(G, cfg["ell"], cfg["seed"], s, seeds, gains)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sk.skim_greedy_exact(G, cfg["ell"], cfg["seed"], s, seeds, gains)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t
+    ex = float(gains[:s].sum().item()) / cfg["ell"]
+    sk_inf = float(skim_gains[:s].sum().item()) / cfg["ell"]
+    return {"seeds": s, "exact_greedy_ms": t * 1e3, "exact_greedy_influence": ex,
+            "skim_influence": sk_inf, "skim_over_exact": sk_inf / ex}
 
 
 def bench_fresh(torch, sk, G, cfg, seeds, gains, groups=8):
@@ -348,6 +368,46 @@ def bench_adaptive(torch, sk, G, cfg, s, reps, bins=4096, rel=0.25):
             "conv_tflops": flops / t / 1e12, "fp64_peak_tflops": 78.6,
             "filled_seeds": int((tau != -1).sum().item()),
             "p_total_discrepancy_at_least": at}
+
+
+def bench_oracle_quality(torch, sk, g, cfg, sets_per_size=100):
+    """The influence oracle's accuracy as the paper tabulates it (Section 6.2):
+    seed sets of 1, 50 and 1000 nodes, drawn uniformly or by the neighbourhood
+    generator; estimates from the sketches (bottom-k and Cohen-Kaplan) against
+    the exact influence on the same l instances (skim_influence_batch)."""
+    from workloads import neighbourhood_query_sets, uniform_query_sets
+    dev = torch.device("cuda:0")
+    ell, k, seed = cfg["ell"], cfg["k"], cfg["seed"]
+    G = sk.DeviceGraph.from_host(g, dev)
+    ranks = torch.empty(g.n * k, dtype=torch.int64, device=dev)
+    size = torch.empty(g.n, dtype=torch.int32, device=dev)
+    sk.skim_build_sketches(G, ell, k, seed, ranks, size)
+    out = {}
+    for s in (1, 50, 1000):
+        gens = {"uniform": uniform_query_sets(sets_per_size, g.n, 500 + s, s, s),
+                "neighbourhood": neighbourhood_query_sets(g.row_ptr, g.col, g.n, sets_per_size, s,
+                                                          600 + s)}
+        for name, (off, nodes) in gens.items():
+            qo = torch.from_numpy(off.view(np.int64)).to(dev)
+            qn = torch.from_numpy(nodes.view(np.int32)).to(dev)
+            q = off.size - 1
+            reach = torch.empty(q, dtype=torch.int64, device=dev)
+            sk.skim_influence_batch(G, ell, seed, qo, qn, reach)
+            exact = reach.cpu().numpy().astype(np.float64) / ell
+            row = {"exact_mean": float(exact.mean())}
+            for est_name, estimator in (("bottom_k", 0), ("cohen_kaplan", 1)):
+                est = torch.empty(q, dtype=torch.float64, device=dev)
+                sk.skim_query_batch(ranks, size, g.n, k, ell, qo, qn, est, estimator=estimator)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                sk.skim_query_batch(ranks, size, g.n, k, ell, qo, qn, est, estimator=estimator)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t
+                e = est.cpu().numpy()
+                row[est_name] = {"mean_rel_error_pct": float(np.mean(np.abs(e - exact) / exact)) * 100,
+                                 "us_per_query_batched": t / q * 1e6}
+            out[f"s{s}_{name}"] = row
+    return out
 
 
 def bench_ic(torch, sk, reps=3):
@@ -501,6 +561,8 @@ def main():
         out["queries"] = bench_queries(torch, sk)
         log("skim")
         out["skim"] = bench_skim(torch, sk)
+        log("oracle quality")
+        out["oracle_quality"] = bench_oracle_quality(torch, sk, g, cfg)
         log("ic-model sketches")
         out["ic_sketches"] = bench_ic(torch, sk)
         log("serving")

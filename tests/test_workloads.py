@@ -12,7 +12,8 @@ import numpy as np
 from workloads.configs import make_config, make_graph
 from workloads.graphs import (UINT32_MAX, chung_lu_graph, er_graph, rmat_graph,
                               trivalency_thresholds, uniform_thresholds, wc_thresholds)
-from workloads.queries import lognormal_query_sets, poisson_arrivals, uniform_query_sets
+from workloads.queries import (lognormal_query_sets, neighbourhood_query_sets, poisson_arrivals,
+                               uniform_query_sets)
 
 
 def _check_simple_csr(n, row_ptr, col):
@@ -131,3 +132,48 @@ def test_bench_algorithmic_bytes():
     # each pair sum_{j=0..bins} (j + 1) multiply-adds
     assert bench.tail_convolution_flops(5, 3) == 2 * 4 * (1 + 2 + 3 + 4)
     assert bench.tail_convolution_flops(1, 100) == 0
+
+
+def _bfs_depths(row_ptr, col, n, u):
+    depth = np.full(n, -1)
+    depth[u] = 0
+    frontier = [u]
+    d = 0
+    while frontier:
+        d += 1
+        nxt = []
+        for x in frontier:
+            for v in col[row_ptr[x]:row_ptr[x + 1]]:
+                if depth[v] < 0:
+                    depth[v] = d
+                    nxt.append(int(v))
+        frontier = nxt
+    return depth
+
+
+def test_neighbourhood_query_sets_stay_within_the_smallest_ball():
+    rp, col = er_graph(400, 2400, seed=13)
+    rp = rp.astype(np.int64)
+    depths = {u: _bfs_depths(rp, col, 400, u) for u in range(400) if rp[u + 1] > rp[u]}
+    for s in (1, 5, 40):
+        off, nodes = neighbourhood_query_sets(rp, col, 400, 30, s, seed=s)
+        sizes = _check_sets(off, nodes, 400, 30)
+        assert np.all(sizes == s)
+        for q in range(30):
+            S = nodes[off[q]:off[q + 1]].astype(np.int64)
+            # some start u has all of S within the smallest depth whose ball holds >= s nodes
+            ok = False
+            for u, dep in depths.items():  # starts have out-edges (chosen by out-degree)
+                if np.any(dep[S] < 0):
+                    continue
+                need = 0
+                while np.sum((dep >= 0) & (dep <= need)) < s:
+                    need += 1
+                if dep[S].max() <= need:
+                    ok = True
+                    break
+            assert ok, (s, q)
+    # reproducible, and different from uniform sets: members cluster
+    a = neighbourhood_query_sets(rp, col, 400, 5, 40, seed=3)
+    b = neighbourhood_query_sets(rp, col, 400, 5, 40, seed=3)
+    assert np.array_equal(a[1], b[1])

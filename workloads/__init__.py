@@ -19,5 +19,10 @@ from .graphs import (  # noqa: F401
     wc_thresholds,
     trivalency_thresholds,
 )
-from .queries import lognormal_query_sets, uniform_query_sets, poisson_arrivals  # noqa: F401
+from .queries import (  # noqa: F401
+    lognormal_query_sets,
+    neighbourhood_query_sets,
+    poisson_arrivals,
+    uniform_query_sets,
+)
 from .configs import CONFIGS, make_config  # noqa: F401

@@ -67,3 +67,50 @@ def poisson_arrivals(rate: float, duration_s: float, seed: int) -> np.ndarray:
         more = np.cumsum(rng.exponential(1.0 / rate, size=expect)) + t[-1]
         t = np.concatenate([t, more])
     return t[t < duration_s]
+
+
+def neighbourhood_query_sets(row_ptr: np.ndarray, col: np.ndarray, n: int, Q: int, s: int,
+                             seed: int, max_tries: int = 64):
+    """Seed sets whose members sit close together (the paper's neighbourhood
+    generator, Section 6.2): pick a start node with probability proportional
+    to its out-degree, grow a breadth-first search along out-edges level by
+    level until the levels so far hold at least s nodes, and draw the s
+    members uniformly without replacement from them.  A start whose search
+    dies out below s nodes is redrawn (up to max_tries times; then the
+    members are drawn uniformly from all nodes).  Returns (offsets, nodes)."""
+    rng = np.random.default_rng(seed)
+    row_ptr = np.asarray(row_ptr, dtype=np.int64)
+    col = np.asarray(col, dtype=np.int64)
+    outdeg = np.diff(row_ptr).astype(np.float64)
+    if s > n:
+        raise ValueError("set size out of range")
+    prob = outdeg / outdeg.sum() if outdeg.sum() > 0 else None
+    offsets = np.arange(Q + 1, dtype=np.uint64) * np.uint64(s)
+    nodes = np.empty(Q * s, dtype=np.uint32)
+    seen = np.zeros(n, dtype=bool)
+    for q in range(Q):
+        members = None
+        for _ in range(max_tries if prob is not None else 0):
+            u = int(rng.choice(n, p=prob))
+            tree = [np.array([u], dtype=np.int64)]
+            seen[u] = True
+            count, frontier = 1, tree[0]
+            while count < s and frontier.size:
+                starts, ends = row_ptr[frontier], row_ptr[frontier + 1]
+                idx = np.concatenate([np.arange(a, b) for a, b in zip(starts, ends)]) \
+                    if frontier.size else np.empty(0, dtype=np.int64)
+                nxt = np.unique(col[idx])
+                nxt = nxt[~seen[nxt]]
+                seen[nxt] = True
+                tree.append(nxt)
+                count += nxt.size
+                frontier = nxt
+            allnodes = np.concatenate(tree)
+            seen[allnodes] = False
+            if count >= s:
+                members = rng.choice(allnodes, size=s, replace=False)
+                break
+        if members is None:
+            members = rng.choice(n, size=s, replace=False)
+        nodes[q * s:(q + 1) * s] = members
+    return offsets, nodes
