@@ -410,6 +410,48 @@ def bench_oracle_quality(torch, sk, g, cfg, sets_per_size=100):
     return out
 
 
+def bench_error_vs_ell(torch, sk, groups=128, nodes=200, k=64):
+    """Error against the IC model itself (Section 6.2's figure on l): the
+    influence of sample nodes estimated from sketches built on l instances,
+    and from the IC-model sketches, against their influence on 64 * groups
+    fresh instances (exact evaluator), on a 20,000-node weighted-cascade
+    Chung-Lu graph."""
+    from workloads.graphs import Graph, chung_lu_graph, wc_thresholds
+    dev = torch.device("cuda:0")
+    n = 20000
+    rp, col = chung_lu_graph(n, 320000, 2.1, 57)
+    g = Graph(n, rp, col, wc_thresholds(rp, col, n))
+    G = sk.DeviceGraph.from_host(g, dev)
+    rng = np.random.default_rng(58)
+    sample = np.sort(rng.choice(n, size=nodes, replace=False)).astype(np.uint32)
+    off = np.arange(nodes + 1, dtype=np.uint64)
+    qo = torch.from_numpy(off.view(np.int64)).to(dev)
+    qn = torch.from_numpy(sample.view(np.int32)).to(dev)
+    reach = torch.empty(nodes, dtype=torch.int64, device=dev)
+    truth = np.zeros(nodes)
+    t = time.perf_counter()
+    for gi in range(groups):
+        sk.skim_influence_batch(G, 64, 10_000 + gi, qo, qn, reach)
+        truth += reach.cpu().numpy().astype(np.float64)
+    t_truth = time.perf_counter() - t
+    truth /= 64 * groups
+    out = {"graph": "chung-lu-20k-wc", "sample_nodes": nodes, "k": k,
+           "reference_instances": 64 * groups, "reference_ms": t_truth * 1e3}
+    for ell in (1, 4, 16, 64):
+        ranks = torch.empty(n * k, dtype=torch.int64, device=dev)
+        size = torch.empty(n, dtype=torch.int32, device=dev)
+        est = torch.empty(n, dtype=torch.float64, device=dev)
+        sk.skim_build_sketches(G, ell, k, 1, ranks, size, est)
+        e = est.cpu().numpy()[sample.astype(np.int64)]
+        out[f"l{ell}_mean_rel_error_pct"] = float(np.mean(np.abs(e - truth) / truth)) * 100
+    pos = torch.empty(n * k, dtype=torch.int32, device=dev)
+    est = torch.empty(n, dtype=torch.float64, device=dev)
+    sk.skim_build_ic_sketches(G, k, 1, pos, est)
+    e = est.cpu().numpy()[sample.astype(np.int64)]
+    out["ic_model_mean_rel_error_pct"] = float(np.mean(np.abs(e - truth) / truth)) * 100
+    return out
+
+
 def bench_ic(torch, sk, reps=3):
     """IC-model sketches (structured permutation ranks, Section 3) on served-skim
     and on a 20,000-node weighted-cascade Chung-Lu graph, k = 64."""
@@ -565,6 +607,8 @@ def main():
         out["oracle_quality"] = bench_oracle_quality(torch, sk, g, cfg)
         log("ic-model sketches")
         out["ic_sketches"] = bench_ic(torch, sk)
+        log("error against the ic model")
+        out["error_vs_ell"] = bench_error_vs_ell(torch, sk)
         log("serving")
         out["serving"] = bench_serving(torch, sk)
     if not args.no_cpu_baseline:
