@@ -106,6 +106,9 @@ def _load():
         lib.or_ic_sketches.restype = C.c_int
         lib.or_ic_sketches.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint32, C.c_uint64, P32,
                                        PD, P64]
+        lib.or_ic_union_query.restype = None
+        lib.or_ic_union_query.argtypes = [C.c_uint32, C.c_uint32, P32, C.c_uint64, P64, P32,
+                                          C.c_uint32, PD, PI32]
         _lib = lib
     return _lib
 
@@ -304,3 +307,18 @@ def ic_sketches(g, k: int, seed: int):
     if rc == -2:
         raise AssertionError("or_ic_sketches: a node holds fewer than k positions")
     return pos[:g.n * k].reshape(g.n, k), est[:g.n], int(visits[0])
+
+
+def ic_union_query(pos, n: int, k: int, offsets, nodes, estimator: int = 0):
+    """Union estimates over IC-model sketches (estimator 0 bottom-k, 1
+    Cohen-Kaplan) and per-query status."""
+    pos = np.ascontiguousarray(pos, dtype=np.uint32).reshape(-1)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nd = np.ascontiguousarray(nodes, dtype=np.uint32)
+    q = off.size - 1
+    est = np.zeros(max(q, 1))
+    st = np.zeros(max(q, 1), dtype=np.int32)
+    ndp = nd if nd.size else np.zeros(1, dtype=np.uint32)
+    _load().or_ic_union_query(n, k, _p(pos, P32), q, _p(off, P64), _p(ndp, P32), estimator,
+                              _p(est, PD), _p(st, PI32))
+    return est[:q], st[:q]

@@ -39,6 +39,9 @@
  *   or_ic_live, or_ic_order, or_ic_sketches  Section 3, structured permutation
  *                                          ranks and sketches for an IC model
  *                                          (the l -> infinity limit)
+ *   or_ic_union_query ..................... Section 3 and 5.1: bottom-k and
+ *                                          Cohen-Kaplan unions of IC-model
+ *                                          sketches (permutation ranks)
  *   or_skim ............................... Section 4, Algorithm 1; per-seed
  *                                          records for the adaptive error
  *                                          estimate (Section 4, adaptive error
@@ -867,4 +870,63 @@ int or_ic_sketches(uint32_t n, const uint64_t *row_ptr, const uint32_t *col, con
     free(rptr); free(rsrc); free(rthr); free(fill); free(node_at);
     free(cnt); free(stamp); free(queue);
     return rc;
+}
+
+static int cmp_u32(const void *a, const void *b)
+{
+    uint32_t x = *(const uint32_t *)a, y = *(const uint32_t *)b;
+    return x < y ? -1 : x > y;
+}
+
+/* Union queries over IC-model sketches (Section 3 and 5.1 with structured
+ * permutation ranks in the l -> infinity limit).  pos[n k]: each row
+ * ascending, always k positions.  Set j = qnodes[qoff[j] .. qoff[j+1]).
+ *   estimator 0 (bottom-k): T = the k-th smallest distinct position of the
+ *     union of the members' sketches; est = n (k - 1) / (T - 1).
+ *   estimator 1 (Cohen-Kaplan, eq. unionest with permutation ranks): every
+ *     distinct position z held by some member u outside u's own threshold
+ *     position T_u = X_u[k-1] weighs n / (T_max(z) - 1), T_max(z) the largest
+ *     T_u over those members; the weights are added in increasing z.
+ * Duplicate members act once; an empty set gives 0; a node >= n gives
+ * status -1 and est 0. */
+void or_ic_union_query(uint32_t n, uint32_t k, const uint32_t *pos, uint64_t q,
+                       const uint64_t *qoff, const uint32_t *qnodes, uint32_t estimator,
+                       double *out_est, int32_t *out_status)
+{
+    for (uint64_t j = 0; j < q; j++) {
+        uint64_t a = qoff[j], b = qoff[j + 1], S = b - a;
+        int bad = 0;
+        for (uint64_t t = a; t < b; t++) if (qnodes[t] >= n) bad = 1;
+        out_est[j] = 0.0;
+        if (out_status) out_status[j] = bad ? -1 : 0;
+        if (bad || S == 0) continue;
+        uint32_t *vals = malloc(sizeof(uint32_t) * S * k);
+        uint64_t c = 0;
+        for (uint64_t t = a; t < b; t++) {
+            const uint32_t *row = pos + (uint64_t)qnodes[t] * k;
+            uint32_t lim = estimator == 1 ? k - 1 : k;
+            for (uint32_t x = 0; x < lim; x++) vals[c++] = row[x];
+        }
+        qsort(vals, c, sizeof(uint32_t), cmp_u32);
+        if (estimator == 0) {
+            uint32_t d = 0, T = 0;
+            for (uint64_t x = 0; x < c && d < k; x++)
+                if (x == 0 || vals[x] != vals[x - 1]) { d++; T = vals[x]; }
+            out_est[j] = ((double)n * (double)(k - 1)) / (double)(T - 1);
+        } else {
+            double sum = 0.0;
+            for (uint64_t x = 0; x < c; x++) {
+                if (x > 0 && vals[x] == vals[x - 1]) continue;
+                uint32_t z = vals[x], Tmax = 0;
+                for (uint64_t t = a; t < b; t++) {
+                    const uint32_t *row = pos + (uint64_t)qnodes[t] * k;
+                    for (uint32_t y = 0; y + 1 < k; y++)
+                        if (row[y] == z && row[k - 1] > Tmax) Tmax = row[k - 1];
+                }
+                sum += (double)n / (double)(Tmax - 1);
+            }
+            out_est[j] = sum;
+        }
+        free(vals);
+    }
 }

@@ -125,3 +125,70 @@ def test_estimator_closed_form_without_edges(oracle_lib):
             est = oracle_lib.ic_sketches(g, k, seed)[1]
             assert est.mean() == pytest.approx(float(want), rel=1e-13)
         assert float(want) <= 1.0
+
+
+# ------------------------------------------------------------ union queries
+
+def _sets(groups):
+    off = np.zeros(len(groups) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum([len(s) for s in groups])
+    nodes = np.array([v for s in groups for v in s], dtype=np.uint32)
+    return off, nodes
+
+
+def test_union_of_one_is_the_node_estimate(oracle_lib):
+    rng = np.random.default_rng(21)
+    n, k = 40, 9
+    src, dst = rng.integers(0, n, 100), rng.integers(0, n, 100)
+    keep = src != dst
+    pairs = sorted(set(zip(src[keep].tolist(), dst[keep].tolist())))
+    g = from_edges(n, [p[0] for p in pairs], [p[1] for p in pairs], U32 // 3)
+    pos, est, _ = oracle_lib.ic_sketches(g, k, 4)
+    off, nodes = _sets([[u] for u in range(n)] + [[u, u, u] for u in range(n)])
+    bk, st = oracle_lib.ic_union_query(pos, n, k, off, nodes, 0)
+    assert np.all(st == 0)
+    assert np.array_equal(bk, np.concatenate([est, est]))  # same operands, same division
+    ck, _ = oracle_lib.ic_union_query(pos, n, k, off, nodes, 1)
+    want = np.array([(k - 1) * n / (pos[u, k - 1] - 1.0) for u in range(n)] * 2)
+    assert np.allclose(ck, want, rtol=1e-13)
+
+
+def test_union_on_a_deterministic_graph_reads_the_permutation(oracle_lib):
+    # p = 1: the union's positions are those of the nodes the set reaches
+    rng = np.random.default_rng(22)
+    n, k, seed = 30, 6, 19
+    src, dst = rng.integers(0, n, 45), rng.integers(0, n, 45)
+    keep = src != dst
+    pairs = sorted(set(zip(src[keep].tolist(), dst[keep].tolist())))
+    g = from_edges(n, [p[0] for p in pairs], [p[1] for p in pairs])
+    pos, _, _ = oracle_lib.ic_sketches(g, k, seed)
+    at = oracle_lib.ic_order(seed, n, k)
+    place = {}
+    for t, v in enumerate(at.tolist(), start=1):
+        place.setdefault(v, []).append(t)
+    adj = [[] for _ in range(n)]
+    for u, v in pairs:
+        adj[u].append(v)
+    groups = [rng.choice(n, size=int(rng.integers(1, 6)), replace=False).tolist()
+              for _ in range(40)]
+    off, nodes = _sets(groups)
+    est, _ = oracle_lib.ic_union_query(pos, n, k, off, nodes, 0)
+    for j, S in enumerate(groups):
+        T = sorted(t for v in reach(adj, S) for t in place[v])[k - 1]
+        assert est[j] == (n * (k - 1)) / (T - 1)
+
+
+def test_cohen_kaplan_adds_up_over_disjoint_sketches(oracle_lib):
+    # no edges: sketches are disjoint, so every value has one holder and the
+    # Cohen-Kaplan union is the sum of the members' (k-1) n / (T_u - 1)
+    n, k = 25, 7
+    g = from_edges(n, [], [])
+    pos, _, _ = oracle_lib.ic_sketches(g, k, 5)
+    groups = [[0, 1], [2, 3, 4, 5], list(range(n)), [], [7, 7, 8], [3, n]]
+    off, nodes = _sets(groups)
+    ck, st = oracle_lib.ic_union_query(pos, n, k, off, nodes, 1)
+    assert st.tolist() == [0, 0, 0, 0, 0, -1] and ck[3] == 0.0 and ck[5] == 0.0
+    for j in (0, 1, 2, 4):
+        members = sorted(set(groups[j]))
+        want = sum((k - 1) * n / (pos[u, k - 1] - 1.0) for u in members)
+        assert ck[j] == pytest.approx(want, rel=1e-12)
