@@ -914,18 +914,25 @@ void or_ic_union_query(uint32_t n, uint32_t k, const uint32_t *pos, uint64_t q,
                 if (x == 0 || vals[x] != vals[x - 1]) { d++; T = vals[x]; }
             out_est[j] = ((double)n * (double)(k - 1)) / (double)(T - 1);
         } else {
+            /* (value, holder's threshold) pairs sorted by value: each run of
+             * one value gives its largest holder threshold */
+            uint64_t *pairs = malloc(sizeof(uint64_t) * S * k);
+            uint64_t cp = 0;
+            for (uint64_t t = a; t < b; t++) {
+                const uint32_t *row = pos + (uint64_t)qnodes[t] * k;
+                for (uint32_t y = 0; y + 1 < k; y++)
+                    pairs[cp++] = ((uint64_t)row[y] << 32) | row[k - 1];
+            }
+            qsort(pairs, cp, sizeof(uint64_t), cmp_u64);
             double sum = 0.0;
-            for (uint64_t x = 0; x < c; x++) {
-                if (x > 0 && vals[x] == vals[x - 1]) continue;
-                uint32_t z = vals[x], Tmax = 0;
-                for (uint64_t t = a; t < b; t++) {
-                    const uint32_t *row = pos + (uint64_t)qnodes[t] * k;
-                    for (uint32_t y = 0; y + 1 < k; y++)
-                        if (row[y] == z && row[k - 1] > Tmax) Tmax = row[k - 1];
-                }
+            for (uint64_t x = 0; x < cp; x++) {
+                uint32_t z = (uint32_t)(pairs[x] >> 32);
+                if (x + 1 < cp && (uint32_t)(pairs[x + 1] >> 32) == z) continue;  /* last = max */
+                uint32_t Tmax = (uint32_t)pairs[x];
                 sum += (double)n / (double)(Tmax - 1);
             }
             out_est[j] = sum;
+            free(pairs);
         }
         free(vals);
     }
