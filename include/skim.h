@@ -212,6 +212,26 @@ skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, uint64_t see
                                    uint32_t *positions, double *est, void *stream);
 
 /*
+ * skim_ic_query_batch -- union queries over IC-model sketches (Section 3,
+ * permutation ranks; Section 5.1, union estimators) for q seed sets.
+ *   positions  [n k] device: as written by skim_build_ic_sketches.
+ *   qoff, qnodes: as for skim_query_batch (qoff[0] = 0, non-decreasing;
+ *     qnodes may be NULL when every set is empty; duplicates act once).
+ *   estimator 0 (bottom-k): n (k - 1) / (T - 1), T the k-th smallest distinct
+ *     position of the union of the members' sketches.
+ *   estimator 1 (Cohen-Kaplan, eq. unionest with permutation ranks): every
+ *     distinct position z some member u holds outside its own threshold
+ *     T_u = X_u[k-1] weighs n / (T_max(z) - 1), T_max(z) the largest T_u over
+ *     those members; the weights are added in increasing z.
+ *   est [q] out, device; qstatus [q] out, device, may be NULL: 0; -1 for a
+ *     node >= n and -2 for more than 1024 members (est 0 for both); an empty
+ *     set gives 0.
+ */
+skim_status skim_ic_query_batch(const uint32_t *positions, uint32_t n, uint32_t k, uint64_t q,
+                                const uint64_t *qoff, const uint32_t *qnodes, uint32_t estimator,
+                                double *est, int32_t *qstatus, void *stream);
+
+/*
  * skim_influence_batch -- exact influence of q seed sets over the l
  * instances of `seed` (Section 2, eqs. (Inf) and (timedinf)):
  * reach_pairs[j] = sum_i |reach_i(S_j)| = l Inf({G^(i)}, S_j), the number of

@@ -28,7 +28,7 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_get_build_params", "skim_tune_build", "skim_query_plan_create",
            "skim_query_plan_launch", "skim_query_plan_free", "skim_greedy_records",
            "skim_discrepancy_tail", "skim_influence_batch", "skim_build_ic_sketches",
-           "skim_greedy_exact"]
+           "skim_greedy_exact", "skim_ic_query_batch"]
 
 
 class SkimError(RuntimeError):
@@ -95,6 +95,9 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_selected.argtypes = [vp]
     lib.skim_greedy_records.restype = C.c_int
     lib.skim_greedy_records.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, vp]
+    lib.skim_ic_query_batch.restype = C.c_int
+    lib.skim_ic_query_batch.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp,
+                                        C.c_uint32, vp, vp, vp]
     lib.skim_greedy_exact.restype = C.c_int
     lib.skim_greedy_exact.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint64, C.c_uint32,
                                       vp, vp, vp]
@@ -326,6 +329,17 @@ def skim_greedy(graph: DeviceGraph, ell: int, k: int, seed: int, s: int, seeds, 
 
 def skim_greedy_state_free(state: GreedyState):
     state.free()
+
+
+def skim_ic_query_batch(positions, n: int, k: int, qoff, qnodes, est, qstatus=None,
+                        estimator: int = 0, stream=None):
+    """Union estimates over IC-model sketches into the float64 device tensor est."""
+    q = int(qoff.numel()) - 1
+    st = load_library().skim_ic_query_batch(
+        _ptr(positions), n, k, q, _ptr(qoff),
+        _ptr(qnodes) if qnodes is not None and qnodes.numel() else None, estimator, _ptr(est),
+        _ptr(qstatus), _stream(stream))
+    _check("skim_ic_query_batch", st)
 
 
 def skim_greedy_exact(graph: DeviceGraph, ell: int, seed: int, s: int, seeds, gain_pairs,

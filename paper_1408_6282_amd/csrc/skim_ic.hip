@@ -146,9 +146,138 @@ __global__ void k_ic_select(const uint64_t *rec, const uint64_t *start, uint32_t
     }
 }
 
+// ------------------------------------------------------------ union queries
+// One wave per query; the members' current heads and thresholds sit in LDS,
+// so a step of the k-way merge reads global memory only for the members
+// holding the current minimum.
+constexpr uint32_t kIcMaxMembers = 1024;
+constexpr uint32_t kIcNoPos = 0xFFFFFFFFu;
+
+__global__ void k_icq_offsets(const uint64_t *qoff, uint64_t q, uint32_t *err) {
+    for (uint64_t j = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; j <= q;
+         j += (uint64_t)gridDim.x * blockDim.x) {
+        const bool bad = j == 0 ? qoff[0] != 0 : qoff[j - 1] > qoff[j];
+        if (bad) atomicOr(err, 1u);
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t y = __shfl_xor(x, off);
+        x = y < x ? y : x;
+    }
+    return x;
+}
+
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint32_t y = __shfl_xor(x, off);
+        x = y > x ? y : x;
+    }
+    return x;
+}
+
+__global__ void __launch_bounds__(64) k_ic_query(const uint32_t *pos, uint32_t n, uint32_t k,
+                                                 uint64_t q, const uint64_t *qoff,
+                                                 const uint32_t *qnodes, uint32_t estimator,
+                                                 double *est, int32_t *qstatus) {
+    __shared__ uint32_t mnode[kIcMaxMembers], mhead[kIcMaxMembers], mthr[kIcMaxMembers];
+    __shared__ uint16_t mpos[kIcMaxMembers];
+    const uint32_t lane = threadIdx.x;
+    const uint32_t lim = estimator == 1 ? k - 1 : k;  // CK leaves out each threshold
+    for (uint64_t j = blockIdx.x; j < q; j += gridDim.x) {
+        const uint64_t a = qoff[j], b = qoff[j + 1], S = b - a;
+        bool bad = false;
+        for (uint64_t t = a + lane; t < b; t += 64) bad |= qnodes[t] >= n;
+        bad = __ballot(bad) != 0;
+        if (bad || S == 0 || S > kIcMaxMembers) {
+            if (lane == 0) {
+                est[j] = 0.0;
+                if (qstatus) qstatus[j] = bad ? -1 : (S == 0 ? 0 : -2);
+            }
+            continue;
+        }
+        for (uint32_t t = lane; t < S; t += 64) {
+            const uint32_t u = qnodes[a + t];
+            mnode[t] = u;
+            mpos[t] = 0;
+            mhead[t] = pos[(uint64_t)u * k];
+            mthr[t] = pos[(uint64_t)u * k + k - 1];
+        }
+        __syncthreads();
+        uint32_t d = 0, T = 0;
+        double sum = 0.0;
+        for (;;) {
+            uint32_t lmin = kIcNoPos;
+            for (uint32_t t = lane; t < S; t += 64) lmin = mhead[t] < lmin ? mhead[t] : lmin;
+            const uint32_t g = wave_min_u32(lmin);
+            if (g == kIcNoPos) break;
+            uint32_t tmax = 0;
+            for (uint32_t t = lane; t < S; t += 64)
+                if (mhead[t] == g) {
+                    const uint32_t p = mpos[t] + 1u;
+                    mpos[t] = (uint16_t)p;
+                    mhead[t] = p < lim ? pos[(uint64_t)mnode[t] * k + p] : kIcNoPos;
+                    tmax = mthr[t] > tmax ? mthr[t] : tmax;
+                }
+            __syncthreads();
+            if (estimator == 1) {
+                tmax = wave_max_u32(tmax);
+                if (lane == 0) sum += (double)n / (double)(tmax - 1);
+            } else if (++d == k) {
+                T = g;
+                break;
+            }
+        }
+        if (lane == 0) {
+            est[j] = estimator == 1 ? sum : ((double)n * (double)(k - 1)) / (double)(T - 1);
+            if (qstatus) qstatus[j] = 0;
+        }
+        __syncthreads();  // LDS is reused by the next query of the stride
+    }
+}
+
 }  // namespace
 
 }  // namespace skim
+
+extern "C" skim_status skim_ic_query_batch(const uint32_t *positions, uint32_t n, uint32_t k,
+                                           uint64_t q, const uint64_t *qoff,
+                                           const uint32_t *qnodes, uint32_t estimator,
+                                           double *est, int32_t *qstatus, void *stream) {
+    using namespace skim;
+    clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    try {
+        SKIM_REQUIRE(k >= 2 && k <= 256, "k must be in [2, 256]");
+        SKIM_REQUIRE(n >= 1 && (uint64_t)n * k < (1ull << 32), "n must be >= 1 with k n < 2^32");
+        SKIM_REQUIRE(estimator <= 1, "estimator must be 0 (bottom-k) or 1 (Cohen-Kaplan)");
+        SKIM_REQUIRE(positions != nullptr, "positions is NULL");
+        if (q == 0) return SKIM_OK;
+        SKIM_REQUIRE(qoff && est, "qoff/est is NULL");
+        Arena T(hs);
+        uint32_t *err = T.alloc<uint32_t>(1);
+        fill_u32(err, 0, 1, hs);
+        k_icq_offsets<<<grid_for(q + 1, 256, 4096), 256, 0, hs>>>(qoff, q, err);
+        SKIM_LAUNCH_CHECK();
+        uint32_t herr = 0;
+        read_back(&herr, err, sizeof herr, hs);
+        SKIM_REQUIRE(herr == 0, "qoff must start at 0 and be non-decreasing");
+        uint64_t total = 0;
+        read_back(&total, qoff + q, sizeof total, hs);
+        SKIM_REQUIRE(total == 0 || qnodes, "qnodes is NULL");
+        {
+            LaunchTimer t("k_ic_query", hs);
+            k_ic_query<<<(unsigned)std::min<uint64_t>(q, 16384), 64, 0, hs>>>(
+                positions, n, k, q, qoff, qnodes, estimator, est, qstatus);
+            SKIM_LAUNCH_CHECK();
+        }
+        SKIM_HIP(hipStreamSynchronize(hs));
+        return SKIM_OK;
+    } catch (const Fail &f) {
+        return f.st;
+    }
+}
 
 extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, uint64_t seed,
                                               uint32_t *positions, double *est, void *stream) {

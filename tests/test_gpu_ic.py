@@ -84,3 +84,59 @@ def test_bad_parameters():
     with pytest.raises(sk.SkimError) as ei:
         sk.skim_build_ic_sketches(G, 4, 1, None)
     assert ei.value.status == sk.SKIM_EINVAL
+
+
+def gpu_ic_query(pos_t, n, k, off, nodes, estimator):
+    import torch
+    import paper_1408_6282_amd as sk
+    from gpu_util import to_dev_u32, to_dev_u64
+    q = len(off) - 1
+    est = torch.full((max(q, 1),), -9.0, dtype=torch.float64, device=dev())
+    st = torch.full((max(q, 1),), 9, dtype=torch.int32, device=dev())
+    sk.skim_ic_query_batch(pos_t, n, k, to_dev_u64(off), to_dev_u32(nodes) if len(nodes) else None,
+                           est, st, estimator=estimator)
+    torch.cuda.synchronize()
+    return est.cpu().numpy()[:q], st.cpu().numpy()[:q]
+
+
+@pytest.mark.parametrize("name,k", [("served-skim", 64), ("tiny-ic", 16)])
+def test_union_queries(oracle_lib, name, k):
+    import torch
+    from workloads import uniform_query_sets
+    cfg = make_config(name)
+    g = make_graph(cfg)
+    pos, _ = gpu_ic(g, k, cfg["seed"])
+    pos_t = torch.from_numpy(pos.view(np.int32).reshape(-1).copy()).to(dev())
+    off, nodes = uniform_query_sets(3000, g.n, 41, 1, 512)
+    # extra cases: empty, duplicates, an invalid node, more than 1024 members
+    extra = [[], [5, 5, 9, 5], [3, g.n], list(range(g.n)) * 2]  # the last: 2000 members
+    sizes = np.diff(off.astype(np.int64)).tolist() + [len(e) for e in extra]
+    nodes = np.concatenate([nodes, np.array([v for e in extra for v in e], dtype=np.uint32)])
+    off = np.zeros(len(sizes) + 1, dtype=np.uint64)
+    off[1:] = np.cumsum(sizes)
+    for estimator in (0, 1):
+        log(f"ic union queries {name} estimator={estimator}")
+        est, st = gpu_ic_query(pos_t, g.n, k, off, nodes, estimator)
+        west, wst = oracle_lib.ic_union_query(pos, g.n, k, off, nodes, estimator)
+        assert st[-1] == -2 and est[-1] == 0.0
+        assert np.array_equal(st[:-1], wst[:-1])
+        assert np.array_equal(est[:-1], west[:-1])
+
+
+def test_union_query_errors():
+    import torch
+    import paper_1408_6282_amd as sk
+    from gpu_util import to_dev_u32, to_dev_u64
+    pos = torch.ones(10 * 4, dtype=torch.int32, device=dev())
+    est = torch.empty(2, dtype=torch.float64, device=dev())
+    nodes = to_dev_u32([0, 1])
+    for kw in ({"k": 1}, {"k": 257}, {"estimator": 2}):
+        k = kw.get("k", 4)
+        with pytest.raises(sk.SkimError) as ei:
+            sk.skim_ic_query_batch(pos, 10, k, to_dev_u64([0, 1, 2]), nodes, est,
+                                   estimator=kw.get("estimator", 0))
+        assert ei.value.status == sk.SKIM_EINVAL
+    for off in ([1, 1, 2], [0, 2, 1]):
+        with pytest.raises(sk.SkimError) as ei:
+            sk.skim_ic_query_batch(pos, 10, 4, to_dev_u64(off), nodes, est)
+        assert ei.value.status == sk.SKIM_EINVAL
