@@ -479,6 +479,28 @@ def bench_ic(torch, sk, reps=3):
         out[name] = {"n": g.n, "m": g.m, "k": k, "ms": t * 1e3,
                      "positions_per_s": g.n * k / t,
                      "mean_estimate": float(est.mean().item())}
+        if name == "served-skim":
+            out[name]["union_queries"] = bench_ic_queries(torch, sk, pos, g.n, k)
+    return out
+
+
+def bench_ic_queries(torch, sk, pos, n, k, Q=1_000_000):
+    """Union queries over IC-model sketches: the lognormal batch of the
+    batched-query workload (mean |S| about 12), both estimators."""
+    from workloads import lognormal_query_sets
+    dev = torch.device("cuda:0")
+    off, nodes = lognormal_query_sets(Q, n, 3)
+    qo = torch.from_numpy(off.view(np.int64)).to(dev)
+    qn = torch.from_numpy(nodes.view(np.int32)).to(dev)
+    est = torch.empty(Q, dtype=torch.float64, device=dev)
+    out = {"queries": Q}
+    for name, estimator in (("bottom_k", 0), ("cohen_kaplan", 1)):
+        sk.skim_ic_query_batch(pos, n, k, qo, qn, est, estimator=estimator)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sk.skim_ic_query_batch(pos, n, k, qo, qn, est, estimator=estimator)
+        torch.cuda.synchronize()
+        out[f"{name}_queries_per_s"] = Q / (time.perf_counter() - t)
     return out
 
 
