@@ -10,6 +10,8 @@
 //    value; its weight is 1/rho(max tau_u over the members holding it), a
 //    non-full member counting as rho = 1; lane 0 adds the weights in
 //    increasing order of the value.
+// Each lane keeps its members' current heads in registers, so a merge step
+// touches global memory only for the members that advance.
 // The batched path is one persistent launch whose waves pull queries from a
 // device counter; the plain path launches the same device code once per
 // query.
@@ -23,6 +25,7 @@ namespace {
 
 constexpr uint32_t kMaxMembers = 1024;  // members per query (LDS state)
 constexpr int kQBlock = 64;             // one wave per block
+constexpr int kPerLane = kMaxMembers / 64;
 
 using QArgs = QueryArgs;
 
@@ -44,6 +47,59 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
         x = y > x ? y : x;
     }
     return x;
+}
+
+// The k-way merge over S members (R >= S / 64 register slots per lane).
+// Each lane keeps the current head of its members t = lane + 64 r in
+// registers; a step reads global memory only for the members that advance.
+// Bottom-k stops at the k-th distinct value (d, tau); Cohen-Kaplan adds each
+// distinct value's weight in increasing order on lane 0 (sum).
+template <int R>
+__device__ __forceinline__ void merge_members(const QArgs &Q, uint64_t S, uint32_t k,
+                                              const uint32_t *mnode, uint16_t *mpos,
+                                              const uint16_t *mlim, uint32_t &d, uint64_t &tau,
+                                              double &sum) {
+    const uint32_t lane = lane_id();
+    uint64_t head[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t t = lane + 64u * r;
+        head[r] = kNone;
+        if (t < S && mlim[t] > 0) head[r] = Q.ranks[(uint64_t)mnode[t] * k];
+    }
+    for (;;) {
+        uint64_t lmin = kNone;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lmin = head[r] < lmin ? head[r] : lmin;
+        const uint64_t g = wave_min_u64(lmin);
+        if (g == kNone) break;
+        // advance the holders of g; for CK also find their largest threshold
+        uint64_t tmax = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (head[r] == g) {
+                const uint32_t t = lane + 64u * r;
+                const uint32_t u = mnode[t];
+                const uint32_t p = mpos[t] + 1u;
+                mpos[t] = (uint16_t)p;
+                head[r] = p < mlim[t] ? Q.ranks[(uint64_t)u * k + p] : kNone;
+                if (Q.estimator == 1) {
+                    const uint64_t tu = Q.size[u] >= k ? Q.ranks[(uint64_t)u * k + k - 1] : kNone;
+                    tmax = tu > tmax ? tu : tmax;
+                }
+            }
+        }
+        if (Q.estimator == 1) {
+            tmax = wave_max_u64(tmax);
+            if (lane == 0) sum += tmax == kNone ? 1.0 : 1.0 / rank_real(tmax);
+        } else {
+            ++d;
+            if (d == k) {
+                tau = g;
+                break;
+            }
+        }
+    }
 }
 
 // Answer query j with the calling wave (all 64 lanes, converged).
@@ -102,44 +158,12 @@ __device__ void answer_query(const QArgs &Q, uint64_t j, uint32_t *mnode, uint16
     uint32_t d = 0;
     uint64_t tau = 0;
     double sum = 0.0;
-    for (;;) {
-        uint64_t lmin = kNone;
-        for (uint32_t t = lane; t < S; t += 64) {
-            const uint32_t p = mpos[t];
-            if (p < mlim[t]) {
-                const uint64_t h = Q.ranks[(uint64_t)mnode[t] * k + p];
-                lmin = h < lmin ? h : lmin;
-            }
-        }
-        const uint64_t g = wave_min_u64(lmin);
-        if (g == kNone) break;
-        // advance the holders of g; for CK also find their largest threshold
-        uint64_t tmax = 0;
-        for (uint32_t t = lane; t < S; t += 64) {
-            const uint32_t p = mpos[t];
-            if (p < mlim[t]) {
-                const uint32_t u = mnode[t];
-                if (Q.ranks[(uint64_t)u * k + p] == g) {
-                    mpos[t] = (uint16_t)(p + 1);
-                    if (Q.estimator == 1) {
-                        const uint64_t tu = Q.size[u] >= k ? Q.ranks[(uint64_t)u * k + k - 1] : kNone;
-                        tmax = tu > tmax ? tu : tmax;
-                    }
-                }
-            }
-        }
-        __syncthreads();
-        if (Q.estimator == 1) {
-            tmax = wave_max_u64(tmax);
-            if (lane == 0) sum += tmax == kNone ? 1.0 : 1.0 / rank_real(tmax);
-        } else {
-            ++d;
-            if (d == k) {
-                tau = g;
-                break;
-            }
-        }
-    }
+    if (S <= 64)
+        merge_members<1>(Q, S, k, mnode, mpos, mlim, d, tau, sum);
+    else if (S <= 256)
+        merge_members<4>(Q, S, k, mnode, mpos, mlim, d, tau, sum);
+    else
+        merge_members<kPerLane>(Q, S, k, mnode, mpos, mlim, d, tau, sum);
     if (lane == 0) {
         Q.est[j] = Q.estimator == 1 ? sum / (double)Q.ell : bottomk_estimate(d, tau, k, Q.ell);
         if (Q.qstatus) Q.qstatus[j] = 0;
