@@ -147,9 +147,9 @@ __global__ void k_ic_select(const uint64_t *rec, const uint64_t *start, uint32_t
 }
 
 // ------------------------------------------------------------ union queries
-// One wave per query; the members' current heads and thresholds sit in LDS,
-// so a step of the k-way merge reads global memory only for the members
-// holding the current minimum.
+// One wave per query; each lane keeps the current heads and thresholds of
+// its members in registers, so a step of the k-way merge reads global memory
+// only for the members holding the current minimum.
 constexpr uint32_t kIcMaxMembers = 1024;
 constexpr uint32_t kIcNoPos = 0xFFFFFFFFu;
 
@@ -177,14 +177,58 @@ __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
     return x;
 }
 
+// The k-way merge over S members with R >= S / 64 register slots per lane:
+// lane l keeps the current head and threshold of members l + 64 r.
+template <int R>
+__device__ __forceinline__ void ic_merge(const uint32_t *pos, uint32_t n, uint32_t k,
+                                         uint32_t estimator, uint32_t S, const uint32_t *mnode,
+                                         uint32_t &T, double &sum) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t lim = estimator == 1 ? k - 1 : k;  // CK leaves out each threshold
+    uint32_t head[R], thr[R], at[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t t = lane + 64u * r;
+        head[r] = kIcNoPos;
+        thr[r] = 0;
+        at[r] = 0;
+        if (t < S) {
+            const uint64_t row = (uint64_t)mnode[t] * k;
+            head[r] = pos[row];
+            thr[r] = pos[row + k - 1];
+        }
+    }
+    uint32_t d = 0;
+    for (;;) {
+        uint32_t lmin = kIcNoPos;
+#pragma unroll
+        for (int r = 0; r < R; ++r) lmin = head[r] < lmin ? head[r] : lmin;
+        const uint32_t g = wave_min_u32(lmin);
+        if (g == kIcNoPos) break;
+        uint32_t tmax = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            if (head[r] == g) {
+                const uint32_t p = ++at[r];
+                head[r] = p < lim ? pos[(uint64_t)mnode[lane + 64u * r] * k + p] : kIcNoPos;
+                tmax = thr[r] > tmax ? thr[r] : tmax;
+            }
+        if (estimator == 1) {
+            tmax = wave_max_u32(tmax);
+            if (lane == 0) sum += (double)n / (double)(tmax - 1);
+        } else if (++d == k) {
+            T = g;
+            break;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(64) k_ic_query(const uint32_t *pos, uint32_t n, uint32_t k,
                                                  uint64_t q, const uint64_t *qoff,
                                                  const uint32_t *qnodes, uint32_t estimator,
                                                  double *est, int32_t *qstatus) {
-    __shared__ uint32_t mnode[kIcMaxMembers], mhead[kIcMaxMembers], mthr[kIcMaxMembers];
-    __shared__ uint16_t mpos[kIcMaxMembers];
+    __shared__ uint32_t mnode[kIcMaxMembers];
     const uint32_t lane = threadIdx.x;
-    const uint32_t lim = estimator == 1 ? k - 1 : k;  // CK leaves out each threshold
     for (uint64_t j = blockIdx.x; j < q; j += gridDim.x) {
         const uint64_t a = qoff[j], b = qoff[j + 1], S = b - a;
         bool bad = false;
@@ -197,38 +241,16 @@ __global__ void __launch_bounds__(64) k_ic_query(const uint32_t *pos, uint32_t n
             }
             continue;
         }
-        for (uint32_t t = lane; t < S; t += 64) {
-            const uint32_t u = qnodes[a + t];
-            mnode[t] = u;
-            mpos[t] = 0;
-            mhead[t] = pos[(uint64_t)u * k];
-            mthr[t] = pos[(uint64_t)u * k + k - 1];
-        }
+        for (uint32_t t = lane; t < S; t += 64) mnode[t] = qnodes[a + t];
         __syncthreads();
-        uint32_t d = 0, T = 0;
+        uint32_t T = 0;
         double sum = 0.0;
-        for (;;) {
-            uint32_t lmin = kIcNoPos;
-            for (uint32_t t = lane; t < S; t += 64) lmin = mhead[t] < lmin ? mhead[t] : lmin;
-            const uint32_t g = wave_min_u32(lmin);
-            if (g == kIcNoPos) break;
-            uint32_t tmax = 0;
-            for (uint32_t t = lane; t < S; t += 64)
-                if (mhead[t] == g) {
-                    const uint32_t p = mpos[t] + 1u;
-                    mpos[t] = (uint16_t)p;
-                    mhead[t] = p < lim ? pos[(uint64_t)mnode[t] * k + p] : kIcNoPos;
-                    tmax = mthr[t] > tmax ? mthr[t] : tmax;
-                }
-            __syncthreads();
-            if (estimator == 1) {
-                tmax = wave_max_u32(tmax);
-                if (lane == 0) sum += (double)n / (double)(tmax - 1);
-            } else if (++d == k) {
-                T = g;
-                break;
-            }
-        }
+        if (S <= 64)
+            ic_merge<1>(pos, n, k, estimator, (uint32_t)S, mnode, T, sum);
+        else if (S <= 256)
+            ic_merge<4>(pos, n, k, estimator, (uint32_t)S, mnode, T, sum);
+        else
+            ic_merge<kIcMaxMembers / 64>(pos, n, k, estimator, (uint32_t)S, mnode, T, sum);
         if (lane == 0) {
             est[j] = estimator == 1 ? sum : ((double)n * (double)(k - 1)) / (double)(T - 1);
             if (qstatus) qstatus[j] = 0;
