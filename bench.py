@@ -269,7 +269,29 @@ def bench_skim(torch, sk, reps=3):
     out["adaptive_error"] = bench_adaptive(torch, sk, G, cfg, s, reps)
     out["fresh_instances"] = bench_fresh(torch, sk, G, cfg, seeds, gains)
     out["vs_exact_greedy"] = bench_exact_greedy(torch, sk, G, cfg, gains)
+    out["chung_lu_20k_wc"] = bench_skim_20k(torch, sk)
     return out
+
+
+def bench_skim_20k(torch, sk, s=50):
+    """SKIM on a heavy-tailed graph: Chung-Lu n = 20,000, m = 320,000, weighted
+    cascade, l = k = 64, 50 seeds (one call, state built inside)."""
+    from workloads.graphs import Graph, chung_lu_graph, wc_thresholds
+    dev = torch.device("cuda:0")
+    n = 20000
+    rp, col = chung_lu_graph(n, 320000, 2.1, 56)
+    g = Graph(n, rp, col, wc_thresholds(rp, col, n))
+    G = sk.DeviceGraph.from_host(g, dev)
+    seeds = torch.empty(s, dtype=torch.int32, device=dev)
+    gains = torch.empty(s, dtype=torch.int64, device=dev)
+    sk.skim_greedy(G, 64, 64, 1, s, seeds, gains)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sk.skim_greedy(G, 64, 64, 1, s, seeds, gains)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t
+    return {"n": n, "m": g.m, "ell": 64, "k": 64, "seeds": s, "ms": t * 1e3,
+            "influence": float(gains.sum().item()) / 64}
 
 
 def bench_exact_greedy(torch, sk, G, cfg, skim_gains, s=50):

@@ -21,10 +21,11 @@
 //    the seed's sketch and the second largest sketch k' (largest size among
 //    the other unselected nodes, one less for nodes in that pair's search)
 //    are stored per seed for the adaptive error estimate (Section 4).
-//  * residual: one thread per instance runs the forward search from the seed
-//    over live out-edges, not entering covered pairs; every newly covered
-//    pair counts towards the seed's gain and decrements the size of every
-//    node in its index entry, which is then erased.
+//  * residual: a level-synchronous forward search from the seed over all
+//    instances at once (the whole workgroup shares each level's frontier of
+//    pairs) over live out-edges, not entering covered pairs; every newly
+//    covered pair counts towards the seed's gain and decrements the size of
+//    every node in its index entry, which is then erased.
 //
 // The adaptive error estimate itself (skim_discrepancy_tail) bounds each
 // seed's discrepancy with eq. (chernoff) on a grid of discrepancy values and
@@ -105,7 +106,7 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
 __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, uint32_t *seeds,
                                                      uint64_t *gains, double *gain_d,
                                                      uint64_t *rec_tau, uint32_t *rec_second) {
-    __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_total, s_tau;
+    __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_total, s_tau, s_fcnt[2];
     __shared__ int s_x, s_filler;
     __shared__ uint32_t s_found, s_stop, s_fill_cnt, s_second;
     // size[] and the batch counters live in LDS when the graph is small
@@ -292,34 +293,53 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             rec_second[it] = s_second;
         }
         // ------------------------------------------------- residual problem
-        if (tid == 0) s_gain = 0;
+        // Level-synchronous over all instances at once: a frontier of pairs
+        // (64 v + i) in two halves of the queue area (free here: the scan's
+        // searches are done and the filler's queue has been read).  A pair is
+        // claimed by the CAS that covers it; its index entry is erased then.
+        uint32_t *F[2] = {A.queues, A.queues + (uint64_t)A.n * kPairStride};
+        if (tid == 0) {
+            s_gain = 0;
+            s_fcnt[0] = 0;
+        }
         __syncthreads();
-        if (tid < A.ell) {
-            const uint32_t i = tid;
-            const uint32_t px = x * kPairStride + i;
-            if (!ld(A.covered + px)) {
-                st(A.covered + px, 1u);
-                Q[0] = x;
-                uint32_t cnt = 1;
-                for (uint32_t head = 0; head < cnt; ++head) {
-                    const uint32_t v = Q[head];
-                    const uint32_t q = v * kPairStride + i;
-                    const uint32_t c = ld(A.idx_cnt + q);
-                    if (c) {
-                        const uint32_t o = ld(A.idx_off + q);
-                        for (uint32_t j = 0; j < c; ++j) atomicSub(SZ + ld(A.pool + o + j), 1u);
-                        st(A.idx_cnt + q, 0u);
-                    }
-                    for (uint64_t e = A.fptr[q]; e < A.fptr[q + 1]; ++e) {
-                        const uint32_t w = A.fadj[e];
-                        const uint32_t qw = w * kPairStride + i;
-                        if (!ld(A.covered + qw)) {
-                            st(A.covered + qw, 1u);
-                            Q[cnt++] = w;
-                        }
-                    }
+        {
+            bool add = false;
+            uint32_t px = 0;
+            if (tid < A.ell) {
+                px = x * kPairStride + tid;
+                add = atomicCAS(A.covered + px, 0u, 1u) == 0u;
+            }
+            if (tid < 64) {  // the first wave holds every instance (l <= 64)
+                const uint64_t slot = wave_reserve(&s_fcnt[0], add);
+                if (add) st(F[0] + slot, px);
+            }
+        }
+        for (uint32_t cur = 0;; cur ^= 1u) {
+            __syncthreads();
+            const uint64_t fc = s_fcnt[cur];
+            __syncthreads();  // every thread has read the count
+            if (fc == 0) break;
+            if (tid == 0) {
+                s_fcnt[cur ^ 1u] = 0;
+                s_gain += fc;
+            }
+            __syncthreads();
+            for (uint64_t e = tid; e < fc; e += kSkimBlock) {
+                const uint32_t q = ld(F[cur] + e);
+                const uint32_t i = q % kPairStride;
+                const uint32_t c = ld(A.idx_cnt + q);
+                if (c) {
+                    const uint32_t o = ld(A.idx_off + q);
+                    for (uint32_t j = 0; j < c; ++j) atomicSub(SZ + ld(A.pool + o + j), 1u);
+                    st(A.idx_cnt + q, 0u);
                 }
-                atomicAdd(&s_gain, (unsigned long long)cnt);
+                for (uint64_t x2 = A.fptr[q]; x2 < A.fptr[q + 1]; ++x2) {
+                    const uint32_t qw = A.fadj[x2] * kPairStride + i;
+                    const bool add = !ld(A.covered + qw) && atomicCAS(A.covered + qw, 0u, 1u) == 0u;
+                    const uint64_t slot = wave_reserve(&s_fcnt[cur ^ 1u], add);
+                    if (add) st(F[cur ^ 1u] + slot, qw);
+                }
             }
         }
         __syncthreads();

@@ -66,3 +66,16 @@ def test_too_many_seeds_rejected():
     with pytest.raises(sk.SkimError) as ei:
         sk.skim_greedy(G, 4, 4, 1, 6, a, b)
     assert ei.value.status == sk.SKIM_EINVAL
+
+
+def test_weighted_cascade_20k(oracle_lib):
+    # heavy-tailed reach: seeds whose residual searches cover thousands of pairs
+    from workloads.graphs import Graph, chung_lu_graph, wc_thresholds
+    n = 20000
+    rp, col = chung_lu_graph(n, 320000, 2.1, 56)
+    g = Graph(n, rp, col, wc_thresholds(rp, col, n))
+    for ell, k, s in ((16, 16, 20), (64, 64, 30)):
+        log(f"skim chung-lu 20k wc ell={ell} k={k} s={s}")
+        seeds, gains, _, _ = gpu_greedy(g, ell, k, 1, [s])
+        ws, wg, _ = oracle_lib.skim(g, 1, ell, k, s)
+        assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
