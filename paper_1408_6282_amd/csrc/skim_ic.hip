@@ -11,7 +11,9 @@
 //  * one thread per position runs the complete reverse search from v_t over
 //    the in-edges whose coin in instance t is live (coins on the fly from a
 //    per-edge SplitMix64 stream), deduplicating with a visited bitmap of its
-//    own and clearing only the bits it set;
+//    own and clearing only the bits it set; a search that grows beyond
+//    kIcLight nodes is handed to a workgroup (the heavy searches of hubs
+//    would otherwise serialise in one thread);
 //  * a first pass counts the nodes each search reaches, a scan gives every
 //    position its record range, and a second pass writes the records
 //    (node << 32 | t) there, so no record needs an atomic;
@@ -32,6 +34,9 @@ constexpr uint64_t kIcChunk = 1ull << 63;                  // counters of the ch
 constexpr uint64_t kIcEdge = (1ull << 63) | (1ull << 62);  // counters of the per-edge streams
 constexpr int kIcBlock = 256;
 constexpr uint64_t kIcStateBudget = 8ull << 30;            // bytes of per-thread search state
+constexpr uint32_t kIcLight = 1024;   // a thread's search hands over beyond this many nodes
+constexpr int kIcHeavyBlock = 1024;   // one workgroup per handed-over search
+constexpr uint64_t kIcHeavyBudget = 2ull << 30;            // bytes of per-workgroup state
 
 // Coin of edge (u -> w) in the instance of position t (>= 1): the high
 // (t - 1 even) or low (t - 1 odd) half of output floor((t - 1) / 2) of the
@@ -86,41 +91,123 @@ struct IcArgs {
     const uint64_t *offsets;  // [k n + 1] pass 1 in
     uint64_t *records;        // pass 1 out
     uint32_t *bitmaps;        // [threads][(n + 31) / 32]
-    uint32_t *queues;         // [threads][n]
+    uint32_t *queues;         // [threads][kIcLight]
+    uint32_t *heavy;          // positions handed to the workgroup search
+    unsigned long long *nheavy;
+    uint32_t *hbitmaps;       // [workgroups][(n + 31) / 32]
+    uint32_t *hqueues;        // [workgroups][n]
 };
 
+template <class T> __device__ __forceinline__ T ic_ld(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T> __device__ __forceinline__ void ic_st(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One thread per position.  A search that would reach more than kIcLight
+// nodes stops, clears what it marked and hands the position to the
+// workgroup search (first pass: appended to the heavy list; second pass:
+// skipped, its count being above kIcLight).
 template <int kPass>
 __global__ void __launch_bounds__(kIcBlock) k_ic_search(IcArgs A) {
     const uint64_t tid = blockIdx.x * (uint64_t)kIcBlock + threadIdx.x;
     const uint64_t threads = (uint64_t)gridDim.x * kIcBlock;
     const uint32_t words = (A.n + 31) / 32;
     uint32_t *bm = A.bitmaps + tid * words;
-    uint32_t *Q = A.queues + tid * A.n;
+    uint32_t *Q = A.queues + tid * kIcLight;
     const uint64_t total = (uint64_t)A.n * A.k;
-    for (uint64_t x = tid; x < total; x += threads) {
-        const uint32_t t = (uint32_t)(x + 1);
-        const uint32_t v = A.node_at[x];
-        Q[0] = v;
-        bm[v >> 5] |= 1u << (v & 31);
-        uint32_t cnt = 1;
-        for (uint32_t head = 0; head < cnt; ++head) {
-            const uint32_t y = Q[head];
-            for (uint64_t e = A.rptr[y]; e < A.rptr[y + 1]; ++e) {
-                const uint32_t u = A.rsrc[e];
-                const uint32_t bit = 1u << (u & 31);
-                if ((bm[u >> 5] & bit) == 0 && ic_live(A.seed, A.n, u, y, t, A.rthr[e])) {
-                    bm[u >> 5] |= bit;
-                    Q[cnt++] = u;
+    for (uint64_t x0 = 0; x0 < total; x0 += threads) {
+        const uint64_t x = x0 + tid;
+        bool heavy = false;
+        if (x < total && !(kPass == 1 && A.counts[x] > kIcLight)) {
+            const uint32_t t = (uint32_t)(x + 1);
+            const uint32_t v = A.node_at[x];
+            Q[0] = v;
+            bm[v >> 5] |= 1u << (v & 31);
+            uint32_t cnt = 1;
+            for (uint32_t head = 0; head < cnt && !heavy; ++head) {
+                const uint32_t y = Q[head];
+                for (uint64_t e = A.rptr[y]; e < A.rptr[y + 1]; ++e) {
+                    const uint32_t u = A.rsrc[e];
+                    const uint32_t bit = 1u << (u & 31);
+                    if ((bm[u >> 5] & bit) == 0 && ic_live(A.seed, A.n, u, y, t, A.rthr[e])) {
+                        if (cnt == kIcLight) {
+                            heavy = true;
+                            break;
+                        }
+                        bm[u >> 5] |= bit;
+                        Q[cnt++] = u;
+                    }
                 }
             }
+            if (kPass == 0) {
+                A.counts[x] = heavy ? 0u : cnt;
+            } else {
+                uint64_t *out = A.records + A.offsets[x];
+                for (uint32_t j = 0; j < cnt; ++j) out[j] = ((uint64_t)Q[j] << 32) | t;
+            }
+            for (uint32_t j = 0; j < cnt; ++j) bm[Q[j] >> 5] = 0;
         }
+        if (kPass == 0) {  // every lane of the wave takes part in the reservation
+            const uint64_t slot = wave_reserve(A.nheavy, heavy);
+            if (heavy) A.heavy[slot] = (uint32_t)x;
+        }
+    }
+}
+
+// One workgroup per handed-over position: the breadth-first search takes up
+// to kIcHeavyBlock queue entries per round, one per thread; new nodes are
+// marked in the workgroup's bitmap with an atomic OR and appended with one
+// LDS atomic per wave.
+template <int kPass>
+__global__ void __launch_bounds__(kIcHeavyBlock) k_ic_heavy(IcArgs A, uint64_t nheavy) {
+    __shared__ unsigned long long s_tail;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t words = (A.n + 31) / 32;
+    uint32_t *bm = A.hbitmaps + (uint64_t)blockIdx.x * words;
+    uint32_t *Q = A.hqueues + (uint64_t)blockIdx.x * A.n;
+    for (uint64_t h = blockIdx.x; h < nheavy; h += gridDim.x) {
+        const uint64_t x = A.heavy[h];
+        const uint32_t t = (uint32_t)(x + 1);
+        if (tid == 0) {
+            const uint32_t v = A.node_at[x];
+            atomicOr(bm + (v >> 5), 1u << (v & 31));
+            ic_st(Q, v);
+            s_tail = 1;
+        }
+        __syncthreads();
+        uint64_t head = 0;
+        for (;;) {
+            const uint64_t tail = s_tail;
+            __syncthreads();  // every thread has the same tail before any append
+            if (head >= tail) break;
+            const uint64_t chunk = tail - head < (uint64_t)kIcHeavyBlock ? tail - head : kIcHeavyBlock;
+            if (tid < chunk) {
+                const uint32_t y = ic_ld(Q + head + tid);
+                for (uint64_t e = A.rptr[y]; e < A.rptr[y + 1]; ++e) {
+                    const uint32_t u = A.rsrc[e];
+                    const uint32_t bit = 1u << (u & 31);
+                    bool add = (ic_ld(bm + (u >> 5)) & bit) == 0 &&
+                               ic_live(A.seed, A.n, u, y, t, A.rthr[e]);
+                    if (add) add = (atomicOr(bm + (u >> 5), bit) & bit) == 0;
+                    const uint64_t slot = wave_reserve(&s_tail, add);
+                    if (add) ic_st(Q + slot, u);
+                }
+            }
+            head += chunk;
+            __syncthreads();  // this round's appends are in the queue and s_tail
+        }
+        const uint64_t cnt = s_tail;
         if (kPass == 0) {
-            A.counts[x] = cnt;
+            if (tid == 0) A.counts[x] = (uint32_t)cnt;
         } else {
             uint64_t *out = A.records + A.offsets[x];
-            for (uint32_t j = 0; j < cnt; ++j) out[j] = ((uint64_t)Q[j] << 32) | t;
+            for (uint64_t j = tid; j < cnt; j += kIcHeavyBlock)
+                out[j] = ((uint64_t)ic_ld(Q + j) << 32) | t;
         }
-        for (uint32_t j = 0; j < cnt; ++j) bm[Q[j] >> 5] = 0;
+        for (uint64_t j = tid; j < cnt; j += kIcHeavyBlock) ic_st(bm + (ic_ld(Q + j) >> 5), 0u);
+        __syncthreads();  // the bitmap is clean before the next position
     }
 }
 
@@ -356,10 +443,10 @@ extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, u
         T.release(hvals);
         // per-thread search state within the budget
         const uint32_t words = (n + 31) / 32;
-        const uint64_t per_thread = ((uint64_t)words + n) * sizeof(uint32_t);
+        const uint64_t per_thread = ((uint64_t)words + kIcLight) * sizeof(uint32_t);
         uint64_t threads = std::max<uint64_t>(kIcBlock, kIcStateBudget / per_thread);
         threads = std::min<uint64_t>(threads, (total + kIcBlock - 1) / kIcBlock * kIcBlock);
-        threads = std::min<uint64_t>(threads, 65536ull * kIcBlock);
+        threads = std::min<uint64_t>(threads, 1ull << 19);  // enough to fill the chip
         threads = threads / kIcBlock * kIcBlock;
         IcArgs A{};
         A.n = n;
@@ -370,13 +457,31 @@ extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, u
         A.rthr = rthr;
         A.node_at = node_at;
         A.bitmaps = T.alloc<uint32_t>(threads * words);
-        A.queues = T.alloc<uint32_t>(threads * n);
+        A.queues = T.alloc<uint32_t>(threads * kIcLight);
         fill_u32(A.bitmaps, 0, threads * words, hs);
         A.counts = T.alloc<uint32_t>(total);
+        A.heavy = T.alloc<uint32_t>(total);
+        A.nheavy = T.alloc<unsigned long long>(1);
+        fill_u64((uint64_t *)A.nheavy, 0, 1, hs);
         const unsigned grid = (unsigned)(threads / kIcBlock);
         {
             LaunchTimer t("k_ic_search", hs);
             k_ic_search<0><<<grid, kIcBlock, 0, hs>>>(A);
+            SKIM_LAUNCH_CHECK();
+        }
+        uint64_t nheavy = 0;
+        read_back(&nheavy, A.nheavy, sizeof nheavy, hs);
+        unsigned hgrid = 1;
+        if (nheavy) {
+            const uint64_t per_block = ((uint64_t)words + n) * sizeof(uint32_t);
+            uint64_t blocks = std::max<uint64_t>(1, kIcHeavyBudget / per_block);
+            blocks = std::min<uint64_t>(std::min<uint64_t>(blocks, 1024), nheavy);
+            hgrid = (unsigned)blocks;
+            A.hbitmaps = T.alloc<uint32_t>(blocks * words);
+            A.hqueues = T.alloc<uint32_t>(blocks * n);
+            fill_u32(A.hbitmaps, 0, blocks * words, hs);
+            LaunchTimer t("k_ic_heavy", hs);
+            k_ic_heavy<0><<<hgrid, kIcHeavyBlock, 0, hs>>>(A, nheavy);
             SKIM_LAUNCH_CHECK();
         }
         uint64_t *offsets = T.alloc<uint64_t>(total + 1);
@@ -390,8 +495,17 @@ extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, u
             k_ic_search<1><<<grid, kIcBlock, 0, hs>>>(A);
             SKIM_LAUNCH_CHECK();
         }
+        if (nheavy) {
+            LaunchTimer t("k_ic_heavy", hs);
+            k_ic_heavy<1><<<hgrid, kIcHeavyBlock, 0, hs>>>(A, nheavy);
+            SKIM_LAUNCH_CHECK();
+        }
         T.release(A.bitmaps);
         T.release(A.queues);
+        if (nheavy) {
+            T.release(A.hbitmaps);
+            T.release(A.hqueues);
+        }
         // records by (node, position); every node keeps its first k
         uint64_t *sorted = T.alloc<uint64_t>(R);
         tmp_bytes = 0;
