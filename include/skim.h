@@ -205,8 +205,10 @@ uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
  * k in [2, 256], k n < 2^32; same graph conventions and validation as
  * skim_build_sketches.  Every position runs a complete reverse search (an
  * instance has one source, so nothing prunes): the work is about k times
- * the sum of all nodes' influence, and the per-thread search state (n / 8 +
- * 4 n bytes) is budgeted at 8 GiB, which suits graphs up to about 2^18 nodes.
+ * the sum of all nodes' influence.  Scratch: a visited bitmap (n / 8 bytes)
+ * and a 4 KiB queue per search thread, at most 8 GiB in all, plus n / 8 + 4 n
+ * bytes per workgroup for the searches that reach more than 1024 nodes, at
+ * most 2 GiB; this suits graphs up to about 2^20 nodes.
  */
 skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, uint64_t seed,
                                    uint32_t *positions, double *est, void *stream);
