@@ -140,3 +140,21 @@ def test_union_query_errors():
         with pytest.raises(sk.SkimError) as ei:
             sk.skim_ic_query_batch(pos, 10, 4, to_dev_u64(off), nodes, est)
         assert ei.value.status == sk.SKIM_EINVAL
+
+
+def test_searches_handed_to_workgroups(oracle_lib):
+    # p = 1: a 3000-node path (position t's search reaches every predecessor
+    # of v_t) and a random graph whose giant component exceeds 1024 nodes,
+    # so most searches outgrow a thread's queue and go to the workgroup path
+    from workloads.graphs import Graph, er_graph
+    n = 3000
+    log("ic path 3000 p=1 k=4")
+    _check(oracle_lib, from_edges(n, list(range(n - 1)), list(range(1, n)), 0xFFFFFFFF), 4, 12)
+    rp, col = er_graph(2500, 10000, 61)
+    g = Graph(2500, rp, col, np.full(col.size, 0xFFFFFFFF, dtype=np.uint32))
+    log("ic ER 2500 p=1 k=3")
+    _check(oracle_lib, g, 3, 13)
+    rp, col = er_graph(4000, 12000, 62)
+    g = Graph(4000, rp, col, np.full(col.size, 0xFFFFFFFF // 2, dtype=np.uint32))
+    log("ic ER 4000 p=1/2 k=5")
+    _check(oracle_lib, g, 5, 14)
