@@ -43,7 +43,8 @@ namespace skim {
 namespace {
 
 constexpr int kSkimBlock = 1024;
-constexpr uint32_t kSkimLdsNodes = 8192;  // graphs up to this size keep size[] in LDS
+constexpr uint32_t kSkimLdsNodes = 20480;  // graphs up to this size keep size[] in LDS
+constexpr uint32_t kSkimLdsWords = kSkimLdsNodes / 2;
 constexpr uint32_t kFlagPool = 1u;
 
 struct SkCtl {
@@ -63,13 +64,13 @@ struct SkArgs {
     const uint32_t *fadj;
     const uint32_t *order;  // pair ids by increasing rank
     uint32_t *covered;      // [64 n] 0/1
-    uint32_t *size;         // [n]
+    uint32_t *size;         // [(n + 1) / 2] packed 16-bit counters
     uint32_t *sel;          // [n] 0/1
     uint32_t *idx_off;      // [64 n]
     uint32_t *idx_cnt;      // [64 n], 0 = no entry
     uint32_t *pool;
     uint64_t pool_cap;
-    uint32_t *bcnt;         // [n] per-batch increment counters
+    uint32_t *bcnt;         // [(n + 1) / 2] per-batch increment counters, packed
     uint32_t *queues;       // [kSkimBlock * n]
     SkCtl *ctl;
     uint64_t seed;
@@ -83,6 +84,12 @@ __device__ __forceinline__ bool in_queue(const uint32_t *Q, uint32_t cnt, uint32
     return false;
 }
 
+// size[] and the batch counters are 16-bit halves of 32-bit words (sizes
+// never exceed k <= 256, batch counts never exceed one batch of 1024 pairs),
+// so twice as many nodes fit in LDS.  Adds and subtracts never carry across
+// halves.
+__device__ __forceinline__ uint32_t half_shift(uint32_t v) { return (v & 1u) << 4; }
+
 // State shared between the block's threads goes through agent-scope atomic
 // loads and stores, so no thread reads a stale cached copy of it.
 template <class T> __device__ __forceinline__ T ld(const T *p) {
@@ -90,6 +97,19 @@ template <class T> __device__ __forceinline__ T ld(const T *p) {
 }
 template <class T> __device__ __forceinline__ void st(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ uint32_t cget(const uint32_t *c, uint32_t v) {
+    return (ld(c + (v >> 1)) >> half_shift(v)) & 0xFFFFu;
+}
+__device__ __forceinline__ void cadd(uint32_t *c, uint32_t v, uint32_t d) {
+    atomicAdd(c + (v >> 1), d << half_shift(v));
+}
+__device__ __forceinline__ void csub(uint32_t *c, uint32_t v, uint32_t d) {
+    atomicSub(c + (v >> 1), d << half_shift(v));
+}
+__device__ __forceinline__ void czero(uint32_t *c, uint32_t v) {
+    atomicAnd(c + (v >> 1), ~(0xFFFFu << half_shift(v)));
 }
 
 // Inclusive prefix sum of v over the 64 lanes of a wave.
@@ -112,16 +132,16 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
     // size[] and the batch counters live in LDS when the graph is small
     // enough: every pair's search adds to them, and device atomics from
     // different waves on one cache line are serialised.
-    __shared__ uint32_t s_size[kSkimLdsNodes], s_bcnt[kSkimLdsNodes];
+    __shared__ uint32_t s_size[kSkimLdsWords], s_bcnt[kSkimLdsWords];
     const uint32_t tid = threadIdx.x;
     const uint32_t n = A.n, k = A.k;
     const bool in_lds = n <= kSkimLdsNodes;
     uint32_t *SZ = in_lds ? s_size : A.size;
     uint32_t *BC = in_lds ? s_bcnt : A.bcnt;
     if (in_lds)
-        for (uint32_t v = tid; v < n; v += kSkimBlock) {
-            s_size[v] = ld(A.size + v);
-            s_bcnt[v] = 0;
+        for (uint32_t w = tid; w < (n + 1) / 2; w += kSkimBlock) {
+            s_size[w] = ld(A.size + w);
+            s_bcnt[w] = 0;
         }
     uint32_t *Q = A.queues + (uint64_t)tid * n;
     if (tid == 0) {
@@ -166,16 +186,16 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             uint32_t lo = 0, hi = B, T = B;
             for (;;) {
                 if (tid < T)
-                    for (uint32_t j = 0; j < cnt; ++j) atomicAdd(BC + Q[j], 1u);
+                    for (uint32_t j = 0; j < cnt; ++j) cadd(BC, Q[j], 1u);
                 __syncthreads();
                 bool cand = false;
                 if (tid < T)
-                    for (uint32_t j = 0; j < cnt; ++j) cand |= ld(SZ + Q[j]) + ld(BC + Q[j]) >= k;
+                    for (uint32_t j = 0; j < cnt; ++j) cand |= cget(SZ, Q[j]) + cget(BC, Q[j]) >= k;
                 if (__any(cand) && (tid & 63u) == 0) atomicOr(&s_found, 1u);
                 __syncthreads();
                 const bool f = s_found != 0;
                 if (tid < T)
-                    for (uint32_t j = 0; j < cnt; ++j) st(BC + Q[j], 0u);
+                    for (uint32_t j = 0; j < cnt; ++j) czero(BC, Q[j]);
                 __syncthreads();
                 if (tid == 0) s_found = 0;
                 __syncthreads();
@@ -219,7 +239,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 const unsigned long long off = wave_base + (incl - mine);
                 for (uint32_t j = 0; j < cnt; ++j) {
                     st(A.pool + off + j, Q[j]);
-                    atomicAdd(SZ + Q[j], 1u);
+                    cadd(SZ, Q[j], 1u);
                 }
                 st(A.idx_off + p, (uint32_t)off);
                 st(A.idx_cnt + p, cnt);
@@ -229,7 +249,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 // the nodes that just reached k are in this pair's search
                 int x = -1;
                 for (uint32_t j = 0; j < cnt; ++j)
-                    if (ld(SZ + Q[j]) >= k && (x < 0 || Q[j] < (uint32_t)x)) x = (int)Q[j];
+                    if (cget(SZ, Q[j]) >= k && (x < 0 || Q[j] < (uint32_t)x)) x = (int)Q[j];
                 s_x = x;
                 s_filler = (int)tid;
                 s_fill_cnt = cnt;
@@ -247,7 +267,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             for (uint32_t v = tid; v < n; v += kSkimBlock)
                 if (!ld(A.sel + v)) {
                     const unsigned long long key =
-                        ((unsigned long long)ld(SZ + v) << 32) | (0xFFFFFFFFu - v);
+                        ((unsigned long long)cget(SZ, v) << 32) | (0xFFFFFFFFu - v);
                     best = key > best ? key : best;
                 }
             atomicMax(&s_best, best);
@@ -266,7 +286,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         // counters are all zero here and mark it while the sizes are scanned.
         const uint32_t *Qf = s_filler >= 0 ? A.queues + (uint64_t)s_filler * n : nullptr;
         const uint32_t fcnt = s_filler >= 0 ? s_fill_cnt : 0u;
-        for (uint32_t j = tid; j < fcnt; j += kSkimBlock) st(BC + ld(Qf + j), 1u);
+        for (uint32_t j = tid; j < fcnt; j += kSkimBlock) cadd(BC, ld(Qf + j), 1u);
         if (tid == 0) s_second = 0;
         __syncthreads();
         {
@@ -276,7 +296,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             uint32_t best2 = 0;
             for (uint32_t v = tid; v < n; v += kSkimBlock)
                 if (v != x) {
-                    const uint32_t sz = ld(SZ + v) - ld(BC + v);
+                    const uint32_t sz = cget(SZ, v) - cget(BC, v);
                     best2 = sz > best2 ? sz : best2;
                 }
             // one LDS atomic per wave: lanes on one address are serialised
@@ -287,7 +307,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             if ((tid & 63) == 0 && best2) atomicMax(&s_second, best2);
         }
         __syncthreads();
-        for (uint32_t j = tid; j < fcnt; j += kSkimBlock) st(BC + ld(Qf + j), 0u);
+        for (uint32_t j = tid; j < fcnt; j += kSkimBlock) czero(BC, ld(Qf + j));
         if (tid == 0) {
             rec_tau[it] = s_filler >= 0 ? (uint64_t)s_tau : ~0ull;
             rec_second[it] = s_second;
@@ -331,7 +351,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 const uint32_t c = ld(A.idx_cnt + q);
                 if (c) {
                     const uint32_t o = ld(A.idx_off + q);
-                    for (uint32_t j = 0; j < c; ++j) atomicSub(SZ + ld(A.pool + o + j), 1u);
+                    for (uint32_t j = 0; j < c; ++j) csub(SZ, ld(A.pool + o + j), 1u);
                     st(A.idx_cnt + q, 0u);
                 }
                 for (uint64_t x2 = A.fptr[q]; x2 < A.fptr[q + 1]; ++x2) {
@@ -354,7 +374,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
     }
     if (in_lds) {
         __syncthreads();
-        for (uint32_t v = tid; v < n; v += kSkimBlock) st(A.size + v, s_size[v]);
+        for (uint32_t w = tid; w < (n + 1) / 2; w += kSkimBlock) st(A.size + w, s_size[w]);
     }
     if (tid == 0) {
         A.ctl->cursor = s_cursor;
@@ -600,11 +620,11 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
     A.ell = ell;
     A.k = k;
     A.covered = M.alloc<uint32_t>(npairs);
-    A.size = M.alloc<uint32_t>(n);
+    A.size = M.alloc<uint32_t>((n + 1) / 2);
     A.sel = M.alloc<uint32_t>(n);
     A.idx_off = M.alloc<uint32_t>(npairs);
     A.idx_cnt = M.alloc<uint32_t>(npairs);
-    A.bcnt = M.alloc<uint32_t>(n);
+    A.bcnt = M.alloc<uint32_t>((n + 1) / 2);
     A.queues = M.alloc<uint32_t>((uint64_t)kSkimBlock * n);
     A.pool_cap = std::max<uint64_t>(1ull << 16, 2 * A.nsrc);
     A.pool = M.alloc<uint32_t>(A.pool_cap);
@@ -613,10 +633,10 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
     A.rec_tau = M.alloc<uint64_t>(n);
     A.rec_second = M.alloc<uint32_t>(n);
     fill_u32(A.covered, 0, npairs, s);
-    fill_u32(A.size, 0, n, s);
+    fill_u32(A.size, 0, (n + 1) / 2, s);
     fill_u32(A.sel, 0, n, s);
     fill_u32(A.idx_cnt, 0, npairs, s);
-    fill_u32(A.bcnt, 0, n, s);
+    fill_u32(A.bcnt, 0, (n + 1) / 2, s);
     fill_u64((uint64_t *)A.ctl, 0, sizeof(SkCtl) / 8, s);
     st->n = n;
     st->ell = ell;

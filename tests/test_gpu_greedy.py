@@ -79,3 +79,15 @@ def test_weighted_cascade_20k(oracle_lib):
         seeds, gains, _, _ = gpu_greedy(g, ell, k, 1, [s])
         ws, wg, _ = oracle_lib.skim(g, 1, ell, k, s)
         assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+
+
+def test_counters_outside_lds(oracle_lib):
+    # more nodes than the LDS copy of the counters holds: they stay in global memory
+    from workloads.graphs import Graph, er_graph
+    n = 30000
+    rp, col = er_graph(n, 150000, 71)
+    g = Graph(n, rp, col, np.full(col.size, 0xFFFFFFFF // 8, dtype=np.uint32))
+    log("skim ER 30k p=1/8 ell=8 k=8 s=12")
+    seeds, gains, _, _ = gpu_greedy(g, 8, 8, 3, [5, 7])
+    ws, wg, _ = oracle_lib.skim(g, 3, 8, 8, 12)
+    assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
