@@ -158,9 +158,12 @@ def bench_build(args, torch, sk, g, cfg):
     stream = torch.cuda.current_stream()
     tuning = None
     if not args.no_tune:
-        best, best_ms, start_ms = sk.skim_tune_build(G, ell, k, seed, ranks, size, reps=2,
-                                                    stream=stream)
-        tuning = {"params": best, "best_ms": best_ms, "default_ms": start_ms}
+        cache = args.tune_cache
+        os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+        best, best_ms, start_ms, hit = sk.skim_tune_build_cached(G, ell, k, seed, ranks, size,
+                                                                 cache, reps=2, stream=stream)
+        tuning = {"params": best, "best_ms": best_ms, "default_ms": start_ms, "cache_hit": hit,
+                  "cache": cache}
         log(f"autotuned {tuning}")
     for w in range(args.warmup):
         work = sk.skim_build_sketches(G, ell, k, seed, ranks, size, est, stream=stream)
@@ -582,6 +585,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="build only (no query/SKIM legs)")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the build with the default launch shapes (no autotuning)")
+    ap.add_argument("--tune-cache", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                         "_build", "tune_cache.txt"),
+                    help="file of cached autotuner choices (keyed by device and configuration)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB copy (for PMC byte calibration)")
     args = ap.parse_args()

@@ -434,6 +434,26 @@ skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32_t k, uint6
                             void *stream);
 
 /*
+ * skim_tune_build_cached -- skim_tune_build behind a persistent cache keyed
+ * by the device (architecture name, compute units) and the configuration
+ * (n, m, l, k, seed and 64 evenly spaced samples of each graph array).
+ * cache_path (HOST string) names a text file, one line per key; it is read
+ * and created or appended to as needed.  On a hit the stored shapes are put
+ * in force without timing anything (*hit = 1, *best_ms = the stored time,
+ * *start_ms = 0, ranks/size untouched); on a miss the tuner runs as
+ * skim_tune_build and its choice is appended (*hit = 0).  Unreadable lines
+ * are skipped.  best, hit: HOST out; best_ms, start_ms: HOST out, may be
+ * NULL.  Concurrent calls in one process are serialised; calls from several
+ * processes on one file may both tune and both append (the first matching
+ * line wins).
+ */
+skim_status skim_tune_build_cached(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+                                   uint64_t *ranks, uint32_t *size, uint32_t reps,
+                                   const char *cache_path, skim_build_params *best,
+                                   double *best_ms, double *start_ms, uint32_t *hit,
+                                   void *stream);
+
+/*
  * Kernel timing, for measurement: while a kernel name is enabled, every
  * launch of that kernel (e.g. "k_expand", the level expansion of the pruned
  * reverse search) made by the calling thread is bracketed by HIP events on

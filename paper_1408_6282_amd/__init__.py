@@ -28,7 +28,7 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_get_build_params", "skim_tune_build", "skim_query_plan_create",
            "skim_query_plan_launch", "skim_query_plan_free", "skim_greedy_records",
            "skim_discrepancy_tail", "skim_influence_batch", "skim_build_ic_sketches",
-           "skim_greedy_exact", "skim_ic_query_batch"]
+           "skim_greedy_exact", "skim_ic_query_batch", "skim_tune_build_cached"]
 
 
 class SkimError(RuntimeError):
@@ -95,6 +95,11 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_selected.argtypes = [vp]
     lib.skim_greedy_records.restype = C.c_int
     lib.skim_greedy_records.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, vp]
+    lib.skim_tune_build_cached.restype = C.c_int
+    lib.skim_tune_build_cached.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint32,
+                                           C.c_uint64, vp, vp, C.c_uint32, C.c_char_p,
+                                           C.POINTER(skim_build_params), C.POINTER(C.c_double),
+                                           C.POINTER(C.c_double), C.POINTER(C.c_uint32), vp]
     lib.skim_ic_query_batch.restype = C.c_int
     lib.skim_ic_query_batch.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint64, vp, vp,
                                         C.c_uint32, vp, vp, vp]
@@ -293,6 +298,23 @@ def skim_tune_build(graph: DeviceGraph, ell: int, k: int, seed: int, ranks, size
                              C.byref(start_ms), _stream(stream))
     _check("skim_tune_build", st)
     return best.as_dict(), float(best_ms.value), float(start_ms.value)
+
+
+def skim_tune_build_cached(graph: DeviceGraph, ell: int, k: int, seed: int, ranks, size,
+                           cache_path: str, reps: int = 2, stream=None):
+    """skim_tune_build behind a persistent cache keyed by device and configuration;
+    returns (params, best_ms, start_ms, hit)."""
+    lib = load_library()
+    best = skim_build_params()
+    best_ms = C.c_double(0)
+    start_ms = C.c_double(0)
+    hit = C.c_uint32(0)
+    st = lib.skim_tune_build_cached(C.byref(graph.struct), ell, k, seed & 0xFFFFFFFFFFFFFFFF,
+                                    _ptr(ranks), _ptr(size), reps, cache_path.encode(),
+                                    C.byref(best), C.byref(best_ms), C.byref(start_ms),
+                                    C.byref(hit), _stream(stream))
+    _check("skim_tune_build_cached", st)
+    return best.as_dict(), float(best_ms.value), float(start_ms.value), bool(hit.value)
 
 
 class GreedyState:

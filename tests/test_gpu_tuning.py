@@ -73,3 +73,35 @@ def test_out_of_range_params_refused(restore_params, field, value):
         sk.skim_set_build_params({field: value})
     assert ei.value.status == sk.SKIM_EINVAL
     assert sk.skim_get_build_params() == before
+
+
+def test_tuning_cache(tmp_path):
+    import torch
+    import paper_1408_6282_amd as sk
+    from workloads.configs import make_config, make_graph
+    cfg = make_config("tiny-ic")
+    g = make_graph(cfg)
+    G = sk.DeviceGraph.from_host(g, "cuda:0")
+    ranks = torch.empty(g.n * 16, dtype=torch.int64, device="cuda:0")
+    size = torch.empty(g.n, dtype=torch.int32, device="cuda:0")
+    path = str(tmp_path / "tune.txt")
+    try:
+        p1, ms1, _, hit1 = sk.skim_tune_build_cached(G, 16, 16, 1, ranks, size, path, reps=1)
+        assert not hit1
+        lines = open(path).read().splitlines()
+        assert len(lines) == 1 and len(lines[0].split()) == 9
+        sk.skim_set_build_params(None)
+        p2, ms2, start2, hit2 = sk.skim_tune_build_cached(G, 16, 16, 1, ranks, size, path, reps=1)
+        assert hit2 and p2 == p1 and start2 == 0.0
+        assert sk.skim_get_build_params() == p1  # the stored shapes are in force
+        # another configuration (k), another key; a garbage line is skipped
+        with open(path, "a") as f:
+            f.write("not a cache line\n")
+        _, _, _, hit3 = sk.skim_tune_build_cached(G, 16, 8, 1, ranks, size, path, reps=1)
+        assert not hit3 and len(open(path).read().splitlines()) == 3
+        _, _, _, hit4 = sk.skim_tune_build_cached(G, 16, 8, 1, ranks, size, path, reps=1)
+        assert hit4
+        with pytest.raises(sk.SkimError):
+            sk.skim_tune_build_cached(G, 16, 16, 1, ranks, size, "", reps=1)
+    finally:
+        sk.skim_set_build_params(None)
