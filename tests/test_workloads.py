@@ -177,3 +177,15 @@ def test_neighbourhood_query_sets_stay_within_the_smallest_ball():
     a = neighbourhood_query_sets(rp, col, 400, 5, 40, seed=3)
     b = neighbourhood_query_sets(rp, col, 400, 5, 40, seed=3)
     assert np.array_equal(a[1], b[1])
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: bench.py says so and exits before touching a device
+    import subprocess
+    import sys
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+    assert r.stdout == ""
