@@ -192,3 +192,37 @@ def test_cohen_kaplan_adds_up_over_disjoint_sketches(oracle_lib):
         members = sorted(set(groups[j]))
         want = sum((k - 1) * n / (pos[u, k - 1] - 1.0) for u in members)
         assert ck[j] == pytest.approx(want, rel=1e-12)
+
+
+def test_cohen_kaplan_overlapping_sketches_by_hand(oracle_lib):
+    # Eq. unionest with permutation ranks: a position z held outside the
+    # holders' own thresholds weighs n / (T_max(z) - 1), T_max the largest
+    # threshold position among the sketches that hold it.  Worked by hand:
+    # A = [1, 3, 5 | 7], B = [1, 4, 9 | 12], n = 10, k = 4.
+    n, k = 10, 4
+    pos = np.array([[1, 3, 5, 7], [1, 4, 9, 12]], dtype=np.uint32)
+    off = np.array([0, 2, 3], dtype=np.uint64)
+    nodes = np.array([0, 1, 0], dtype=np.uint32)
+    est, st = oracle_lib.ic_union_query(pos, n, k, off, nodes, estimator=1)
+    assert (st == 0).all()
+    # {A, B}: 1 -> 10/11 (B's threshold, the larger), 3 -> 10/6, 4 -> 10/11,
+    # 5 -> 10/6, 9 -> 10/11 (the smaller threshold for 1 would give 10/6).
+    assert est[0] == pytest.approx(3 * 10 / 11 + 2 * 10 / 6, rel=1e-15)
+    assert est[1] == pytest.approx(3 * 10 / 6, rel=1e-15)
+
+
+def test_cohen_kaplan_unbiased_on_nested_reach_sets(oracle_lib):
+    # p = 1 path 0 -> ... -> 99: R_25 is inside R_0, and the influence of
+    # {0, 25} is 100 in every instance.  Shared positions weigh by the larger
+    # threshold; the smaller one (the threshold of node 0) over-counts them,
+    # which puts the mean near 118, about 50 standard errors away.
+    n, k = 100, 16
+    g = from_edges(n, list(range(n - 1)), list(range(1, n)), U32)
+    off = np.array([0, 2], dtype=np.uint64)
+    nodes = np.array([0, 25], dtype=np.uint32)
+    ck = []
+    for s in range(300):
+        pos, _, _ = oracle_lib.ic_sketches(g, k, 700 + s)
+        ck.append(oracle_lib.ic_union_query(pos, n, k, off, nodes, estimator=1)[0][0])
+    ck = np.array(ck)
+    assert abs(ck.mean() - 100) < 5 * ck.std() / np.sqrt(len(ck))

@@ -12,6 +12,7 @@
   bottom-k estimate; unbiased over seeds.
 """
 import numpy as np
+import pytest
 
 from workloads import from_edges
 from brute import live_adjacency, reach, random_small_graph
@@ -115,3 +116,54 @@ def test_ck_unbiased_on_disjoint_sets(oracle_lib):
     assert abs(ck.mean() - 100) < 5 * ck.std() / np.sqrt(len(ck))
     assert abs(bk.mean() - 100) < 5 * bk.std() / np.sqrt(len(bk))
     assert ck.std() < bk.std()  # CK uses more of the sketches: lower variance
+
+
+def _rank_for_rho(e):
+    """A rank T whose real reading rho(T) = ((T >> 11) + 1) 2^-53 is exactly 2^-e."""
+    return ((1 << (53 - e)) - 1) << 11
+
+
+def test_ck_overlapping_sketches_by_hand(oracle_lib):
+    # Eq. unionest: each distinct non-threshold value z of the union weighs
+    # 1 / rho(max tau_u over the sketches holding z); a non-full holder has
+    # tau = 1 (weight 1).  Values worked out by hand, with thresholds whose
+    # real readings are exact powers of two (1/4 for A, 1/2 for B).
+    k, ell = 4, 2
+    ta, tb = _rank_for_rho(2), _rank_for_rho(1)
+    z = 1 << 50  # held by A, B and C
+    A = [z, 1 << 51, 1 << 52, ta]           # full, rho(tau) = 1/4
+    B = [z, 1 << 53, 3 << 53, tb]           # full, rho(tau) = 1/2
+    C = [z, 5 << 49]                        # not full: tau = 1
+    NONE = 0xFFFFFFFFFFFFFFFF
+    ranks = np.array([A, B, C + [NONE, NONE]], dtype=np.uint64)
+    size = np.array([4, 4, 2], dtype=np.uint32)
+    off, nodes = _qs([[0, 1], [0, 2], [0], [1, 2], [0, 1, 2]])
+    c, st = oracle_lib.ck_query(ranks, size, k, ell, off, nodes)
+    assert (st == 0).all()
+    # {A, B}: z takes B's larger threshold (weight 2); A's other two values
+    # weigh 4 each, B's other two 2 each: 2 + 4 + 4 + 2 + 2 = 14.  (Taking
+    # the smaller threshold for z would give 16.)
+    # {A, C}: z is held by the non-full C, weight 1: 1 + 4 + 4 + 1 = 10.
+    # {A}: 3 values of weight 4 = 12 = (k - 1) / rho(tau).
+    # {B, C}: 1 + 2 + 2 + 1 = 6.
+    # {A, B, C}: 1 + 4 + 4 + 2 + 2 + 1 = 14.
+    want = np.array([14.0, 10.0, 12.0, 6.0, 14.0]) / ell
+    assert np.allclose(c, want, rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("ell,k", [(1, 16), (8, 16)])
+def test_ck_unbiased_on_nested_reach_sets(oracle_lib, ell, k):
+    # A p = 1 path 0 -> 1 -> ... -> 99: R_25 is a subset of R_0 and
+    # Inf({0, 25}) = 100 in every instance.  The ranks shared by the two
+    # sketches must weigh 1 / rho of the LARGER threshold (tau_25 >= tau_0):
+    # weighting them by the smaller one over-counts them, which puts the mean
+    # near 118 (about 10 standard errors away over these seeds).
+    n = 100
+    g = from_edges(n, list(range(n - 1)), list(range(1, n)), 0xFFFFFFFF)
+    off, nodes = _qs([[0, 25]])
+    ck = []
+    for s in range(300):
+        ranks, size, _ = oracle_lib.build_alg2(g, 900 + s, ell, k, threads=1)
+        ck.append(oracle_lib.ck_query(ranks, size, k, ell, off, nodes)[0][0])
+    ck = np.array(ck)
+    assert abs(ck.mean() - 100) < 5 * ck.std() / np.sqrt(len(ck))
