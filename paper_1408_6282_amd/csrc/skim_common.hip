@@ -3,6 +3,8 @@
 // per-node estimate entry point.
 #include "skim_internal.h"
 
+#include <atomic>
+
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -110,7 +112,21 @@ Arena::~Arena() {
     if (C.cached > C.limit) trim_cache(dev_, C.limit);
 }
 
+std::atomic<uint32_t> g_fault[3];
+
+bool take_fault(FaultKind what) {
+    std::atomic<uint32_t> &c = g_fault[what];
+    uint32_t v = c.load();
+    while (v && !c.compare_exchange_weak(v, v - 1)) {
+    }
+    return v != 0;
+}
+
 void *Arena::get(size_t bytes) {
+    if (take_fault(kFaultAlloc)) {
+        set_error("device allocation of %zu bytes failed: injected failure", bytes);
+        throw Fail{SKIM_ENOMEM};
+    }
     if (bytes == 0) bytes = 8;
     const size_t cls = size_class(bytes);
     void *p = nullptr;
@@ -510,6 +526,16 @@ void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, u
 using namespace skim;
 
 extern "C" uint32_t skim_abi_version(void) { return SKIM_ABI_VERSION; }
+
+extern "C" skim_status skim_debug_inject(uint32_t what, uint32_t count) {
+    skim::clear_error();
+    if (what != SKIM_FAULT_ALLOC && what != SKIM_FAULT_SERVE) {
+        skim::set_error("unknown fault kind %u", what);
+        return SKIM_EINVAL;
+    }
+    skim::g_fault[what].store(count);
+    return SKIM_OK;
+}
 
 extern "C" void skim_timing_enable(const char *kernel) {
     std::lock_guard<std::mutex> lk(g_time_mu);

@@ -106,6 +106,12 @@ __device__ __forceinline__ uint64_t load_relaxed(const uint64_t *p) {
 void set_error(const char *fmt, ...);
 void clear_error();
 
+// Host-side fault injection (skim_debug_inject): the next `count` device
+// allocations (kFaultAlloc) or serving-loop copies and launches
+// (kFaultServe) are treated as failed.  take_fault() consumes one.
+enum FaultKind : uint32_t { kFaultAlloc = 1, kFaultServe = 2 };
+bool take_fault(FaultKind what);
+
 struct Fail {
     skim_status st;
 };

@@ -10,6 +10,11 @@
 // second worker runs SKIM requests in order on their own stream, resuming one
 // device-resident SKIM state.  Latency runs from the request's arrival to the
 // moment the host observes its batch complete.
+//
+// Failures never leave a slot busy: a batch whose copy, launch or
+// completion event reports an error completes with status -5 for every
+// request in it, and its slot is freed, so skim_server_destroy always
+// returns.  Requests can be cancelled (status -6).
 #include "skim_internal.h"
 
 #include <algorithm>
@@ -45,6 +50,7 @@ struct GreedyReq {
     uint64_t ticket;
     uint32_t s;
     Clock::time_point t0;
+    size_t bytes;
 };
 
 struct QueryDone {
@@ -76,6 +82,9 @@ struct Slot {
 };
 
 size_t query_bytes(size_t count) { return count * 4 + 8 + 8 + 4; }
+size_t greedy_bytes(uint32_t s) { return (size_t)s * 12 + 64; }
+
+constexpr int32_t kStatusFailed = -5, kStatusCancelled = -6;
 
 }  // namespace
 
@@ -92,6 +101,7 @@ struct skim_server {
     std::unordered_map<uint64_t, QueryDone> done;
     std::unordered_map<uint64_t, GreedyDone> gdone;
     std::unordered_map<uint64_t, int> live;  // ticket -> 1 query, 2 greedy
+    std::unordered_map<uint64_t, bool> cancelled;  // in a batch on the GPU, result dropped
     uint64_t next_ticket = 1;
     size_t inflight_bytes = 0;
     std::atomic<bool> stop{false};
@@ -109,6 +119,7 @@ struct skim_server {
     void run_greedy();
     bool launch_batch(Slot &sl);
     void retire(Slot &sl);
+    void fail_batch(Slot &sl);
 };
 
 void skim_server::retire(Slot &sl) {
@@ -119,12 +130,28 @@ void skim_server::retire(Slot &sl) {
     const int32_t *st = (const int32_t *)(sl.h_out + q * 8);
     for (size_t j = 0; j < q; ++j) {
         auto &r = sl.reqs[j];
-        done[r.ticket] = {est[j], st[j],
-                          std::chrono::duration<double, std::micro>(now - r.t0).count()};
+        const double lat = std::chrono::duration<double, std::micro>(now - r.t0).count();
+        if (cancelled.erase(r.ticket)) done[r.ticket] = {0.0, kStatusCancelled, lat};
+        else done[r.ticket] = {est[j], st[j], lat};
         inflight_bytes -= r.bytes;
     }
     sl.reqs.clear();
     sl.busy = false;
+}
+
+// The batch's copy, launch or completion failed: every request in it
+// completes with status -5 and the slot is free again.  The stream is
+// synchronised first (its error, if any, is only reported) so that no copy
+// into the slot's buffers is still queued when the slot is reused.
+void skim_server::fail_batch(Slot &sl) {
+    (void)hipStreamSynchronize(sl.stream);
+    (void)hipGetLastError();
+    const size_t q = sl.reqs.size();
+    for (size_t j = 0; j < q; ++j) {
+        ((double *)sl.h_out)[j] = 0.0;
+        ((int32_t *)(sl.h_out + q * 8))[j] = kStatusFailed;
+    }
+    retire(sl);
 }
 
 bool skim_server::launch_batch(Slot &sl) {
@@ -151,7 +178,12 @@ bool skim_server::launch_batch(Slot &sl) {
     }
     h_off[q] = o;
     hipStream_t s = sl.stream;
-    (void)hipMemcpyAsync(sl.d_in, sl.h_in, (q + 1) * 8 + o * 4, hipMemcpyHostToDevice, s);
+    if (skim::take_fault(skim::kFaultServe) ||
+        hipMemcpyAsync(sl.d_in, sl.h_in, (q + 1) * 8 + o * 4, hipMemcpyHostToDevice, s) !=
+            hipSuccess) {
+        fail_batch(sl);
+        return true;
+    }
     skim::QueryArgs Q = base;
     Q.q = q;
     Q.qoff = (const uint64_t *)sl.d_in;
@@ -161,17 +193,14 @@ bool skim_server::launch_batch(Slot &sl) {
     try {
         skim::launch_queries_async(Q, q, sl.d_next, s);
     } catch (const skim::Fail &) {
-        // mark the batch failed; its requests complete with status -5
-        for (uint64_t j = 0; j < q; ++j) {
-            ((double *)sl.h_out)[j] = 0.0;
-            ((int32_t *)(sl.h_out + q * 8))[j] = -5;
-        }
-        (void)hipStreamSynchronize(s);
-        retire(sl);
+        fail_batch(sl);
         return true;
     }
-    (void)hipMemcpyAsync(sl.h_out, sl.d_out, q * 12, hipMemcpyDeviceToHost, s);
-    (void)hipEventRecord(sl.ev, s);
+    if (hipMemcpyAsync(sl.h_out, sl.d_out, q * 12, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipEventRecord(sl.ev, s) != hipSuccess) {
+        fail_batch(sl);
+        return true;
+    }
     sl.busy = true;
     return true;
 }
@@ -186,6 +215,9 @@ void skim_server::run_queries() {
                 (void)hipGetLastError();  // "not ready" is not a failure
                 if (q == hipSuccess) {
                     retire(sl);
+                    progressed = true;
+                } else if (q != hipErrorNotReady) {  // the batch failed on the device
+                    fail_batch(sl);
                     progressed = true;
                 }
             }
@@ -242,6 +274,7 @@ void skim_server::run_greedy() {
         }
         d.lat_us = std::chrono::duration<double, std::micro>(Clock::now() - r.t0).count();
         std::lock_guard<std::mutex> lk(mu);
+        inflight_bytes -= r.bytes;
         gdone[r.ticket] = std::move(d);
         cv.notify_all();
     }
@@ -368,6 +401,31 @@ extern "C" skim_status skim_server_poll(skim_server *sv, uint64_t ticket, double
     return SKIM_OK;
 }
 
+extern "C" skim_status skim_server_cancel(skim_server *sv, uint64_t ticket) {
+    skim::clear_error();
+    if (!sv) {
+        skim::set_error("NULL argument");
+        return SKIM_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(sv->mu);
+    auto lv = sv->live.find(ticket);
+    if (lv == sv->live.end() || lv->second != 1 || sv->done.count(ticket)) {
+        skim::set_error("unknown or finished query ticket");
+        return SKIM_EINVAL;
+    }
+    for (auto it = sv->pending.begin(); it != sv->pending.end(); ++it)
+        if (it->ticket == ticket) {  // not in a batch yet: withdraw it
+            const double lat =
+                std::chrono::duration<double, std::micro>(Clock::now() - it->t0).count();
+            sv->inflight_bytes -= it->bytes;
+            sv->pending.erase(it);
+            sv->done[ticket] = {0.0, kStatusCancelled, lat};
+            return SKIM_OK;
+        }
+    sv->cancelled[ticket] = true;  // on the GPU: drop its result when the batch retires
+    return SKIM_OK;
+}
+
 extern "C" skim_status skim_server_set_graph(skim_server *sv, const skim_graph *g, uint32_t ell,
                                              uint32_t k, uint64_t seed) {
     skim::clear_error();
@@ -394,12 +452,19 @@ extern "C" skim_status skim_server_submit_greedy(skim_server *sv, uint32_t s, ui
         skim::set_error("NULL argument");
         return SKIM_EINVAL;
     }
+    const size_t b = greedy_bytes(s);
+    if (b > sv->cfg.budget_bytes) {
+        skim::set_error("SKIM request of %u seeds can never fit the budget", s);
+        return SKIM_EUNSUPPORTED;
+    }
     std::lock_guard<std::mutex> lk(sv->mu);
     if (!sv->has_graph) {
         skim::set_error("no SKIM graph: call skim_server_set_graph first");
         return SKIM_EINVAL;
     }
-    GreedyReq r{sv->next_ticket++, s, Clock::now()};
+    if (sv->inflight_bytes + b > sv->cfg.budget_bytes) return SKIM_EBUSY;
+    sv->inflight_bytes += b;
+    GreedyReq r{sv->next_ticket++, s, Clock::now(), b};
     *ticket = r.ticket;
     sv->live[r.ticket] = 2;
     sv->gpending.push_back(r);
@@ -456,7 +521,7 @@ extern "C" skim_status skim_server_replay(skim_server *sv, uint64_t q, const uin
                 std::this_thread::yield();
                 continue;
             }
-            est[next_poll] = e;
+            est[next_poll] = r == SKIM_OK ? e : 0.0;
             if (status) status[next_poll] = r == SKIM_OK ? st : -4;
             if (latency_us) latency_us[next_poll] = l;
             ++next_poll;

@@ -81,3 +81,91 @@ def test_submit_poll_and_admission(served):
             srv.poll(t1)  # retired ticket
     finally:
         srv.close()
+
+
+def test_failed_batch_completes_with_status_and_frees_its_slot(served):
+    # The host-side hook makes the serving loop treat the next batch copy as
+    # failed (nothing goes wrong on the device): that batch's requests
+    # complete with -5, the slot serves the next batch normally, and the
+    # server shuts down.
+    import paper_1408_6282_amd as sk
+    cfg, g, rt, st = served
+    n, ell, k = g.n, cfg["ell"], cfg["k"]
+    srv = sk.Server(rt, st, n, k, ell, budget_bytes=1 << 20, max_batch=64, streams=1)
+    try:
+        sk.skim_debug_inject(sk.SKIM_FAULT_SERVE, 1)
+        t1 = srv.submit([1, 2, 3])
+        r1 = _wait(lambda: srv.poll(t1))
+        assert r1[1] == -5 and r1[0] == 0.0
+        t2 = srv.submit([1, 2, 3])
+        r2 = _wait(lambda: srv.poll(t2))
+        want, _ = gpu_query(rt, st, n, k, ell, np.array([0, 3], dtype=np.uint64),
+                            np.array([1, 2, 3], dtype=np.uint32))
+        assert r2[1] == 0 and r2[0] == want[0]
+    finally:
+        sk.skim_debug_inject(sk.SKIM_FAULT_SERVE, 0)
+        t0 = time.time()
+        srv.close()
+        assert time.time() - t0 < 30
+
+
+def test_cancelled_requests_complete_with_status(served):
+    import paper_1408_6282_amd as sk
+    cfg, g, rt, st = served
+    n, ell, k = g.n, cfg["ell"], cfg["k"]
+    srv = sk.Server(rt, st, n, k, ell, budget_bytes=8 << 20, max_batch=16, streams=1)
+    try:
+        tickets = [srv.submit(np.arange(512) % n) for _ in range(200)]
+        for t in tickets[::2]:
+            srv.cancel(t)
+        for j, t in enumerate(tickets):
+            r = _wait(lambda: srv.poll(t))
+            if j % 2 == 0:
+                assert r[1] == -6 and r[0] == 0.0
+            else:
+                assert r[1] == 0
+        with pytest.raises(sk.SkimError):
+            srv.cancel(tickets[1])  # finished
+    finally:
+        srv.close()
+
+
+def test_skim_requests_are_admitted_by_budget(served):
+    import paper_1408_6282_amd as sk
+    cfg, g, rt, st = served
+    n, ell, k = g.n, cfg["ell"], cfg["k"]
+    srv = sk.Server(rt, st, n, k, ell, budget_bytes=4096, max_batch=8, streams=1)
+    try:
+        srv.set_graph(sk.DeviceGraph.from_host(g, "cuda:0"), ell, k, cfg["seed"])
+        with pytest.raises(sk.SkimError) as ei:
+            srv.submit_greedy(1000)  # 12 * 1000 + 64 bytes > the whole budget
+        assert ei.value.status == sk.SKIM_EUNSUPPORTED
+        t = srv.submit_greedy(20)
+        seeds, gains, _ = _wait(lambda: srv.poll_greedy(t, 20))
+    finally:
+        srv.close()
+    ws, wg, _, _ = gpu_greedy(g, ell, k, cfg["seed"], [20])
+    assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+
+
+def test_injected_allocation_failure(served):
+    # The next device allocation fails on the host side: the build returns
+    # SKIM_ENOMEM with its outputs untouched, and the following build works.
+    import torch
+    import paper_1408_6282_amd as sk
+    cfg, g, rt, st = served
+    G = sk.DeviceGraph.from_host(g, "cuda:0")
+    ranks = torch.full((g.n * cfg["k"],), 7, dtype=torch.int64, device="cuda:0")
+    size = torch.full((g.n,), 7, dtype=torch.int32, device="cuda:0")
+    sk.skim_debug_inject(sk.SKIM_FAULT_ALLOC, 1)
+    try:
+        with pytest.raises(sk.SkimError) as ei:
+            sk.skim_build_sketches(G, cfg["ell"], cfg["k"], cfg["seed"], ranks, size)
+        assert ei.value.status == sk.SKIM_ENOMEM
+    finally:
+        sk.skim_debug_inject(sk.SKIM_FAULT_ALLOC, 0)
+    torch.cuda.synchronize()
+    assert (ranks.cpu() == 7).all() and (size.cpu() == 7).all()
+    sk.skim_build_sketches(G, cfg["ell"], cfg["k"], cfg["seed"], ranks, size)
+    torch.cuda.synchronize()
+    assert torch.equal(ranks, rt) and torch.equal(size, st)
