@@ -47,7 +47,7 @@
 extern "C" {
 #endif
 
-#define SKIM_ABI_VERSION 4u
+#define SKIM_ABI_VERSION 5u
 
 typedef enum {
     SKIM_OK = 0,
@@ -71,6 +71,20 @@ uint32_t skim_abi_version(void);
 
 /* Text of the last failure on the calling thread ("" if none). */
 const char *skim_last_error(void);
+
+/*
+ * Fault injection, for tests of the error paths.  Host side only: nothing
+ * is done wrong on the device.  what = SKIM_FAULT_ALLOC: the next `count`
+ * device allocations the library makes fail as if the device were out of
+ * memory (the call that makes one returns SKIM_ENOMEM and writes no
+ * result); SKIM_FAULT_SERVE: the next `count` batch copies or launches of
+ * the serving loop are treated as failed (the batch's requests complete
+ * with status -5 and its slot is freed).  count = 0 disarms.  Process-wide.
+ * SKIM_EINVAL for an unknown kind.
+ */
+#define SKIM_FAULT_ALLOC 1u
+#define SKIM_FAULT_SERVE 2u
+skim_status skim_debug_inject(uint32_t what, uint32_t count);
 
 /*
  * skim_build_sketches -- combined bottom-k reachability sketches of every
@@ -355,11 +369,20 @@ skim_status skim_server_submit(skim_server *server, const uint32_t *nodes, uint3
 skim_status skim_server_poll(skim_server *server, uint64_t ticket, double *est, int32_t *status,
                              double *latency_us);
 
+/* Cancel query request `ticket`: it completes with status -6 and est 0
+ * (skim_server_poll then returns SKIM_OK).  A request still waiting is
+ * withdrawn at once; one already in a batch on the GPU finishes there and
+ * its result is dropped.  SKIM_EINVAL for an unknown or finished ticket. */
+skim_status skim_server_cancel(skim_server *server, uint64_t ticket);
+
 /* Attach the graph for SKIM requests (once per server). */
 skim_status skim_server_set_graph(skim_server *server, const skim_graph *g, uint32_t ell,
                                   uint32_t k, uint64_t seed);
 
-/* Request the next s seeds of the server's SKIM run (skim_greedy semantics). */
+/* Request the next s seeds of the server's SKIM run (skim_greedy semantics).
+ * Admitted when its result bytes (12 per seed + 64) fit the free part of
+ * budget_bytes beside the queries in flight, else SKIM_EBUSY (retry later);
+ * SKIM_EUNSUPPORTED if it could never fit. */
 skim_status skim_server_submit_greedy(skim_server *server, uint32_t s, uint64_t *ticket);
 
 /* seeds [s], gain_pairs [s]: HOST arrays; SKIM_EBUSY while running. */
@@ -371,7 +394,7 @@ skim_status skim_server_poll_greedy(skim_server *server, uint64_t ticket, uint32
  * nodes) at arrival_s[j] seconds after the call starts (retrying on
  * SKIM_EBUSY; latency still counts from the scheduled arrival) and collects
  * every result into HOST arrays est[q], status[q] (-4 = rejected, -5 = the
- * batch's launch failed),
+ * batch's copy, launch or completion failed; est is 0 for both),
  * latency_us[q] (may be NULL).  busy_retries (HOST, may be NULL) counts
  * admission refusals.
  */
@@ -400,7 +423,10 @@ skim_status skim_server_replay(skim_server *server, uint64_t q, const uint64_t *
  *                    per pair (default 2, 1..8); bucket 0 holds about k/2
  *                    ranks per instance and each later bucket doubles the
  *                    rank range.  Wider windows mean fewer search levels and
- *                    more visits past k.
+ *                    more visits past k;
+ *   first_span       rank buckets of the first window (default 5, 1..16);
+ *                    a first window that outgrows its buffers is given up
+ *                    and the build starts again from bucket 0 alone.
  * skim_set_build_params(NULL) restores the defaults; fields out of range give
  * SKIM_EINVAL and change nothing.
  */
@@ -412,6 +438,7 @@ typedef struct {
     uint32_t heavy_visits;
     uint32_t sort_frontier;
     uint32_t window_span;
+    uint32_t first_span;
 } skim_build_params;
 
 skim_status skim_set_build_params(const skim_build_params *params);
@@ -422,7 +449,7 @@ void skim_get_build_params(skim_build_params *params);
  * seed) into ranks/size (device, as for skim_build_sketches) with the
  * current parameters and then with candidate values of one parameter at a
  * time (coordinate descent over small_frontier, small_batch, large_batch,
- * thread_frontier, sort_frontier, window_span), each timed as the best of `reps` builds
+ * thread_frontier, sort_frontier, window_span, first_span), each timed as the best of `reps` builds
  * with HIP events on `stream` after one warm-up build.  The fastest set becomes the current
  * parameters and is written to *best (HOST); *best_ms and *start_ms (HOST,
  * may be NULL) receive its time and that of the parameters in force at the

@@ -28,7 +28,10 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_get_build_params", "skim_tune_build", "skim_query_plan_create",
            "skim_query_plan_launch", "skim_query_plan_free", "skim_greedy_records",
            "skim_discrepancy_tail", "skim_influence_batch", "skim_build_ic_sketches",
-           "skim_greedy_exact", "skim_ic_query_batch", "skim_tune_build_cached"]
+           "skim_greedy_exact", "skim_ic_query_batch", "skim_tune_build_cached",
+           "skim_debug_inject", "skim_server_cancel"]
+
+SKIM_FAULT_ALLOC, SKIM_FAULT_SERVE = 1, 2
 
 
 class SkimError(RuntimeError):
@@ -46,7 +49,7 @@ class skim_build_params(C.Structure):
     _fields_ = [("small_frontier", C.c_uint32), ("small_batch", C.c_uint32),
                 ("large_batch", C.c_uint32), ("thread_frontier", C.c_uint32),
                 ("heavy_visits", C.c_uint32), ("sort_frontier", C.c_uint32),
-                ("window_span", C.c_uint32)]
+                ("window_span", C.c_uint32), ("first_span", C.c_uint32)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}
@@ -130,6 +133,10 @@ def load_library(path: str | None = None):
                                           C.c_uint64]
     lib.skim_server_submit_greedy.restype = C.c_int
     lib.skim_server_submit_greedy.argtypes = [vp, C.c_uint32, P64]
+    lib.skim_server_cancel.restype = C.c_int
+    lib.skim_server_cancel.argtypes = [vp, C.c_uint64]
+    lib.skim_debug_inject.restype = C.c_int
+    lib.skim_debug_inject.argtypes = [C.c_uint32, C.c_uint32]
     lib.skim_server_poll_greedy.restype = C.c_int
     lib.skim_server_poll_greedy.argtypes = [vp, C.c_uint64, vp, vp, PD]
     lib.skim_server_replay.restype = C.c_int
@@ -217,6 +224,12 @@ def skim_build_sketches(graph: DeviceGraph, ell: int, k: int, seed: int, ranks, 
     _check("skim_build_sketches", st)
     return {"visits": int(work[0]), "scans": int(work[1]), "records": int(work[2]),
             "windows": int(work[3]), "restarts": int(work[4]), "restart_flags": int(work[5])}
+
+
+def skim_debug_inject(what: int, count: int = 1):
+    """Make the next `count` device allocations (SKIM_FAULT_ALLOC) or serving
+    batch copies/launches (SKIM_FAULT_SERVE) fail on the host side; 0 disarms."""
+    _check("skim_debug_inject", load_library().skim_debug_inject(what, count))
 
 
 def skim_estimates(ranks, size, n: int, k: int, ell: int, est, stream=None):
@@ -457,6 +470,10 @@ class Server:
             return None
         _check("skim_server_poll", st)
         return float(e.value), int(s.value), float(l.value)
+
+    def cancel(self, ticket: int):
+        """Cancel a query request: it completes with status -6."""
+        _check("skim_server_cancel", _lib.skim_server_cancel(self.handle, ticket))
 
     def set_graph(self, graph: DeviceGraph, ell: int, k: int, seed: int):
         self._graph = graph
