@@ -60,3 +60,12 @@ def make_config(name: str, **overrides) -> dict:
     cfg.update(overrides)
     cfg["name"] = name
     return cfg
+
+
+def graph_sha256(g: Graph) -> str:
+    """SHA-256 of a graph's arrays (row_ptr, col, thr), to tie stored results to their input."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in (g.row_ptr, g.col, g.thr):
+        h.update(memoryview(a).cast("B"))
+    return h.hexdigest()
