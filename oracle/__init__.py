@@ -109,6 +109,20 @@ def _load():
         lib.or_ic_union_query.restype = None
         lib.or_ic_union_query.argtypes = [C.c_uint32, C.c_uint32, P32, C.c_uint64, P64, P32,
                                           C.c_uint32, PD, PI32]
+        lib.or_perm_positions.restype = None
+        lib.or_perm_positions.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, P64]
+        lib.or_build_alg2_table.restype = C.c_int
+        lib.or_build_alg2_table.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32,
+                                            C.c_uint32, P64, C.c_uint32, P64, P32,
+                                            C.POINTER(BuildCounters)]
+        lib.or_sketch_brute_table.restype = None
+        lib.or_sketch_brute_table.argtypes = [C.c_uint32, P64, P32, P32, C.c_uint64, C.c_uint32,
+                                              C.c_uint32, P64, P32, C.c_uint64, P64, P32]
+        lib.or_perm_estimates.restype = None
+        lib.or_perm_estimates.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, P64, P32, PD]
+        lib.or_perm_union_query.restype = None
+        lib.or_perm_union_query.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, P64, P32,
+                                            C.c_uint64, P64, P32, C.c_uint32, PD, PI32]
         _lib = lib
     return _lib
 
@@ -321,4 +335,69 @@ def ic_union_query(pos, n: int, k: int, offsets, nodes, estimator: int = 0):
     ndp = nd if nd.size else np.zeros(1, dtype=np.uint32)
     _load().or_ic_union_query(n, k, _p(pos, P32), q, _p(off, P64), _p(ndp, P32), estimator,
                               _p(est, PD), _p(st, PI32))
+    return est[:q], st[:q]
+
+
+# ---------------------------------------------- structured permutation ranks
+
+def perm_positions(seed: int, n: int, ell: int) -> np.ndarray:
+    """[n, 64] uint64: the position (1..n l) of pair (v, i) in the structured
+    permutation of Section 3.1 (0 for i >= l)."""
+    out = np.zeros(n * 64, dtype=np.uint64)
+    _load().or_perm_positions(seed, n, ell, _p(out, P64))
+    return out.reshape(n, 64)
+
+
+def build_alg2_perm(g, seed: int, ell: int, k: int, threads: int | None = None):
+    """Algorithm 2 with permutation positions as ranks -> (sketches[n, k] of
+    positions, size[n], counters)."""
+    rp, col, thr = _g(g)
+    pos = np.ascontiguousarray(perm_positions(seed, g.n, ell).reshape(-1))
+    ranks = np.empty(g.n * k, dtype=np.uint64)
+    size = np.empty(g.n, dtype=np.uint32)
+    cnt = BuildCounters()
+    if threads is None:
+        threads = os.cpu_count() or 1
+    rc = _load().or_build_alg2_table(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell, k,
+                                     _p(pos, P64), threads, _p(ranks, P64), _p(size, P32),
+                                     C.byref(cnt))
+    if rc != 0:
+        raise ValueError("or_build_alg2_table: bad arguments")
+    return ranks.reshape(g.n, k), size, cnt.as_dict()
+
+
+def sketch_brute_perm(g, seed: int, ell: int, k: int, nodes=None):
+    """The definition (forward search per node and instance) with permutation
+    positions as ranks -> (sketches[len(nodes), k], size)."""
+    rp, col, thr = _g(g)
+    pos = np.ascontiguousarray(perm_positions(seed, g.n, ell).reshape(-1))
+    nodes = np.arange(g.n, dtype=np.uint32) if nodes is None else \
+        np.ascontiguousarray(nodes, dtype=np.uint32)
+    ranks = np.empty(max(nodes.size, 1) * k, dtype=np.uint64)
+    size = np.empty(max(nodes.size, 1), dtype=np.uint32)
+    _load().or_sketch_brute_table(g.n, _p(rp, P64), _p(col, P32), _p(thr, P32), seed, ell, k,
+                                  _p(pos, P64), _p(nodes, P32), nodes.size, _p(ranks, P64),
+                                  _p(size, P32))
+    return ranks[:nodes.size * k].reshape(nodes.size, k), size[:nodes.size]
+
+
+def perm_estimates(ranks, size, n: int, k: int, ell: int) -> np.ndarray:
+    r = np.ascontiguousarray(ranks, dtype=np.uint64).reshape(-1)
+    sz = np.ascontiguousarray(size, dtype=np.uint32)
+    out = np.empty(n)
+    _load().or_perm_estimates(n, k, ell, _p(r, P64), _p(sz, P32), _p(out, PD))
+    return out
+
+
+def perm_union_query(ranks, size, n: int, k: int, ell: int, offsets, nodes, estimator: int = 0):
+    r = np.ascontiguousarray(ranks, dtype=np.uint64).reshape(-1)
+    sz = np.ascontiguousarray(size, dtype=np.uint32)
+    off = np.ascontiguousarray(offsets, dtype=np.uint64)
+    nd = np.ascontiguousarray(nodes, dtype=np.uint32)
+    q = off.size - 1
+    est = np.zeros(max(q, 1))
+    st = np.zeros(max(q, 1), dtype=np.int32)
+    ndp = nd if nd.size else np.zeros(1, dtype=np.uint32)
+    _load().or_perm_union_query(n, k, ell, _p(r, P64), _p(sz, P32), q, _p(off, P64),
+                                _p(ndp, P32), estimator, _p(est, PD), _p(st, PI32))
     return est[:q], st[:q]

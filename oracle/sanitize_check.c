@@ -5,7 +5,8 @@
  *
  * It compiles the oracle into the same translation unit and checks, on
  * random graphs: Algorithm 2 (one and several threads) against the plain
- * definition; the estimates and both union estimators on every singleton;
+ * definition, with hashed ranks and with structured permutation positions;
+ * the estimates and the union estimators on every singleton;
  * SKIM to the full permutation (its gains add up to every pair); the
  * IC-model sketches and their unions.  Exit status 0 when every check
  * holds; the sanitizers abort on the first memory or undefined-behaviour
@@ -125,6 +126,20 @@ int main(void)
             free(ie);
             free(is);
         }
+        /* structured permutation positions as ranks */
+        uint64_t *ppos = malloc(sizeof(uint64_t) * n * 64);
+        or_perm_positions(seed, n, ell, ppos);
+        if (build_alg2(n, rp, col, thr, seed, ell, k, ppos, 3, R1, S1, NULL) != 0) return 1;
+        or_sketch_brute_table(n, rp, col, thr, seed, ell, k, ppos, nodes, n, RB, SB);
+        if (memcmp(R1, RB, sizeof(uint64_t) * n * k) || memcmp(S1, SB, sizeof(uint32_t) * n))
+            return fail("permutation sketches vs the definition", n, ell, k);
+        or_perm_estimates(n, k, ell, R1, S1, est);
+        or_perm_union_query(n, k, ell, R1, S1, n, off, nodes, 0, qe, qs);
+        for (uint32_t v = 0; v < n; v++)
+            if (qe[v] != est[v]) return fail("permutation singleton union", n, ell, k);
+        or_perm_union_query(n, k, ell, R1, S1, n, off, nodes, 1, ce, qs);
+        free(ppos);
+
         free(R1); free(R4); free(RB); free(reach); free(S1); free(S4); free(SB); free(nodes);
         free(est); free(qe); free(ce); free(qs); free(off);
         free(seeds); free(second); free(gain); free(tau); free(pos); free(ice);

@@ -42,6 +42,14 @@
  *   or_ic_union_query ..................... Section 3 and 5.1: bottom-k and
  *                                          Cohen-Kaplan unions of IC-model
  *                                          sketches (permutation ranks)
+ *   or_perm_positions, or_build_alg2_table, or_sketch_brute_table,
+ *   or_perm_estimates, or_perm_union_query  Section 3.1, structured
+ *                                          permutation ranks for finite l:
+ *                                          positions, sketches of positions
+ *                                          (Algorithm 2 and the definition),
+ *                                          the permutation estimator, and
+ *                                          bottom-k and Cohen-Kaplan unions
+ *                                          (Section 5.1, last paragraph)
  *   or_skim ............................... Section 4, Algorithm 1; per-seed
  *                                          records for the adaptive error
  *                                          estimate (Section 4, adaptive error
@@ -200,6 +208,7 @@ typedef struct {
     uint64_t *out_ranks, *out_reach;
     uint32_t *out_size;
     uint8_t *out_ok;
+    const uint64_t *rank_table;  /* [64 n] ranks of the pairs, or NULL: r(v, i) */
 } brute_job;
 
 static void *brute_worker(void *arg)
@@ -221,7 +230,9 @@ static void *brute_worker(void *arg)
                 while (cnt + reached > cap) cap *= 2;
                 all = realloc(all, sizeof(uint64_t) * cap);
             }
-            for (uint64_t t = 0; t < reached; t++) all[cnt++] = or_rank(J->seed, queue[t], i);
+            for (uint64_t t = 0; t < reached; t++)
+                all[cnt++] = J->rank_table ? J->rank_table[(uint64_t)queue[t] * 64 + i]
+                                           : or_rank(J->seed, queue[t], i);
         }
         if (J->out_ok) J->out_ok[j] = (uint8_t)ok;
         if (!ok) continue;
@@ -249,12 +260,24 @@ void or_sketch_brute_budget(uint32_t n, const uint64_t *row_ptr, const uint32_t 
     pthread_t tid[256];
     for (uint32_t t = 0; t < threads; t++) {
         brute_job J = {{n, row_ptr, col, thr}, seed, budget, ell, k, nodes, nq, t, threads,
-                       out_ranks, out_reach, out_size, out_ok};
+                       out_ranks, out_reach, out_size, out_ok, NULL};
         jobs[t] = J;
     }
     for (uint32_t t = 1; t < threads; t++) pthread_create(&tid[t], NULL, brute_worker, &jobs[t]);
     brute_worker(&jobs[0]);
     for (uint32_t t = 1; t < threads; t++) pthread_join(tid[t], NULL);
+}
+
+/* The definition with the ranks of a table (rank_table[64 v + i] for pair
+ * (v, i)) in place of r(v, i): structured permutation positions. */
+void or_sketch_brute_table(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                           const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
+                           const uint64_t *rank_table, const uint32_t *nodes, uint64_t nq,
+                           uint64_t *out_ranks, uint32_t *out_size)
+{
+    brute_job J = {{n, row_ptr, col, thr}, seed, UINT64_MAX, ell, k, nodes, nq, 0, 1,
+                   out_ranks, NULL, out_size, NULL, rank_table};
+    brute_worker(&J);
 }
 
 void or_sketch_brute(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
@@ -279,6 +302,7 @@ typedef struct {
     const or_graph *g;
     uint64_t seed;
     uint32_t ell, k;
+    const uint64_t *rank_table;  /* [64 n] pair ranks, or NULL: r(v, i) */
     uint64_t *X;          /* [n*k] global sketches */
     uint32_t *Xs;         /* [n]   global sizes    */
     uint16_t *emax;       /* [n]   max_i E_{v,i} (under lock) */
@@ -340,7 +364,8 @@ static void *alg2_worker(void *arg)
 
         /* Pairs (u, i) of this instance by increasing rank. */
         for (uint32_t u = 0; u < n; u++) {
-            order[u].r = or_rank(c->seed, u, i);
+            order[u].r = c->rank_table ? c->rank_table[(uint64_t)u * 64 + i]
+                                       : or_rank(c->seed, u, i);
             order[u].v = u;
         }
         qsort(order, n, sizeof(rank_node), cmp_rank_node);
@@ -423,16 +448,16 @@ static void *alg2_worker(void *arg)
 /* Combined bottom-k sketches of every node by Algorithm 2.
  * out_ranks[n*k] ascending with UINT64_MAX padding, out_size[n].
  * Returns 0 on success, -1 on bad arguments. */
-int or_build_alg2(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
-                  const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
-                  uint32_t nthreads, uint64_t *out_ranks, uint32_t *out_size,
-                  or_build_counters *counters)
+static int build_alg2(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                      const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
+                      const uint64_t *rank_table, uint32_t nthreads, uint64_t *out_ranks,
+                      uint32_t *out_size, or_build_counters *counters)
 {
     if (ell < 1 || ell > 64 || k < 1 || k > 65535 || n == 0) return -1;
     or_graph g = {n, row_ptr, col, thr};
     alg2_ctx c;
     memset(&c, 0, sizeof c);
-    c.g = &g; c.seed = seed; c.ell = ell; c.k = k;
+    c.g = &g; c.seed = seed; c.ell = ell; c.k = k; c.rank_table = rank_table;
     c.X = out_ranks; c.Xs = out_size;
     for (uint64_t j = 0; j < (uint64_t)n * k; j++) out_ranks[j] = OR_NONE;
     for (uint32_t v = 0; v < n; v++) out_size[v] = 0;
@@ -461,6 +486,27 @@ int or_build_alg2(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
     pthread_mutex_destroy(&c.qlock);
     free(c.locks); free(c.emax); free(th);
     return 0;
+}
+
+int or_build_alg2(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                  const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
+                  uint32_t nthreads, uint64_t *out_ranks, uint32_t *out_size,
+                  or_build_counters *counters)
+{
+    return build_alg2(n, row_ptr, col, thr, seed, ell, k, NULL, nthreads, out_ranks, out_size,
+                      counters);
+}
+
+/* Algorithm 2 with the ranks of a table (rank_table[64 v + i]): the same
+ * searches, pairs taken in increasing order of their table rank. */
+int or_build_alg2_table(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                        const uint32_t *thr, uint64_t seed, uint32_t ell, uint32_t k,
+                        const uint64_t *rank_table, uint32_t nthreads, uint64_t *out_ranks,
+                        uint32_t *out_size, or_build_counters *counters)
+{
+    if (!rank_table) return -1;
+    return build_alg2(n, row_ptr, col, thr, seed, ell, k, rank_table, nthreads, out_ranks,
+                      out_size, counters);
 }
 
 /* ------------------------------------------------------------ estimates */
@@ -935,5 +981,124 @@ void or_ic_union_query(uint32_t n, uint32_t k, const uint32_t *pos, uint64_t q,
             free(pairs);
         }
         free(vals);
+    }
+}
+
+/* ------------------------------- structured permutation ranks (3.1) -----
+ * Finite-l structured permutation ranks: the n l node-instance pairs are
+ * placed at positions 1 .. n l in l chunks of n positions; chunk c holds
+ * every node exactly once, in the order of h_c(v) = SM(seed, 2^63 + c n + v)
+ * (the chunk order the IC-model sketches use), and the instance a node takes
+ * in chunk c is drawn from the instances it has not taken in earlier chunks.
+ * The draw without replacement is a uniform permutation of the node's l
+ * instances: instance i goes to the chunk given by the place of
+ * g_v(i) = SM(seed, 2^61 + 64 v + i) among g_v(0 .. l-1).
+ * out[64 v + i] = the position of pair (v, i) (1-based), 0 for i >= l.
+ * Only the first min(k, l) n positions can enter a sketch. */
+#define OR_PERM_INST (1ULL << 61)
+
+void or_perm_positions(uint64_t seed, uint32_t n, uint32_t ell, uint64_t *out)
+{
+    rank_node *tmp = malloc(sizeof(rank_node) * (n ? n : 1));
+    uint32_t *place = malloc(sizeof(uint32_t) * (uint64_t)ell * (n ? n : 1));  /* [c n + v] */
+    memset(out, 0, sizeof(uint64_t) * (uint64_t)n * 64);
+    for (uint32_t c = 0; c < ell; c++) {  /* the node order of every chunk */
+        for (uint32_t v = 0; v < n; v++) {
+            tmp[v].r = or_sm64(seed, OR_IC_CHUNK + (uint64_t)c * n + v);
+            tmp[v].v = v;
+        }
+        qsort(tmp, n, sizeof(rank_node), cmp_rank_node);
+        for (uint32_t j = 0; j < n; j++) place[(uint64_t)c * n + tmp[j].v] = j;
+    }
+    for (uint32_t v = 0; v < n; v++) {  /* the instance of every chunk */
+        rank_node inst[64];
+        for (uint32_t i = 0; i < ell; i++) {
+            inst[i].r = or_sm64(seed, OR_PERM_INST + (uint64_t)v * 64 + i);
+            inst[i].v = i;
+        }
+        qsort(inst, ell, sizeof(rank_node), cmp_rank_node);
+        for (uint32_t c = 0; c < ell; c++)
+            out[(uint64_t)v * 64 + inst[c].v] = (uint64_t)c * n + place[(uint64_t)c * n + v] + 1;
+    }
+    free(tmp);
+    free(place);
+}
+
+/* Influence estimate from permutation ranks (Section 3.1): with T the k-th
+ * smallest position of X_v and D = n l, the cardinality estimate is
+ * 1 + (k - 1)(D - 1)/(T - 1), divided by l (Section 3.2 gives the same
+ * form: 1/l + (k - 1)(n l - 1)/(l (T - 1))); |X_v| / l when |X_v| < k.
+ * Computed as (1 + ((k-1)(D-1)) / (T-1)) / l in IEEE double. */
+static double or_perm_estimate_one(uint64_t size, uint64_t T, uint32_t k, uint32_t n, uint32_t ell)
+{
+    if (size < k) return (double)size / (double)ell;
+    const double D = (double)n * (double)ell;
+    return (1.0 + ((double)(k - 1) * (D - 1.0)) / (double)(T - 1)) / (double)ell;
+}
+
+void or_perm_estimates(uint32_t n, uint32_t k, uint32_t ell, const uint64_t *ranks,
+                       const uint32_t *size, double *out_est)
+{
+    for (uint32_t v = 0; v < n; v++)
+        out_est[v] = or_perm_estimate_one(size[v], size[v] >= k ? ranks[(uint64_t)v * k + k - 1] : 0,
+                                          k, n, ell);
+}
+
+/* Union queries over sketches of permutation positions.
+ *   estimator 0: the k smallest distinct positions of the union of the
+ *     members' sketches; the estimate above with T = the k-th of them.
+ *   estimator 1: Cohen-Kaplan (eq. unionest) with the permutation rank T of
+ *     a threshold read as the uniform rank r = (T - 1)/(l n - 1) (Section
+ *     5.1): each distinct position z held by a member outside its own
+ *     threshold element weighs 1/r of the largest threshold among those
+ *     members, (l n - 1)/(T_max - 1); a non-full member has threshold 1
+ *     (weight 1); the weights are added in increasing z and divided by l.
+ * Duplicates act once; an empty set gives 0; a node >= n gives status -1. */
+void or_perm_union_query(uint32_t n, uint32_t k, uint32_t ell, const uint64_t *ranks,
+                         const uint32_t *size, uint64_t Q, const uint64_t *offsets,
+                         const uint32_t *nodes, uint32_t estimator, double *out_est,
+                         int32_t *out_status)
+{
+    const double Dm1 = (double)n * (double)ell - 1.0;
+    for (uint64_t q = 0; q < Q; q++) {
+        uint64_t a = offsets[q], b = offsets[q + 1], cnt = 0;
+        int bad = 0;
+        for (uint64_t j = a; j < b; j++) if (nodes[j] >= n) bad = 1;
+        out_est[q] = 0.0;
+        if (out_status) out_status[q] = bad ? -1 : 0;
+        if (bad || a == b) continue;
+        uint64_t *buf = malloc(sizeof(uint64_t) * 2 * (b - a) * k);
+        for (uint64_t j = a; j < b; j++) {
+            uint32_t u = nodes[j], s = size[u];
+            int full = s == k;
+            uint64_t tau = full ? ranks[(uint64_t)u * k + k - 1] : OR_NONE;
+            uint32_t lim = estimator == 1 && full ? k - 1 : s;
+            for (uint32_t t = 0; t < lim; t++) {
+                buf[2 * cnt] = ranks[(uint64_t)u * k + t];
+                buf[2 * cnt + 1] = tau;
+                cnt++;
+            }
+        }
+        qsort(buf, cnt, 2 * sizeof(uint64_t), cmp_u64); /* by position (first word) */
+        if (estimator == 0) {
+            uint64_t d = 0, T = 0;
+            for (uint64_t x = 0; x < cnt && d < k; x++)
+                if (x == 0 || buf[2 * x] != buf[2 * (x - 1)]) { d++; T = buf[2 * x]; }
+            out_est[q] = or_perm_estimate_one(d, T, k, n, ell);
+        } else {
+            double sum = 0.0;
+            uint64_t x = 0;
+            while (x < cnt) {
+                uint64_t z = buf[2 * x], tmax = buf[2 * x + 1], y = x + 1;
+                while (y < cnt && buf[2 * y] == z) {
+                    if (buf[2 * y + 1] > tmax) tmax = buf[2 * y + 1];
+                    y++;
+                }
+                sum += tmax == OR_NONE ? 1.0 : Dm1 / (double)(tmax - 1);
+                x = y;
+            }
+            out_est[q] = sum / (double)ell;
+        }
+        free(buf);
     }
 }
