@@ -5,9 +5,9 @@
 // edges evaluates all l coins of each edge (half a SplitMix64 output per
 // instance) into a 64-bit instance mask.  Two builders group the live edges
 // by pair p = 64 v + i:
-//  * build_pair_lists (the sketch build): each edge writes its live (pair,
-//    source) entries at its prefix offset, a radix sort groups them by pair
-//    and each pair's run is located; no atomics.
+//  * build_pair_lists (the sketch build): edges sorted by head, then one
+//    wave per node writes the live lists of its 64 pairs (two passes: count,
+//    then place); no atomics.
 //  * build_live_lists (SKIM, which also needs out-lists): per-pair counts,
 //    a scan and a scatter into one CSR over pair ids.
 // Searches then read only the live edges of their own instance.
@@ -64,58 +64,116 @@ __global__ void k_live_fill(const uint32_t *esrc, const uint32_t *col, const uin
     }
 }
 
-// Pair lists without atomics: each edge's live (pair, source) entries are
-// written at its prefix offset, sorted by pair (a stable radix sort keeps
-// the sources of a pair in edge order), and every pair's run is located.
-__global__ void k_live_pc(const uint32_t *esrc, const uint32_t *col, const uint32_t *thr,
-                          uint64_t m, uint32_t n, uint32_t ell, uint64_t seed, uint64_t *masks,
-                          uint32_t *pc) {
+// Pair lists without atomics, grouped by node.  Edges are keyed
+// (head << 32 | source) with their coin masks as values and radix-sorted on
+// the head bits: the in-edges of every node become one run, in source order
+// (the sort is stable and the forward CSR lists sources in order).  One wave
+// per node then turns its run into the live lists of its 64 pairs, lane i
+// taking instance i: a first pass counts each pair's live in-edges (the
+// lanes' bits of 64 masks at a time are gathered by ballots), a scan over
+// the nodes places every list, and a second pass writes the sources.  Lists
+// of one source live in the pair's word itself, so only longer lists take
+// room in the source array.
+__global__ void k_edge_keys(const uint32_t *esrc, const uint32_t *col, const uint32_t *thr,
+                            uint64_t m, uint32_t n, uint32_t ell, uint64_t seed, uint64_t *key,
+                            uint64_t *mask) {
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
          e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t mask = live_mask(seed, n, esrc[e], col[e], thr[e], ell);
-        masks[e] = mask;
-        pc[e] = (uint32_t)__popcll(mask);
+        const uint32_t u = esrc[e], v = col[e];
+        key[e] = ((uint64_t)v << 32) | u;
+        mask[e] = live_mask(seed, n, u, v, thr[e], ell);
     }
 }
 
-__global__ void k_live_emit(const uint32_t *esrc, const uint32_t *col, const uint64_t *masks,
-                            const uint64_t *off, uint64_t m, uint64_t *ent) {
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t mask = masks[e];
-        if (!mask) continue;
-        const uint64_t u = esrc[e], p0 = (uint64_t)col[e] * kPairStride;
-        uint64_t o = off[e];
-        while (mask) {
-            const int i = __ffsll((long long)mask) - 1;
-            mask &= mask - 1;
-            ent[o++] = ((p0 + (uint64_t)i) << 32) | u;
+// Run [beg[v], end[v]) of node v's in-edges in the sorted keys (both arrays
+// zero for a node without in-edges).
+__global__ void k_in_runs(const uint64_t *key, uint64_t m, uint64_t *beg, uint64_t *end) {
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < m;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = (uint32_t)(key[t] >> 32);
+        if (t == 0 || (uint32_t)(key[t - 1] >> 32) != v) beg[v] = t;
+        if (t + 1 == m || (uint32_t)(key[t + 1] >> 32) != v) end[v] = t + 1;
+    }
+}
+
+// Bits of instance `lane` among the 64 masks held by the wave's lanes
+// (lane j holds edge j of the chunk): bit j of the result is set when edge j
+// is live in the lane's instance.
+__device__ __forceinline__ uint64_t column_bits(uint64_t mask, uint32_t ell, uint32_t lane) {
+    uint64_t mine = 0;
+    for (uint32_t i = 0; i < ell; ++i) {
+        const uint64_t b = __ballot((mask >> i) & 1ull);
+        if (lane == i) mine = b;
+    }
+    return mine;
+}
+
+// Pass 1: live in-edges of every pair (kept in live[p] until pass 2) and,
+// per node, the source-array room its lists of two or more take.
+__global__ void __launch_bounds__(256) k_pair_count(const uint64_t *mask, const uint64_t *beg,
+                                                    const uint64_t *end, uint32_t n, uint32_t ell,
+                                                    uint64_t *live, uint32_t *room,
+                                                    uint32_t *too_long) {
+    const uint32_t lane = lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+    for (uint64_t v = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; v < n;
+         v += waves) {
+        const uint64_t b = beg[v], e = end[v];
+        uint64_t c = 0;
+        for (uint64_t j0 = b; j0 < e; j0 += 64) {
+            const uint64_t mk = j0 + lane < e ? mask[j0 + lane] : 0;
+            c += (uint64_t)__popcll(column_bits(mk, ell, lane));
         }
-    }
-}
-
-// Runs of the sorted entries: the first entry of a pair's run leaves its
-// index in live[p], the last one turns it into the pair's live-list word.
-__global__ void k_live_run_starts(const uint64_t *ent, uint64_t nlive, uint64_t *live,
-                                  uint32_t *adj) {
-    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nlive;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t x = ent[t];
-        const uint32_t p = (uint32_t)(x >> 32);
-        adj[t] = (uint32_t)x;
-        if (t == 0 || (uint32_t)(ent[t - 1] >> 32) != p) live[p] = t;
-    }
-}
-
-__global__ void k_live_run_ends(const uint64_t *ent, uint64_t nlive, uint64_t *live,
-                                uint32_t *too_long) {
-    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < nlive;
-         t += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t p = (uint32_t)(ent[t] >> 32);
-        if (t + 1 < nlive && (uint32_t)(ent[t + 1] >> 32) == p) continue;
-        const uint64_t b = live[p], c = t + 1 - b;
         if (c >> kLiveCountBits) atomicOr(too_long, 1u);
-        live[p] = c == 1 ? kLiveOne | (uint32_t)ent[t] : (b << kLiveCountBits) | c;
+        live[v * kPairStride + lane] = c;
+        uint64_t r = c >= 2 ? c : 0;
+        for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
+        if (lane == 0) room[v] = (uint32_t)r;
+    }
+}
+
+// Pass 2: sources of every list of two or more at its place (node base from
+// the scan, then the lanes' lists in instance order); the pair's word.
+__global__ void __launch_bounds__(256) k_pair_emit(const uint64_t *key, const uint64_t *mask,
+                                                   const uint64_t *beg, const uint64_t *end,
+                                                   const uint64_t *node_off, uint32_t n,
+                                                   uint32_t ell, uint64_t *live, uint32_t *adj) {
+    __shared__ uint32_t src[256];
+    const uint32_t lane = lane_id(), wbase = threadIdx.x & ~63u;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+    for (uint64_t v = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; v < n;
+         v += waves) {
+        const uint64_t b = beg[v], e = end[v];
+        const uint64_t c = live[v * kPairStride + lane];
+        const uint64_t mine = c >= 2 ? c : 0;
+        uint64_t incl = mine;  // inclusive scan of the list lengths over the lanes
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint64_t x = __shfl_up(incl, off);
+            if ((int)lane >= off) incl += x;
+        }
+        uint64_t at = node_off[v] + incl - mine;
+        const uint64_t first = at;
+        uint32_t single = 0;
+        for (uint64_t j0 = b; j0 < e; j0 += 64) {
+            const bool in = j0 + lane < e;
+            const uint64_t mk = in ? mask[j0 + lane] : 0;
+            src[wbase + lane] = in ? (uint32_t)key[j0 + lane] : 0;
+            uint64_t bits = column_bits(mk, ell, lane);
+            // the lanes' sources are read by other lanes of the same wave
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            while (bits) {
+                const int j = __ffsll((long long)bits) - 1;
+                bits &= bits - 1;
+                const uint32_t u = src[wbase + j];
+                if (c >= 2) adj[at++] = u;
+                else single = u;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        live[v * kPairStride + lane] =
+            c == 0 ? 0ull : c == 1 ? (kLiveOne | single) : ((first << kLiveCountBits) | c);
     }
 }
 
@@ -129,58 +187,70 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     const uint64_t npairs = (uint64_t)n * kPairStride;
     PairLists L;
     L.live = a.alloc<uint64_t>(npairs);
-    fill_u64(L.live, 0, npairs, s);
     if (!m) {
+        fill_u64(L.live, 0, npairs, s);
         L.adj = a.alloc<uint32_t>(1);
         return L;
     }
-    const unsigned grid = grid_for(m, 256, 32768);
-    uint64_t *masks = a.alloc<uint64_t>(m);
-    uint32_t *pc = a.alloc<uint32_t>(m);
+    // coin masks of every edge, keyed by (head, source)
+    uint64_t *key = a.alloc<uint64_t>(m), *mask = a.alloc<uint64_t>(m);
     {
-        LaunchTimer t("k_live_pc", s);
-        k_live_pc<<<grid, 256, 0, s>>>(esrc, g->col, g->thr, m, n, ell, seed, masks, pc);
+        LaunchTimer t("k_edge_keys", s);
+        k_edge_keys<<<grid_for(m, 256, 32768), 256, 0, s>>>(esrc, g->col, g->thr, m, n, ell, seed,
+                                                            key, mask);
     }
     SKIM_LAUNCH_CHECK();
-    uint64_t *off = a.alloc<uint64_t>(m + 1);
-    exclusive_scan_u32(pc, off, m, a);
-    a.release(pc);
-    uint64_t tot = 0;
-    read_back(&tot, off + m, sizeof tot, s);
-    L.nlive = tot;
-    L.adj = a.alloc<uint32_t>(tot ? tot : 1);
-    if (!tot) {
-        a.release(masks);
-        a.release(off);
-        return L;
-    }
-    uint64_t *ent = a.alloc<uint64_t>(tot);
-    k_live_emit<<<grid, 256, 0, s>>>(esrc, g->col, masks, off, m, ent);
-    SKIM_LAUNCH_CHECK();
-    a.release(masks);
-    a.release(off);
-    int pair_bits = 1;
-    while (pair_bits < 32 && (1ull << pair_bits) < npairs) ++pair_bits;
-    uint64_t *sorted = a.alloc<uint64_t>(tot);
+    int head_bits = 1;
+    while (head_bits < 32 && (1ull << head_bits) < n) ++head_bits;
+    uint64_t *skey = a.alloc<uint64_t>(m), *smask = a.alloc<uint64_t>(m);
     size_t tb = 0;
-    SKIM_HIP(rocprim::radix_sort_keys(nullptr, tb, ent, sorted, (size_t)tot, 32, 32 + pair_bits, s));
+    SKIM_HIP(rocprim::radix_sort_pairs(nullptr, tb, key, skey, mask, smask, (size_t)m, 32,
+                                       32 + head_bits, s));
     void *tmp = a.get(tb ? tb : 1);
-    SKIM_HIP(rocprim::radix_sort_keys(tmp, tb, ent, sorted, (size_t)tot, 32, 32 + pair_bits, s));
+    SKIM_HIP(rocprim::radix_sort_pairs(tmp, tb, key, skey, mask, smask, (size_t)m, 32,
+                                       32 + head_bits, s));
     a.release(tmp);
-    a.release(ent);
+    a.release(key);
+    a.release(mask);
+    // in-edge runs per node
+    uint64_t *beg = a.alloc<uint64_t>(n), *end = a.alloc<uint64_t>(n);
+    fill_u64(beg, 0, n, s);
+    fill_u64(end, 0, n, s);
+    k_in_runs<<<grid_for(m, 256, 65536), 256, 0, s>>>(skey, m, beg, end);
+    SKIM_LAUNCH_CHECK();
+    // pass 1: counts; the room of every node's lists; scan over the nodes
+    uint32_t *room = a.alloc<uint32_t>(n);
     uint32_t *too_long = a.alloc<uint32_t>(1);
     fill_u32(too_long, 0, 1, s);
-    k_live_run_starts<<<grid_for(tot, 256, 65536), 256, 0, s>>>(sorted, tot, L.live, L.adj);
+    const unsigned wgrid = grid_for(n, 4, 65536);  // four waves (nodes) per block
+    {
+        LaunchTimer t("k_pair_count", s);
+        k_pair_count<<<wgrid, 256, 0, s>>>(smask, beg, end, n, ell, L.live, room, too_long);
+    }
     SKIM_LAUNCH_CHECK();
-    k_live_run_ends<<<grid_for(tot, 256, 65536), 256, 0, s>>>(sorted, tot, L.live, too_long);
-    SKIM_LAUNCH_CHECK();
-    a.release(sorted);
+    uint64_t *node_off = a.alloc<uint64_t>((uint64_t)n + 1);
+    exclusive_scan_u32(room, node_off, n, a);
+    a.release(room);
+    uint64_t tot = 0;
     uint32_t bad = 0;
+    read_back(&tot, node_off + n, sizeof tot, s);
     read_back(&bad, too_long, sizeof bad, s);
     if (bad) {
         set_error("a pair has 2^%u or more live in-edges", kLiveCountBits);
         throw Fail{SKIM_EUNSUPPORTED};
     }
+    L.nlive = tot;
+    L.adj = a.alloc<uint32_t>(tot ? tot : 1);
+    {
+        LaunchTimer t("k_pair_emit", s);
+        k_pair_emit<<<wgrid, 256, 0, s>>>(skey, smask, beg, end, node_off, n, ell, L.live, L.adj);
+    }
+    SKIM_LAUNCH_CHECK();
+    a.release(node_off);
+    a.release(beg);
+    a.release(end);
+    a.release(skey);
+    a.release(smask);
     return L;
 }
 
