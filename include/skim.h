@@ -20,7 +20,7 @@
  *     r(v, i) = SM(64 v + i)                      rank of node-instance pair
  *     coin    = high (i even) / low (i odd) 32 bits of
  *               SM(2^62 + 32 (u n + v) + floor(i / 2))
- * Sketch k: 2 <= k <= 256.
+ * Sketch k: 2 <= k <= 256 (skim_greedy: 2 <= k <= 65535).
  * Pointers: every array argument is a DEVICE pointer (HIP global memory on
  *   the current device) unless stated otherwise.  The caller owns every
  *   buffer; inputs must stay valid and unmodified until the stream reaches
@@ -31,9 +31,12 @@
  *   A HIP runtime failure returns SKIM_EDEVICE; an allocation failure
  *   SKIM_ENOMEM.  skim_last_error() describes the last failure of the
  *   calling thread.  Nothing throws across this boundary.
- * Synchronisation: each call may synchronise `stream` internally (it reads
- *   small device counters to schedule its work); results are complete when
- *   the call returns SKIM_OK.
+ * Synchronisation: skim_sketches_query, skim_sketches_create and
+ *   skim_query_plan_launch only enqueue work on `stream` (results are
+ *   complete when the stream reaches them).  The other calls may synchronise
+ *   `stream` internally (they read small device counters to schedule their
+ *   work: the build's search is driven level by level from the host); their
+ *   results are complete when they return SKIM_OK.
  * Determinism: for the same inputs every call returns the same bits, on any
  *   stream and in any batch mix.
  */
@@ -47,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SKIM_ABI_VERSION 5u
+#define SKIM_ABI_VERSION 7u
 
 typedef enum {
     SKIM_OK = 0,
@@ -110,6 +113,41 @@ skim_status skim_build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, u
                                 uint64_t *work, void *stream);
 
 /*
+ * skim_build_sketches_perm -- combined bottom-k sketches with structured
+ * permutation ranks instead of hashed ones (Section 3.1, structured
+ * permutation ranks): the n l pairs take positions 1 .. n l in l chunks of n
+ * positions; chunk c holds every node once, in the order of
+ * h_c(v) = SM(2^63 + c n + v); the instance a node takes in chunk c is drawn
+ * from those it has not taken before (instance i goes to the chunk given by
+ * the place of SM(2^61 + 64 v + i) among the node's l keys).  The instances
+ * (live edges) are those of skim_build_sketches.  Only the first
+ * min(k, l) n positions can enter a sketch.
+ *   ranks [n*k] out, device: X_v, the k smallest positions (as uint64) of
+ *         the pairs v reaches, ascending, padded with UINT64_MAX.
+ *   size  [n]   out, device; est [n] out, device, may be NULL:
+ *         |X_v| / l if |X_v| < k, else (1 + (k-1)(D-1)/(T-1)) / l with
+ *         D = n l and T = the k-th position (IEEE double, in that order).
+ *   work as for skim_build_sketches.  n l < 2^32.
+ */
+skim_status skim_build_sketches_perm(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+                                     uint64_t *ranks, uint32_t *size, double *est,
+                                     uint64_t *work, void *stream);
+
+/*
+ * skim_perm_query_batch -- union estimates over sketches of permutation
+ * positions (skim_build_sketches_perm), as skim_query_batch (mode 0) with
+ * the permutation reading: estimator 0 applies the estimator above to the
+ * k-th smallest distinct position of the union; estimator 1 (Cohen-Kaplan,
+ * Section 5.1, last paragraph) reads a threshold position T as the uniform
+ * rank r = (T - 1)/(l n - 1), so a held value weighs (l n - 1)/(T_max - 1)
+ * (1 when a holder is not full), summed in increasing order, divided by l.
+ */
+skim_status skim_perm_query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
+                                  uint32_t k, uint32_t ell, uint64_t q, const uint64_t *qoff,
+                                  const uint32_t *qnodes, uint32_t estimator, double *est,
+                                  int32_t *qstatus, void *stream);
+
+/*
  * skim_estimates -- per-node estimates from existing sketches, same formula
  * as the `est` output of skim_build_sketches.
  *   ranks [n*k], size [n] in, device; est [n] out, device.
@@ -141,6 +179,46 @@ skim_status skim_query_batch(const uint64_t *ranks, const uint32_t *size, uint32
                              uint32_t k, uint32_t ell, uint64_t q, const uint64_t *qoff,
                              const uint32_t *qnodes, uint32_t estimator, uint32_t mode,
                              double *est, int32_t *qstatus, void *stream);
+
+/*
+ * Resident sketches: a library-owned copy of a sketch table (ranks, sizes and
+ * per-node estimates) kept in device memory for answering queries (Section 5:
+ * the sketches are computed once and every query is answered from them).
+ *   skim_sketches_create: copies ranks [n*k] and size [n] (device, as
+ *     skim_build_sketches writes them) and computes the estimates, all
+ *     enqueued on `stream` without waiting; the sources may be released once
+ *     the stream has passed the copies.  *out receives the handle.
+ *   skim_build_sketches_resident: skim_build_sketches straight into a new
+ *     handle's buffers (synchronises as that call does); work as there.
+ *   skim_sketches_data: the handle's device arrays (read-only) and shape;
+ *     any output pointer may be NULL.
+ *   skim_sketches_query: the union estimates of skim_query_batch (mode 0,
+ *     same estimators and statuses) for q sets, ENQUEUED ONLY: no host check
+ *     and no wait, so the call may be captured into a HIP graph.  qoff
+ *     [q+1], qnodes [nnodes] (device); the offsets are checked by the
+ *     kernel: a set whose offsets are out of order or reach past qoff[q] or
+ *     nnodes gets status -3 and est 0.  workspace: NULL, or 128 device bytes
+ *     of the caller's for the launch's work counter (give one when capturing
+ *     into a graph or when more than 64 calls on one handle may be in flight
+ *     at once: without it, calls take the handle's 64 counters in turn).
+ *   skim_sketches_free: waits for the device, then releases the handle
+ *     (NULL is ignored).
+ * Errors: SKIM_EINVAL (bad shape or NULL), SKIM_ENOMEM, SKIM_EDEVICE.
+ */
+typedef struct skim_sketches skim_sketches;
+
+skim_status skim_sketches_create(const uint64_t *ranks, const uint32_t *size, uint32_t n,
+                                 uint32_t k, uint32_t ell, void *stream, skim_sketches **out);
+skim_status skim_build_sketches_resident(const skim_graph *g, uint32_t ell, uint32_t k,
+                                         uint64_t seed, uint64_t *work, void *stream,
+                                         skim_sketches **out);
+skim_status skim_sketches_data(const skim_sketches *sk, const uint64_t **ranks,
+                               const uint32_t **size, const double **est, uint32_t *n,
+                               uint32_t *k, uint32_t *ell);
+skim_status skim_sketches_query(const skim_sketches *sk, uint64_t q, const uint64_t *qoff,
+                                const uint32_t *qnodes, uint64_t nnodes, uint32_t estimator,
+                                double *est, int32_t *qstatus, void *workspace, void *stream);
+void skim_sketches_free(skim_sketches *sk);
 
 /*
  * Query plans: the batched launch of skim_query_batch (mode 0) for fixed
@@ -176,7 +254,8 @@ void skim_query_plan_free(skim_query_plan *plan);
  * the unselected node of largest size (smallest id on ties).  The residual
  * problem then covers every pair the seed reaches (forward search per
  * instance, not entering covered pairs) and removes their ranks from the
- * partial sketches.
+ * partial sketches.  Here 2 <= k <= 65535 (sizes are 16-bit counters): a k
+ * above every reach set gives exact greedy on the instances.
  *   seeds      [s] out, device: selected nodes in order.
  *   gain_pairs [s] out, device: newly covered node-instance pairs of each
  *              seed (l times its exact marginal influence, Section 4.1.1).

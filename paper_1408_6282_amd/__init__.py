@@ -29,7 +29,10 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_query_plan_launch", "skim_query_plan_free", "skim_greedy_records",
            "skim_discrepancy_tail", "skim_influence_batch", "skim_build_ic_sketches",
            "skim_greedy_exact", "skim_ic_query_batch", "skim_tune_build_cached",
-           "skim_debug_inject", "skim_server_cancel"]
+           "skim_debug_inject", "skim_server_cancel", "skim_sketches_create",
+           "skim_build_sketches_resident", "skim_sketches_data", "skim_sketches_query",
+           "skim_sketches_free", "skim_build_sketches_perm",
+           "skim_perm_query_batch"]
 
 SKIM_FAULT_ALLOC, SKIM_FAULT_SERVE = 1, 2
 
@@ -133,6 +136,27 @@ def load_library(path: str | None = None):
                                           C.c_uint64]
     lib.skim_server_submit_greedy.restype = C.c_int
     lib.skim_server_submit_greedy.argtypes = [vp, C.c_uint32, P64]
+    lib.skim_build_sketches_perm.restype = C.c_int
+    lib.skim_build_sketches_perm.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint32,
+                                             C.c_uint64, vp, vp, vp, vp, vp]
+    lib.skim_perm_query_batch.restype = C.c_int
+    lib.skim_perm_query_batch.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint64,
+                                          vp, vp, C.c_uint32, vp, vp, vp]
+    lib.skim_sketches_create.restype = C.c_int
+    lib.skim_sketches_create.argtypes = [vp, vp, C.c_uint32, C.c_uint32, C.c_uint32, vp,
+                                         C.POINTER(vp)]
+    lib.skim_build_sketches_resident.restype = C.c_int
+    lib.skim_build_sketches_resident.argtypes = [C.POINTER(skim_graph), C.c_uint32, C.c_uint32,
+                                                 C.c_uint64, vp, vp, C.POINTER(vp)]
+    lib.skim_sketches_data.restype = C.c_int
+    lib.skim_sketches_data.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                       C.POINTER(C.c_uint32), C.POINTER(C.c_uint32),
+                                       C.POINTER(C.c_uint32)]
+    lib.skim_sketches_query.restype = C.c_int
+    lib.skim_sketches_query.argtypes = [vp, C.c_uint64, vp, vp, C.c_uint64, C.c_uint32, vp, vp,
+                                        vp, vp]
+    lib.skim_sketches_free.restype = None
+    lib.skim_sketches_free.argtypes = [vp]
     lib.skim_server_cancel.restype = C.c_int
     lib.skim_server_cancel.argtypes = [vp, C.c_uint64]
     lib.skim_debug_inject.restype = C.c_int
@@ -232,6 +256,30 @@ def skim_debug_inject(what: int, count: int = 1):
     _check("skim_debug_inject", load_library().skim_debug_inject(what, count))
 
 
+def skim_build_sketches_perm(graph: DeviceGraph, ell: int, k: int, seed: int, ranks, size,
+                             est=None, stream=None):
+    """Sketches of structured permutation positions (Section 3.1): as
+    skim_build_sketches, with positions 1..n l as the ranks."""
+    lib = load_library()
+    work = (C.c_uint64 * 6)()
+    st = lib.skim_build_sketches_perm(C.byref(graph.struct), ell, k, seed & 0xFFFFFFFFFFFFFFFF,
+                                      _ptr(ranks), _ptr(size), _ptr(est), work, _stream(stream))
+    _check("skim_build_sketches_perm", st)
+    return {"visits": int(work[0]), "scans": int(work[1]), "records": int(work[2]),
+            "windows": int(work[3]), "restarts": int(work[4]), "restart_flags": int(work[5])}
+
+
+def skim_perm_query_batch(ranks, size, n: int, k: int, ell: int, qoff, qnodes, est, qstatus=None,
+                          estimator: int = 0, stream=None):
+    """Union estimates over sketches of permutation positions."""
+    lib = load_library()
+    q = int(qoff.numel()) - 1
+    st = lib.skim_perm_query_batch(_ptr(ranks), _ptr(size), n, k, ell, max(q, 0), _ptr(qoff),
+                                   _ptr(qnodes) if qnodes is not None and qnodes.numel() else None,
+                                   estimator, _ptr(est), _ptr(qstatus), _stream(stream))
+    _check("skim_perm_query_batch", st)
+
+
 def skim_estimates(ranks, size, n: int, k: int, ell: int, est, stream=None):
     lib = load_library()
     st = lib.skim_estimates(_ptr(ranks), _ptr(size), n, k, ell, _ptr(est), _stream(stream))
@@ -247,6 +295,86 @@ def skim_query_batch(ranks, size, n: int, k: int, ell: int, qoff, qnodes, est, q
                               _ptr(qnodes) if qnodes is not None and qnodes.numel() else None,
                               estimator, mode, _ptr(est), _ptr(qstatus), _stream(stream))
     _check("skim_query_batch", st)
+
+
+class Sketches:
+    """skim_sketches_*: a resident, library-owned sketch table; query() only
+    enqueues its launch on the stream (capturable into a HIP graph)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        lib = load_library()
+        r, s, e = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        n, k, ell = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check("skim_sketches_data", lib.skim_sketches_data(self.handle, C.byref(r), C.byref(s),
+                                                            C.byref(e), C.byref(n), C.byref(k),
+                                                            C.byref(ell)))
+        self.n, self.k, self.ell = int(n.value), int(k.value), int(ell.value)
+        self.ranks_ptr, self.size_ptr, self.est_ptr = r.value, s.value, e.value
+
+    @classmethod
+    def from_tables(cls, ranks, size, n: int, k: int, ell: int, stream=None):
+        h = C.c_void_p(None)
+        _check("skim_sketches_create", load_library().skim_sketches_create(
+            _ptr(ranks), _ptr(size), n, k, ell, _stream(stream), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def build(cls, graph: DeviceGraph, ell: int, k: int, seed: int, stream=None):
+        h = C.c_void_p(None)
+        work = (C.c_uint64 * 6)()
+        _check("skim_build_sketches_resident", load_library().skim_build_sketches_resident(
+            C.byref(graph.struct), ell, k, seed & 0xFFFFFFFFFFFFFFFF, work, _stream(stream),
+            C.byref(h)))
+        return cls(h)
+
+    def query(self, qoff, qnodes, est, qstatus=None, estimator: int = 0, workspace=None,
+              stream=None):
+        q = int(qoff.numel()) - 1
+        nn = int(qnodes.numel()) if qnodes is not None else 0
+        _check("skim_sketches_query", load_library().skim_sketches_query(
+            self.handle, max(q, 0), _ptr(qoff), _ptr(qnodes) if nn else None, nn, estimator,
+            _ptr(est), _ptr(qstatus), _ptr(workspace), _stream(stream)))
+
+    def tables(self, torch):
+        """Host copies of the resident (ranks, size, est) as numpy arrays."""
+        import numpy as _np
+        n, k = self.n, self.k
+        out = []
+        for ptr, count, dt in ((self.ranks_ptr, n * k, _np.uint64), (self.size_ptr, n, _np.uint32),
+                               (self.est_ptr, n, _np.float64)):
+            a = _np.empty(count, dtype=dt)
+            torch.cuda.synchronize()
+            if not _copy_d2h(a, ptr):
+                raise SkimError("hipMemcpy", SKIM_EDEVICE, "copy of the resident sketches failed")
+            out.append(a)
+        return out[0].reshape(n, k), out[1], out[2]
+
+    def free(self):
+        if self.handle:
+            load_library().skim_sketches_free(self.handle)
+            self.handle = C.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def _copy_d2h(dst, src_ptr) -> bool:
+    """Blocking copy of dst.nbytes from device address src_ptr into the host
+    numpy array dst (hipMemcpy of the HIP runtime torch has loaded)."""
+    global _hip_rt
+    if _hip_rt is None:
+        _hip_rt = C.CDLL("libamdhip64.so")
+        _hip_rt.hipMemcpy.restype = C.c_int
+        _hip_rt.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    return _hip_rt.hipMemcpy(dst.ctypes.data_as(C.c_void_p), C.c_void_p(src_ptr), dst.nbytes,
+                             2) == 0  # hipMemcpyDeviceToHost
+
+
+_hip_rt = None
 
 
 class QueryPlan:

@@ -15,7 +15,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libskim_hip.so")
 SOURCES = ["skim_common.hip", "skim_live.hip", "skim_build.hip", "skim_query.hip",
            "skim_greedy.hip", "skim_server.hip", "skim_eval.hip",
-           "skim_ic.hip", "skim_tune_cache.hip"]
+           "skim_ic.hip", "skim_tune_cache.hip", "skim_perm.hip"]
 ARCH = os.environ.get("SKIM_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

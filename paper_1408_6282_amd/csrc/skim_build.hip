@@ -65,8 +65,6 @@
 
 namespace skim {
 
-void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
-                      uint32_t ell, double *est, hipStream_t s);
 
 namespace {
 
@@ -117,6 +115,12 @@ __device__ __forceinline__ uint32_t bucket_of(uint64_t r, uint32_t b0) {
     return bits <= (int)b0 ? 0u : (uint32_t)(bits - (int)b0);
 }
 
+// Rank of pair p: the hashed rank r(v, i), or the pair's entry of a rank
+// table (structured permutation positions).
+__device__ __forceinline__ uint64_t rank_of(uint64_t seed, const uint64_t *table, uint32_t p) {
+    return table ? table[p] : pair_rank(seed, p);
+}
+
 constexpr int kRankPer = 8;  // pairs per thread in the bucketing kernels
 
 // Bucketing is a stable counting sort: each block counts its pairs per
@@ -124,8 +128,10 @@ constexpr int kRankPer = 8;  // pairs per thread in the bucketing kernels
 // its place inside every bucket), then writes its pairs in pair order.
 // Every bucket of the sources array is therefore in increasing pair order,
 // and a window's pair records are visited in memory order.
-__global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W, uint32_t b0,
-                            uint32_t *bcount, uint32_t nblocks) {
+// Pairs whose rank exceeds `limit` can enter no sketch and are left out.
+__global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, const uint64_t *table,
+                            uint64_t limit, uint32_t W, uint32_t b0, uint32_t *bcount,
+                            uint32_t nblocks) {
     __shared__ uint32_t h[64];
     if (threadIdx.x < 64) h[threadIdx.x] = 0;
     __syncthreads();
@@ -135,7 +141,8 @@ __global__ void k_rank_hist(uint32_t n, uint32_t ell, uint64_t seed, uint32_t W,
         const uint64_t t = base + (uint64_t)j * kBlock + threadIdx.x;
         if (t < total) {
             const uint32_t v = (uint32_t)(t / ell), i = (uint32_t)(t % ell);
-            atomicAdd(&h[bucket_of(pair_rank(seed, v * kPairStride + i), b0)], 1u);
+            const uint64_t r = rank_of(seed, table, v * kPairStride + i);
+            if (r <= limit) atomicAdd(&h[bucket_of(r, b0)], 1u);
         }
     }
     __syncthreads();
@@ -152,6 +159,7 @@ __global__ void k_bucket_bases(const uint64_t *boff, uint32_t nblocks, uint32_t 
 // j every wave ranks its lanes per bucket by ballots, and the waves of the
 // block and the earlier rounds are added in order.
 __global__ void __launch_bounds__(kBlock) k_rank_scatter(uint32_t n, uint32_t ell, uint64_t seed,
+                                                         const uint64_t *table, uint64_t limit,
                                                          uint32_t W, uint32_t b0,
                                                          const uint64_t *boff, uint32_t nblocks,
                                                          uint32_t *sources) {
@@ -170,7 +178,8 @@ __global__ void __launch_bounds__(kBlock) k_rank_scatter(uint32_t n, uint32_t el
         if (t < total) {
             const uint32_t v = (uint32_t)(t / ell), i = (uint32_t)(t % ell);
             pid = v * kPairStride + i;
-            b = bucket_of(pair_rank(seed, pid), b0);
+            const uint64_t r = rank_of(seed, table, pid);
+            if (r <= limit) b = bucket_of(r, b0);
         }
         bool todo = b != 0xFFFFFFFFu;
         for (;;) {  // one bucket of this wave per pass (wave-uniform loop)
@@ -243,11 +252,15 @@ __device__ __forceinline__ bool hslot_free(uint64_t cur, uint32_t tag) {
 
 // 1 = inserted, 0 = already present, -1 = table full.  Slots only go from
 // free to live within a window, so a probe chain never loses a key.
+// Each probe starts with a CAS that expects an empty slot (the common case
+// at the set's load): its return value is the slot's content, so no load
+// precedes it.
 __device__ int hset_insert(uint64_t *T, uint32_t logcap, uint64_t key, uint32_t tag) {
     const uint64_t mask = (1ull << logcap) - 1;
     uint64_t h = hmix(key) & mask;
     for (int probe = 0; probe < 256; ++probe) {
-        uint64_t cur = load_relaxed(T + h);
+        uint64_t cur = atomicCAS((unsigned long long *)(T + h), kNone, key);
+        if (cur == kNone) return 1;
         if (cur == key) return 0;
         if (hslot_free(cur, tag)) {
             const uint64_t prev = atomicCAS((unsigned long long *)(T + h), cur, key);
@@ -883,67 +896,118 @@ __global__ void k_bounds(const uint64_t *seg, uint64_t nrec, uint64_t *start, ui
 
 // ------------------------------------------------------------- 5. merge
 
-// Bitonic sort of P (power of two, <= 512) keys in LDS by one 64-lane block.
-__device__ void lds_bitonic(uint64_t *x, uint32_t P) {
-    for (uint32_t size = 2; size <= P; size <<= 1) {
+// LDS written by some lanes of a wave, then read by others of the same wave.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Bitonic sort of 64 R keys held in registers by one wave: key r of lane l
+// is element r * 64 + l.  Strides below 64 pair lanes (shuffles), larger
+// strides pair the registers of one lane.  Ascending on return.
+template <int R>
+__device__ __forceinline__ void wave_bitonic(uint64_t (&x)[R], uint32_t lane) {
+#pragma unroll
+    for (uint32_t size = 2; size <= 64u * R; size <<= 1) {
+#pragma unroll
         for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-            for (uint32_t t = threadIdx.x; t < P / 2; t += blockDim.x) {
-                const uint32_t lo = 2 * t - (t & (stride - 1));
-                const uint32_t hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint64_t a = x[lo], b = x[hi];
-                if ((a > b) == up) {
-                    x[lo] = b;
-                    x[hi] = a;
+            if (stride >= 64) {
+                const uint32_t rs = stride / 64;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    if ((r & rs) == 0) {
+                        const bool up = ((r * 64u + lane) & size) == 0;
+                        const uint64_t a = x[r], b = x[r | rs];
+                        const bool swap = (a > b) == up;
+                        x[r] = swap ? b : a;
+                        x[r | rs] = swap ? a : b;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const uint64_t o = shfl_xor_u64(x[r], (int)stride);
+                    const bool up = ((r * 64u + lane) & size) == 0;
+                    const bool low = (lane & stride) == 0;
+                    x[r] = (low == up) ? (x[r] < o ? x[r] : o) : (x[r] < o ? o : x[r]);
                 }
             }
-            __syncthreads();
         }
     }
 }
 
-// One block (one wave) per node: keep the k smallest ranks of the node's
-// records seg[start[v], end[v]) (records sorted by node).
-__global__ void __launch_bounds__(64) k_select(const uint64_t *start, const uint64_t *end,
-                                               const uint64_t *seg, uint32_t n, uint32_t k,
-                                               uint64_t seed, uint64_t *ranks, uint32_t *size) {
-    __shared__ uint64_t buf[512];
-    for (uint32_t v = blockIdx.x; v < n; v += gridDim.x) {
+// The k smallest of the S <= 64 R ranks of segment `a` (records sorted by
+// node), written ascending to `row` with kNone padding.
+template <int R>
+__device__ __forceinline__ void select_regs(const uint64_t *seg, uint64_t a, uint64_t S,
+                                            uint32_t k, uint64_t seed, const uint64_t *table,
+                                            uint64_t *row, uint32_t lane) {
+    uint64_t x[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint64_t j = r * 64u + lane;
+        x[r] = j < S ? rank_of(seed, table, (uint32_t)seg[a + j]) : kNone;
+    }
+    wave_bitonic<R>(x, lane);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint32_t j = r * 64u + lane;
+        if (j < k) row[j] = x[r];  // positions at or past S hold kNone
+    }
+    for (uint32_t j = 64u * R + lane; j < k; j += 64) row[j] = kNone;  // k above 64 R
+}
+
+// One wave per node: keep the k smallest ranks of the node's records
+// seg[start[v], end[v]).  Up to 512 records are sorted in registers; a
+// longer segment goes through LDS in chunks of 256, keeping the 256
+// smallest so far (k <= 256).
+__global__ void __launch_bounds__(256) k_select(const uint64_t *start, const uint64_t *end,
+                                                const uint64_t *seg, uint32_t n, uint32_t k,
+                                                uint64_t seed, const uint64_t *table,
+                                                uint64_t *ranks, uint32_t *size) {
+    __shared__ uint64_t lbuf[4][512];
+    const uint32_t lane = lane_id(), wave = threadIdx.x / 64;
+    uint64_t *buf = lbuf[wave];
+    const uint64_t waves = (uint64_t)gridDim.x * 4;
+    for (uint64_t v = blockIdx.x * 4ull + wave; v < n; v += waves) {
         const uint64_t a = start[v], b = end[v];
         const uint64_t S = b - a;
-        uint32_t keep;
-        if (S <= 512) {
-            uint32_t P = 64;
-            while (P < S) P <<= 1;
-            for (uint32_t j = threadIdx.x; j < P; j += blockDim.x)
-                buf[j] = j < S ? pair_rank(seed, (uint32_t)seg[a + j]) : kNone;
-            __syncthreads();
-            if (S > 1) lds_bitonic(buf, P);
-            keep = (uint32_t)(S < k ? S : k);
-        } else {
-            for (uint32_t j = threadIdx.x; j < 256; j += blockDim.x) buf[j] = kNone;
+        uint64_t *row = ranks + v * k;
+        if (S <= 64) select_regs<1>(seg, a, S, k, seed, table, row, lane);
+        else if (S <= 128) select_regs<2>(seg, a, S, k, seed, table, row, lane);
+        else if (S <= 256) select_regs<4>(seg, a, S, k, seed, table, row, lane);
+        else if (S <= 512) select_regs<8>(seg, a, S, k, seed, table, row, lane);
+        else {
+            for (uint32_t j = lane; j < 256; j += 64) buf[j] = kNone;
             for (uint64_t c = a; c < b; c += 256) {
-                for (uint32_t j = threadIdx.x; j < 256; j += blockDim.x)
-                    buf[256 + j] = c + j < b ? pair_rank(seed, (uint32_t)seg[c + j]) : kNone;
-                __syncthreads();
-                lds_bitonic(buf, 512);
+                for (uint32_t j = lane; j < 256; j += 64)
+                    buf[256 + j] = c + j < b ? rank_of(seed, table, (uint32_t)seg[c + j]) : kNone;
+                wave_lds_sync();
+                uint64_t x[8];
+#pragma unroll
+                for (int r = 0; r < 8; ++r) x[r] = buf[r * 64 + lane];
+                wave_bitonic<8>(x, lane);
+#pragma unroll
+                for (int r = 0; r < 8; ++r) buf[r * 64 + lane] = x[r];
+                wave_lds_sync();
             }
-            keep = k;
+            for (uint32_t j = lane; j < k; j += 64) row[j] = buf[j];
+            wave_lds_sync();  // buf is refilled for the wave's next node
         }
-        uint64_t *row = ranks + (uint64_t)v * k;
-        for (uint32_t j = threadIdx.x; j < k; j += blockDim.x) row[j] = j < keep ? buf[j] : kNone;
-        if (threadIdx.x == 0) size[v] = keep;
-        __syncthreads();
+        if (lane == 0) size[v] = (uint32_t)(S < k ? S : k);
     }
 }
 
 // Bucket 0 holds about k/2 sources per instance (ranks of at most b0 bits,
-// a fraction 2^(b0-64) of all); NB buckets in all.
-void choose_buckets(uint32_t n, uint32_t k, uint32_t &NB, uint32_t &b0) {
+// a fraction 2^(b0 - bits) of all, for ranks spread over `bits` bits: 64
+// for hashed ranks, the bit length of n l for permutation positions); NB
+// buckets in all.
+void choose_buckets(uint32_t n, uint32_t k, uint32_t bits, uint32_t &NB, uint32_t &b0) {
     const double x = 2.0 * n / (double)k;  // 1 / (bucket-0 fraction)
     uint32_t lg = 0;
-    while (lg < 63 && (double)(1ull << lg) < x) ++lg;
-    b0 = 64 - lg;
+    while (lg + 1 < bits && (double)(1ull << lg) < x) ++lg;
+    b0 = bits - lg;
     NB = 1 + lg;
 }
 
@@ -962,10 +1026,11 @@ struct Shapes {
     double heavy = 4.0;
     uint64_t sort_frontier = 0;  // 0: never sort
     uint32_t window_span = 2;    // buckets per window after a light one
+    uint32_t first_span = kFirstSpan;  // buckets of the first window
 };
 
 std::mutex g_shapes_mu;
-skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0, 2};
+skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0, 2, kFirstSpan};
 
 Shapes current_shapes() {
     std::lock_guard<std::mutex> lk(g_shapes_mu);
@@ -977,6 +1042,7 @@ Shapes current_shapes() {
     sh.heavy = (double)g_params.heavy_visits;
     sh.sort_frontier = g_params.sort_frontier;
     sh.window_span = g_params.window_span;
+    sh.first_span = g_params.first_span;
     return sh;
 }
 
@@ -988,9 +1054,20 @@ struct Capacity {
 
 }  // namespace
 
+// Where the ranks come from: hashed r(v, i) (table NULL), or a table of
+// structured permutation positions 1 .. n l, of which only those up to
+// `limit` = min(k, l) n can enter a sketch.
+struct RankSource {
+    const uint64_t *table = nullptr;
+    uint64_t limit = ~0ull;
+    uint32_t bits = 64;    // bit length of the largest rank
+    uint64_t perm_d = 0;   // n l for positions (the permutation estimator), 0 if hashed
+};
+
 // One attempt at the windows and the merge; throws Retry when a buffer was
 // too small (the caller's outputs are written only by the merge).
-static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const PairLists &live,
+static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const RankSource &rs,
+                        const PairLists &live,
                         const uint32_t *sources, const unsigned long long *wb, uint32_t W,
                         const Capacity &cap, const Shapes &sh, uint64_t *ranks_out,
                         uint32_t *size_out, uint64_t *work, Arena &A) {
@@ -1330,8 +1407,8 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
     }
     {
         LaunchTimer t("k_select", s);
-        k_select<<<grid_for(n, 1, 65536), 64, 0, s>>>(gstart, gend, seg, n, k, seed, ranks_out,
-                                                      size_out);
+        k_select<<<grid_for(n, 4, 65536), 256, 0, s>>>(gstart, gend, seg, n, k, seed, rs.table,
+                                                      ranks_out, size_out);
     }
     SKIM_LAUNCH_CHECK();
     if (work) {
@@ -1345,7 +1422,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Pa
 // Host orchestration of one sketch build.
 static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
                            uint64_t *ranks_out, uint32_t *size_out, double *est_out,
-                           uint64_t *work, hipStream_t s) {
+                           uint64_t *work, hipStream_t s, bool permutation = false) {
     const Shapes shapes = current_shapes();
     SKIM_REQUIRE(ell >= 1 && ell <= 64, "l must be in [1, 64]");
     SKIM_REQUIRE(k >= 2 && k <= 256, "k must be in [2, 256]");
@@ -1368,12 +1445,25 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
 
     // ---- 2. rank buckets
     uint32_t W = 1, b0 = 64;  // W: number of buckets
-    choose_buckets(n, k, W, b0);
+    // ---- rank source: hashed, or structured permutation positions
+    RankSource rs;
+    if (permutation) {
+        const uint64_t D = (uint64_t)n * ell;
+        uint64_t *table = A.alloc<uint64_t>((uint64_t)n * kPairStride);
+        perm_positions(n, ell, seed, table, A);
+        rs.table = table;
+        rs.limit = (uint64_t)n * std::min<uint32_t>(k, ell);
+        rs.bits = 1;
+        while (rs.bits < 64 && (1ull << rs.bits) <= D) ++rs.bits;
+        rs.perm_d = D;
+    }
+    choose_buckets(n, k, rs.bits, W, b0);
     unsigned long long *wbuf = A.alloc<unsigned long long>(65);
     const unsigned rblocks = (unsigned)((nsrc + (uint64_t)kBlock * kRankPer - 1) /
                                         ((uint64_t)kBlock * kRankPer));
     uint32_t *bcount = A.alloc<uint32_t>((uint64_t)W * rblocks);
-    k_rank_hist<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, bcount, rblocks);
+    k_rank_hist<<<rblocks, kBlock, 0, s>>>(n, ell, seed, rs.table, rs.limit, W, b0, bcount,
+                                           rblocks);
     SKIM_LAUNCH_CHECK();
     uint64_t *boff = A.alloc<uint64_t>((uint64_t)W * rblocks + 1);
     exclusive_scan_u32(bcount, boff, (uint64_t)W * rblocks, A);
@@ -1384,7 +1474,8 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     read_back(wb, wbuf, sizeof(unsigned long long) * (W + 1), s);
     for (uint32_t w = 0; w < W; ++w) hw[w] = wb[w + 1] - wb[w];
     uint32_t *sources = A.alloc<uint32_t>(nsrc);
-    k_rank_scatter<<<rblocks, kBlock, 0, s>>>(n, ell, seed, W, b0, boff, rblocks, sources);
+    k_rank_scatter<<<rblocks, kBlock, 0, s>>>(n, ell, seed, rs.table, rs.limit, W, b0, boff,
+                                              rblocks, sources);
     SKIM_LAUNCH_CHECK();
     A.release(boff);
 
@@ -1397,13 +1488,13 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     Capacity cap{std::max<uint64_t>(1ull << 20, 3 * (uint64_t)n * k),
                  std::max<uint64_t>(1ull << 20, 3 * biggest),
                  next_pow2(std::max<uint64_t>(1ull << 16, 8 * bucket_max)), 1ull << 16,
-                 kFirstSpan};
+                 shapes.first_span};
     uint32_t retry_flags = 0;
     int attempt = 0;
     for (;; ++attempt) {
         try {
             Arena B(s);
-            run_windows(g, k, seed, live, sources, wb, W, cap, shapes, ranks_out, size_out, work,
+            run_windows(g, k, seed, rs, live, sources, wb, W, cap, shapes, ranks_out, size_out, work,
                         B);
             break;
         } catch (const Retry &r) {
@@ -1431,7 +1522,7 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
         work[4] = (uint64_t)attempt;
         work[5] = retry_flags;
     }
-    if (est_out) launch_estimates(ranks_out, size_out, n, k, ell, est_out, s);
+    if (est_out) launch_estimates(ranks_out, size_out, n, k, ell, est_out, s, rs.perm_d);
     SKIM_HIP(hipStreamSynchronize(s));
     timing_resolve();
 }
@@ -1450,13 +1541,26 @@ extern "C" skim_status skim_build_sketches(const skim_graph *g, uint32_t ell, ui
     }
 }
 
+extern "C" skim_status skim_build_sketches_perm(const skim_graph *g, uint32_t ell, uint32_t k,
+                                                uint64_t seed, uint64_t *ranks, uint32_t *size,
+                                                double *est, uint64_t *work, void *stream) {
+    skim::clear_error();
+    try {
+        skim::build_sketches(g, ell, k, seed, ranks, size, est, work, (hipStream_t)stream, true);
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
 extern "C" skim_status skim_set_build_params(const skim_build_params *p) {
     skim::clear_error();
-    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4, 0, 2};
+    skim_build_params v{65536, 8, 3, skim::kBlock * 2048, 4, 0, 2, skim::kFirstSpan};
     if (p) {
         if (p->small_frontier < 1 || p->small_batch < 1 || p->small_batch > 64 ||
             p->large_batch < 1 || p->large_batch > 64 || p->thread_frontier < 1 ||
-            p->heavy_visits < 1 || p->window_span < 1 || p->window_span > 8) {
+            p->heavy_visits < 1 || p->window_span < 1 || p->window_span > 8 ||
+            p->first_span < 1 || p->first_span > 16) {
             skim::set_error("build parameters out of range");
             return SKIM_EINVAL;
         }
@@ -1518,7 +1622,8 @@ extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32
         const uint32_t tf[] = {131072, 524288, 2097152};
         const uint32_t so[] = {0, 1u << 20, 1u << 22};
         const uint32_t fw[] = {2, 3, 4};
-        for (int field = 0; field < 6 && st == SKIM_OK; ++field) {
+        const uint32_t fs[] = {3, 5, 7};
+        for (int field = 0; field < 7 && st == SKIM_OK; ++field) {
             for (int c = 0; c < 3 && st == SKIM_OK; ++c) {
                 skim_build_params p = cur;
                 uint32_t *slot = field == 0   ? &p.small_frontier
@@ -1526,13 +1631,15 @@ extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32
                                  : field == 2 ? &p.large_batch
                                  : field == 3 ? &p.thread_frontier
                                  : field == 4 ? &p.sort_frontier
-                                              : &p.window_span;
+                                 : field == 5 ? &p.window_span
+                                              : &p.first_span;
                 const uint32_t v = field == 0   ? sf[c]
                                    : field == 1 ? sb[c]
                                    : field == 2 ? lb[c]
                                    : field == 3 ? tf[c]
                                    : field == 4 ? so[c]
-                                                : fw[c];
+                                   : field == 5 ? fw[c]
+                                                : fs[c];
                 if (*slot == v) continue;
                 *slot = v;
                 const double t = time_with(p, st);

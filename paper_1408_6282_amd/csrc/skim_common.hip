@@ -505,19 +505,21 @@ void validate_graph(const skim_graph *g, uint32_t *esrc, Arena &a) {
 }
 
 // ---------------------------------------------------------------- estimates
+// perm_d = 0: hashed ranks, the bottom-k estimator; else sketches of
+// structured permutation positions over perm_d = n l pairs.
 __global__ void k_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
-                            uint32_t ell, double *est) {
+                            uint32_t ell, double *est, uint64_t perm_d) {
     for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
          v += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t sz = size[v];
         const uint64_t tau = sz >= k ? ranks[v * k + (k - 1)] : 0;
-        est[v] = bottomk_estimate(sz, tau, k, ell);
+        est[v] = perm_d ? perm_estimate(sz, tau, k, ell, perm_d) : bottomk_estimate(sz, tau, k, ell);
     }
 }
 
 void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
-                      uint32_t ell, double *est, hipStream_t s) {
-    k_estimates<<<grid_for(n, 256, 8192), 256, 0, s>>>(ranks, size, n, k, ell, est);
+                      uint32_t ell, double *est, hipStream_t s, uint64_t perm_d) {
+    k_estimates<<<grid_for(n, 256, 8192), 256, 0, s>>>(ranks, size, n, k, ell, est, perm_d);
     SKIM_LAUNCH_CHECK();
 }
 

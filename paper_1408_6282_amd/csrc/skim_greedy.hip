@@ -575,7 +575,8 @@ namespace skim {
 skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
                                         hipStream_t s) {
     SKIM_REQUIRE(ell >= 1 && ell <= 64, "l must be in [1, 64]");
-    SKIM_REQUIRE(k >= 2 && k <= 256, "k must be in [2, 256]");
+    // sizes and batch counters are 16-bit halves of words
+    SKIM_REQUIRE(k >= 2 && k <= 65535, "k must be in [2, 65535]");
     SKIM_REQUIRE(g != nullptr, "graph is NULL");
     if ((uint64_t)g->n * kSkimBlock * 4 > (1ull << 30)) {
         set_error("skim_greedy supports n <= 262144 (per-thread search queues)");

@@ -57,6 +57,15 @@ __device__ __forceinline__ uint64_t live_mask(uint64_t seed, uint32_t n, uint32_
     return ell == 64 ? mask : (mask & ((1ull << ell) - 1));
 }
 
+// Influence estimate from structured permutation positions (Section 3.1):
+// the cardinality estimate 1 + (k - 1)(D - 1)/(T - 1), D = n l positions,
+// divided by l; the exact count when the sketch holds fewer than k.
+__device__ __forceinline__ double perm_estimate(uint64_t size, uint64_t T, uint32_t k, uint32_t ell,
+                                                uint64_t D) {
+    if (size < k) return (double)size / (double)ell;
+    return (1.0 + ((double)(k - 1) * ((double)D - 1.0)) / (double)(T - 1)) / (double)ell;
+}
+
 // Real reading of a threshold rank: rho(T) = ((T >> 11) + 1) * 2^-53 in (0, 1].
 __device__ __forceinline__ double rank_real(uint64_t T) {
     return (double)((T >> 11) + 1) * 0x1p-53;
@@ -235,7 +244,17 @@ struct QueryArgs {
     double *est;
     int32_t *qstatus;
     uint32_t estimator;
+    uint64_t nodes_cap = ~0ull;  // entries qnodes holds (a set reaching past them: status -3)
+    uint64_t perm_d = 0;  // n l for sketches of permutation positions, 0 for hashed ranks
 };
+// Per-node estimates of sketches (perm_d = 0: hashed ranks; else sketches of
+// permutation positions over perm_d = n l pairs), enqueued on `s`.
+void launch_estimates(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
+                      uint32_t ell, double *est, hipStream_t s, uint64_t perm_d = 0);
+// Structured permutation positions of every pair (table[64 v + i], 1-based;
+// Section 3.1), computed on the stream of `a`.
+void perm_positions(uint32_t n, uint32_t ell, uint64_t seed, uint64_t *table, Arena &a);
+
 // Launch the persistent query kernel for q sets on `s` without waiting;
 // `next` is a device work counter (zeroed here on the stream).
 void launch_queries_async(const QueryArgs &Q, uint64_t q, unsigned long long *next, hipStream_t s);

@@ -17,6 +17,7 @@
 // query.
 #include "skim_internal.h"
 
+#include <atomic>
 #include <memory>
 
 namespace skim {
@@ -91,7 +92,12 @@ __device__ __forceinline__ void merge_members(const QArgs &Q, uint64_t S, uint32
         }
         if (Q.estimator == 1) {
             tmax = wave_max_u64(tmax);
-            if (lane == 0) sum += tmax == kNone ? 1.0 : 1.0 / rank_real(tmax);
+            // the weight 1/r of the largest holder threshold: r = rho(T) for
+            // hashed ranks, (T - 1)/(l n - 1) for permutation positions
+            if (lane == 0)
+                sum += tmax == kNone ? 1.0
+                       : Q.perm_d    ? ((double)Q.perm_d - 1.0) / (double)(tmax - 1)
+                                     : 1.0 / rank_real(tmax);
         } else {
             ++d;
             if (d == k) {
@@ -110,7 +116,7 @@ __device__ void answer_query(const QArgs &Q, uint64_t j, uint32_t *mnode, uint16
     const uint32_t k = Q.k;
     // Offsets are validated before a batch; a replayed plan re-checks its
     // own set here (non-decreasing, within qoff[q]) and never reads outside.
-    if (b < a || b > Q.qoff[Q.q] || (j == 0 && a != 0)) {
+    if (b < a || b > Q.qoff[Q.q] || b > Q.nodes_cap || (j == 0 && a != 0)) {
         if (lane == 0) {
             Q.est[j] = 0.0;
             if (Q.qstatus) Q.qstatus[j] = -3;
@@ -140,7 +146,9 @@ __device__ void answer_query(const QArgs &Q, uint64_t j, uint32_t *mnode, uint16
         if (lane == 0) {
             const uint32_t u = Q.qnodes[a];
             const uint32_t sz = Q.size[u];
-            Q.est[j] = bottomk_estimate(sz, sz >= k ? Q.ranks[(uint64_t)u * k + k - 1] : 0, k, Q.ell);
+            const uint64_t T = sz >= k ? Q.ranks[(uint64_t)u * k + k - 1] : 0;
+            Q.est[j] = Q.perm_d ? perm_estimate(sz, T, k, Q.ell, Q.perm_d)
+                                : bottomk_estimate(sz, T, k, Q.ell);
             if (Q.qstatus) Q.qstatus[j] = 0;
         }
         return;
@@ -165,7 +173,9 @@ __device__ void answer_query(const QArgs &Q, uint64_t j, uint32_t *mnode, uint16
     else
         merge_members<kPerLane>(Q, S, k, mnode, mpos, mlim, d, tau, sum);
     if (lane == 0) {
-        Q.est[j] = Q.estimator == 1 ? sum / (double)Q.ell : bottomk_estimate(d, tau, k, Q.ell);
+        Q.est[j] = Q.estimator == 1 ? sum / (double)Q.ell
+                   : Q.perm_d          ? perm_estimate(d, tau, k, Q.ell, Q.perm_d)
+                                       : bottomk_estimate(d, tau, k, Q.ell);
         if (Q.qstatus) Q.qstatus[j] = 0;
     }
     __syncthreads();
@@ -236,7 +246,7 @@ void launch_queries_async(const QueryArgs &Q, uint64_t q, unsigned long long *ne
 static void query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n, uint32_t k,
                         uint32_t ell, uint64_t q, const uint64_t *qoff, const uint32_t *qnodes,
                         uint32_t estimator, uint32_t mode, double *est, int32_t *qstatus,
-                        hipStream_t s) {
+                        hipStream_t s, bool permutation = false) {
     SKIM_REQUIRE(ranks && size, "sketches are NULL");
     SKIM_REQUIRE(n >= 1 && k >= 2 && k <= 256 && ell >= 1 && ell <= 64,
                  "need n >= 1, 2 <= k <= 256, 1 <= l <= 64");
@@ -256,6 +266,7 @@ static void query_batch(const uint64_t *ranks, const uint32_t *size, uint32_t n,
     read_back(&total, qoff + q, sizeof total, s);
     SKIM_REQUIRE(total == 0 || qnodes, "qnodes is NULL");
     QArgs Q{ranks, size, n, k, ell, q, qoff, qnodes, est, qstatus, estimator};
+    if (permutation) Q.perm_d = (uint64_t)n * ell;
     if (mode == 0) {
         unsigned long long *next = A.alloc<unsigned long long>(1);
         LaunchTimer t("k_query_persistent", s);
@@ -280,6 +291,21 @@ extern "C" skim_status skim_query_batch(const uint64_t *ranks, const uint32_t *s
     try {
         skim::query_batch(ranks, size, n, k, ell, q, qoff, qnodes, estimator, mode, est, qstatus,
                           (hipStream_t)stream);
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
+extern "C" skim_status skim_perm_query_batch(const uint64_t *ranks, const uint32_t *size,
+                                             uint32_t n, uint32_t k, uint32_t ell, uint64_t q,
+                                             const uint64_t *qoff, const uint32_t *qnodes,
+                                             uint32_t estimator, double *est, int32_t *qstatus,
+                                             void *stream) {
+    skim::clear_error();
+    try {
+        skim::query_batch(ranks, size, n, k, ell, q, qoff, qnodes, estimator, 0, est, qstatus,
+                          (hipStream_t)stream, true);
         return SKIM_OK;
     } catch (const skim::Fail &f) {
         return f.st;
@@ -401,3 +427,161 @@ extern "C" skim_status skim_query_plan_launch(skim_query_plan *plan, void *strea
 }
 
 extern "C" void skim_query_plan_free(skim_query_plan *plan) { skim::plan_free(plan); }
+
+// -------------------------------------------------------- resident sketches
+// A library-owned copy of a sketch table (ranks, sizes, per-node estimates)
+// answering union queries with one enqueue-only launch: no host check of the
+// offsets (the query kernel checks every set on the device, status -3) and
+// no wait, so the call can be captured into a HIP graph.  The persistent
+// kernel's work counter is reset by a fill kernel on the stream (no memset
+// node) and comes from a ring of per-handle counters, or from a workspace the
+// caller passes.
+struct skim_sketches {
+    int device = 0;
+    uint32_t n = 0, k = 0, ell = 0;
+    uint64_t *ranks = nullptr;
+    uint32_t *size = nullptr;
+    double *est = nullptr;
+    unsigned long long *counters = nullptr;  // kRing counters, one 128-byte line each
+    std::atomic<uint32_t> turn{0};
+};
+
+namespace skim {
+
+constexpr uint32_t kRing = 64;
+
+static void sketches_free(skim_sketches *h) {
+    if (!h) return;
+    int cur = 0;
+    const bool have = hipGetDevice(&cur) == hipSuccess;
+    if (have) (void)hipSetDevice(h->device);
+    (void)hipDeviceSynchronize();  // no queued work may still use the buffers
+    (void)hipFree(h->ranks);
+    (void)hipFree(h->size);
+    (void)hipFree(h->est);
+    (void)hipFree(h->counters);
+    if (have) (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+    delete h;
+}
+
+static skim_sketches *sketches_alloc(uint32_t n, uint32_t k, uint32_t ell) {
+    SKIM_REQUIRE(n >= 1 && k >= 2 && k <= 256 && ell >= 1 && ell <= 64,
+                 "need n >= 1, 2 <= k <= 256, 1 <= l <= 64");
+    if (take_fault(kFaultAlloc)) {
+        set_error("device allocation for resident sketches failed: injected failure");
+        throw Fail{SKIM_ENOMEM};
+    }
+    std::unique_ptr<skim_sketches, void (*)(skim_sketches *)> h(new skim_sketches,
+                                                                sketches_free);
+    SKIM_HIP(hipGetDevice(&h->device));
+    h->n = n;
+    h->k = k;
+    h->ell = ell;
+    SKIM_HIP(hipMalloc(&h->ranks, (size_t)n * k * sizeof(uint64_t)));
+    SKIM_HIP(hipMalloc(&h->size, (size_t)n * sizeof(uint32_t)));
+    SKIM_HIP(hipMalloc(&h->est, (size_t)n * sizeof(double)));
+    SKIM_HIP(hipMalloc(&h->counters, (size_t)kRing * 128));
+    return h.release();
+}
+
+}  // namespace skim
+
+extern "C" skim_status skim_sketches_create(const uint64_t *ranks, const uint32_t *size,
+                                            uint32_t n, uint32_t k, uint32_t ell, void *stream,
+                                            skim_sketches **out) {
+    skim::clear_error();
+    if (!out) {
+        skim::set_error("out is NULL");
+        return SKIM_EINVAL;
+    }
+    *out = nullptr;
+    try {
+        SKIM_REQUIRE(ranks && size, "sketches are NULL");
+        skim_sketches *h = skim::sketches_alloc(n, k, ell);
+        hipStream_t s = (hipStream_t)stream;
+        try {
+            SKIM_HIP(hipMemcpyAsync(h->ranks, ranks, (size_t)n * k * 8, hipMemcpyDeviceToDevice, s));
+            SKIM_HIP(hipMemcpyAsync(h->size, size, (size_t)n * 4, hipMemcpyDeviceToDevice, s));
+            skim::launch_estimates(h->ranks, h->size, n, k, ell, h->est, s);
+        } catch (const skim::Fail &) {
+            skim::sketches_free(h);
+            throw;
+        }
+        *out = h;
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
+extern "C" skim_status skim_build_sketches_resident(const skim_graph *g, uint32_t ell, uint32_t k,
+                                                    uint64_t seed, uint64_t *work, void *stream,
+                                                    skim_sketches **out) {
+    skim::clear_error();
+    if (!out || !g) {
+        skim::set_error("NULL argument");
+        return SKIM_EINVAL;
+    }
+    *out = nullptr;
+    skim_sketches *h = nullptr;
+    try {
+        h = skim::sketches_alloc(g->n, k, ell);
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+    const skim_status st =
+        skim_build_sketches(g, ell, k, seed, h->ranks, h->size, h->est, work, stream);
+    if (st != SKIM_OK) {
+        skim::sketches_free(h);
+        return st;
+    }
+    *out = h;
+    return SKIM_OK;
+}
+
+extern "C" skim_status skim_sketches_data(const skim_sketches *h, const uint64_t **ranks,
+                                          const uint32_t **size, const double **est, uint32_t *n,
+                                          uint32_t *k, uint32_t *ell) {
+    skim::clear_error();
+    if (!h) {
+        skim::set_error("handle is NULL");
+        return SKIM_EINVAL;
+    }
+    if (ranks) *ranks = h->ranks;
+    if (size) *size = h->size;
+    if (est) *est = h->est;
+    if (n) *n = h->n;
+    if (k) *k = h->k;
+    if (ell) *ell = h->ell;
+    return SKIM_OK;
+}
+
+extern "C" skim_status skim_sketches_query(const skim_sketches *hc, uint64_t q, const uint64_t *qoff,
+                                           const uint32_t *qnodes, uint64_t nnodes,
+                                           uint32_t estimator, double *est, int32_t *qstatus,
+                                           void *workspace, void *stream) {
+    skim::clear_error();
+    skim_sketches *h = const_cast<skim_sketches *>(hc);
+    if (!h) {
+        skim::set_error("handle is NULL");
+        return SKIM_EINVAL;
+    }
+    try {
+        SKIM_REQUIRE(estimator <= 1, "estimator must be 0 (bottom-k) or 1 (Cohen-Kaplan)");
+        if (q == 0) return SKIM_OK;
+        SKIM_REQUIRE(qoff && est, "qoff/est is NULL");
+        SKIM_REQUIRE(nnodes == 0 || qnodes, "qnodes is NULL");
+        skim::QueryArgs Q{h->ranks, h->size, h->n, h->k, h->ell, q, qoff, qnodes, est, qstatus,
+                          estimator, nnodes};
+        unsigned long long *next =
+            workspace ? (unsigned long long *)workspace
+                      : h->counters + 16 * (h->turn.fetch_add(1) % skim::kRing);
+        skim::launch_queries_async(Q, q, next, (hipStream_t)stream);
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
+extern "C" void skim_sketches_free(skim_sketches *h) { skim::sketches_free(h); }

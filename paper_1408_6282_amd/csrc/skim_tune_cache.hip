@@ -6,7 +6,7 @@
 // each of row_ptr, col and thr, gathered on the device by one small kernel.
 // The cache is a text file with one line per key:
 //   <key hex> <small_frontier> <small_batch> <large_batch> <thread_frontier>
-//   <heavy_visits> <sort_frontier> <window_span> <best_ms>
+//   <heavy_visits> <sort_frontier> <window_span> <first_span> <best_ms>
 // A hit applies the stored launch shapes (skim_set_build_params) without
 // timing anything; a miss runs skim_tune_build and appends its choice.
 // Lines that do not parse, or whose shapes the library refuses, are skipped.
@@ -93,7 +93,7 @@ extern "C" skim_status skim_tune_build_cached(const skim_graph *g, uint32_t ell,
                 double ms = 0;
                 if (!(ls >> k2 >> p.small_frontier >> p.small_batch >> p.large_batch >>
                       p.thread_frontier >> p.heavy_visits >> p.sort_frontier >> p.window_span >>
-                      ms))
+                      p.first_span >> ms))
                     continue;
                 if (k2 != key) continue;
                 if (skim_set_build_params(&p) != SKIM_OK) continue;  // refused: tune again
@@ -115,7 +115,8 @@ extern "C" skim_status skim_tune_build_cached(const skim_graph *g, uint32_t ell,
         }
         out << key << ' ' << best->small_frontier << ' ' << best->small_batch << ' '
             << best->large_batch << ' ' << best->thread_frontier << ' ' << best->heavy_visits << ' '
-            << best->sort_frontier << ' ' << best->window_span << ' ' << bms << '\n';
+            << best->sort_frontier << ' ' << best->window_span << ' ' << best->first_span << ' '
+            << bms << '\n';
         if (best_ms) *best_ms = bms;
         if (start_ms) *start_ms = sms;
         *hit = 0;

@@ -84,3 +84,30 @@ def gpu_greedy(g, ell, k, seed, chunks, G=None, records=False):
         state.free()
     out = (np.concatenate(seeds), np.concatenate(gains), np.concatenate(gd), sel)
     return out + rec if records else out
+
+
+def sha256(a) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).view(np.uint8)).hexdigest()
+
+
+def golden(tag):
+    """The oracle's stored counters and result digests (tests/golden/<tag>_counters.json,
+    written by tests/golden/make_counters.py from the oracle alone)."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        f"{tag}_counters.json")
+    with open(path) as f:
+        return json.load(f)
+
+
+def check_digests(gold, g, R, S, E):
+    """The GPU's sketches, sizes and estimates equal the oracle's, by digest."""
+    from workloads.configs import graph_sha256
+    assert gold["graph_sha256"] == graph_sha256(g), "stored digests are for another graph"
+    d = gold["digests"]
+    assert sha256(S.astype(np.uint32)) == d["size_sha256"], "sizes differ from the oracle's"
+    assert sha256(R.astype(np.uint64)) == d["ranks_sha256"], "sketches differ from the oracle's"
+    if E is not None:
+        assert sha256(E.astype(np.float64)) == d["est_sha256"], "estimates differ from the oracle's"

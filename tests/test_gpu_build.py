@@ -124,16 +124,38 @@ def test_bad_parameters():
         assert ei.value.status == sk.SKIM_EINVAL
 
 
-@pytest.mark.slow
-def test_chung_lu_1m_full_parity(oracle_lib):
+# Launch shapes of the full-size parity runs: the defaults, the shapes the
+# autotuner picks on this workload (the launch the bench times), and the
+# widest windows and batches.
+CL_SHAPES = {
+    "default": None,
+    "tuned": dict(small_frontier=262144, small_batch=16, large_batch=2, thread_frontier=524288,
+                  heavy_visits=4, sort_frontier=0, window_span=3, first_span=5),
+    "wide": dict(small_frontier=1 << 24, small_batch=64, large_batch=64, thread_frontier=1 << 30,
+                 heavy_visits=1000, sort_frontier=0, window_span=8, first_span=16),
+}
+
+
+@pytest.fixture(scope="module")
+def chung_lu_1m():
     cfg = make_config("chung-lu-1m")
     log("generating chung-lu-1m")
-    g = make_graph(cfg)
-    log("gpu build chung-lu-1m")
-    R, S, E, work, _ = gpu_build(g, cfg["ell"], cfg["k"], cfg["seed"])
-    log(f"gpu work {work}; oracle build")
-    R0, S0, cnt = oracle_lib.build_alg2(g, cfg["seed"], cfg["ell"], cfg["k"])
-    assert np.array_equal(S, S0)
-    assert np.array_equal(R, R0)
-    assert np.array_equal(E, oracle_lib.estimates(R0, S0, cfg["k"], cfg["ell"]))
-    log(f"oracle counters {cnt}")
+    return cfg, make_graph(cfg)
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("shape", list(CL_SHAPES))
+def test_chung_lu_1m_full_parity(chung_lu_1m, shape):
+    # every sketch, size and estimate of the full workload equals the
+    # oracle's Algorithm 2 (by the digests its committed script stored)
+    import paper_1408_6282_amd as sk
+    from gpu_util import check_digests, golden
+    cfg, g = chung_lu_1m
+    sk.skim_set_build_params(CL_SHAPES[shape])
+    try:
+        log(f"gpu build chung-lu-1m, {shape} shapes")
+        R, S, E, work, _ = gpu_build(g, cfg["ell"], cfg["k"], cfg["seed"])
+    finally:
+        sk.skim_set_build_params(None)
+    log(f"gpu work {work}")
+    check_digests(golden("chung_lu_1m"), g, R, S, E)

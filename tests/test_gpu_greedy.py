@@ -66,8 +66,8 @@ def test_too_many_seeds_rejected():
     with pytest.raises(sk.SkimError) as ei:
         sk.skim_greedy(G, 4, 4, 1, 6, a, b)
     assert ei.value.status == sk.SKIM_EINVAL
-    # sizes and batch counters are 16-bit halves of words: k <= 256 as for the build
-    for ell, k in [(4, 257), (65, 4), (4, 1)]:
+    # sizes and batch counters are 16-bit halves of words: k <= 65535
+    for ell, k in [(4, 65536), (65, 4), (4, 1)]:
         with pytest.raises(sk.SkimError) as ei:
             sk.skim_greedy(G, ell, k, 1, 2, a, b)
         assert ei.value.status == sk.SKIM_EINVAL

@@ -110,22 +110,34 @@ def test_failed_batch_completes_with_status_and_frees_its_slot(served):
 
 
 def test_cancelled_requests_complete_with_status(served):
+    # One query per batch on one stream, so that later requests still wait
+    # when they are cancelled (a finished request cannot be cancelled:
+    # SKIM_EINVAL).  The latest requests are cancelled first.
     import paper_1408_6282_amd as sk
     cfg, g, rt, st = served
     n, ell, k = g.n, cfg["ell"], cfg["k"]
-    srv = sk.Server(rt, st, n, k, ell, budget_bytes=8 << 20, max_batch=16, streams=1)
+    nodes = np.arange(512) % n
+    want, _ = gpu_query(rt, st, n, k, ell, np.array([0, 512], dtype=np.uint64),
+                        nodes.astype(np.uint32))
+    srv = sk.Server(rt, st, n, k, ell, budget_bytes=64 << 20, max_batch=1, streams=1)
     try:
-        tickets = [srv.submit(np.arange(512) % n) for _ in range(200)]
-        for t in tickets[::2]:
-            srv.cancel(t)
-        for j, t in enumerate(tickets):
+        tickets = [srv.submit(nodes) for _ in range(2000)]
+        cancelled = set()
+        for t in reversed(tickets[::2]):
+            try:
+                srv.cancel(t)
+                cancelled.add(t)
+            except sk.SkimError as e:
+                assert e.status == sk.SKIM_EINVAL  # already finished
+        assert cancelled, "no request was still waiting"
+        for t in tickets:
             r = _wait(lambda: srv.poll(t))
-            if j % 2 == 0:
+            if t in cancelled:
                 assert r[1] == -6 and r[0] == 0.0
             else:
-                assert r[1] == 0
+                assert r[1] == 0 and r[0] == want[0]
         with pytest.raises(sk.SkimError):
-            srv.cancel(tickets[1])  # finished
+            srv.cancel(tickets[1])  # finished and retired
     finally:
         srv.close()
 

@@ -11,9 +11,9 @@ from gpu_util import gpu_build, log
 pytestmark = pytest.mark.gpu
 
 EXTREME = dict(small_frontier=1, small_batch=1, large_batch=1, thread_frontier=1, heavy_visits=1,
-               sort_frontier=1, window_span=1)
+               sort_frontier=1, window_span=1, first_span=1)
 WIDE = dict(small_frontier=1 << 24, small_batch=64, large_batch=64, thread_frontier=1 << 30,
-            heavy_visits=1000, sort_frontier=0, window_span=8)
+            heavy_visits=1000, sort_frontier=0, window_span=8, first_span=16)
 
 
 @pytest.fixture
@@ -65,7 +65,8 @@ def test_tuner_keeps_results_and_sets_params(oracle_lib, restore_params):
 @pytest.mark.parametrize("field,value", [("small_frontier", 0), ("small_batch", 0),
                                          ("small_batch", 65), ("large_batch", 0),
                                          ("thread_frontier", 0), ("heavy_visits", 0),
-                                         ("window_span", 0), ("window_span", 9)])
+                                         ("window_span", 0), ("window_span", 9),
+                                         ("first_span", 0), ("first_span", 17)])
 def test_out_of_range_params_refused(restore_params, field, value):
     import paper_1408_6282_amd as sk
     before = sk.skim_get_build_params()
@@ -89,7 +90,7 @@ def test_tuning_cache(tmp_path):
         p1, ms1, _, hit1 = sk.skim_tune_build_cached(G, 16, 16, 1, ranks, size, path, reps=1)
         assert not hit1
         lines = open(path).read().splitlines()
-        assert len(lines) == 1 and len(lines[0].split()) == 9
+        assert len(lines) == 1 and len(lines[0].split()) == 10  # key, 8 shapes, time
         sk.skim_set_build_params(None)
         p2, ms2, start2, hit2 = sk.skim_tune_build_cached(G, 16, 16, 1, ranks, size, path, reps=1)
         assert hit2 and p2 == p1 and start2 == 0.0
