@@ -412,6 +412,23 @@ skim_status skim_discrepancy_tail(uint32_t s, const uint64_t *tau, const uint32_
                                   double max_rel_error, double *tail, void *stream);
 
 /*
+ * skim_discrepancy_tail_noalloc -- skim_discrepancy_tail for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments and
+ * result; it allocates nothing and only enqueues its work on `stream` (the
+ * caller synchronises).  Its scratch is a file-scope device array of about
+ * 12.3 MiB that each GPU the library runs on holds until the process ends:
+ * s * (bins + 1) may be at most 2^20 (1,048,576), else SKIM_EUNSUPPORTED
+ * with nothing enqueued.  Every call on one GPU shares that GPU's array, so
+ * calls that overlap on one GPU (other streams or threads, before the
+ * previous call's work has finished) race and must be serialised by the
+ * caller.
+ */
+skim_status skim_discrepancy_tail_noalloc(uint32_t s, const uint64_t *tau, const uint32_t *second,
+                                          const uint64_t *gain_pairs, uint32_t bins,
+                                          double max_rel_error, double *tail, void *stream);
+
+/*
  * Serving: a request loop over resident sketches.  Union queries are
  * admitted when their bytes (4 per node + 20) fit the free part of
  * budget_bytes, else SKIM_EBUSY (retry later); a request that can never fit

@@ -31,7 +31,7 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_greedy_exact", "skim_ic_query_batch", "skim_tune_build_cached",
            "skim_debug_inject", "skim_server_cancel", "skim_sketches_create",
            "skim_build_sketches_resident", "skim_sketches_data", "skim_sketches_query",
-           "skim_sketches_free", "skim_build_sketches_perm",
+           "skim_sketches_free", "skim_discrepancy_tail_noalloc", "skim_build_sketches_perm",
            "skim_perm_query_batch"]
 
 SKIM_FAULT_ALLOC, SKIM_FAULT_SERVE = 1, 2
@@ -120,6 +120,9 @@ def load_library(path: str | None = None):
                                          C.c_uint64, vp, vp, vp, vp, vp]
     lib.skim_discrepancy_tail.restype = C.c_int
     lib.skim_discrepancy_tail.argtypes = [C.c_uint32, vp, vp, vp, C.c_uint32, C.c_double, vp, vp]
+    lib.skim_discrepancy_tail_noalloc.restype = C.c_int
+    lib.skim_discrepancy_tail_noalloc.argtypes = [C.c_uint32, vp, vp, vp, C.c_uint32, C.c_double,
+                                                  vp, vp]
     P64 = C.POINTER(C.c_uint64)
     PD = C.POINTER(C.c_double)
     lib.skim_server_create.restype = C.c_int
@@ -552,6 +555,17 @@ def skim_discrepancy_tail(tau, second, gain_pairs, bins: int, max_rel_error: flo
     st = load_library().skim_discrepancy_tail(s, _ptr(tau), _ptr(second), _ptr(gain_pairs), bins,
                                               float(max_rel_error), _ptr(tail), _stream(stream))
     _check("skim_discrepancy_tail", st)
+
+
+def skim_discrepancy_tail_noalloc(tau, second, gain_pairs, bins: int, max_rel_error: float,
+                                  tail, stream=None):
+    """skim_discrepancy_tail without allocation: only enqueued on the stream
+    (the caller synchronises); s * (bins + 1) <= 2^20."""
+    s = 0 if tau is None else int(tau.numel())
+    st = load_library().skim_discrepancy_tail_noalloc(s, _ptr(tau), _ptr(second), _ptr(gain_pairs),
+                                                      bins, float(max_rel_error), _ptr(tail),
+                                                      _stream(stream))
+    _check("skim_discrepancy_tail_noalloc", st)
 
 
 def skim_timing_enable(kernel: str | None):

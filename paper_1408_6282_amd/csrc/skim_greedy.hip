@@ -32,6 +32,8 @@
 // convolves the per-seed distributions pairwise in a tree of launches.
 #include "skim_internal.h"
 
+#include <mutex>
+
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
@@ -740,6 +742,100 @@ extern "C" skim_status skim_greedy_records(const skim_greedy_state *state, uint3
         SKIM_HIP(hipStreamSynchronize(hs));
         return SKIM_OK;
     } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
+// ------------------------------------------- the tail without allocation
+// skim_discrepancy_tail_noalloc: the same kernels, with their scratch (the
+// gain total, the per-seed survival functions and one level of the pairwise
+// convolution tree) in a file-scope device array instead of memory the call
+// allocates.  Each GPU holds its own copy of `scratch` at its own address,
+// looked up once per device with hipGetSymbolAddress; host code only ever
+// uses that address.
+namespace skim {
+namespace {
+
+// seeds * (bins + 1) at most; the words hold the gain total (one 256-byte
+// slot), s (bins + 1) survival values and ceil(s / 2) (bins + 1) values of
+// a tree level (at most half the cells plus half a row): about 12.3 MiB.
+constexpr uint64_t kNoAllocCells = 1ull << 20;
+constexpr uint64_t kNoAllocWords = 32 + kNoAllocCells + kNoAllocCells / 2 + 32800;
+
+}  // namespace
+}  // namespace skim
+
+static __device__ __align__(256) double scratch[skim::kNoAllocWords];
+
+namespace skim {
+namespace {
+
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[64] = {};
+
+double *scratch_on_device(int dev) {
+    SKIM_REQUIRE(dev >= 0 && dev < 64, "device index %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        SKIM_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+}  // namespace skim
+
+extern "C" skim_status skim_discrepancy_tail_noalloc(uint32_t s, const uint64_t *tau,
+                                                     const uint32_t *second,
+                                                     const uint64_t *gain_pairs, uint32_t bins,
+                                                     double max_rel_error, double *tail,
+                                                     void *stream) {
+    using namespace skim;
+    clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    try {
+        SKIM_REQUIRE(bins >= 1 && bins <= kTailMaxBins, "bins must be in [1, %u]", kTailMaxBins);
+        SKIM_REQUIRE(max_rel_error > 0.0 && max_rel_error <= 1e300,
+                     "max_rel_error must be positive and finite");
+        SKIM_REQUIRE(tail != nullptr, "tail is NULL");
+        SKIM_REQUIRE(s == 0 || (tau && second && gain_pairs), "tau/second/gain_pairs is NULL");
+        const uint64_t W = (uint64_t)bins + 1;
+        if ((uint64_t)s * W > kNoAllocCells) {
+            set_error("seeds * (bins + 1) = %llu exceeds the %llu cells of the no-allocation "
+                      "scratch", (unsigned long long)((uint64_t)s * W),
+                      (unsigned long long)kNoAllocCells);
+            throw Fail{SKIM_EUNSUPPORTED};
+        }
+        if (s == 0) {  // the empty sum is 0 with certainty
+            fill_u64((uint64_t *)tail, 0, W, hs);
+            fill_u64((uint64_t *)tail, 0x3FF0000000000000ull, 1, hs);  // 1.0
+            return SKIM_OK;
+        }
+        int dev = 0;
+        SKIM_HIP(hipGetDevice(&dev));
+        double *base = scratch_on_device(dev);
+        // layout: gain total (one 256-byte slot), survival functions, tree level
+        uint64_t *total = (uint64_t *)base;
+        double *bufA = base + 32;
+        double *bufB = bufA + (uint64_t)s * W;
+        k_tail_total<<<1, kTailBlock, 0, hs>>>(s, gain_pairs, total);
+        SKIM_LAUNCH_CHECK();
+        k_tail_survival<<<grid_for((uint64_t)s * W, kTailBlock), kTailBlock, 0, hs>>>(
+            s, tau, second, gain_pairs, total, bins, max_rel_error, bufA);
+        SKIM_LAUNCH_CHECK();
+        double *in = bufA, *out = bufB;
+        for (uint32_t rows = s; rows > 1; rows = (rows + 1) / 2) {
+            const uint64_t blocks = ((uint64_t)rows + 1) / 2 * ((W + kTailOut - 1) / kTailOut);
+            k_tail_pair<<<(unsigned)std::min<uint64_t>(blocks, 65536), kTailPairBlock, 0, hs>>>(
+                in, out, rows, bins);
+            SKIM_LAUNCH_CHECK();
+            std::swap(in, out);
+        }
+        SKIM_HIP(hipMemcpyAsync(tail, in, W * sizeof(double), hipMemcpyDeviceToDevice, hs));
+        return SKIM_OK;
+    } catch (const Fail &f) {
         return f.st;
     }
 }
