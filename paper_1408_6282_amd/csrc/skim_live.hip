@@ -64,16 +64,27 @@ __global__ void k_live_fill(const uint32_t *esrc, const uint32_t *col, const uin
     }
 }
 
-// Pair lists without atomics, grouped by node.  Edges are keyed
+// Pair lists without atomics per entry, grouped by node.  Edges are keyed
 // (head << 32 | source) with their coin masks as values and radix-sorted on
 // the head bits: the in-edges of every node become one run, in source order
-// (the sort is stable and the forward CSR lists sources in order).  One wave
-// per node then turns its run into the live lists of its 64 pairs, lane i
-// taking instance i: a first pass counts each pair's live in-edges (the
-// lanes' bits of 64 masks at a time are gathered by ballots), a scan over
-// the nodes places every list, and a second pass writes the sources.  Lists
-// of one source live in the pair's word itself, so only longer lists take
-// room in the source array.
+// (the sort is stable and the forward CSR lists sources in order).  Each run
+// is cut into chunks of at most kChunkEdges in-edges (a node without
+// in-edges gets one empty chunk), and one wave per chunk turns its edges
+// into the live lists of the node's 64 pairs, lane i taking instance i (the
+// lanes' bits of 64 masks at a time are gathered by ballots):
+//  1. count: per chunk and instance; the node's totals (atomics only for
+//     nodes of several chunks, the in-degree hubs);
+//  2. room: per node, the source-array room of its lists of two or more,
+//     then a scan over the nodes;
+//  3. chunk offsets: for nodes of several chunks, each chunk's place inside
+//     each list (a prefix over the node's chunks);
+//  4. write: the sources at their places and every pair's word, written
+//     once (by the node's first chunk, or for a list of one by the chunk that
+//     holds its source, the source itself being the word).
+// Cutting hubs into chunks keeps every wave's work short: one wave per whole
+// node left a 180,000-in-edge hub to a single wave.
+constexpr uint32_t kChunkEdges = 1024;
+
 __global__ void k_edge_keys(const uint32_t *esrc, const uint32_t *col, const uint32_t *thr,
                             uint64_t m, uint32_t n, uint32_t ell, uint64_t seed, uint64_t *key,
                             uint64_t *mask) {
@@ -96,6 +107,21 @@ __global__ void k_in_runs(const uint64_t *key, uint64_t m, uint64_t *beg, uint64
     }
 }
 
+__global__ void k_chunks_per_node(const uint64_t *beg, const uint64_t *end, uint32_t n,
+                                  uint32_t *nch) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t d = end[v] - beg[v];
+        nch[v] = d ? (uint32_t)((d + kChunkEdges - 1) / kChunkEdges) : 1u;
+    }
+}
+
+__global__ void k_chunk_nodes(const uint64_t *choff, uint32_t n, uint32_t *chnode) {
+    for (uint64_t v = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; v < n;
+         v += (uint64_t)gridDim.x * blockDim.x)
+        for (uint64_t c = choff[v]; c < choff[v + 1]; ++c) chnode[c] = (uint32_t)v;
+}
+
 // Bits of instance `lane` among the 64 masks held by the wave's lanes
 // (lane j holds edge j of the chunk): bit j of the result is set when edge j
 // is live in the lane's instance.
@@ -108,72 +134,129 @@ __device__ __forceinline__ uint64_t column_bits(uint64_t mask, uint32_t ell, uin
     return mine;
 }
 
-// Pass 1: live in-edges of every pair (kept in live[p] until pass 2) and,
-// per node, the source-array room its lists of two or more take.
-__global__ void __launch_bounds__(256) k_pair_count(const uint64_t *mask, const uint64_t *beg,
-                                                    const uint64_t *end, uint32_t n, uint32_t ell,
-                                                    uint64_t *live, uint32_t *room,
-                                                    uint32_t *too_long) {
+struct ChunkArgs {
+    const uint64_t *key, *mask, *beg, *end, *choff;
+    const uint32_t *chnode;
+    uint64_t nchunks;
+    uint32_t ell;
+};
+
+// Edges [j0, j1) of chunk c of node v.
+__device__ __forceinline__ void chunk_range(const ChunkArgs &C, uint64_t c, uint32_t &v,
+                                            uint64_t &j0, uint64_t &j1, bool &multi) {
+    v = C.chnode[c];
+    const uint64_t first = C.choff[v];
+    multi = C.choff[v + 1] - first > 1;
+    j0 = C.beg[v] + (c - first) * kChunkEdges;
+    const uint64_t e = C.end[v];
+    j1 = j0 + kChunkEdges < e ? j0 + kChunkEdges : e;
+    if (j0 > j1) j0 = j1;  // a node without in-edges: one empty chunk
+}
+
+// 1. count
+__global__ void __launch_bounds__(256) k_pair_count(ChunkArgs C, uint32_t *ccnt, uint32_t *pcnt) {
+    const uint32_t lane = lane_id();
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+    for (uint64_t c = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; c < C.nchunks;
+         c += waves) {
+        uint32_t v;
+        uint64_t j0, j1;
+        bool multi;
+        chunk_range(C, c, v, j0, j1, multi);
+        uint32_t cnt = 0;
+        for (uint64_t j = j0; j < j1; j += 64) {
+            const uint64_t mk = j + lane < j1 ? C.mask[j + lane] : 0;
+            cnt += (uint32_t)__popcll(column_bits(mk, C.ell, lane));
+        }
+        ccnt[c * kPairStride + lane] = cnt;
+        if (!multi) pcnt[(uint64_t)v * kPairStride + lane] = cnt;
+        else if (cnt) atomicAdd(pcnt + (uint64_t)v * kPairStride + lane, cnt);
+    }
+}
+
+// 2. room per node (lists of two or more), and a flag for a list too long
+// for the pair word's count field
+__global__ void k_pair_room(const uint32_t *pcnt, uint32_t n, uint32_t *room, uint32_t *too_long) {
     const uint32_t lane = lane_id();
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     for (uint64_t v = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; v < n;
          v += waves) {
-        const uint64_t b = beg[v], e = end[v];
-        uint64_t c = 0;
-        for (uint64_t j0 = b; j0 < e; j0 += 64) {
-            const uint64_t mk = j0 + lane < e ? mask[j0 + lane] : 0;
-            c += (uint64_t)__popcll(column_bits(mk, ell, lane));
-        }
+        const uint32_t c = pcnt[v * kPairStride + lane];
         if (c >> kLiveCountBits) atomicOr(too_long, 1u);
-        live[v * kPairStride + lane] = c;
-        uint64_t r = c >= 2 ? c : 0;
+        uint32_t r = c >= 2 ? c : 0;
         for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
-        if (lane == 0) room[v] = (uint32_t)r;
+        if (lane == 0) room[v] = r;
     }
 }
 
-// Pass 2: sources of every list of two or more at its place (node base from
-// the scan, then the lanes' lists in instance order); the pair's word.
-__global__ void __launch_bounds__(256) k_pair_emit(const uint64_t *key, const uint64_t *mask,
-                                                   const uint64_t *beg, const uint64_t *end,
-                                                   const uint64_t *node_off, uint32_t n,
-                                                   uint32_t ell, uint64_t *live, uint32_t *adj) {
-    __shared__ uint32_t src[256];
-    const uint32_t lane = lane_id(), wbase = threadIdx.x & ~63u;
+// 3. for nodes of several chunks: ccnt becomes each chunk's exclusive prefix
+// within each of the node's lists
+__global__ void k_chunk_prefix(const uint64_t *choff, uint32_t n, uint32_t *ccnt) {
+    const uint32_t lane = lane_id();
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     for (uint64_t v = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; v < n;
          v += waves) {
-        const uint64_t b = beg[v], e = end[v];
-        const uint64_t c = live[v * kPairStride + lane];
-        const uint64_t mine = c >= 2 ? c : 0;
+        const uint64_t c0 = choff[v], c1 = choff[v + 1];
+        if (c1 - c0 < 2) continue;
+        uint32_t run = 0;
+        for (uint64_t c = c0; c < c1; ++c) {
+            const uint32_t x = ccnt[c * kPairStride + lane];
+            ccnt[c * kPairStride + lane] = run;
+            run += x;
+        }
+    }
+}
+
+// 4. write
+__global__ void __launch_bounds__(256) k_pair_emit(ChunkArgs C, const uint32_t *ccnt,
+                                                   const uint32_t *pcnt, const uint64_t *node_off,
+                                                   uint64_t *live, uint32_t *adj) {
+    __shared__ uint32_t src[256];
+    const uint32_t lane = lane_id(), wbase = threadIdx.x & ~63u;
+    const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
+    for (uint64_t c = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; c < C.nchunks;
+         c += waves) {
+        uint32_t v;
+        uint64_t j0, j1;
+        bool multi;
+        chunk_range(C, c, v, j0, j1, multi);
+        const uint64_t cnt = pcnt[(uint64_t)v * kPairStride + lane];
+        const uint64_t mine = cnt >= 2 ? cnt : 0;
         uint64_t incl = mine;  // inclusive scan of the list lengths over the lanes
         for (int off = 1; off < 64; off <<= 1) {
             const uint64_t x = __shfl_up(incl, off);
             if ((int)lane >= off) incl += x;
         }
-        uint64_t at = node_off[v] + incl - mine;
-        const uint64_t first = at;
+        const uint64_t first = node_off[v] + incl - mine;  // the list's start
+        uint64_t at = first + (multi ? ccnt[c * kPairStride + lane] : 0);
+        bool have_single = false;
         uint32_t single = 0;
-        for (uint64_t j0 = b; j0 < e; j0 += 64) {
-            const bool in = j0 + lane < e;
-            const uint64_t mk = in ? mask[j0 + lane] : 0;
-            src[wbase + lane] = in ? (uint32_t)key[j0 + lane] : 0;
-            uint64_t bits = column_bits(mk, ell, lane);
+        for (uint64_t j = j0; j < j1; j += 64) {
+            const bool in = j + lane < j1;
+            const uint64_t mk = in ? C.mask[j + lane] : 0;
+            src[wbase + lane] = in ? (uint32_t)C.key[j + lane] : 0;
+            uint64_t bits = column_bits(mk, C.ell, lane);
             // the lanes' sources are read by other lanes of the same wave
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             while (bits) {
-                const int j = __ffsll((long long)bits) - 1;
+                const int b = __ffsll((long long)bits) - 1;
                 bits &= bits - 1;
-                const uint32_t u = src[wbase + j];
-                if (c >= 2) adj[at++] = u;
-                else single = u;
+                const uint32_t u = src[wbase + b];
+                if (cnt >= 2) {
+                    adj[at++] = u;
+                } else {
+                    single = u;
+                    have_single = true;
+                }
             }
             __builtin_amdgcn_wave_barrier();
         }
-        live[v * kPairStride + lane] =
-            c == 0 ? 0ull : c == 1 ? (kLiveOne | single) : ((first << kLiveCountBits) | c);
+        const bool head = c == C.choff[v];  // the node's first chunk
+        if (cnt == 1 ? have_single : head)
+            live[(uint64_t)v * kPairStride + lane] =
+                cnt == 0 ? 0ull : cnt == 1 ? (kLiveOne | single) : ((first << kLiveCountBits) | cnt);
     }
 }
 
@@ -212,25 +295,46 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     a.release(tmp);
     a.release(key);
     a.release(mask);
-    // in-edge runs per node
+    // in-edge runs and their chunks
     uint64_t *beg = a.alloc<uint64_t>(n), *end = a.alloc<uint64_t>(n);
     fill_u64(beg, 0, n, s);
     fill_u64(end, 0, n, s);
     k_in_runs<<<grid_for(m, 256, 65536), 256, 0, s>>>(skey, m, beg, end);
     SKIM_LAUNCH_CHECK();
-    // pass 1: counts; the room of every node's lists; scan over the nodes
+    uint32_t *nch = a.alloc<uint32_t>(n);
+    k_chunks_per_node<<<grid_for(n, 256, 65536), 256, 0, s>>>(beg, end, n, nch);
+    SKIM_LAUNCH_CHECK();
+    uint64_t *choff = a.alloc<uint64_t>((uint64_t)n + 1);
+    exclusive_scan_u32(nch, choff, n, a);
+    a.release(nch);
+    uint64_t nchunks = 0;
+    read_back(&nchunks, choff + n, sizeof nchunks, s);
+    uint32_t *chnode = a.alloc<uint32_t>(nchunks);
+    k_chunk_nodes<<<grid_for(n, 256, 65536), 256, 0, s>>>(choff, n, chnode);
+    SKIM_LAUNCH_CHECK();
+    const ChunkArgs C{skey, smask, beg, end, choff, chnode, nchunks, ell};
+    // 1. counts per chunk and per pair
+    uint32_t *ccnt = a.alloc<uint32_t>(nchunks * kPairStride);
+    uint32_t *pcnt = a.alloc<uint32_t>(npairs);
+    fill_u32(pcnt, 0, npairs, s);
+    const unsigned cgrid = grid_for(nchunks, 4, 65536);  // four waves (chunks) per block
+    {
+        LaunchTimer t("k_pair_count", s);
+        k_pair_count<<<cgrid, 256, 0, s>>>(C, ccnt, pcnt);
+    }
+    SKIM_LAUNCH_CHECK();
+    // 2. room per node, scan over the nodes
     uint32_t *room = a.alloc<uint32_t>(n);
     uint32_t *too_long = a.alloc<uint32_t>(1);
     fill_u32(too_long, 0, 1, s);
-    const unsigned wgrid = grid_for(n, 4, 65536);  // four waves (nodes) per block
-    {
-        LaunchTimer t("k_pair_count", s);
-        k_pair_count<<<wgrid, 256, 0, s>>>(smask, beg, end, n, ell, L.live, room, too_long);
-    }
+    k_pair_room<<<grid_for(n, 4, 65536), 256, 0, s>>>(pcnt, n, room, too_long);
     SKIM_LAUNCH_CHECK();
     uint64_t *node_off = a.alloc<uint64_t>((uint64_t)n + 1);
     exclusive_scan_u32(room, node_off, n, a);
     a.release(room);
+    // 3. chunk places within the hubs' lists
+    k_chunk_prefix<<<grid_for(n, 4, 65536), 256, 0, s>>>(choff, n, ccnt);
+    SKIM_LAUNCH_CHECK();
     uint64_t tot = 0;
     uint32_t bad = 0;
     read_back(&tot, node_off + n, sizeof tot, s);
@@ -241,16 +345,15 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     }
     L.nlive = tot;
     L.adj = a.alloc<uint32_t>(tot ? tot : 1);
+    // 4. sources and pair words
     {
         LaunchTimer t("k_pair_emit", s);
-        k_pair_emit<<<wgrid, 256, 0, s>>>(skey, smask, beg, end, node_off, n, ell, L.live, L.adj);
+        k_pair_emit<<<cgrid, 256, 0, s>>>(C, ccnt, pcnt, node_off, L.live, L.adj);
     }
     SKIM_LAUNCH_CHECK();
-    a.release(node_off);
-    a.release(beg);
-    a.release(end);
-    a.release(skey);
-    a.release(smask);
+    for (void *p : {(void *)node_off, (void *)beg, (void *)end, (void *)skey, (void *)smask,
+                    (void *)choff, (void *)chnode, (void *)ccnt, (void *)pcnt})
+        a.release(p);
     return L;
 }
 
