@@ -33,9 +33,11 @@
 //     unpruned pair receives every rank of its instance in the window, so
 //     the rule is exact whatever order the window's searches run in.  All
 //     searches of a window advance together, level by level: one
-//     whole-grid launch per level (small frontiers in batches of levels
-//     launched without reading their sizes back), and once the frontier
-//     fits in LDS the remaining levels inside one workgroup.  Visits are
+//     whole-grid launch per level (frontiers in batches of levels launched
+//     without reading their sizes back); once the frontier is small it is
+//     split over many workgroups that each run the remaining levels of their
+//     part in LDS, without waiting for each other (the window's result does
+//     not depend on the order of its visits).  Visits are
 //     deduplicated per source exactly: the first visitor of a pair in the
 //     window claims the pair's state word; later visitors go through a
 //     hash set keyed by (pair, source).  The same word counts the pair's
@@ -103,6 +105,8 @@ struct alignas(128) Ctl {
     char pad4[120];
     uint32_t flags;                   // overflow bits
     uint32_t level;                   // level reached by the tail kernel
+    char pad5[120];
+    unsigned long long budget;        // visits reserved by the workgroup tails (k_tails)
 };
 
 // ------------------------------------------------------- 2. rank windows
@@ -630,64 +634,56 @@ __global__ void k_pair_init(const uint64_t *live, uint64_t npairs, uint64_t *pre
     }
 }
 
-// ------------------------------------------- tail levels in one workgroup
-// Once a window's frontier is small, its remaining levels run inside one
-// workgroup: the frontier stays in LDS from level to level and levels are
-// separated by workgroup barriers, so no launch and no host round trip
-// stands between them.  The kernel hands the search back to the host (the
-// frontier in global memory, ctl->level = the level reached) when the
-// frontier outgrows LDS, the next level could outgrow the records, the hash
-// set (40% load) or the frontier arrays, a claim overflowed, or after
-// max_levels levels.
-constexpr uint32_t kTailCap = 1024;  // frontier entries held in LDS
-constexpr int kTailBlock = 1024;
-constexpr uint32_t kTailLevels = 4096;         // levels per launch at most
-constexpr uint64_t kTailRecords = 1ull << 20;  // record room the host adds before a launch
+constexpr uint64_t kTailRecords = 1ull << 20;  // record room the host adds before the tails
 
-struct TailShared {
-    uint64_t key[2][kTailCap];
-    uint64_t live[2][kTailCap];
-    uint32_t n[2];  // entries of each level (beyond kTailCap: in global memory)
+// ------------------------------------- tails in many independent workgroups
+// The last levels of a window, once its frontier is small, in many
+// workgroups that never wait for each other: the frontier is split between
+// them and each runs its own level-synchronous search over its part, its
+// frontier in LDS, until that part dies out.  A window's result does not
+// depend on the order of its visits (pruning reads only counts from before
+// the window, and every (pair, source) visit is claimed exactly once, on
+// the device), so workgroups at different levels stay exact.  A workgroup
+// hands its frontier back to global memory (appended to the next level's
+// array, which the host then continues level by level) when its next level
+// could outgrow its LDS frontier or the visits reserved by all tails could
+// outgrow the room for records or hash-set inserts that the host gave.
+// There is no inter-workgroup barrier: every workgroup leaves its loop on
+// its own.
+constexpr uint32_t kTailsCap = 512;    // frontier entries per workgroup (LDS)
+constexpr int kTailsBlock = 256;
+constexpr uint32_t kTailsGrid = 1024;  // workgroups that fit on the device at once (4 per CU)
+constexpr uint32_t kTailsPer = 16;     // entries per workgroup at the start, or more
+constexpr uint64_t kTailsMax = (uint64_t)kTailsGrid * 192;  // frontiers handed to the tails
+
+struct TailsShared {
+    uint64_t key[2][kTailsCap];
+    uint64_t live[2][kTailsCap];
+    uint32_t n[2];
     StageR R;
     uint32_t heavy[kHeavyCap];
     uint32_t nheavy;
-    uint32_t hashed;  // hash inserts of the current level
-    uint32_t spilled;  // records of the current level that bypassed the stage
-    unsigned long long work;  // live in-edges the current level scans
-    unsigned long long recs, hins;  // running totals of records and hash inserts
-    uint32_t stop;    // 1: leave the loop
-    uint32_t give;    // 1: the frontier goes back to global memory
+    uint32_t hashed;
+    uint32_t spilled;
+    unsigned long long work;
+    uint32_t dump;
+    unsigned long long rbase;
 };
 
-// A new frontier entry: in LDS while it fits, past that at the same index in
-// the next level's global array.
-__device__ __forceinline__ void tail_push(TailShared &T, uint32_t nxt, uint64_t key, uint64_t live,
-                                          uint64_t *gkey, uint64_t *glive, uint64_t cap,
-                                          uint32_t *flags) {
-    const uint32_t pos = stage_slots(&T.n[nxt]);
-    if (pos < kTailCap) {
-        T.key[nxt][pos] = key;
-        T.live[nxt][pos] = live;
-    } else if (pos < cap) {
-        gkey[pos] = key;
-        glive[pos] = live;
-    } else {
-        atomicOr(flags, kOvfSpill);
-    }
-}
-
-__device__ __forceinline__ void tail_visit(const WinArgs &A, TailShared &T, uint32_t nxt, uint32_t w,
-                                           uint32_t i, uint32_t src, uint64_t *gkey,
-                                           uint64_t *glive, uint32_t &scans, uint32_t &hashed,
-                                           uint32_t &visits) {
+__device__ __forceinline__ void tails_visit(const WinArgs &A, TailsShared &T, uint32_t nxt,
+                                            uint32_t w, uint32_t i, uint32_t src,
+                                            uint32_t &scans, uint32_t &hashed, uint32_t &visits) {
     const uint32_t q = w * kPairStride + i;
     ++scans;
     const bool want = wants_record(A, w);
     uint64_t live;
     if (claim(A, q, src, want, hashed, live) == 1) {
         ++visits;
-        if (live) tail_push(T, nxt, ((uint64_t)q << 32) | src, live, gkey, glive, A.front_cap,
-                            &A.ctl->flags);
+        if (live) {  // room: the level's visits were bounded by kTailsCap before it ran
+            const uint32_t pos = stage_slots(&T.n[nxt]);
+            T.key[nxt][pos] = ((uint64_t)q << 32) | src;
+            T.live[nxt][pos] = live;
+        }
         if (want) {
             const uint32_t pos = stage_slots(&T.R.n);
             if (pos < kStageR) {
@@ -702,43 +698,39 @@ __device__ __forceinline__ void tail_visit(const WinArgs &A, TailShared &T, uint
     }
 }
 
-// Levels L0, L0 + 1, ... of the current window; the frontier of level L0
-// (at most kTailCap entries; a larger one is left untouched) is in global
-// memory.
-__global__ void __launch_bounds__(kTailBlock) k_tail(WinArgs A, uint32_t L0, uint32_t max_levels) {
-    __shared__ TailShared T;
+// The frontier of level L (nin entries at fkey/flive[L & 1]) split over the
+// grid; entries handed back go to level L + 1's arrays, counted in
+// ctl->size[(L + 1) % 3] (zero at launch).  room: visits all tails may
+// reserve in total (bounded by the free records and hash-set room).
+__global__ void __launch_bounds__(kTailsBlock) k_tails(WinArgs A, uint32_t L, uint64_t nin,
+                                                       unsigned long long room) {
+    __shared__ TailsShared T;
     const uint32_t tid = threadIdx.x;
+    const uint64_t a = nin * blockIdx.x / gridDim.x, b = nin * (blockIdx.x + 1) / gridDim.x;
+    const uint32_t n0 = (uint32_t)(b - a);  // <= kTailsCap (the host sizes the grid)
     if (tid == 0) {
-        const unsigned long long f = A.ctl->size[16 * (L0 % 3)];
-        const uint32_t fl =
-            __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        T.stop = f == 0 || f > kTailCap || fl != 0;
-        T.n[0] = T.stop ? 0 : (uint32_t)f;
+        T.n[0] = n0;
         T.R.n = 0;
-        T.give = 0;
-        T.recs = A.ctl->records;  // the kernel is the only writer while it runs
-        T.hins = A.ctl->hinserts;
-        if (T.stop) A.ctl->level = L0;  // not taken: everything stays as it is
     }
-    __syncthreads();
-    if (T.stop) return;
-    for (uint32_t t = tid; t < T.n[0]; t += blockDim.x) {
-        T.key[0][t] = A.fkey[L0 & 1][t];
-        T.live[0][t] = A.flive[L0 & 1][t];
+    for (uint32_t t = tid; t < n0; t += blockDim.x) {
+        T.key[0][t] = A.fkey[L & 1][a + t];
+        T.live[0][t] = A.flive[L & 1][a + t];
     }
-    uint32_t scans = 0, visits = 0, L = L0, cur = 0;
-    unsigned long long recs = T.recs;  // records count, kept alike by every thread
-    for (uint32_t lv = 0;; ++lv) {
+    uint32_t scans = 0, visits = 0, cur = 0;
+    uint64_t *okey = A.fkey[(L + 1) & 1], *olive = A.flive[(L + 1) & 1];
+    unsigned long long *ocount = &A.ctl->size[16 * ((L + 1) % 3)];
+    for (;;) {
         if (tid == 0) {
             T.n[cur ^ 1] = 0;
             T.nheavy = 0;
             T.hashed = 0;
             T.spilled = 0;
             T.work = 0;
+            T.dump = 0;
         }
         __syncthreads();
         const uint32_t nc = T.n[cur];
-        if (T.stop || nc == 0) break;  // uniform: read after the barrier
+        if (nc == 0) break;  // uniform: read after the barrier
         {   // the level's live in-edges bound its visits, records and inserts
             unsigned long long wk = 0;
             for (uint32_t t = tid; t < nc; t += blockDim.x) {
@@ -750,23 +742,36 @@ __global__ void __launch_bounds__(kTailBlock) k_tail(WinArgs A, uint32_t L0, uin
         __syncthreads();
         if (tid == 0) {
             const unsigned long long W = T.work;
-            if (lv >= max_levels || recs + W > A.rec_cap ||
-                5 * (T.hins + W) > 2 * (1ull << A.logcap) || W > A.front_cap) {
-                T.stop = 1;
-                T.give = 1;
+            const uint32_t fl =
+                __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (fl || W > kTailsCap) {
+                T.dump = 1;
+            } else if (atomicAdd(&A.ctl->budget, W) + W > room) {
+                T.dump = 1;  // the reservation stays: it only makes later tails stop sooner
             }
         }
         __syncthreads();
-        if (T.stop) break;
+        if (T.dump) {  // hand the level's entries back to global memory
+            if (tid == 0) T.rbase = atomicAdd(ocount, (unsigned long long)nc);
+            __syncthreads();
+            const unsigned long long base = T.rbase;
+            if (tid == 0 && base + nc > A.front_cap) atomicOr(&A.ctl->flags, kOvfSpill);
+            for (uint32_t t = tid; t < nc; t += blockDim.x) {
+                if (base + t < A.front_cap) {
+                    okey[base + t] = T.key[cur][t];
+                    olive[base + t] = T.live[cur][t];
+                }
+            }
+            break;
+        }
         const uint32_t nxt = cur ^ 1;
-        uint64_t *gkey = A.fkey[(L + 1) & 1], *glive = A.flive[(L + 1) & 1];
         uint32_t hashed = 0;
         for (uint32_t t = tid; t < nc; t += blockDim.x) {
             const uint64_t it = T.key[cur][t], live = T.live[cur][t];
             const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
             const uint32_t src = (uint32_t)it;
             if (live & kLiveOne) {
-                tail_visit(A, T, nxt, (uint32_t)live, i, src, gkey, glive, scans, hashed, visits);
+                tails_visit(A, T, nxt, (uint32_t)live, i, src, scans, hashed, visits);
                 continue;
             }
             const uint32_t cnt = live_count(live);
@@ -779,7 +784,7 @@ __global__ void __launch_bounds__(kTailBlock) k_tail(WinArgs A, uint32_t L0, uin
             }
             const uint64_t e0 = live >> kLiveCountBits;
             for (uint64_t e = e0; e < e0 + cnt; ++e)
-                tail_visit(A, T, nxt, A.lsrc[e], i, src, gkey, glive, scans, hashed, visits);
+                tails_visit(A, T, nxt, A.lsrc[e], i, src, scans, hashed, visits);
         }
         __syncthreads();
         const uint32_t nh = T.nheavy < kHeavyCap ? T.nheavy : kHeavyCap;
@@ -790,54 +795,35 @@ __global__ void __launch_bounds__(kTailBlock) k_tail(WinArgs A, uint32_t L0, uin
             const uint32_t src = (uint32_t)it;
             const uint64_t e0 = live >> kLiveCountBits, e1 = e0 + live_count(live);
             for (uint64_t e = e0 + tid; e < e1; e += blockDim.x)
-                tail_visit(A, T, nxt, A.lsrc[e], i, src, gkey, glive, scans, hashed, visits);
+                tails_visit(A, T, nxt, A.lsrc[e], i, src, scans, hashed, visits);
         }
         if (hashed) atomicAdd(&T.hashed, hashed);
-        // records of this level to global memory; the flags are read while
-        // they are written
-        uint32_t fl = 0;
-        if (tid == 0) fl = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __syncthreads();
+        // the level's staged records to global memory, one reservation
         const uint32_t mr = T.R.n < kStageR ? T.R.n : kStageR;
-        const uint32_t sp = T.spilled, hs = T.hashed, nn = T.n[nxt];
-        __syncthreads();  // every thread has read the level's counters
-        // The kernel is the only writer of the records count, so the stage
-        // goes right after the records this level spilled past it.
-        const unsigned long long rb = recs + sp;
+        if (tid == 0) {
+            T.rbase = mr ? atomicAdd(&A.ctl->records, (unsigned long long)mr) : 0;
+            if (mr && T.rbase + mr > A.rec_cap) atomicOr(&A.ctl->flags, kOvfRecords);
+            if (T.hashed) atomicAdd(&A.ctl->hinserts, (unsigned long long)T.hashed);
+        }
+        __syncthreads();
+        const unsigned long long rb = T.rbase;
         for (uint32_t j = tid; j < mr; j += blockDim.x)
             if (rb + j < A.rec_cap) A.rec[rb + j] = T.R.buf[j];
-        recs += mr + sp;
-        if (tid == 0) {
-            if (mr) atomicAdd(&A.ctl->records, (unsigned long long)mr);
-            if (mr && rb + mr > A.rec_cap) atomicOr(&A.ctl->flags, kOvfRecords);
-            T.R.n = 0;
-            // the level is done: decide whether to go on
-            if (hs) atomicAdd(&A.ctl->hinserts, (unsigned long long)hs);
-            T.hins += hs;
-            if (fl || nn == 0) {
-                T.stop = 1;
-                T.give = 0;
-            } else if (nn > kTailCap) {
-                T.stop = 1;
-                T.give = 1;
-            }
-        }
-        L += 1;
-        cur ^= 1;
+        __syncthreads();
+        if (tid == 0) T.R.n = 0;
+        cur = nxt;
     }
-    // hand the frontier of level L back (its entries past kTailCap are there already)
-    const uint32_t nn = T.n[cur];
-    if (T.give)
-        for (uint32_t t = tid; t < nn && t < kTailCap; t += blockDim.x) {
-            A.fkey[L & 1][t] = T.key[cur][t];
-            A.flive[L & 1][t] = T.live[cur][t];
-        }
-    if (tid == 0) {
-        A.ctl->size[16 * (L % 3)] = T.give ? nn : 0;
-        A.ctl->size[16 * ((L + 1) % 3)] = 0;
-        A.ctl->level = L;
-    }
-    block_add3(T.R.buf, &A.ctl->scans, scans, &A.ctl->visits, visits, nullptr, 0);
+    block_add3((uint64_t *)T.R.buf, &A.ctl->scans, scans, &A.ctl->visits, visits, nullptr, 0);
+}
+
+// Before the tails at level L: the counter of the entries they hand back
+// (level L + 1) and that of the level after it (L + 2, which the next
+// expansion appends to; it still holds level L - 1's size) start at zero.
+__global__ void k_tails_begin(Ctl *ctl, uint32_t L) {
+    ctl->size[16 * ((L + 1) % 3)] = 0;
+    ctl->size[16 * ((L + 2) % 3)] = 0;
+    ctl->budget = 0;
 }
 
 // Start of a window (or of its redo): clear the per-window fields and set
@@ -1198,14 +1184,9 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Ra
             uint32_t L = 0;
             uint32_t overflow = 0;
             uint64_t f_prev = 0;
-            uint32_t tail_from = ~0u, tail_stuck = ~0u;  // level the tail kernel started at
+            bool tails_ok = true;  // false right after the tails handed entries back
             for (;;) {
                 read_back(&h, ctl, sizeof h, s);
-                if (tail_from != ~0u) {
-                    if (h.level == tail_from) tail_stuck = tail_from;  // it made no progress
-                    L = h.level;
-                    tail_from = ~0u;
-                }
                 if (h.flags) {
                     overflow = h.flags;
                     if (debug)
@@ -1248,19 +1229,48 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Ra
                         std::fprintf(stderr, "skim window %u: hash set grown to %llu\n", w,
                                      (unsigned long long)ns);
                 }
-                if (f <= kTailCap && L != tail_stuck) {
-                    // the rest of the window in one workgroup, with room for
-                    // the records of many levels
-                    grow_u64(rec, rec_cap, h.records, h.records + kTailRecords);
-                    const WinArgs WA = args();
-                    LaunchTimer t("k_tail", s);
-                    k_tail<<<1, kTailBlock, 0, s>>>(WA, L, kTailLevels);
-                    SKIM_LAUNCH_CHECK();
-                    tail_from = L;
-                    f_prev = 0;
-                    continue;
+                const bool after_tails = !tails_ok;
+                if (f <= kTailsMax && tails_ok) {
+                    // the rest of the window in independent workgroups (about
+                    // kTailsPer entries each, as many as fit on the device at
+                    // once), with room for the records of many levels; what
+                    // they hand back continues here as level L + 1
+                    const uint32_t G = (uint32_t)std::min<uint64_t>(
+                        kTailsGrid, std::max<uint64_t>(1, (f + kTailsPer - 1) / kTailsPer));
+                    const uint64_t per = (f + G - 1) / G;
+                    if (per <= kTailsCap) {
+                        grow_u64(rec, rec_cap, h.records,
+                                 h.records + std::max<uint64_t>(kTailRecords, 4 * f));
+                        {
+                            uint64_t c[2] = {front_cap, front_cap};
+                            grow_u64(fkey[(L + 1) & 1], c[0], 0, f);
+                            grow_u64(flive[(L + 1) & 1], c[1], 0, f);
+                            front_cap = std::min(front_cap, std::min(c[0], c[1]));
+                        }
+                        const uint64_t hroom = 2 * hsize / 5 > h.hinserts
+                                                   ? 2 * hsize / 5 - h.hinserts : 0;
+                        const uint64_t room = std::min<uint64_t>(rec_cap - h.records, hroom);
+                        k_tails_begin<<<1, 1, 0, s>>>(ctl, L);
+                        SKIM_LAUNCH_CHECK();
+                        const WinArgs WA = args();
+                        LaunchTimer t("k_tails", s);
+                        k_tails<<<G, kTailsBlock, 0, s>>>(WA, L, f, room);
+                        SKIM_LAUNCH_CHECK();
+                        ++L;
+                        tails_ok = false;  // at least one level by k_expand before the next
+                        f_prev = 0;
+                        continue;
+                    }
                 }
-                int batch = f > kSmall ? sh.large_batch : sh.small_batch;
+                tails_ok = true;
+                // what the tails handed back grows past their LDS: one level
+                // here, then back to the tails; a frontier a little above
+                // what the tails take goes two levels at a time, so that it
+                // reaches them without a long blind batch
+                int batch = after_tails            ? 1
+                            : f <= 4 * kTailsMax   ? 2
+                            : f > kSmall           ? sh.large_batch
+                                                   : sh.small_batch;
                 if (sh.sort_frontier && f > sh.sort_frontier) {
                     // the frontier in pair order: live-list bounds and entries
                     // are then read nearly sequentially
