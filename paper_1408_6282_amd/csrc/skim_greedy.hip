@@ -74,16 +74,22 @@ struct SkArgs {
     uint64_t pool_cap;
     uint32_t *bcnt;         // [(n + 1) / 2] per-batch increment counters, packed
     uint32_t *queues;       // [kSkimBlock * n]
+    uint32_t *vis;          // [kSkimBlock * vis_words] per-thread visited bitmaps, kept zero
+    uint32_t vis_words;     // ceil(n / 32)
     SkCtl *ctl;
     uint64_t seed;
     uint64_t *rec_tau;      // [n] per selected seed: rank that filled its sketch
     uint32_t *rec_second;   // [n] per selected seed: second largest sketch
 };
 
-__device__ __forceinline__ bool in_queue(const uint32_t *Q, uint32_t cnt, uint32_t w) {
-    for (uint32_t j = 0; j < cnt; ++j)
-        if (Q[j] == w) return true;
-    return false;
+// A thread's reverse search marks the nodes it has queued in its own bitmap
+// (test and set: one load and at most one store per scanned edge, instead of
+// a scan of the queue) and clears the words it touched when it is done.
+__device__ __forceinline__ bool mark_new(uint32_t *V, uint32_t w) {
+    const uint32_t bit = 1u << (w & 31u), word = V[w >> 5];
+    if (word & bit) return false;
+    V[w >> 5] = word | bit;
+    return true;
 }
 
 // size[] and the batch counters are 16-bit halves of 32-bit words (sizes
@@ -146,6 +152,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             s_bcnt[w] = 0;
         }
     uint32_t *Q = A.queues + (uint64_t)tid * n;
+    uint32_t *V = A.vis + (uint64_t)tid * A.vis_words;
     if (tid == 0) {
         s_cursor = A.ctl->cursor;
         s_pool = A.ctl->pool_used;
@@ -171,14 +178,16 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 if (!ld(A.covered + p)) {
                     const uint32_t i = p % kPairStride;
                     Q[0] = p / kPairStride;
+                    mark_new(V, Q[0]);
                     cnt = 1;
                     for (uint32_t head = 0; head < cnt; ++head) {
                         const uint32_t q = Q[head] * kPairStride + i;
                         for (uint64_t e = A.rptr[q]; e < A.rptr[q + 1]; ++e) {
                             const uint32_t w = A.radj[e];
-                            if (!in_queue(Q, cnt, w)) Q[cnt++] = w;
+                            if (mark_new(V, w)) Q[cnt++] = w;
                         }
                     }
+                    for (uint32_t j = 0; j < cnt; ++j) V[Q[j] >> 5] = 0u;  // back to zero
                 }
             }
             // Does some node reach k within the first T pairs?  Sizes are
@@ -580,8 +589,8 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
     // sizes and batch counters are 16-bit halves of words
     SKIM_REQUIRE(k >= 2 && k <= 65535, "k must be in [2, 65535]");
     SKIM_REQUIRE(g != nullptr, "graph is NULL");
-    if ((uint64_t)g->n * kSkimBlock * 4 > (1ull << 30)) {
-        set_error("skim_greedy supports n <= 262144 (per-thread search queues)");
+    if ((uint64_t)g->n > (1ull << 22)) {
+        set_error("skim_greedy supports n <= 4194304 (per-thread search queues of n entries)");
         throw Fail{SKIM_EUNSUPPORTED};
     }
     auto st = std::make_unique<skim_greedy_state>();
@@ -629,6 +638,9 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
     A.idx_cnt = M.alloc<uint32_t>(npairs);
     A.bcnt = M.alloc<uint32_t>((n + 1) / 2);
     A.queues = M.alloc<uint32_t>((uint64_t)kSkimBlock * n);
+    A.vis_words = (n + 31) / 32;
+    A.vis = M.alloc<uint32_t>((uint64_t)kSkimBlock * A.vis_words);
+    fill_u32(A.vis, 0, (uint64_t)kSkimBlock * A.vis_words, s);
     A.pool_cap = std::max<uint64_t>(1ull << 16, 2 * A.nsrc);
     A.pool = M.alloc<uint32_t>(A.pool_cap);
     A.ctl = M.alloc<SkCtl>(1);

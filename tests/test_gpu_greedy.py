@@ -96,3 +96,25 @@ def test_counters_outside_lds(oracle_lib):
     seeds, gains, _, _ = gpu_greedy(g, 8, 8, 3, [5, 7])
     ws, wg, _ = oracle_lib.skim(g, 3, 8, 8, 12)
     assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+
+
+@pytest.mark.slow
+def test_chung_lu_1m_equals_oracle():
+    # SKIM on the 1M-node weighted-cascade graph (l = k = 64), 50 seeds in two
+    # resumed calls, against the oracle's sequence stored by
+    # tests/golden/make_skim.py (single-threaded Algorithm 1)
+    import json
+    import os
+    from workloads.configs import graph_sha256, make_config, make_graph
+    from gpu_util import log
+    cfg = make_config("chung-lu-1m")
+    g = make_graph(cfg)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "chung_lu_1m_skim.json")
+    with open(path) as f:
+        gold = json.load(f)
+    assert gold["graph_sha256"] == graph_sha256(g)
+    log("gpu SKIM on chung-lu-1m")
+    seeds, gains, _, _ = gpu_greedy(g, cfg["ell"], cfg["k"], cfg["seed"], [20, 30])
+    assert seeds.tolist() == gold["seeds"]
+    assert gains.tolist() == gold["gain_pairs"]
