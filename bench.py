@@ -28,7 +28,11 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "live-edge traversals/s (sketch build); batched vs plain queries/s, p99 latency"
-DOMINANT = "k_expand"
+# The dominant work: the pruned reverse searches, run by three kernels (the
+# seed level of each window, whole-grid levels, and the workgroup tails);
+# they are timed and counted together.
+SEARCH_KERNELS = ["k_seed_window", "k_expand", "k_tails"]
+DOMINANT = "search"
 # Sources of the dominant kernel: measured HBM traffic is reported only while
 # these are unchanged since the counters were taken.
 DOMINANT_SOURCES = ["paper_1408_6282_amd/csrc/skim_build.hip",
@@ -130,18 +134,141 @@ def visit_model_bytes(cnt):
     return cnt["n_ins"] * (16 + 16 + 16 + 8) + cnt["w_live"] * (4 + 16)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads(max_threads=16):
+    return max(1, min(max_threads, os.cpu_count() or 1))
+
+
 def cpu_baseline(g, cfg, max_threads=16):
     """The oracle's Algorithm 2 on the same workload (all l instances, one
     instance per thread at a time), on at most 16 host threads."""
     import oracle
-    cores = max(1, min(max_threads, os.cpu_count() or 1))
+    cores = host_threads(max_threads)
     t = time.perf_counter()
     _, _, cnt = oracle.build_alg2(g, cfg["seed"], cfg["ell"], cfg["k"], threads=cores)
     dt = time.perf_counter() - t
     return {"value": cnt["w_live"] / dt, "unit": "live-edge traversals/s",
             "cores": min(cores, cfg["ell"]), "kind": "oracle", "seconds": round(dt, 3),
+            "cpu": cpu_model(),
             "sample": f"the whole workload: Algorithm 2 over all {cfg['ell']} instances "
                       f"(k={cfg['k']}, seed {cfg['seed']}); W_live = {cnt['w_live']}"}
+
+
+def oracle_times(max_threads=16):
+    """The oracle on the query and SKIM workloads, timed on this host: the
+    1M lognormal union queries of batched-query (split over the host threads;
+    the C oracle releases the interpreter lock) and SKIM's 200 seeds on
+    served-skim (one thread: Algorithm 1 is sequential)."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    from workloads import lognormal_query_sets
+    from workloads.configs import make_config, make_graph
+    cores = host_threads(max_threads)
+    out = {"cpu": cpu_model(), "threads": cores}
+    cfg = make_config("batched-query")
+    g = make_graph(cfg)
+    R, S, _ = oracle.build_alg2(g, cfg["seed"], cfg["ell"], cfg["k"], threads=cores)
+    off, nodes = lognormal_query_sets(cfg["Q"], g.n, cfg["qseed"])
+    Q = cfg["Q"]
+    cuts = np.linspace(0, Q, cores + 1).astype(np.int64)
+
+    def part(j):
+        a, b = cuts[j], cuts[j + 1]
+        return oracle.union_query(R, S, cfg["k"], cfg["ell"], off[a:b + 1] - off[a],
+                                  nodes[off[a]:off[b]])
+    t = time.perf_counter()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(part, range(cores)))
+    dt = time.perf_counter() - t
+    out["batched_query"] = {"queries": Q, "seconds": round(dt, 3), "queries_per_s": Q / dt,
+                            "threads": cores}
+    c5 = make_config("served-skim")
+    g5 = make_graph(c5)
+    t = time.perf_counter()
+    oracle.skim(g5, c5["seed"], c5["ell"], c5["k"], c5["s"])
+    dt = time.perf_counter() - t
+    out["served_skim"] = {"seeds": c5["s"], "seconds": round(dt, 3), "threads": 1}
+    return out
+
+
+def bench_rmat(torch, sk, steps=2):
+    """The rmat-24 build (scale 24, trivalency, l = 64, k = 32): time per
+    build, live-edge traversals/s from the oracle's W_live, the whole-build
+    floor, parity of the timed output against the oracle's stored digests,
+    and the oracle's own time as stored with its host and threads."""
+    from workloads.configs import make_config, make_graph
+    cfg = make_config("rmat-24")
+    log("generating rmat-24")
+    g = make_graph(cfg)
+    gold = golden_record("rmat_24")
+    if gold is None or gold["graph_sha256"] != graph_digest(g):
+        return {"skipped": "no stored oracle result for this graph"}
+    cnt = gold["counters"]
+    dev = torch.device("cuda:0")
+    G = sk.DeviceGraph.from_host(g, dev)
+    n, ell, k, seed = g.n, cfg["ell"], cfg["k"], cfg["seed"]
+    ranks = torch.empty(n * k, dtype=torch.int64, device=dev)
+    size = torch.empty(n, dtype=torch.int32, device=dev)
+    est = torch.empty(n, dtype=torch.float64, device=dev)
+    log("rmat-24 warm-up build")
+    work = sk.skim_build_sketches(G, ell, k, seed, ranks, size, est)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(steps):
+        work = sk.skim_build_sketches(G, ell, k, seed, ranks, size, est)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t) / steps
+    log(f"rmat-24: {sec * 1e3:.1f} ms per build; {work}")
+    floor = algorithmic_bytes_build(cnt, n, k)
+    out = {"workload": "rmat-24", "n": n, "m": g.m, "ell": ell, "k": k, "steps": steps,
+           "ms_per_build": sec * 1e3, "live_edge_traversals_per_s": cnt["w_live"] / sec,
+           "oracle_counters": cnt, "device_work": work,
+           "build_floor_bytes": floor, "build_floor_ms": floor / (HBM_PEAK_GBS * 1e9) * 1e3,
+           "build_floor_over_measured": floor / (HBM_PEAK_GBS * 1e9) / sec,
+           "parity": output_parity("rmat-24", g, cfg, ranks, size, est),
+           "oracle_stored": {"seconds": gold.get("oracle_seconds"),
+                             "threads": gold.get("oracle_threads"), "cpu": gold.get("oracle_cpu"),
+                             "live_edge_traversals_per_s":
+                                 cnt["w_live"] / gold["oracle_seconds"]
+                                 if gold.get("oracle_seconds") else None}}
+    del G, ranks, size, est
+    torch.cuda.empty_cache()
+    return out
+
+
+def golden_record(tag):
+    path = os.path.join(ROOT, "tests", "golden", f"{tag}_counters.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def output_parity(tag, g, cfg, ranks, size, est):
+    """The build's outputs against the oracle's stored result digests (SHA-256
+    of the sketches, sizes and estimates that tests/golden/make_counters.py
+    wrote from the oracle alone): True/False, or None when no digest matches
+    this graph and configuration."""
+    import hashlib
+    d = golden_record(tag.replace("-", "_"))
+    if (d is None or "digests" not in d or d["graph_sha256"] != graph_digest(g)
+            or d["ell"] != cfg["ell"] or d["k"] != cfg["k"] or d["seed"] != cfg["seed"]):
+        return None
+    dig = lambda t: hashlib.sha256(t.cpu().numpy().view(np.uint8)).hexdigest()  # noqa: E731
+    ok = dig(ranks) == d["digests"]["ranks_sha256"] and dig(size) == d["digests"]["size_sha256"]
+    if est is not None:
+        ok = ok and dig(est) == d["digests"]["est_sha256"]
+    return bool(ok)
 
 
 def bench_build(args, torch, sk, g, cfg):
@@ -176,10 +303,12 @@ def bench_build(args, torch, sk, g, cfg):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     log(f"timed {args.steps} steps: {(t1 - t0) * 1e3 / args.steps:.3f} ms/step; {work}")
+    parity = output_parity(args.workload, g, cfg, ranks, size, est)
+    log(f"parity of the last timed build: {parity}")
     # kernel pass: every launch of the dominant kernel bracketed by HIP events
     # on the stream it is launched on
     sk.skim_timing_reset()
-    sk.skim_timing_enable(DOMINANT)
+    sk.skim_timing_enable(",".join(SEARCH_KERNELS))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     for s in range(args.steps):
@@ -187,9 +316,15 @@ def bench_build(args, torch, sk, g, cfg):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     sk.skim_timing_enable(None)
-    kms, klaunch = sk.skim_timing_read(DOMINANT)
+    kms, klaunch, per_kernel = 0.0, 0, {}
+    for name in SEARCH_KERNELS:
+        ms_, n_ = sk.skim_timing_read(name)
+        per_kernel[name] = {"ms_per_step": ms_ / args.steps, "launches_per_step": n_ / args.steps}
+        kms += ms_
+        klaunch += n_
     log(f"kernel pass {args.steps} steps: {(t3 - t2) * 1e3 / args.steps:.3f} ms/step")
-    return (t1 - t0) / args.steps, work, kms, klaunch, (t3 - t2) / args.steps, tuning
+    return (t1 - t0) / args.steps, work, kms, klaunch, (t3 - t2) / args.steps, tuning, parity, \
+        per_kernel
 
 
 def bench_queries(torch, sk, reps=5, plain_q=20000):
@@ -295,6 +430,39 @@ def bench_skim_20k(torch, sk, s=50):
     t = time.perf_counter() - t
     return {"n": n, "m": g.m, "ell": 64, "k": 64, "seeds": s, "ms": t * 1e3,
             "influence": float(gains.sum().item()) / 64}
+
+
+def bench_skim_1m(torch, sk, g, cfg, reps=3):
+    """SKIM on the 1M-node weighted-cascade graph (l = k = 64), as many seeds
+    as the oracle's stored run, one call with the state built inside; the
+    sequence is compared with the oracle's and the oracle's single-thread time
+    is reported beside it."""
+    path = os.path.join(ROOT, "tests", "golden", "chung_lu_1m_skim.json")
+    with open(path) as f:
+        gold = json.load(f)
+    from workloads.configs import graph_sha256
+    if gold["graph_sha256"] != graph_sha256(g):
+        return {"skipped": "stored oracle sequence is for another graph"}
+    dev = torch.device("cuda:0")
+    G = sk.DeviceGraph.from_host(g, dev)
+    s = gold["s"]
+    seeds = torch.empty(s, dtype=torch.int32, device=dev)
+    gains = torch.empty(s, dtype=torch.int64, device=dev)
+    times = []
+    for _ in range(reps + 1):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sk.skim_greedy(G, cfg["ell"], cfg["k"], cfg["seed"], s, seeds, gains)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    t = float(np.median(times[1:]))
+    parity = (seeds.cpu().numpy().view(np.uint32).tolist() == gold["seeds"]
+              and gains.cpu().numpy().view(np.uint64).tolist() == gold["gain_pairs"])
+    return {"workload": "chung-lu-1m", "n": g.n, "m": g.m, "ell": cfg["ell"], "k": cfg["k"],
+            "seeds": s, "ms": t * 1e3, "parity": parity,
+            "influence": float(gains.sum().item()) / cfg["ell"],
+            "oracle_seconds": gold["oracle_seconds"], "oracle_threads": gold["oracle_threads"],
+            "oracle_cpu": gold["oracle_cpu"], "oracle_over_gpu": gold["oracle_seconds"] / t}
 
 
 def bench_exact_greedy(torch, sk, G, cfg, skim_gains, s=50):
@@ -529,12 +697,21 @@ def bench_ic_queries(torch, sk, pos, n, k, Q=1_000_000):
     return out
 
 
-def bench_serving(torch, sk, duration=2.0):
-    """Open-loop Poisson stream of union queries against resident sketches,
-    with incremental SKIM requests overlapping on the device."""
+def bench_serving(torch, sk, duration=None, sweep_queries=300_000):
+    """Served queries on the served-skim sketches (sets of U[1, 512] nodes):
+
+    * the configured open-loop Poisson stream (50k queries/s for 10 s) with
+      four incremental 50-seed SKIM requests overlapping on the device:
+      p50/p99 latency and completed queries/s;
+    * a capacity sweep: open-loop streams offered above the plain path's
+      rate (0.5M/s and 2M/s) and every request at t = 0 (saturation),
+      completed queries/s, p50/p99 and admission retries each;
+    * the plain path (one launch per query) on the same kind of sets, so that
+      served capacity is compared with it at identical estimates."""
     from workloads import uniform_query_sets, poisson_arrivals
     from workloads.configs import make_config, make_graph
     cfg = make_config("served-skim")
+    duration = cfg["duration"] if duration is None else duration
     g = make_graph(cfg)
     dev = torch.device("cuda:0")
     G = sk.DeviceGraph.from_host(g, dev)
@@ -542,6 +719,14 @@ def bench_serving(torch, sk, duration=2.0):
     ranks = torch.empty(n * k, dtype=torch.int64, device=dev)
     size = torch.empty(n, dtype=torch.int32, device=dev)
     sk.skim_build_sketches(G, ell, k, cfg["seed"], ranks, size)
+
+    def reference(off, nodes):
+        qo = torch.from_numpy(off.view(np.int64)).to(dev)
+        qn = torch.from_numpy(nodes.view(np.int32)).to(dev)
+        ref = torch.empty(off.size - 1, dtype=torch.float64, device=dev)
+        sk.skim_query_batch(ranks, size, n, k, ell, qo, qn, ref)
+        return ref.cpu().numpy()
+
     arr = poisson_arrivals(cfg["rate"], duration, cfg["qseed"])
     off, nodes = uniform_query_sets(arr.size, n, cfg["qseed"] + 1, 1, 512)
     srv = sk.Server(ranks, size, n, k, ell, budget_bytes=64 << 20, max_batch=4096, streams=4)
@@ -561,18 +746,62 @@ def bench_serving(torch, sk, duration=2.0):
                 time.sleep(0.001)
     finally:
         srv.close()
-    # every served result equals the batch call's result for the same set
-    qo = torch.from_numpy(off.view(np.int64)).to(dev)
-    qn = torch.from_numpy(nodes.view(np.int32)).to(dev)
-    ref = torch.empty(arr.size, dtype=torch.float64, device=dev)
-    sk.skim_query_batch(ranks, size, n, k, ell, qo, qn, ref)
-    same = bool(np.array_equal(ref.cpu().numpy(), est))
-    return {"workload": "served-skim", "rate_per_s": cfg["rate"], "duration_s": duration,
-            "queries": int(arr.size), "completed_queries_per_s": arr.size / wall,
-            "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
-            "admission_retries": retries, "skim_requests": len(tickets),
-            "skim_request_latency_ms": [round(x / 1e3, 3) for x in greedy_lat],
-            "identical_to_batch": same}
+    same = bool(np.array_equal(reference(off, nodes), est))
+    out = {"workload": "served-skim", "rate_per_s": cfg["rate"], "duration_s": duration,
+           "queries": int(arr.size), "completed_queries_per_s": arr.size / wall,
+           "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+           "admission_retries": retries, "skim_requests": len(tickets),
+           "skim_request_latency_ms": [round(x / 1e3, 3) for x in greedy_lat],
+           "identical_to_batch": same}
+    del off, nodes, est, lat
+
+    # the plain path on U[1, 512] sets: one launch per query
+    poff, pnodes = uniform_query_sets(20_000, n, cfg["qseed"] + 2, 1, 512)
+    qo = torch.from_numpy(poff.view(np.int64)).to(dev)
+    qn = torch.from_numpy(pnodes.view(np.int32)).to(dev)
+    pest = torch.empty(poff.size - 1, dtype=torch.float64, device=dev)
+    sk.skim_query_batch(ranks, size, n, k, ell, qo, qn, pest, mode=1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sk.skim_query_batch(ranks, size, n, k, ell, qo, qn, pest, mode=1)
+    torch.cuda.synchronize()
+    plain = (poff.size - 1) / (time.perf_counter() - t)
+    plain_same = bool(np.array_equal(pest.cpu().numpy(), reference(poff, pnodes)))
+    out["plain_queries_per_s"] = plain
+    out["plain_identical_to_batch"] = plain_same
+
+    # capacity: offered loads above the plain rate, then saturation
+    sweep = []
+    soff, snodes = uniform_query_sets(sweep_queries, n, cfg["qseed"] + 3, 1, 512)
+    want = reference(soff, snodes)
+    for rate in (500_000.0, 2_000_000.0, None):
+        if rate is None:
+            a = np.zeros(sweep_queries)
+        else:
+            a = np.cumsum(np.random.default_rng(cfg["qseed"] + 4).exponential(1.0 / rate,
+                                                                              sweep_queries))
+        srv = sk.Server(ranks, size, n, k, ell, budget_bytes=256 << 20, max_batch=8192,
+                        streams=4)
+        try:
+            t = time.perf_counter()
+            e, st, lt, rt = srv.replay(soff, snodes, a)
+            wall = time.perf_counter() - t
+        finally:
+            srv.close()
+        ok = bool(np.array_equal(e, want) and (st == 0).all())
+        sweep.append({"offered_per_s": rate if rate is not None else "all at t=0",
+                      "completed_queries_per_s": sweep_queries / wall,
+                      "p50_us": float(np.percentile(lt, 50)),
+                      "p99_us": float(np.percentile(lt, 99)), "admission_retries": rt,
+                      "identical_to_batch": ok})
+        log(f"serving sweep {sweep[-1]}")
+        if not ok:
+            break
+    out["capacity_sweep"] = {"queries_per_point": sweep_queries, "points": sweep}
+    best = max(p["completed_queries_per_s"] for p in sweep)
+    out["served_capacity_queries_per_s"] = best
+    out["served_over_plain"] = best / plain
+    return out
 
 
 def main():
@@ -583,6 +812,7 @@ def main():
     ap.add_argument("--workload", default="chung-lu-1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="build only (no query/SKIM legs)")
+    ap.add_argument("--no-rmat", action="store_true", help="skip the rmat-24 build leg")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the build with the default launch shapes (no autotuning)")
     ap.add_argument("--tune-cache", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -613,7 +843,8 @@ def main():
     cnt = oracle_counters(args.workload, g, cfg)
     log(f"oracle counters {cnt}")
 
-    sec, work, kms, klaunch, sec_events, tuning = bench_build(args, torch, sk, g, cfg)
+    sec, work, kms, klaunch, sec_events, tuning, parity, per_kernel = bench_build(args, torch, sk,
+                                                                                  g, cfg)
     value = cnt["w_live"] / sec
     alg_bytes = algorithmic_bytes_search(cnt)
     floor = algorithmic_bytes_build(cnt, g.n, cfg["k"])
@@ -625,7 +856,8 @@ def main():
         per_build = measured_traffic(args.workload)
         # per launch like `achieved`: this run's launches share the build's bytes
         traffic = None if per_build is None else per_build * args.steps / klaunch
-        roof = {"bound": "hbm", "kernel": DOMINANT, "achieved": achieved, "peak": HBM_PEAK_GBS,
+        roof = {"bound": "hbm", "kernel": DOMINANT, "kernels": per_kernel,
+                "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "launches_per_step": klaunch / args.steps, "avg_launch_us": avg_s * 1e6,
                 "kernel_ms_per_step": kms / args.steps,
@@ -645,6 +877,9 @@ def main():
                    "n": g.n, "m": g.m, "ell": cfg["ell"], "k": cfg["k"], "seed": cfg["seed"],
                    "probabilities": "weighted cascade 1/indeg(head)",
                    "parallelism": "single GPU"},
+        "parity": parity,
+        "parity_check": "SHA-256 of the last timed build's sketches, sizes and estimates against "
+                        "the oracle's stored digests (tests/golden)",
         "oracle_counters": cnt, "device_work": work, "roofline": roof,
         "build_params": sk.skim_get_build_params(), "autotune": tuning,
     }
@@ -653,6 +888,9 @@ def main():
         out["queries"] = bench_queries(torch, sk)
         log("skim")
         out["skim"] = bench_skim(torch, sk)
+        if args.workload == "chung-lu-1m":
+            log("skim on chung-lu-1m")
+            out["skim"]["chung_lu_1m_wc"] = bench_skim_1m(torch, sk, g, cfg)
         log("oracle quality")
         out["oracle_quality"] = bench_oracle_quality(torch, sk, g, cfg)
         log("ic-model sketches")
@@ -661,9 +899,14 @@ def main():
         out["error_vs_ell"] = bench_error_vs_ell(torch, sk)
         log("serving")
         out["serving"] = bench_serving(torch, sk)
+        if not args.no_rmat:
+            out["rmat_24"] = bench_rmat(torch, sk)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(g, cfg)
+        if not args.no_extras:
+            log("oracle times of the query and SKIM workloads")
+            out["oracle_times"] = oracle_times()
     print(json.dumps(out), flush=True)
 
 

@@ -581,7 +581,8 @@ skim_status skim_tune_build_cached(const skim_graph *g, uint32_t ell, uint32_t k
  * launch of that kernel (e.g. "k_expand", the level expansion of the pruned
  * reverse search) made by the calling thread is bracketed by HIP events on
  * the call's stream.  Totals accumulate across calls until reset.
- *   skim_timing_enable(name): time launches of `name` (NULL = off).
+ *   skim_timing_enable(names): time launches of the kernels named in the
+ *     comma-separated list `names` (NULL or "" = off).
  *   skim_timing_read(name, total_ms, launches): totals so far (HOST
  *   pointers, may be NULL); returns 1 if the kernel has entries, else 0.
  */

@@ -230,7 +230,7 @@ void read_back(void *host, const void *dev, size_t bytes, hipStream_t s) {
 // ------------------------------------------------------------ kernel timing
 namespace {
 std::mutex g_time_mu;
-std::string g_time_kernel;  // empty = timing off
+std::string g_time_kernel;  // ",name,name," of the kernels timed; empty = timing off
 struct TimeAcc {
     double ms = 0;
     uint64_t launches = 0;
@@ -276,7 +276,9 @@ void give_event(hipEvent_t e) {
 LaunchTimer::LaunchTimer(const char *kernel, hipStream_t s) : s_(s), name_(kernel) {
     {
         std::lock_guard<std::mutex> lk(g_time_mu);
-        if (g_time_kernel.empty() || g_time_kernel != kernel) return;
+        if (g_time_kernel.empty() ||
+            g_time_kernel.find("," + std::string(kernel) + ",") == std::string::npos)
+            return;
     }
     a_ = take_event();
     if (a_ && hipEventRecord(a_, s_) != hipSuccess) {
@@ -541,7 +543,7 @@ extern "C" skim_status skim_debug_inject(uint32_t what, uint32_t count) {
 
 extern "C" void skim_timing_enable(const char *kernel) {
     std::lock_guard<std::mutex> lk(g_time_mu);
-    g_time_kernel = kernel ? kernel : "";
+    g_time_kernel = kernel && *kernel ? "," + std::string(kernel) + "," : "";
 }
 
 extern "C" void skim_timing_reset(void) {
