@@ -4,17 +4,20 @@
 // pairs sorted by rank, covered[pair], size[node], and the inverted index
 // (for every processed pair, the nodes its reverse search reached).
 //
-// One persistent workgroup runs the whole selection loop (the loop is
-// sequential per seed; the state of the configurations this serves fits
-// on-chip caches):
+// One persistent workgroup runs the selection loop (the loop is sequential
+// per seed); residual searches that grow large continue on the whole grid:
 //  * scan: the next B pairs in rank order each run their complete reverse
 //    search in parallel (one thread per pair; an uncovered pair never reaches
 //    a covered one, so the searches are independent of each other's
-//    increments).  The first prefix length T at which some node's size
-//    reaches k is found by binary search over prefixes; pairs [0, T) are
-//    committed (size increments, index entries), the rest are re-scanned
-//    later.  The nodes that reached k all sit in pair T-1's search; the
-//    smallest id among them is the seed.
+//    increments).  If some node's size reaches k with all B pairs, the first
+//    prefix length T at which one does is the smallest position at which a
+//    filling node receives its (k - size)-th entry, found from the entries
+//    of the filling nodes alone (binary search over prefixes when there are
+//    too many); pairs [0, T) are committed (size increments, index entries),
+//    the rest are re-scanned later.  The nodes that reached k all sit in
+//    pair T-1's search; the smallest id among them is the seed.  Batches
+//    with a long search spread the per-entry work over the block by flat
+//    position instead of per thread.
 //  * exhaustion: with every rank processed, the unselected node with the
 //    largest size (smallest id on ties) is the seed.
 //  * records: before the residual update, the rank tau of the pair that filled
@@ -22,10 +25,15 @@
 //    the other unselected nodes, one less for nodes in that pair's search)
 //    are stored per seed for the adaptive error estimate (Section 4).
 //  * residual: a level-synchronous forward search from the seed over all
-//    instances at once (the whole workgroup shares each level's frontier of
-//    pairs) over live out-edges, not entering covered pairs; every newly
-//    covered pair counts towards the seed's gain and decrements the size of
-//    every node in its index entry, which is then erased.
+//    instances at once (each level's frontier of pairs shared by the block)
+//    over live out-edges, not entering covered pairs; every newly covered
+//    pair counts towards the seed's gain and decrements the size of every
+//    node in its index entry, which is then erased.  A level of more than
+//    kSkimHandoff pairs, or a seed with more than kSkimHandoffEdges live
+//    out-edges, ends the workgroup's launch; the host runs the rest of that
+//    search level by level on the whole grid (k_resid_level, with the pairs
+//    of long out-lists expanded edge-balanced by k_resid_heavy) and then
+//    relaunches the loop.
 //
 // The adaptive error estimate itself (skim_discrepancy_tail) bounds each
 // seed's discrepancy with eq. (chernoff) on a grid of discrepancy values and
@@ -48,6 +56,24 @@ constexpr int kSkimBlock = 1024;
 constexpr uint32_t kSkimLdsNodes = 20480;  // graphs up to this size keep size[] in LDS
 constexpr uint32_t kSkimLdsWords = kSkimLdsNodes / 2;
 constexpr uint32_t kFlagPool = 1u;
+// Items whose search, index entry or out-list is at most this long are
+// walked by their own thread; a batch or level with a longer one spreads
+// its work over the block by flat position.
+constexpr uint32_t kSkimSerial = 32;
+// A residual level with more pairs than this continues on the whole grid.
+constexpr uint64_t kSkimHandoff = 8192;
+// ... and so does a seed whose own live out-edges are more than this.
+constexpr uint64_t kSkimHandoffEdges = 16384;
+// On the grid, pairs with more live out-edges than this are expanded by a
+// second launch per level that spreads their edges over every workgroup
+// (at most kHeavyItems per level; more are expanded where they are).
+constexpr uint64_t kSplitEdges = 1024;
+constexpr uint32_t kHeavyItems = 1u << 16;
+// Entries of the nodes that fill within a batch, kept to find the filling
+// prefix directly (more: binary search over prefixes).
+constexpr uint32_t kSkimCand = 1024;
+constexpr int kResidBlock = 256;
+constexpr uint32_t kResidGrid = 1024;
 
 struct SkCtl {
     unsigned long long cursor;     // next position in the rank order
@@ -55,6 +81,15 @@ struct SkCtl {
     unsigned long long need;       // pool entries a failed batch needed
     uint32_t done;                 // seeds completed by the last launch
     uint32_t flags;
+    // A residual search handed to the whole grid (its frontier outgrew the
+    // workgroup): the seed, the frontier buffer of its current level, the
+    // pairs covered so far, and the level sizes (each counter on a line of
+    // its own; level L reads rsize[L % 3], appends to rsize[(L + 1) % 3]).
+    uint32_t pend, px, rcur, pad;
+    unsigned long long rgain;
+    unsigned long long pad2[10];
+    unsigned long long rsize[3 * 16];
+    unsigned long long hsize[2 * 16];  // heavy pairs of level L: hsize[16 (L % 2)]
 };
 
 struct SkArgs {
@@ -66,14 +101,14 @@ struct SkArgs {
     const uint32_t *fadj;
     const uint32_t *order;  // pair ids by increasing rank
     uint32_t *covered;      // [64 n] 0/1
-    uint32_t *size;         // [(n + 1) / 2] packed 16-bit counters
+    uint32_t *size;         // [2 ceil(n / 4)] packed 16-bit counters
     uint32_t *sel;          // [n] 0/1
-    uint32_t *idx_off;      // [64 n]
-    uint32_t *idx_cnt;      // [64 n], 0 = no entry
+    uint64_t *idx;          // [64 n] first pool entry << 32 | entries, 0 = no entry
     uint32_t *pool;
     uint64_t pool_cap;
-    uint32_t *bcnt;         // [(n + 1) / 2] per-batch increment counters, packed
+    uint32_t *bcnt;         // [2 ceil(n / 4)] per-batch increment counters, packed
     uint32_t *queues;       // [kSkimBlock * n]
+    uint64_t *heavy;        // [2 kHeavyItems] grid residual: (pair, first out-edge, count)
     uint32_t *vis;          // [kSkimBlock * vis_words] per-thread visited bitmaps, kept zero
     uint32_t vis_words;     // ceil(n / 32)
     SkCtl *ctl;
@@ -120,35 +155,198 @@ __device__ __forceinline__ void czero(uint32_t *c, uint32_t v) {
     atomicAnd(c + (v >> 1), ~(0xFFFFu << half_shift(v)));
 }
 
-// Inclusive prefix sum of v over the 64 lanes of a wave.
-__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
-    const uint32_t lane = threadIdx.x & 63u;
+// Exclusive prefix sum of v over the block (NT threads, called by all of
+// them) and the block total; wsum holds one word per wave.
+template <uint32_t NT>
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t *wsum, uint64_t &total) {
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+    uint64_t x = v;
 #pragma unroll
     for (uint32_t off = 1; off < 64; off <<= 1) {
-        const uint32_t t = __shfl_up(v, off);
-        if (lane >= off) v += t;
+        const uint32_t lo = __shfl_up((uint32_t)x, off), hi = __shfl_up((uint32_t)(x >> 32), off);
+        if (lane >= off) x += ((uint64_t)hi << 32) | lo;
     }
-    return v;
+    __syncthreads();  // earlier readers of wsum are done
+    if (lane == 63u) wsum[wave] = x;
+    __syncthreads();
+    uint64_t before = 0, tot = 0;
+    for (uint32_t w = 0; w < NT / 64; ++w) {
+        const uint64_t s = wsum[w];
+        before += w < wave ? s : 0;
+        tot += s;
+    }
+    total = tot;
+    return before + x - v;
 }
 
-__global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, uint32_t *seeds,
-                                                     uint64_t *gains, double *gain_d,
-                                                     uint64_t *rec_tau, uint32_t *rec_second) {
-    __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_total, s_tau, s_fcnt[2];
+// The run that holds flat position t: the largest r with ex[r] <= t, for
+// exclusive prefix sums ex[0..NT] (runs of length zero are never returned
+// for t below the total).
+template <uint32_t NT>
+__device__ __forceinline__ uint32_t run_of(const uint64_t *ex, uint64_t t) {
+    uint32_t lo = 0, hi = NT;  // ex[lo] <= t < ex[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (ex[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Work that depends on the length of a search or of an adjacency list is
+// spread over the whole block by flat position (prefix sums over the
+// block's items, then a binary search per position), so one long item
+// does not hold up a level.
+template <uint32_t NT> struct FlatShared {
+    uint64_t ex[NT + 1];   // scan: queue lengths; residual: out-edges
+    uint64_t ex2[NT + 1];  // residual: index entries
+    uint64_t f0[NT];       // residual: first out-edge
+    uint32_t q[NT];        // residual: the pair
+    uint32_t o[NT];        // residual: first index entry
+    uint64_t wsum[NT / 64];
+};
+
+// Appends of a grid-wide residual level, staged in LDS and reserved in
+// global memory once per chunk (one counter serves the whole grid).
+struct ResidStage {
+    uint32_t buf[8 * kResidBlock];
+    uint32_t n;
+    unsigned long long base;
+};
+
+struct ScanShared {
+    uint64_t cand[kSkimCand];  // (pair position << 32) | node, nodes that fill
+    uint32_t ncand, tmin;
+};
+
+// One chunk of a residual level: frontier entries [base, base + NT) of
+// Fin (fc entries).  Each newly covered pair's index entry is erased (its
+// nodes lose one from their sizes), and its live out-edges cover the pairs
+// they reach in the same instance, appended to Fout (counted in *next).
+// Called by all NT threads of the block.
+// Precheck: read a pair's covered flag before the CAS (fewer atomics when
+// many targets are covered already; one more step of latency).
+template <uint32_t NT, bool Precheck>
+__device__ __forceinline__ void resid_chunk(const SkArgs &A, uint32_t *SZ, const uint32_t *Fin,
+                                            uint32_t *Fout, uint64_t fc, uint64_t base,
+                                            FlatShared<NT> &X, unsigned long long *next,
+                                            ResidStage *stage, unsigned long long *hcount) {
+    const uint32_t tid = threadIdx.x;
+    // one wave's newly covered pairs: to the stage (when there is one) or
+    // straight to Fout
+    auto push = [&](bool add, uint32_t qw) {
+        if (!stage) {
+            const uint64_t slot = wave_reserve(next, add);
+            if (add) st(Fout + slot, qw);
+            return;
+        }
+        const unsigned long long m = __ballot(add);
+        if (!m) return;
+        const int leader = __ffsll((long long)m) - 1;
+        const uint32_t lane = lane_id();
+        uint32_t pos0 = 0;
+        if ((int)lane == leader) pos0 = atomicAdd(&stage->n, (uint32_t)__popcll(m));
+        const uint32_t pos = (uint32_t)__shfl((int)pos0, leader) +
+                             (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (!add) return;
+        if (pos < 8 * kResidBlock) stage->buf[pos] = qw;
+        else Fout[atomicAdd(next, 1ull)] = qw;  // stage full
+    };
+    auto flush = [&]() {
+        if (!stage) return;
+        __syncthreads();
+        const uint32_t ns = stage->n < 8 * kResidBlock ? stage->n : 8 * kResidBlock;
+        if (tid == 0 && ns) stage->base = atomicAdd(next, (unsigned long long)ns);
+        __syncthreads();
+        const unsigned long long b = stage->base;
+        for (uint32_t j = tid; j < ns; j += NT) Fout[b + j] = stage->buf[j];
+        __syncthreads();
+        if (tid == 0) stage->n = 0;  // before the next chunk's first barrier
+    };
+    const uint64_t e = base + tid;
+    uint32_t q = 0, o = 0, c = 0;
+    uint64_t f0 = 0, deg = 0;
+    if (e < fc) {
+        q = Fin[e];
+        const uint64_t ix = ld(A.idx + q);
+        c = (uint32_t)ix;
+        if (c) {
+            o = (uint32_t)(ix >> 32);
+            st(A.idx + q, (uint64_t)0);
+        }
+        f0 = A.fptr[q];
+        deg = A.fptr[q + 1] - f0;
+        if (hcount && deg > kSplitEdges) {  // deferred to k_resid_heavy
+            const unsigned long long slot = atomicAdd(hcount, 1ull);
+            if (slot < kHeavyItems) {
+                A.heavy[2 * slot] = ((uint64_t)q << 32) | (uint32_t)deg;
+                A.heavy[2 * slot + 1] = f0;
+                deg = 0;
+            }
+        }
+    }
+    const bool light = __syncthreads_or(c > kSkimSerial || deg > kSkimSerial) == 0;
+    if (light) {
+        for (uint32_t j = 0; j < c; ++j) csub(SZ, ld(A.pool + o + j), 1u);
+        for (uint64_t x2 = f0; x2 < f0 + deg; ++x2) {
+            const uint32_t qw = A.fadj[x2] * kPairStride + q % kPairStride;
+            const bool add =
+                (!Precheck || !ld(A.covered + qw)) && atomicCAS(A.covered + qw, 0u, 1u) == 0u;
+            push(add, qw);
+        }
+        flush();
+        return;
+    }
+    uint64_t ctot, dtot;
+    const uint64_t cex = block_excl_scan<NT>(c, X.wsum, ctot);
+    const uint64_t dex = block_excl_scan<NT>(deg, X.wsum, dtot);
+    X.ex2[tid] = cex;
+    X.ex[tid] = dex;
+    X.q[tid] = q;
+    X.o[tid] = o;
+    X.f0[tid] = f0;
+    if (tid == 0) {
+        X.ex2[NT] = ctot;
+        X.ex[NT] = dtot;
+    }
+    __syncthreads();
+    for (uint64_t t = tid; t < ctot; t += NT) {
+        const uint32_t r = run_of<NT>(X.ex2, t);
+        csub(SZ, ld(A.pool + X.o[r] + (t - X.ex2[r])), 1u);
+    }
+    for (uint64_t t = tid; t < dtot; t += NT) {
+        const uint32_t r = run_of<NT>(X.ex, t);
+        const uint32_t qw = A.fadj[X.f0[r] + (t - X.ex[r])] * kPairStride + X.q[r] % kPairStride;
+        const bool add =
+            (!Precheck || !ld(A.covered + qw)) && atomicCAS(A.covered + qw, 0u, 1u) == 0u;
+        push(add, qw);
+    }
+    flush();
+    __syncthreads();  // the chunk's LDS arrays are reused
+}
+
+__global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, uint64_t handoff,
+                                                     uint32_t *seeds, uint64_t *gains,
+                                                     double *gain_d, uint64_t *rec_tau,
+                                                     uint32_t *rec_second) {
+    __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_tau, s_fcnt[2];
     __shared__ int s_x, s_filler;
-    __shared__ uint32_t s_found, s_stop, s_fill_cnt, s_second;
+    __shared__ uint32_t s_found, s_stop, s_fill_cnt, s_second, s_xmin;
     // size[] and the batch counters live in LDS when the graph is small
     // enough: every pair's search adds to them, and device atomics from
     // different waves on one cache line are serialised.
-    __shared__ uint32_t s_size[kSkimLdsWords], s_bcnt[kSkimLdsWords];
+    __shared__ __align__(8) uint32_t s_size[kSkimLdsWords];
+    __shared__ __align__(8) uint32_t s_bcnt[kSkimLdsWords];
+    __shared__ FlatShared<kSkimBlock> X;
+    __shared__ ScanShared C;
     const uint32_t tid = threadIdx.x;
     const uint32_t n = A.n, k = A.k;
     const bool in_lds = n <= kSkimLdsNodes;
     uint32_t *SZ = in_lds ? s_size : A.size;
     uint32_t *BC = in_lds ? s_bcnt : A.bcnt;
     if (in_lds)
-        for (uint32_t w = tid; w < (n + 1) / 2; w += kSkimBlock) {
-            s_size[w] = ld(A.size + w);
+        for (uint32_t w = tid; w < kSkimLdsWords; w += kSkimBlock) {
+            s_size[w] = w < (n + 1) / 2 ? ld(A.size + w) : 0u;
             s_bcnt[w] = 0;
         }
     uint32_t *Q = A.queues + (uint64_t)tid * n;
@@ -158,8 +356,14 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         s_pool = A.ctl->pool_used;
         s_stop = 0;
         s_found = 0;
+        C.ncand = 0;
     }
     __syncthreads();
+    // entry t of the batch's searches, laid end to end in thread order
+    auto entry = [&](uint64_t t) {
+        const uint32_t r = run_of<kSkimBlock>(X.ex, t);
+        return ld(A.queues + (uint64_t)r * n + (t - X.ex[r]));
+    };
     uint32_t done = 0;
     for (uint32_t it = 0; it < goal; ++it) {
         if (tid == 0) {
@@ -190,29 +394,83 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                     for (uint32_t j = 0; j < cnt; ++j) V[Q[j] >> 5] = 0u;  // back to zero
                 }
             }
+            {
+                uint64_t tot;
+                const uint64_t ex = block_excl_scan<kSkimBlock>(cnt, X.wsum, tot);
+                X.ex[tid] = ex;
+                if (tid == 0) X.ex[kSkimBlock] = tot;
+            }
+            const bool heavy = __syncthreads_or(cnt > kSkimSerial) != 0;
             // Does some node reach k within the first T pairs?  Sizes are
-            // below k at the start of a batch and grow by one per pair, so
-            // the smallest such T is found by binary search over prefixes.
+            // below k at the start of a batch and grow by one per pair.  The
+            // whole batch is tried first; if some node fills, the entries of
+            // every such node are kept, and the first filling prefix is the
+            // smallest position at which one of them receives its
+            // (k - size)-th entry (a search holds a node at most once).  With
+            // too many such entries, the prefix is found by binary search.
             bool filled = false;
             uint32_t lo = 0, hi = B, T = B;
             for (;;) {
-                if (tid < T)
-                    for (uint32_t j = 0; j < cnt; ++j) cadd(BC, Q[j], 1u);
-                __syncthreads();
+                const uint64_t end = X.ex[T];
                 bool cand = false;
-                if (tid < T)
-                    for (uint32_t j = 0; j < cnt; ++j) cand |= cget(SZ, Q[j]) + cget(BC, Q[j]) >= k;
+                auto keep = [&](uint32_t r, uint32_t v) {
+                    if (T != B) return;
+                    const uint32_t slot = atomicAdd(&C.ncand, 1u);
+                    if (slot < kSkimCand) C.cand[slot] = ((uint64_t)r << 32) | v;
+                };
+                if (heavy) {
+                    for (uint64_t t = tid; t < end; t += kSkimBlock) cadd(BC, entry(t), 1u);
+                    __syncthreads();
+                    for (uint64_t t = tid; t < end; t += kSkimBlock) {
+                        const uint32_t v = entry(t);
+                        if (cget(SZ, v) + cget(BC, v) >= k) {
+                            cand = true;
+                            keep(run_of<kSkimBlock>(X.ex, t), v);
+                        }
+                    }
+                } else {
+                    if (tid < T)
+                        for (uint32_t j = 0; j < cnt; ++j) cadd(BC, Q[j], 1u);
+                    __syncthreads();
+                    if (tid < T)
+                        for (uint32_t j = 0; j < cnt; ++j)
+                            if (cget(SZ, Q[j]) + cget(BC, Q[j]) >= k) {
+                                cand = true;
+                                keep(tid, Q[j]);
+                            }
+                }
                 if (__any(cand) && (tid & 63u) == 0) atomicOr(&s_found, 1u);
                 __syncthreads();
                 const bool f = s_found != 0;
-                if (tid < T)
+                if (heavy) {
+                    for (uint64_t t = tid; t < end; t += kSkimBlock) czero(BC, entry(t));
+                } else if (tid < T) {
                     for (uint32_t j = 0; j < cnt; ++j) czero(BC, Q[j]);
+                }
                 __syncthreads();
                 if (tid == 0) s_found = 0;
                 __syncthreads();
                 if (T == B) {
                     filled = f;
                     if (!f) break;
+                    const uint32_t nc = C.ncand;
+                    if (nc <= kSkimCand) {
+                        if (tid == 0) C.tmin = 0xFFFFFFFFu;
+                        __syncthreads();
+                        for (uint32_t c = tid; c < nc; c += kSkimBlock) {
+                            const uint64_t e = C.cand[c];
+                            const uint32_t r = (uint32_t)(e >> 32), v = (uint32_t)e;
+                            uint32_t before = 0;  // entries of v at earlier positions
+                            for (uint32_t c2 = 0; c2 < nc; ++c2) {
+                                const uint64_t e2 = C.cand[c2];
+                                before += (uint32_t)e2 == v && (uint32_t)(e2 >> 32) < r;
+                            }
+                            if (before + 1 == k - cget(SZ, v)) atomicMin(&C.tmin, r);
+                        }
+                        __syncthreads();
+                        hi = C.tmin + 1;
+                        break;
+                    }
                 } else if (f) {
                     hi = T;
                 } else {
@@ -223,50 +481,59 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             }
             T = hi;  // B when nothing fills; else the first filling prefix
             // does the committed prefix fit in the index pool?
-            // (LDS atomics: one per wave, lanes on one address are serialised)
-            const uint32_t mine = tid < T ? cnt : 0u;
-            const uint32_t incl = wave_incl_sum(mine);
-            const uint32_t wave_total = __shfl(incl, 63);
-            if (tid == 0) s_total = 0;
-            __syncthreads();
-            if ((tid & 63u) == 63u && wave_total)
-                atomicAdd(&s_total, (unsigned long long)wave_total);
-            __syncthreads();
-            if (s_pool + s_total > A.pool_cap) {
+            const uint64_t need = X.ex[T], pbase = s_pool;
+            if (pbase + need > A.pool_cap) {
                 if (tid == 0) {
                     A.ctl->flags |= kFlagPool;
-                    A.ctl->need = s_pool + s_total;
+                    A.ctl->need = pbase + need;
                     s_stop = 1;
                 }
                 __syncthreads();
                 break;
             }
-            unsigned long long wave_base = 0;
-            if ((tid & 63u) == 63u && wave_total)
-                wave_base = atomicAdd(&s_pool, (unsigned long long)wave_total);
-            wave_base = ((unsigned long long)__shfl((uint32_t)(wave_base >> 32), 63) << 32) |
-                        __shfl((uint32_t)wave_base, 63);
-            if (tid < T && cnt) {
-                const unsigned long long off = wave_base + (incl - mine);
+            // commit pairs [0, T): index entries in pair order, sizes
+            if (heavy) {
+                for (uint64_t t = tid; t < need; t += kSkimBlock) {
+                    const uint32_t v = entry(t);
+                    st(A.pool + pbase + t, v);
+                    cadd(SZ, v, 1u);
+                }
+            } else if (tid < T) {
                 for (uint32_t j = 0; j < cnt; ++j) {
-                    st(A.pool + off + j, Q[j]);
+                    st(A.pool + pbase + X.ex[tid] + j, Q[j]);
                     cadd(SZ, Q[j], 1u);
                 }
-                st(A.idx_off + p, (uint32_t)off);
-                st(A.idx_cnt + p, cnt);
             }
+            if (tid < T && cnt) {
+                st(A.idx + p, ((pbase + X.ex[tid]) << 32) | cnt);
+            }
+            if (tid == 0) s_xmin = 0xFFFFFFFFu;
             __syncthreads();
-            if (filled && tid == T - 1) {
-                // the nodes that just reached k are in this pair's search
-                int x = -1;
-                for (uint32_t j = 0; j < cnt; ++j)
-                    if (cget(SZ, Q[j]) >= k && (x < 0 || Q[j] < (uint32_t)x)) x = (int)Q[j];
-                s_x = x;
-                s_filler = (int)tid;
-                s_fill_cnt = cnt;
-                s_tau = pair_rank(A.seed, p);
+            if (filled) {
+                // the nodes that just reached k are in pair T - 1's search;
+                // the seed is the smallest of them
+                if (heavy) {
+                    for (uint64_t t = X.ex[T - 1] + tid; t < need; t += kSkimBlock) {
+                        const uint32_t v = entry(t);
+                        if (cget(SZ, v) >= k) atomicMin(&s_xmin, v);
+                    }
+                } else if (tid == T - 1) {
+                    for (uint32_t j = 0; j < cnt; ++j)
+                        if (cget(SZ, Q[j]) >= k) atomicMin(&s_xmin, Q[j]);
+                }
+                if (tid == T - 1) {
+                    s_filler = (int)tid;
+                    s_fill_cnt = cnt;
+                    s_tau = pair_rank(A.seed, p);
+                }
+                __syncthreads();
+                if (tid == 0) s_x = s_xmin == 0xFFFFFFFFu ? -1 : (int)s_xmin;
             }
-            if (tid == 0) s_cursor = cursor + T;
+            if (tid == 0) {
+                s_cursor = cursor + T;
+                s_pool = pbase + need;
+                C.ncand = 0;
+            }
             __syncthreads();
         }
         if (s_stop) break;
@@ -303,13 +570,21 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         {
             // Selected nodes need no test: every pair a seed reaches is
             // covered, so its size is 0 from then on and no later search
-            // reaches it.
+            // reaches it.  Four nodes per 64-bit load (the arrays are padded
+            // to whole pairs of words).
             uint32_t best2 = 0;
-            for (uint32_t v = tid; v < n; v += kSkimBlock)
-                if (v != x) {
-                    const uint32_t sz = cget(SZ, v) - cget(BC, v);
-                    best2 = sz > best2 ? sz : best2;
+            const uint64_t *SZ2 = reinterpret_cast<const uint64_t *>(SZ);
+            const uint64_t *BC2 = reinterpret_cast<const uint64_t *>(BC);
+            for (uint32_t w2 = tid; w2 < (n + 3) / 4; w2 += kSkimBlock) {
+                const uint64_t a = ld(SZ2 + w2), b = ld(BC2 + w2);
+#pragma unroll
+                for (uint32_t h = 0; h < 4; ++h) {
+                    const uint32_t v = 4 * w2 + h;
+                    const uint32_t sz = (uint32_t)((a >> (16 * h)) & 0xFFFFu) -
+                                        (uint32_t)((b >> (16 * h)) & 0xFFFFu);
+                    if (v < n && v != x && sz > best2) best2 = sz;
                 }
+            }
             // one LDS atomic per wave: lanes on one address are serialised
             for (int off = 32; off > 0; off >>= 1) {
                 const uint32_t o = (uint32_t)__shfl_xor((int)best2, off);
@@ -328,6 +603,9 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         // (64 v + i) in two halves of the queue area (free here: the scan's
         // searches are done and the filler's queue has been read).  A pair is
         // claimed by the CAS that covers it; its index entry is erased then.
+        // A level with more than `handoff` pairs (0: none) and the rest of
+        // the search go to the whole grid (k_resid_level); the host then
+        // completes the seed.
         uint32_t *F[2] = {A.queues, A.queues + (uint64_t)A.n * kPairStride};
         if (tid == 0) {
             s_gain = 0;
@@ -346,33 +624,38 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 if (add) st(F[0] + slot, px);
             }
         }
-        for (uint32_t cur = 0;; cur ^= 1u) {
+        bool handed = false;
+        const uint64_t seed_edges = A.fptr[(uint64_t)x * kPairStride + kPairStride] -
+                                    A.fptr[(uint64_t)x * kPairStride];
+        for (uint32_t cur = 0, level = 0;; cur ^= 1u, ++level) {
             __syncthreads();
+            // (the counter reset below is of the next level's counter, read
+            // by nobody in this level)
             const uint64_t fc = s_fcnt[cur];
-            __syncthreads();  // every thread has read the count
             if (fc == 0) break;
+            if (handoff && (fc > handoff || (level == 0 && seed_edges > kSkimHandoffEdges))) {
+                if (tid == 0) {
+                    A.ctl->pend = 1;
+                    A.ctl->px = x;
+                    A.ctl->rcur = cur;
+                    A.ctl->rsize[0] = fc;
+                    A.ctl->rsize[16] = 0;
+                    A.ctl->rsize[32] = 0;
+                    A.ctl->hsize[0] = 0;
+                    A.ctl->rgain = s_gain;
+                }
+                handed = true;
+                break;
+            }
             if (tid == 0) {
                 s_fcnt[cur ^ 1u] = 0;
                 s_gain += fc;
             }
-            __syncthreads();
-            for (uint64_t e = tid; e < fc; e += kSkimBlock) {
-                const uint32_t q = ld(F[cur] + e);
-                const uint32_t i = q % kPairStride;
-                const uint32_t c = ld(A.idx_cnt + q);
-                if (c) {
-                    const uint32_t o = ld(A.idx_off + q);
-                    for (uint32_t j = 0; j < c; ++j) csub(SZ, ld(A.pool + o + j), 1u);
-                    st(A.idx_cnt + q, 0u);
-                }
-                for (uint64_t x2 = A.fptr[q]; x2 < A.fptr[q + 1]; ++x2) {
-                    const uint32_t qw = A.fadj[x2] * kPairStride + i;
-                    const bool add = !ld(A.covered + qw) && atomicCAS(A.covered + qw, 0u, 1u) == 0u;
-                    const uint64_t slot = wave_reserve(&s_fcnt[cur ^ 1u], add);
-                    if (add) st(F[cur ^ 1u] + slot, qw);
-                }
-            }
+            for (uint64_t base = 0; base < fc; base += kSkimBlock)
+                resid_chunk<kSkimBlock, false>(A, SZ, F[cur], F[cur ^ 1u], fc, base, X,
+                                               &s_fcnt[cur ^ 1u], nullptr, nullptr);
         }
+        if (handed) break;  // uniform
         __syncthreads();
         if (tid == 0) {
             st(A.sel + x, 1u);
@@ -392,6 +675,118 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         A.ctl->pool_used = s_pool;
         A.ctl->done = done;
     }
+}
+
+// Level L of a residual search handed over by k_skim, on the whole grid:
+// frontier buffer (r0 + L) & 1 of the queue area, sizes in global memory.
+// A launch whose level is empty does nothing, so the host launches levels
+// in batches and reads the size back after each batch.
+__global__ void __launch_bounds__(kResidBlock) k_resid_level(SkArgs A, uint32_t L, uint32_t r0) {
+    __shared__ FlatShared<kResidBlock> X;
+    __shared__ ResidStage S;
+    __shared__ unsigned long long s_fc;
+    if (threadIdx.x == 0) {
+        S.n = 0;
+        s_fc = ld(&A.ctl->rsize[16 * (L % 3)]);
+        if (blockIdx.x == 0) {
+            A.ctl->rsize[16 * ((L + 2) % 3)] = 0;  // level L + 1 appends there
+            A.ctl->hsize[16 * ((L + 1) % 2)] = 0;  // and defers its heavy pairs there
+            A.ctl->rgain += s_fc;
+        }
+    }
+    __syncthreads();
+    const uint64_t fc = s_fc;
+    if (fc == 0) return;  // uniform
+    const uint32_t cur = (r0 + L) & 1u;
+    const uint64_t half = (uint64_t)A.n * kPairStride;
+    const uint32_t *Fin = A.queues + cur * half;
+    uint32_t *Fout = A.queues + (cur ^ 1u) * half;
+    for (uint64_t base = (uint64_t)blockIdx.x * kResidBlock; base < fc;
+         base += (uint64_t)gridDim.x * kResidBlock)
+        resid_chunk<kResidBlock, true>(A, A.size, Fin, Fout, fc, base, X,
+                                       &A.ctl->rsize[16 * ((L + 1) % 3)], &S,
+                                       &A.ctl->hsize[16 * (L % 2)]);
+}
+
+// The out-edges of level L's deferred pairs, spread evenly over the grid,
+// kResidBlock pairs at a time; appends go to level L + 1 like the level's.
+__global__ void __launch_bounds__(kResidBlock) k_resid_heavy(SkArgs A, uint32_t L, uint32_t r0) {
+    __shared__ uint64_t ex[kResidBlock + 1], wsum[kResidBlock / 64], f0s[kResidBlock];
+    __shared__ uint32_t qs[kResidBlock];
+    __shared__ ResidStage S;
+    const uint32_t tid = threadIdx.x;
+    const unsigned long long hc = A.ctl->hsize[16 * (L % 2)];
+    const uint32_t nh = hc < kHeavyItems ? (uint32_t)hc : kHeavyItems;
+    if (nh == 0) return;  // uniform
+    if (tid == 0) S.n = 0;
+    const uint32_t cur = (r0 + L) & 1u;
+    uint32_t *Fout = A.queues + (cur ^ 1u) * (uint64_t)A.n * kPairStride;
+    unsigned long long *next = &A.ctl->rsize[16 * ((L + 1) % 3)];
+    for (uint32_t h0 = 0; h0 < nh; h0 += kResidBlock) {
+        uint64_t deg = 0, f0 = 0;
+        uint32_t q = 0;
+        if (h0 + tid < nh) {
+            const uint64_t w = A.heavy[2 * (h0 + tid)];
+            q = (uint32_t)(w >> 32);
+            deg = (uint32_t)w;
+            f0 = A.heavy[2 * (h0 + tid) + 1];
+        }
+        uint64_t tot;
+        const uint64_t e = block_excl_scan<kResidBlock>(deg, wsum, tot);
+        ex[tid] = e;
+        qs[tid] = q;
+        f0s[tid] = f0;
+        if (tid == 0) ex[kResidBlock] = tot;
+        __syncthreads();
+        const uint64_t a = tot * blockIdx.x / gridDim.x, b = tot * (blockIdx.x + 1) / gridDim.x;
+        for (uint64_t base = a; base < b; base += kResidBlock) {
+            const uint64_t t = base + tid;
+            bool add = false;
+            uint32_t qw = 0;
+            if (t < b) {
+                const uint32_t r = run_of<kResidBlock>(ex, t);
+                qw = A.fadj[f0s[r] + (t - ex[r])] * kPairStride + qs[r] % kPairStride;
+                add = !ld(A.covered + qw) && atomicCAS(A.covered + qw, 0u, 1u) == 0u;
+            }
+            const unsigned long long m = __ballot(add);
+            if (m) {
+                const int leader = __ffsll((long long)m) - 1;
+                const uint32_t lane = lane_id();
+                uint32_t pos0 = 0;
+                if ((int)lane == leader) pos0 = atomicAdd(&S.n, (uint32_t)__popcll(m));
+                const uint32_t pos = (uint32_t)__shfl((int)pos0, leader) +
+                                     (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                if (add) {
+                    if (pos < 8 * kResidBlock) S.buf[pos] = qw;
+                    else Fout[atomicAdd(next, 1ull)] = qw;
+                }
+            }
+            __syncthreads();
+            const uint32_t ns = S.n < 8 * kResidBlock ? S.n : 8 * kResidBlock;
+            __syncthreads();  // every thread has read S.n: the test below is uniform
+            if (ns > 7 * kResidBlock || base + kResidBlock >= b) {
+                if (tid == 0 && ns) S.base = atomicAdd(next, (unsigned long long)ns);
+                __syncthreads();
+                for (uint32_t j = tid; j < ns; j += kResidBlock) Fout[S.base + j] = S.buf[j];
+                __syncthreads();
+                if (tid == 0) S.n = 0;
+                __syncthreads();
+            }
+        }
+        __syncthreads();  // ex, qs, f0s are reused
+    }
+}
+
+// The handed-over seed is complete: outputs, and the node leaves the
+// candidates.
+__global__ void k_resid_finish(SkArgs A, uint32_t *seeds, uint64_t *gains, double *gain_d) {
+    const uint32_t x = A.ctl->px;
+    const unsigned long long g = A.ctl->rgain;
+    A.sel[x] = 1u;
+    seeds[0] = x;
+    gains[0] = g;
+    if (gain_d) gain_d[0] = (double)g / (double)A.ell;
+    A.ctl->pend = 0;
 }
 
 __global__ void k_pair_keys(uint32_t n, uint32_t ell, uint64_t seed, uint64_t *keys,
@@ -632,11 +1027,12 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
     A.ell = ell;
     A.k = k;
     A.covered = M.alloc<uint32_t>(npairs);
-    A.size = M.alloc<uint32_t>((n + 1) / 2);
+    const uint64_t cwords = 2 * (((uint64_t)n + 3) / 4);  // whole 64-bit words
+    A.size = M.alloc<uint32_t>(cwords);
     A.sel = M.alloc<uint32_t>(n);
-    A.idx_off = M.alloc<uint32_t>(npairs);
-    A.idx_cnt = M.alloc<uint32_t>(npairs);
-    A.bcnt = M.alloc<uint32_t>((n + 1) / 2);
+    A.idx = M.alloc<uint64_t>(npairs);
+    A.heavy = M.alloc<uint64_t>(2 * (uint64_t)kHeavyItems);
+    A.bcnt = M.alloc<uint32_t>(cwords);
     A.queues = M.alloc<uint32_t>((uint64_t)kSkimBlock * n);
     A.vis_words = (n + 31) / 32;
     A.vis = M.alloc<uint32_t>((uint64_t)kSkimBlock * A.vis_words);
@@ -648,10 +1044,10 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
     A.rec_tau = M.alloc<uint64_t>(n);
     A.rec_second = M.alloc<uint32_t>(n);
     fill_u32(A.covered, 0, npairs, s);
-    fill_u32(A.size, 0, (n + 1) / 2, s);
+    fill_u32(A.size, 0, cwords, s);
     fill_u32(A.sel, 0, n, s);
-    fill_u32(A.idx_cnt, 0, npairs, s);
-    fill_u32(A.bcnt, 0, (n + 1) / 2, s);
+    fill_u64(A.idx, 0, npairs, s);
+    fill_u32(A.bcnt, 0, cwords, s);
     fill_u64((uint64_t *)A.ctl, 0, sizeof(SkCtl) / 8, s);
     st->n = n;
     st->ell = ell;
@@ -669,10 +1065,10 @@ void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_
                        double *gain_d, hipStream_t s) {
     SkArgs &A = st->args;
     uint32_t done = 0;
-    for (int attempt = 0; done < s_goal; ++attempt) {
-        SKIM_REQUIRE(attempt < 40, "SKIM index pool did not converge");
-        k_skim<<<1, kSkimBlock, 0, s>>>(A, s_goal - done, seeds + done, gains + done,
-                                        gain_d ? gain_d + done : nullptr,
+    int growths = 0;
+    while (done < s_goal) {
+        k_skim<<<1, kSkimBlock, 0, s>>>(A, s_goal - done, kSkimHandoff, seeds + done,
+                                        gains + done, gain_d ? gain_d + done : nullptr,
                                         A.rec_tau + st->selected, A.rec_second + st->selected);
         SKIM_LAUNCH_CHECK();
         SkCtl c;
@@ -680,6 +1076,7 @@ void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_
         done += c.done;
         st->selected += c.done;
         if (c.flags & kFlagPool) {
+            SKIM_REQUIRE(++growths < 40, "SKIM index pool did not converge");
             // grow the inverted-index pool, keep its contents, continue
             const uint64_t cap = std::max<uint64_t>(2 * A.pool_cap, c.need + c.need / 2);
             uint32_t *np = st->mem->alloc<uint32_t>(cap);
@@ -689,6 +1086,28 @@ void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_
             A.pool = np;
             A.pool_cap = cap;
             fill_u32(&A.ctl->flags, 0, 1, s);
+        } else if (c.pend) {
+            // the seed's residual search continues on the whole grid, levels
+            // in batches (an empty level's launch does nothing); every level
+            // covers at least one new pair
+            const uint64_t max_levels = (uint64_t)A.n * kPairStride + 1;
+            uint32_t L = 0;
+            for (;;) {
+                for (int j = 0; j < 8; ++j, ++L) {
+                    k_resid_level<<<kResidGrid, kResidBlock, 0, s>>>(A, L, c.rcur);
+                    SKIM_LAUNCH_CHECK();
+                    k_resid_heavy<<<kResidGrid, kResidBlock, 0, s>>>(A, L, c.rcur);
+                    SKIM_LAUNCH_CHECK();
+                }
+                read_back(&c, A.ctl, sizeof c, s);
+                if (c.rsize[16 * (L % 3)] == 0) break;
+                SKIM_REQUIRE(L < max_levels, "SKIM residual search did not end");
+            }
+            k_resid_finish<<<1, 1, 0, s>>>(A, seeds + done, gains + done,
+                                           gain_d ? gain_d + done : nullptr);
+            SKIM_LAUNCH_CHECK();
+            ++done;
+            ++st->selected;
         } else if (done < s_goal) {
             set_error("SKIM stopped early");
             throw Fail{SKIM_EDEVICE};
