@@ -114,6 +114,39 @@ def calibrate_copy():
                       "write_bytes": CALIBRATION_BYTES, "launches": 3}), flush=True)
 
 
+def random_access_rates(torch, table_log2=27, n_log2=26, reps=3):
+    """Random-access rates of this GPU, measured with plain library kernels on
+    a 1 GiB table (far beyond the caches): 8-byte gathers (index_select) and
+    8-byte atomic adds (index_add_ on int64) at 2^26 uniform random indices.
+    The search's random accesses are of this kind: a 16-byte pair record read
+    per live-edge scan, one CAS per accepted visit."""
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(7)
+    table = torch.zeros(1 << table_log2, dtype=torch.int64, device=dev)
+    idx = torch.randint(0, 1 << table_log2, (1 << n_log2,), device=dev, generator=gen)
+    out = torch.empty(1 << n_log2, dtype=torch.int64, device=dev)
+    ones = torch.ones_like(out)
+
+    def rate(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return reps * (1 << n_log2) / (a.elapsed_time(b) / 1e3)
+
+    gather = rate(lambda: torch.index_select(table, 0, idx, out=out))
+    atomic = rate(lambda: table.index_add_(0, idx, ones))
+    del table, idx, out, ones
+    torch.cuda.empty_cache()
+    return {"table_bytes": 8 << table_log2, "accesses": 1 << n_log2,
+            "gather_per_s": gather, "atomic_add_per_s": atomic}
+
+
 def algorithmic_bytes_search(cnt):
     """HBM floor of the pruned reverse searches (the traversal terms of the
     build's floor): every CSR edge read under perfect instance packing
@@ -866,7 +899,16 @@ def main():
         per_build = measured_traffic(args.workload)
         # per launch like `achieved`: this run's launches share the build's bytes
         traffic = None if per_build is None else per_build * args.steps / klaunch
+        ra = random_access_rates(torch)
+        # the searches' random accesses at the rates plain gathers and atomics
+        # reach: one pair-record read per scan, one CAS per accepted visit
+        floor_s = work["scans"] / ra["gather_per_s"] + work["visits"] / ra["atomic_add_per_s"]
+        ra.update({"scans_per_step": work["scans"], "visits_per_step": work["visits"],
+                   "search_floor_ms": floor_s * 1e3,
+                   "search_floor_over_measured": floor_s / (kms / args.steps / 1e3)})
+        log(f"random access {ra}")
         roof = {"bound": "hbm", "kernel": DOMINANT, "kernels": per_kernel,
+                "random_access": ra,
                 "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "launches_per_step": klaunch / args.steps, "avg_launch_us": avg_s * 1e6,
