@@ -107,6 +107,8 @@ struct alignas(128) Ctl {
     uint32_t level;                   // level reached by the tail kernel
     char pad5[120];
     unsigned long long budget;        // visits reserved by the workgroup tails (k_tails)
+    char pad6[120];
+    unsigned long long hsize[2 * 16];  // long-list entries of level L: hsize[16 (L % 2)]
 };
 
 // ------------------------------------------------------- 2. rank windows
@@ -308,6 +310,7 @@ struct WinArgs {
     uint64_t *flive[2];    // the pair's live-list word
     uint64_t front_cap;
     Ctl *ctl;
+    uint64_t *heavy;       // [2 kHeavyMax] entries with long lists (key, list word), for k_expand_heavy
 };
 
 // Visit of pair q by the search of source pair src: 1 if it is a new visit
@@ -363,6 +366,11 @@ constexpr uint32_t kStageF = 1024;  // staged frontier entries per round (16 byt
 constexpr uint32_t kStageR = 1912;  // staged records per round (5 workgroups fit in LDS)
 constexpr uint32_t kHeavyCap = 256;  // long live lists per round expanded by the whole block
 constexpr uint32_t kSerialEdges = 16;  // longer lists go to the block
+// Still longer lists (hubs) are deferred to k_expand_heavy, which spreads
+// their entries over every workgroup (at most kHeavyMax per level; more are
+// expanded by their block).
+constexpr uint32_t kSplitLive = 4096;
+constexpr uint32_t kHeavyMax = 1u << 20;
 
 struct StageF {
     uint64_t key[kStageF];
@@ -465,6 +473,11 @@ struct ExpandShared {
     uint32_t nheavy;
 };
 
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t x, uint32_t d) {
+    const uint32_t lo = __shfl_up((uint32_t)x, d), hi = __shfl_up((uint32_t)(x >> 32), d);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t x, int m) {
     const uint32_t lo = __shfl_xor((uint32_t)x, m), hi = __shfl_xor((uint32_t)(x >> 32), m);
     return ((uint64_t)hi << 32) | lo;
@@ -538,6 +551,14 @@ __device__ __forceinline__ void expand_range(const WinArgs &A, uint32_t L,
                 continue;
             }
             const uint32_t cnt = live_count(live);
+            if (cnt > kSplitLive && A.heavy) {  // a hub's list: the whole grid, next launch
+                const unsigned long long slot = atomicAdd(&A.ctl->hsize[16 * (L % 2)], 1ull);
+                if (slot < kHeavyMax) {
+                    A.heavy[2 * slot] = it;
+                    A.heavy[2 * slot + 1] = live;
+                    continue;
+                }
+            }
             if (cnt > kSerialEdges) {  // a long list: the whole block takes it below
                 const uint32_t slot = stage_slots(&X.nheavy);
                 if (slot < kHeavyCap) {
@@ -614,13 +635,93 @@ __global__ void __launch_bounds__(kBlock) k_expand(WinArgs A, uint32_t L, uint32
         X.F.n = X.R.n = X.nheavy = 0;
         s_flags = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         s_size = A.ctl->size[16 * (L % 3)];
-        if (blockIdx.x == 0) A.ctl->size[16 * ((L + 2) % 3)] = 0;  // counter of level L + 2
+        if (blockIdx.x == 0) {
+            A.ctl->size[16 * ((L + 2) % 3)] = 0;  // counter of level L + 2
+            A.ctl->hsize[16 * ((L + 1) % 2)] = 0;  // long lists of level L + 1
+        }
     }
     __syncthreads();
     uint32_t scans = 0, hashed = 0, visits = 0;
     if (!s_flags && s_size) {  // after an overflow the windows are redone with more room
         expand_range(A, L, &A.ctl->size[16 * ((L + 1) % 3)], s_size, chunk, X, scans, hashed, visits);
     }
+    block_add3(X.R.buf, &A.ctl->scans, scans, &A.ctl->hinserts, hashed, &A.ctl->visits, visits);
+}
+
+// The long live lists that level L deferred (hubs), their entries spread
+// evenly over every workgroup: kBlock lists at a time, each workgroup taking
+// an equal range of their entries laid end to end.  Visits, appends and
+// records are those of k_expand for level L.
+__global__ void __launch_bounds__(kBlock) k_expand_heavy(WinArgs A, uint32_t L) {
+    __shared__ ExpandShared X;
+    __shared__ uint64_t ex[kBlock + 1], wsum[kBlock / 64], hk[kBlock], hl[kBlock];
+    __shared__ uint32_t s_flags;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wave = tid >> 6;
+    if (tid == 0) {
+        X.F.n = X.R.n = X.nheavy = 0;
+        s_flags = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const unsigned long long hc = A.ctl->hsize[16 * (L % 2)];  // final: level L has ended
+    const uint32_t nh = hc < kHeavyMax ? (uint32_t)hc : kHeavyMax;
+    if (s_flags || nh == 0) return;  // uniform
+    uint64_t *nkey = A.fkey[(L + 1) & 1], *nlive = A.flive[(L + 1) & 1];
+    unsigned long long *next_count = &A.ctl->size[16 * ((L + 1) % 3)];
+    uint32_t scans = 0, hashed = 0, visits = 0;
+    for (uint32_t h0 = 0; h0 < nh; h0 += kBlock) {
+        uint64_t key = 0, live = 0, cnt = 0;
+        if (h0 + tid < nh) {
+            key = A.heavy[2 * (h0 + tid)];
+            live = A.heavy[2 * (h0 + tid) + 1];
+            cnt = live_count(live);
+        }
+        // exclusive prefix of the list lengths over the block
+        uint64_t x = cnt;
+        for (uint32_t off = 1; off < 64; off <<= 1) {
+            const uint64_t y = shfl_up_u64(x, off);
+            if (lane >= off) x += y;
+        }
+        if (lane == 63u) wsum[wave] = x;
+        __syncthreads();
+        uint64_t before = 0, tot = 0;
+        for (uint32_t w = 0; w < kBlock / 64; ++w) {
+            before += w < wave ? wsum[w] : 0;
+            tot += wsum[w];
+        }
+        ex[tid] = before + x - cnt;
+        hk[tid] = key;
+        hl[tid] = live;
+        if (tid == 0) ex[kBlock] = tot;
+        __syncthreads();
+        const uint64_t a = tot * blockIdx.x / gridDim.x, b = tot * (blockIdx.x + 1) / gridDim.x;
+        for (uint64_t base = a; base < b; base += kBlock) {
+            const uint64_t t = base + tid;
+            if (t < b) {
+                uint32_t lo = 0, hi = kBlock;  // ex[lo] <= t < ex[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (ex[mid] <= t) lo = mid;
+                    else hi = mid;
+                }
+                const uint64_t it = hk[lo];
+                const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
+                const uint64_t e = (hl[lo] >> kLiveCountBits) + (t - ex[lo]);
+                visit_edge(A, A.lsrc[e], i, (uint32_t)it, nkey, nlive, next_count, X, scans,
+                           hashed, visits);
+            }
+            // flush the stages before they can overflow (the test is uniform:
+            // the counts are read between two barriers)
+            __syncthreads();
+            const bool full = X.F.n > kStageF - kBlock || X.R.n > kStageR - kBlock;
+            __syncthreads();
+            if (full)
+                stage_flush2(X.F, nkey, nlive, A.front_cap, next_count, X.R, A.rec, A.rec_cap,
+                             &A.ctl->records, &A.ctl->flags);
+        }
+        __syncthreads();  // ex, hk, hl are reused
+    }
+    stage_flush2(X.F, nkey, nlive, A.front_cap, next_count, X.R, A.rec, A.rec_cap,
+                 &A.ctl->records, &A.ctl->flags);
     block_add3(X.R.buf, &A.ctl->scans, scans, &A.ctl->hinserts, hashed, &A.ctl->visits, visits);
 }
 
@@ -823,6 +924,7 @@ __global__ void __launch_bounds__(kTailsBlock) k_tails(WinArgs A, uint32_t L, ui
 __global__ void k_tails_begin(Ctl *ctl, uint32_t L) {
     ctl->size[16 * ((L + 1) % 3)] = 0;
     ctl->size[16 * ((L + 2) % 3)] = 0;
+    ctl->hsize[16 * ((L + 1) % 2)] = 0;  // the level after the tails may defer long lists
     ctl->budget = 0;
 }
 
@@ -831,6 +933,7 @@ __global__ void k_tails_begin(Ctl *ctl, uint32_t L) {
 __global__ void k_ctl_begin(Ctl *ctl, unsigned long long visits, unsigned long long scans,
                             unsigned long long records) {
     ctl->size[16 * (0)] = ctl->size[16 * (1)] = ctl->size[16 * (2)] = 0;
+    ctl->hsize[0] = ctl->hsize[16] = 0;
     ctl->hinserts = 0;
     ctl->flags = 0;
     ctl->visits = visits;
@@ -1063,6 +1166,9 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Ra
     Ctl *ctl = A.alloc<Ctl>(1);
     fill_u64((uint64_t *)ctl, 0, sizeof(Ctl) / 8, s);
     uint64_t *prec = A.alloc<uint64_t>(2 * npairs);
+    // hub lists for k_expand_heavy, only when some list is long enough
+    uint64_t *heavy =
+        live.maxlen > kSplitLive ? A.alloc<uint64_t>(2 * (uint64_t)kHeavyMax) : nullptr;
     k_pair_init<<<grid_for(npairs, kBlock, 65536), kBlock, 0, s>>>(live.live, npairs, prec);
     SKIM_LAUNCH_CHECK();
     uint8_t *want = A.alloc<uint8_t>((uint64_t)n + 4);
@@ -1173,7 +1279,7 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Ra
                                logcap,  htag,     w,        k,
                                last,    want,     rec,      rec_cap,
                                {fkey[0], fkey[1]}, {flive[0], flive[1]}, front_cap,
-                               ctl};
+                               ctl,     heavy};
             };
             {
                 const WinArgs WA = args();
@@ -1308,9 +1414,17 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Ra
                     const unsigned grid =
                         f > kSmall ? (j == 0 ? grid_for(f, chunk, 2048) : 2048)
                                    : grid_for((growing ? 64 : 1) * f, chunk, 2048);
-                    LaunchTimer t("k_expand", s);
-                    k_expand<<<grid, kBlock, 0, s>>>(WA, L, f > kSmall && j > 0 ? kChunk : chunk);
+                    {
+                        LaunchTimer t("k_expand", s);
+                        k_expand<<<grid, kBlock, 0, s>>>(WA, L,
+                                                         f > kSmall && j > 0 ? kChunk : chunk);
+                    }
                     SKIM_LAUNCH_CHECK();
+                    if (heavy) {
+                        LaunchTimer t("k_expand_heavy", s);
+                        k_expand_heavy<<<2048, kBlock, 0, s>>>(WA, L);
+                        SKIM_LAUNCH_CHECK();
+                    }
                 }
             }
             if (!overflow) {

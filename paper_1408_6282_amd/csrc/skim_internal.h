@@ -214,6 +214,7 @@ struct PairLists {
     uint64_t *live = nullptr;  // [64 n]
     uint32_t *adj = nullptr;
     uint64_t nlive = 0;
+    uint32_t maxlen = 0;  // longest live in-list (0 when none is longer than 16)
 };
 PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
                            Arena &a);

@@ -6,8 +6,9 @@
 // instance) into a 64-bit instance mask.  Two builders group the live edges
 // by pair p = 64 v + i:
 //  * build_pair_lists (the sketch build): edges sorted by head, then one
-//    wave per node writes the live lists of its 64 pairs (two passes: count,
-//    then place); no atomics.
+//    wave per chunk of at most 1024 in-edges of a node writes the chunk's
+//    part of the live lists of the node's 64 pairs (passes: count, room,
+//    place); atomics only for the counts of nodes of several chunks.
 //  * build_live_lists (SKIM, which also needs out-lists): per-pair counts,
 //    a scan and a scatter into one CSR over pair ids.
 // Searches then read only the live edges of their own instance.
@@ -174,18 +175,23 @@ __global__ void __launch_bounds__(256) k_pair_count(ChunkArgs C, uint32_t *ccnt,
     }
 }
 
-// 2. room per node (lists of two or more), and a flag for a list too long
-// for the pair word's count field
-__global__ void k_pair_room(const uint32_t *pcnt, uint32_t n, uint32_t *room, uint32_t *too_long) {
+// 2. room per node (lists of two or more), a flag for a list too long for
+// the pair word's count field (flags[0]) and the longest list (flags[1])
+__global__ void k_pair_room(const uint32_t *pcnt, uint32_t n, uint32_t *room, uint32_t *flags) {
     const uint32_t lane = lane_id();
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     for (uint64_t v = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; v < n;
          v += waves) {
         const uint32_t c = pcnt[v * kPairStride + lane];
-        if (c >> kLiveCountBits) atomicOr(too_long, 1u);
-        uint32_t r = c >= 2 ? c : 0;
-        for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
+        if (c >> kLiveCountBits) atomicOr(flags, 1u);
+        uint32_t r = c >= 2 ? c : 0, mx = c;
+        for (int off = 32; off > 0; off >>= 1) {
+            r += __shfl_xor(r, off);
+            const uint32_t o = (uint32_t)__shfl_xor((int)mx, off);
+            mx = o > mx ? o : mx;
+        }
         if (lane == 0) room[v] = r;
+        if (lane == 0 && mx > 16) atomicMax(flags + 1, mx);  // short lists need no report
     }
 }
 
@@ -325,9 +331,9 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     SKIM_LAUNCH_CHECK();
     // 2. room per node, scan over the nodes
     uint32_t *room = a.alloc<uint32_t>(n);
-    uint32_t *too_long = a.alloc<uint32_t>(1);
-    fill_u32(too_long, 0, 1, s);
-    k_pair_room<<<grid_for(n, 4, 65536), 256, 0, s>>>(pcnt, n, room, too_long);
+    uint32_t *flags = a.alloc<uint32_t>(2);
+    fill_u32(flags, 0, 2, s);
+    k_pair_room<<<grid_for(n, 4, 65536), 256, 0, s>>>(pcnt, n, room, flags);
     SKIM_LAUNCH_CHECK();
     uint64_t *node_off = a.alloc<uint64_t>((uint64_t)n + 1);
     exclusive_scan_u32(room, node_off, n, a);
@@ -336,10 +342,11 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     k_chunk_prefix<<<grid_for(n, 4, 65536), 256, 0, s>>>(choff, n, ccnt);
     SKIM_LAUNCH_CHECK();
     uint64_t tot = 0;
-    uint32_t bad = 0;
+    uint32_t fl[2] = {0, 0};
     read_back(&tot, node_off + n, sizeof tot, s);
-    read_back(&bad, too_long, sizeof bad, s);
-    if (bad) {
+    read_back(fl, flags, sizeof fl, s);
+    L.maxlen = fl[1];
+    if (fl[0]) {
         set_error("a pair has 2^%u or more live in-edges", kLiveCountBits);
         throw Fail{SKIM_EUNSUPPORTED};
     }

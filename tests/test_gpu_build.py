@@ -76,6 +76,32 @@ def test_powerlaw_many_windows(oracle_lib):
     _check(oracle_lib, g2, 32, 16, 2)
 
 
+def test_hub_lists_spread_over_the_grid(oracle_lib):
+    # live in-lists longer than 4096 entries (a p = 1 in-star of 6000
+    # leaves into a hub, the hub feeding a chain, plus random p = 1/2 edges):
+    # the searches from the chain visit the hub and expand its list on the
+    # whole grid (k_expand_heavy) as well as in the tails and levels
+    rng = np.random.default_rng(77)
+    leaves, chain = 6000, 300
+    n = 1 + leaves + chain
+    src = list(range(1, leaves + 1)) + [0] + list(range(leaves + 1, n - 1))
+    dst = [0] * leaves + [leaves + 1] + list(range(leaves + 2, n))
+    thr = [0xFFFFFFFF] * len(src)
+    extra = 20000
+    es, ed = rng.integers(0, n, extra), rng.integers(0, n, extra)
+    seen = set(zip(src, dst))
+    for a, b in zip(es.tolist(), ed.tolist()):
+        if a != b and (a, b) not in seen:
+            seen.add((a, b))
+            src.append(a)
+            dst.append(b)
+            thr.append(0xFFFFFFFF // 2)
+    g = from_edges(n, src, dst, thr)
+    for ell, k, seed in ((64, 16, 5), (8, 64, 6)):
+        log(f"hub lists n={n} m={g.m} l={ell} k={k}")
+        _check(oracle_lib, g, ell, k, seed)
+
+
 def test_deterministic_repeat():
     cfg = make_config("tiny-ic")
     g = make_graph(cfg)
