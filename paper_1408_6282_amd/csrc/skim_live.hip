@@ -20,16 +20,40 @@ namespace skim {
 
 namespace {
 
+// A wave whose 64 edges share one source (the out-edges of a hub: the
+// forward CSR lists them consecutively) adds the forward counts of each
+// instance once, from a ballot, instead of once per live edge: atomics from
+// different waves on the hub's counters are serialised.
+__device__ __forceinline__ bool wave_one_source(bool valid, uint32_t u, uint32_t &u0) {
+    const unsigned long long act = __ballot(valid);
+    if (!act) return false;
+    const int leader = __ffsll((long long)act) - 1;
+    u0 = (uint32_t)__shfl((int)u, leader);
+    return __all(!valid || u == u0);
+}
+
 __global__ void k_live_masks(const uint32_t *esrc, const uint32_t *col, const uint32_t *thr,
                              uint64_t m, uint32_t n, uint32_t ell, uint64_t seed, uint64_t *masks,
                              uint32_t *rcnt, uint32_t *fcnt) {
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        const uint32_t u = esrc[e], v = col[e];
-        uint64_t mask = live_mask(seed, n, u, v, thr[e], ell);
-        masks[e] = mask;
+    const uint32_t lane = lane_id();
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < m;
+         base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = base + threadIdx.x;
+        const bool valid = e < m;
+        const uint32_t u = valid ? esrc[e] : 0u, v = valid ? col[e] : 0u;
+        uint64_t mask = valid ? live_mask(seed, n, u, v, thr[e], ell) : 0ull;
+        if (valid) masks[e] = mask;
+        uint32_t u0 = 0;
+        const bool one = fcnt && wave_one_source(valid, u, u0);
+        if (one) {
+            for (uint32_t i = 0; i < ell; ++i) {
+                const unsigned long long b = __ballot((mask >> i) & 1ull);
+                if (lane == i && b) atomicAdd(fcnt + (uint64_t)u0 * kPairStride + i,
+                                              (uint32_t)__popcll(b));
+            }
+        }
         uint32_t *rrow = rcnt ? rcnt + (uint64_t)v * kPairStride : nullptr;
-        uint32_t *frow = fcnt ? fcnt + (uint64_t)u * kPairStride : nullptr;
+        uint32_t *frow = fcnt && !one ? fcnt + (uint64_t)u * kPairStride : nullptr;
         while (mask) {
             const int i = __ffsll((long long)mask) - 1;
             mask &= mask - 1;
@@ -40,14 +64,34 @@ __global__ void k_live_masks(const uint32_t *esrc, const uint32_t *col, const ui
 }
 
 // Scatter: reverse lists hold sources (in-edges of v), forward lists heads.
+// Lists fill from their end (each entry takes the place its atomic returns);
+// a one-source wave reserves each instance's entries with one atomic.
 __global__ void k_live_fill(const uint32_t *esrc, const uint32_t *col, const uint64_t *masks,
-                            uint64_t m, const uint64_t *rptr, uint32_t *rcnt, uint32_t *radj,
-                            const uint64_t *fptr, uint32_t *fcnt, uint32_t *fadj) {
-    for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
-         e += (uint64_t)gridDim.x * blockDim.x) {
-        uint64_t mask = masks[e];
-        if (!mask) continue;
-        const uint32_t u = esrc[e], v = col[e];
+                            uint64_t m, uint32_t ell, const uint64_t *rptr, uint32_t *rcnt,
+                            uint32_t *radj, const uint64_t *fptr, uint32_t *fcnt, uint32_t *fadj) {
+    const uint32_t lane = lane_id();
+    for (uint64_t base = blockIdx.x * (uint64_t)blockDim.x; base < m;
+         base += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = base + threadIdx.x;
+        const bool valid = e < m;
+        uint64_t mask = valid ? masks[e] : 0ull;
+        const uint32_t u = valid ? esrc[e] : 0u, v = valid ? col[e] : 0u;
+        uint32_t u0 = 0;
+        const bool one = fadj && wave_one_source(valid, u, u0);
+        if (one) {
+            for (uint32_t i = 0; i < ell; ++i) {
+                const unsigned long long b = __ballot((mask >> i) & 1ull);
+                if (!b) continue;  // uniform
+                const int leader = __ffsll((long long)b) - 1;
+                const uint64_t p = (uint64_t)u0 * kPairStride + i;
+                const uint32_t c = (uint32_t)__popcll(b);
+                uint32_t old = 0;
+                if ((int)lane == leader) old = atomicSub(fcnt + p, c);
+                old = (uint32_t)__shfl((int)old, leader);
+                if ((mask >> i) & 1ull)
+                    fadj[fptr[p] + old - c + (uint32_t)__popcll(b & ((1ull << lane) - 1ull))] = v;
+            }
+        }
         while (mask) {
             const int i = __ffsll((long long)mask) - 1;
             mask &= mask - 1;
@@ -56,7 +100,7 @@ __global__ void k_live_fill(const uint32_t *esrc, const uint32_t *col, const uin
                 const uint32_t c = atomicSub(rcnt + p, 1u);
                 radj[rptr[p] + c - 1] = u;
             }
-            if (fadj) {
+            if (fadj && !one) {
                 const uint64_t p = (uint64_t)u * kPairStride + i;
                 const uint32_t c = atomicSub(fcnt + p, 1u);
                 fadj[fptr[p] + c - 1] = v;
@@ -404,8 +448,8 @@ LiveLists build_live_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     }
     if (m) {
         LaunchTimer t("k_live_fill", s);
-        k_live_fill<<<grid, 256, 0, s>>>(esrc, g->col, masks, m, rev.ptr, rcnt, rev.adj, fwd.ptr,
-                                         fcnt, fwd.adj);
+        k_live_fill<<<grid, 256, 0, s>>>(esrc, g->col, masks, m, ell, rev.ptr, rcnt, rev.adj,
+                                         fwd.ptr, fcnt, fwd.adj);
         SKIM_LAUNCH_CHECK();
         a.release(masks);
     }
