@@ -33,7 +33,8 @@
 //    out-edges, ends the workgroup's launch; the host runs the rest of that
 //    search level by level on the whole grid (k_resid_level, with the pairs
 //    of long out-lists expanded edge-balanced by k_resid_heavy) and then
-//    relaunches the loop.
+//    relaunches the loop; a search whose next level there is small again is
+//    handed back, and the relaunched loop resumes it at that level.
 //
 // The adaptive error estimate itself (skim_discrepancy_tail) bounds each
 // seed's discrepancy with eq. (chernoff) on a grid of discrepancy values and
@@ -64,6 +65,9 @@ constexpr uint32_t kSkimSerial = 32;
 constexpr uint64_t kSkimHandoff = 8192;
 // ... and so does a seed whose own live out-edges are more than this.
 constexpr uint64_t kSkimHandoffEdges = 16384;
+// A search on the grid whose next level has at most this many pairs goes
+// back to the workgroup (a level there costs less than two launches).
+constexpr uint64_t kSkimHandBack = 2048;
 // On the grid, pairs with more live out-edges than this are expanded by a
 // second launch per level that spreads their edges over every workgroup
 // (at most kHeavyItems per level; more are expanded where they are).
@@ -331,7 +335,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                                                      uint32_t *rec_second) {
     __shared__ unsigned long long s_cursor, s_pool, s_gain, s_best, s_tau, s_fcnt[2];
     __shared__ int s_x, s_filler;
-    __shared__ uint32_t s_found, s_stop, s_fill_cnt, s_second, s_xmin;
+    __shared__ uint32_t s_found, s_stop, s_fill_cnt, s_second, s_xmin, s_resume, s_rcur;
     // size[] and the batch counters live in LDS when the graph is small
     // enough: every pair's search adds to them, and device atomics from
     // different waves on one cache line are serialised.
@@ -357,6 +361,16 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         s_stop = 0;
         s_found = 0;
         C.ncand = 0;
+        // a residual search the grid handed back (its frontier got small):
+        // the launch starts by finishing that seed
+        s_resume = A.ctl->pend == 2;
+        if (s_resume) {
+            A.ctl->pend = 0;
+            s_x = (int)A.ctl->px;
+            s_rcur = A.ctl->rcur;
+            s_gain = A.ctl->rgain;
+            s_fcnt[s_rcur] = A.ctl->rsize[0];
+        }
     }
     __syncthreads();
     // entry t of the batch's searches, laid end to end in thread order
@@ -366,6 +380,8 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
     };
     uint32_t done = 0;
     for (uint32_t it = 0; it < goal; ++it) {
+        const bool resumed = it == 0 && s_resume;  // uniform
+        if (!resumed) {
         if (tid == 0) {
             s_x = -1;
             s_filler = -1;
@@ -558,7 +574,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             }
             __syncthreads();
         }
-        const uint32_t x = (uint32_t)s_x;
+        const uint32_t xs = (uint32_t)s_x;  // the seed
         // ------------------------------------ records for the error estimate
         // The filling pair's search is still in its thread's queue; the batch
         // counters are all zero here and mark it while the sizes are scanned.
@@ -582,7 +598,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                     const uint32_t v = 4 * w2 + h;
                     const uint32_t sz = (uint32_t)((a >> (16 * h)) & 0xFFFFu) -
                                         (uint32_t)((b >> (16 * h)) & 0xFFFFu);
-                    if (v < n && v != x && sz > best2) best2 = sz;
+                    if (v < n && v != xs && sz > best2) best2 = sz;
                 }
             }
             // one LDS atomic per wave: lanes on one address are serialised
@@ -598,6 +614,8 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             rec_tau[it] = s_filler >= 0 ? (uint64_t)s_tau : ~0ull;
             rec_second[it] = s_second;
         }
+        }  // !resumed
+        const uint32_t x = (uint32_t)s_x;
         // ------------------------------------------------- residual problem
         // Level-synchronous over all instances at once: a frontier of pairs
         // (64 v + i) in two halves of the queue area (free here: the scan's
@@ -607,6 +625,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
         // the search go to the whole grid (k_resid_level); the host then
         // completes the seed.
         uint32_t *F[2] = {A.queues, A.queues + (uint64_t)A.n * kPairStride};
+        if (!resumed) {
         if (tid == 0) {
             s_gain = 0;
             s_fcnt[0] = 0;
@@ -624,10 +643,13 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                 if (add) st(F[0] + slot, px);
             }
         }
+        }  // !resumed
         bool handed = false;
         const uint64_t seed_edges = A.fptr[(uint64_t)x * kPairStride + kPairStride] -
                                     A.fptr[(uint64_t)x * kPairStride];
-        for (uint32_t cur = 0, level = 0;; cur ^= 1u, ++level) {
+        // a resumed search continues at its pending level (not level 0)
+        for (uint32_t cur = resumed ? s_rcur : 0u, level = resumed ? 1u : 0u;;
+             cur ^= 1u, ++level) {
             __syncthreads();
             // (the counter reset below is of the next level's counter, read
             // by nobody in this level)
@@ -775,6 +797,13 @@ __global__ void __launch_bounds__(kResidBlock) k_resid_heavy(SkArgs A, uint32_t 
         }
         __syncthreads();  // ex, qs, f0s are reused
     }
+}
+
+// The handed-over search's next level (L) is small: k_skim finishes it.
+__global__ void k_resid_handback(SkArgs A, uint32_t L, uint32_t r0) {
+    A.ctl->rsize[0] = A.ctl->rsize[16 * (L % 3)];
+    A.ctl->rcur = (r0 + L) & 1u;
+    A.ctl->pend = 2;
 }
 
 // The handed-over seed is complete: outputs, and the node leaves the
@@ -1091,18 +1120,28 @@ void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_
             // in batches (an empty level's launch does nothing); every level
             // covers at least one new pair
             const uint64_t max_levels = (uint64_t)A.n * kPairStride + 1;
+            const uint32_t r0 = c.rcur;
             uint32_t L = 0;
+            bool back = false;
             for (;;) {
                 for (int j = 0; j < 8; ++j, ++L) {
-                    k_resid_level<<<kResidGrid, kResidBlock, 0, s>>>(A, L, c.rcur);
+                    k_resid_level<<<kResidGrid, kResidBlock, 0, s>>>(A, L, r0);
                     SKIM_LAUNCH_CHECK();
-                    k_resid_heavy<<<kResidGrid, kResidBlock, 0, s>>>(A, L, c.rcur);
+                    k_resid_heavy<<<kResidGrid, kResidBlock, 0, s>>>(A, L, r0);
                     SKIM_LAUNCH_CHECK();
                 }
                 read_back(&c, A.ctl, sizeof c, s);
-                if (c.rsize[16 * (L % 3)] == 0) break;
+                const uint64_t f = c.rsize[16 * (L % 3)];
+                if (f == 0) break;
+                if (f <= kSkimHandBack) {  // k_skim resumes the search at level L
+                    k_resid_handback<<<1, 1, 0, s>>>(A, L, r0);
+                    SKIM_LAUNCH_CHECK();
+                    back = true;
+                    break;
+                }
                 SKIM_REQUIRE(L < max_levels, "SKIM residual search did not end");
             }
+            if (back) continue;
             k_resid_finish<<<1, 1, 0, s>>>(A, seeds + done, gains + done,
                                            gain_d ? gain_d + done : nullptr);
             SKIM_LAUNCH_CHECK();

@@ -118,3 +118,29 @@ def test_chung_lu_1m_equals_oracle():
     seeds, gains, _, _ = gpu_greedy(g, cfg["ell"], cfg["k"], cfg["seed"], [20, 30])
     assert seeds.tolist() == gold["seeds"]
     assert gains.tolist() == gold["gain_pairs"]
+
+
+@pytest.mark.parametrize("ell,k", [(16, 8), (64, 16)])
+def test_hub_seed_residual_on_the_grid(oracle_lib, ell, k):
+    # a hub with 20,000 out-edges at p = 0.3 over leaves joined by p = 1/8
+    # edges: the first seed is the hub, whose residual search is handed to the
+    # whole grid at its first level (thousands of live out-edges per instance,
+    # expanded edge-balanced), then the loop resumes in the workgroup with the
+    # sizes the grid left; later seeds are small
+    rng = np.random.default_rng(91)
+    leaves = 20000
+    n = 1 + leaves
+    src, dst = [0] * leaves, list(range(1, n))
+    thr = [int(0xFFFFFFFF * 0.3)] * leaves
+    seen = set(zip(src, dst))
+    for a, b in zip(rng.integers(1, n, 40000).tolist(), rng.integers(1, n, 40000).tolist()):
+        if a != b and (a, b) not in seen:
+            seen.add((a, b))
+            src.append(a)
+            dst.append(b)
+            thr.append(0xFFFFFFFF // 8)
+    g = from_edges(n, src, dst, thr)
+    seeds, gains, _, _ = gpu_greedy(g, ell, k, 3, [5, 7])
+    ws, wg, _ = oracle_lib.skim(g, 3, ell, k, 12)
+    assert seeds[0] == 0
+    assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
