@@ -33,10 +33,12 @@ void clear_error() { g_err[0] = 0; }
 // Calls take their scratch from a per-device cache of device blocks: a block
 // is allocated once (hipMalloc) and reused by later calls, so a build does
 // not map ~20 GB afresh.  (The runtime's stream-ordered pool was measured to
-// get slower with every call in a long-running process.)  Every non-persistent
-// arena synchronises its stream before its blocks go back to the cache, so a
-// cached block is never still in use by a queued kernel; blocks released in
-// the middle of a call are reused only by the same arena (same stream).
+// get slower with every call in a long-running process.)  An arena
+// synchronises its stream (a persistent one, whose state calls on any stream
+// may use, its device) before its blocks go back to the cache, so a cached
+// block is never still in use by a queued kernel; blocks a call arena
+// releases in the middle of the call are reused only by that arena (same
+// stream).
 namespace {
 struct DeviceCache {
     std::multimap<size_t, void *> free;  // block size -> block
@@ -81,19 +83,29 @@ Arena::Arena(hipStream_t s, bool persistent) : s_(s), persistent_(persistent) {
     dev_ = current_device();
 }
 
-Arena::~Arena() {
-    if (persistent_) {
-        for (auto &b : bufs_)
-            if (b.p) (void)hipFree(b.p);
+// Wait until nothing queued on the arena's device can still use its blocks:
+// its stream, or for a persistent arena (state used by calls on any stream)
+// the whole device.
+static void quiesce(int dev, hipStream_t s, bool whole_device) {
+    if (!whole_device) {
+        (void)hipStreamSynchronize(s);
         (void)hipGetLastError();
         return;
     }
+    int cur = dev;
+    (void)hipGetDevice(&cur);
+    if (cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    if (cur != dev) (void)hipSetDevice(cur);
+    (void)hipGetLastError();
+}
+
+Arena::~Arena() {
     bool any = false;
     for (auto &b : bufs_) any |= b.p != nullptr;
     for (auto &b : spare_) any |= b.p != nullptr;
     if (!any) return;
-    (void)hipStreamSynchronize(s_);  // nothing queued may still use the blocks
-    (void)hipGetLastError();
+    quiesce(dev_, s_, persistent_);
     std::lock_guard<std::mutex> lk(g_cache_mu);
     DeviceCache &C = g_cache[dev_];
     if (!C.limit) {
@@ -131,17 +143,8 @@ void *Arena::get(size_t bytes) {
     const size_t cls = size_class(bytes);
     void *p = nullptr;
     size_t got = cls;
-    if (persistent_) {
-        hipError_t e = hipMalloc(&p, cls);
-        if (e != hipSuccess || !p) {
-            (void)hipGetLastError();
-            set_error("device allocation of %zu bytes failed: %s", cls, hipGetErrorString(e));
-            throw Fail{SKIM_ENOMEM};
-        }
-        bufs_.push_back({p, cls});
-        return p;
-    }
-    // a block this arena released earlier (same stream: ordered)
+    // a block this arena released earlier (same stream: ordered; persistent
+    // arenas hand released blocks back to the cache instead)
     for (auto &b : spare_)
         if (b.p && b.bytes >= cls && b.bytes <= cls + cls / 4) {
             bufs_.push_back(b);
@@ -196,9 +199,11 @@ void Arena::release(void *p) {
     if (!p) return;
     for (auto &b : bufs_)
         if (b.p == p) {
-            if (persistent_) {
-                (void)hipStreamSynchronize(s_);
-                (void)hipFree(b.p);
+            if (persistent_) {  // to the cache, once nothing can still use it
+                quiesce(dev_, s_, true);
+                std::lock_guard<std::mutex> lk(g_cache_mu);
+                g_cache[dev_].free.emplace(b.bytes, b.p);
+                g_cache[dev_].cached += b.bytes;
             } else {
                 spare_.push_back(b);  // reusable by this arena's later allocations
             }

@@ -147,8 +147,9 @@ struct Fail {
 
 // Scratch of one call on one stream.  Blocks come from a per-device cache
 // (hipMalloc on a miss) and return to it when the arena dies, after a
-// synchronisation of the stream; a persistent arena owns its blocks outright
-// (hipMalloc / hipFree) for state that outlives a call.
+// synchronisation of the stream.  A persistent arena holds state that
+// outlives a call (used by calls on any stream): its blocks go back to the
+// cache after a synchronisation of the whole device.
 class Arena {
   public:
     explicit Arena(hipStream_t s, bool persistent = false);
