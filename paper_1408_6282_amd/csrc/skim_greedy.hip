@@ -76,6 +76,10 @@ constexpr uint32_t kHeavyItems = 1u << 16;
 // Entries of the nodes that fill within a batch, kept to find the filling
 // prefix directly (more: binary search over prefixes).
 constexpr uint32_t kSkimCand = 1024;
+// The first kSkimLdsFront entries of a residual level in the workgroup live
+// in LDS (the rest in the queue area): small levels never go through global
+// memory between one level and the next.
+constexpr uint32_t kSkimLdsFront = 2048;
 constexpr int kResidBlock = 256;
 constexpr uint32_t kResidGrid = 1024;
 
@@ -234,14 +238,19 @@ template <uint32_t NT, bool Precheck>
 __device__ __forceinline__ void resid_chunk(const SkArgs &A, uint32_t *SZ, const uint32_t *Fin,
                                             uint32_t *Fout, uint64_t fc, uint64_t base,
                                             FlatShared<NT> &X, unsigned long long *next,
-                                            ResidStage *stage, unsigned long long *hcount) {
+                                            ResidStage *stage, unsigned long long *hcount,
+                                            const uint32_t *lfin = nullptr,
+                                            uint32_t *lfout = nullptr) {
     const uint32_t tid = threadIdx.x;
     // one wave's newly covered pairs: to the stage (when there is one) or
     // straight to Fout
     auto push = [&](bool add, uint32_t qw) {
         if (!stage) {
             const uint64_t slot = wave_reserve(next, add);
-            if (add) st(Fout + slot, qw);
+            if (add) {
+                if (lfout && slot < kSkimLdsFront) lfout[slot] = qw;
+                else st(Fout + slot, qw);
+            }
             return;
         }
         const unsigned long long m = __ballot(add);
@@ -271,7 +280,7 @@ __device__ __forceinline__ void resid_chunk(const SkArgs &A, uint32_t *SZ, const
     uint32_t q = 0, o = 0, c = 0;
     uint64_t f0 = 0, deg = 0;
     if (e < fc) {
-        q = Fin[e];
+        q = lfin && e < kSkimLdsFront ? lfin[e] : Fin[e];
         const uint64_t ix = ld(A.idx + q);
         c = (uint32_t)ix;
         if (c) {
@@ -343,6 +352,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
     __shared__ __align__(8) uint32_t s_bcnt[kSkimLdsWords];
     __shared__ FlatShared<kSkimBlock> X;
     __shared__ ScanShared C;
+    __shared__ uint32_t s_front[2][kSkimLdsFront];
     const uint32_t tid = threadIdx.x;
     const uint32_t n = A.n, k = A.k;
     const bool in_lds = n <= kSkimLdsNodes;
@@ -640,10 +650,15 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             }
             if (tid < 64) {  // the first wave holds every instance (l <= 64)
                 const uint64_t slot = wave_reserve(&s_fcnt[0], add);
-                if (add) st(F[0] + slot, px);
+                if (add) s_front[0][slot] = px;
             }
         }
-        }  // !resumed
+        } else {
+            // the grid left the pending level in the queue area
+            const uint64_t fc = s_fcnt[s_rcur];
+            for (uint32_t e = tid; e < fc && e < kSkimLdsFront; e += kSkimBlock)
+                s_front[s_rcur][e] = F[s_rcur][e];
+        }
         bool handed = false;
         const uint64_t seed_edges = A.fptr[(uint64_t)x * kPairStride + kPairStride] -
                                     A.fptr[(uint64_t)x * kPairStride];
@@ -656,6 +671,9 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             const uint64_t fc = s_fcnt[cur];
             if (fc == 0) break;
             if (handoff && (fc > handoff || (level == 0 && seed_edges > kSkimHandoffEdges))) {
+                // the grid reads the level from the queue area
+                for (uint32_t e = tid; e < fc && e < kSkimLdsFront; e += kSkimBlock)
+                    st(F[cur] + e, s_front[cur][e]);
                 if (tid == 0) {
                     A.ctl->pend = 1;
                     A.ctl->px = x;
@@ -675,7 +693,8 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             }
             for (uint64_t base = 0; base < fc; base += kSkimBlock)
                 resid_chunk<kSkimBlock, false>(A, SZ, F[cur], F[cur ^ 1u], fc, base, X,
-                                               &s_fcnt[cur ^ 1u], nullptr, nullptr);
+                                               &s_fcnt[cur ^ 1u], nullptr, nullptr,
+                                               s_front[cur], s_front[cur ^ 1u]);
         }
         if (handed) break;  // uniform
         __syncthreads();
