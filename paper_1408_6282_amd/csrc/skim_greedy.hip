@@ -31,8 +31,8 @@
 //    node in its index entry, which is then erased.  A level of more than
 //    kSkimHandoff pairs, or a seed with more than kSkimHandoffEdges live
 //    out-edges, ends the workgroup's launch; the host runs the rest of that
-//    search level by level on the whole grid (k_resid_level, with the pairs
-//    of long out-lists expanded edge-balanced by k_resid_heavy) and then
+//    search level by level on the whole grid (k_resid_level; pairs of long
+//    out-lists are expanded edge-balanced by the next level's launch) and then
 //    relaunches the loop; a search whose next level there is small again is
 //    handed back, and the relaunched loop resumes it at that level.
 //
@@ -68,9 +68,11 @@ constexpr uint64_t kSkimHandoffEdges = 16384;
 // A search on the grid whose next level has at most this many pairs goes
 // back to the workgroup (a level there costs less than two launches).
 constexpr uint64_t kSkimHandBack = 2048;
-// On the grid, pairs with more live out-edges than this are expanded by a
-// second launch per level that spreads their edges over every workgroup
-// (at most kHeavyItems per level; more are expanded where they are).
+// On the grid, pairs with more live out-edges than this are deferred to the
+// next level's launch, which spreads their edges over every workgroup before
+// it takes its own frontier (their heads join the level after it: the
+// covered set does not depend on the order of the expansions).  At most
+// kHeavyItems per level; more are expanded where they are.
 constexpr uint64_t kSplitEdges = 1024;
 constexpr uint32_t kHeavyItems = 1u << 16;
 // Entries of the nodes that fill within a batch, kept to find the filling
@@ -97,7 +99,7 @@ struct SkCtl {
     unsigned long long rgain;
     unsigned long long pad2[10];
     unsigned long long rsize[3 * 16];
-    unsigned long long hsize[2 * 16];  // heavy pairs of level L: hsize[16 (L % 2)]
+    unsigned long long hsize[3 * 16];  // pairs level L deferred: hsize[16 (L % 3)]
 };
 
 struct SkArgs {
@@ -116,7 +118,7 @@ struct SkArgs {
     uint64_t pool_cap;
     uint32_t *bcnt;         // [2 ceil(n / 4)] per-batch increment counters, packed
     uint32_t *queues;       // [kSkimBlock * n]
-    uint64_t *heavy;        // [2 kHeavyItems] grid residual: (pair, first out-edge, count)
+    uint64_t *heavy;        // [3][2 kHeavyItems] grid residual, deferred (pair, count), first out-edge
     uint32_t *vis;          // [kSkimBlock * vis_words] per-thread visited bitmaps, kept zero
     uint32_t vis_words;     // ceil(n / 32)
     SkCtl *ctl;
@@ -239,7 +241,7 @@ __device__ __forceinline__ void resid_chunk(const SkArgs &A, uint32_t *SZ, const
                                             uint32_t *Fout, uint64_t fc, uint64_t base,
                                             FlatShared<NT> &X, unsigned long long *next,
                                             ResidStage *stage, unsigned long long *hcount,
-                                            const uint32_t *lfin = nullptr,
+                                            uint64_t *hbuf, const uint32_t *lfin = nullptr,
                                             uint32_t *lfout = nullptr) {
     const uint32_t tid = threadIdx.x;
     // one wave's newly covered pairs: to the stage (when there is one) or
@@ -289,11 +291,11 @@ __device__ __forceinline__ void resid_chunk(const SkArgs &A, uint32_t *SZ, const
         }
         f0 = A.fptr[q];
         deg = A.fptr[q + 1] - f0;
-        if (hcount && deg > kSplitEdges) {  // deferred to k_resid_heavy
+        if (hcount && deg > kSplitEdges) {  // deferred to the next level's launch
             const unsigned long long slot = atomicAdd(hcount, 1ull);
             if (slot < kHeavyItems) {
-                A.heavy[2 * slot] = ((uint64_t)q << 32) | (uint32_t)deg;
-                A.heavy[2 * slot + 1] = f0;
+                hbuf[2 * slot] = ((uint64_t)q << 32) | (uint32_t)deg;
+                hbuf[2 * slot + 1] = f0;
                 deg = 0;
             }
         }
@@ -681,7 +683,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                     A.ctl->rsize[0] = fc;
                     A.ctl->rsize[16] = 0;
                     A.ctl->rsize[32] = 0;
-                    A.ctl->hsize[0] = 0;
+                    A.ctl->hsize[0] = A.ctl->hsize[16] = A.ctl->hsize[32] = 0;
                     A.ctl->rgain = s_gain;
                 }
                 handed = true;
@@ -693,7 +695,7 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
             }
             for (uint64_t base = 0; base < fc; base += kSkimBlock)
                 resid_chunk<kSkimBlock, false>(A, SZ, F[cur], F[cur ^ 1u], fc, base, X,
-                                               &s_fcnt[cur ^ 1u], nullptr, nullptr,
+                                               &s_fcnt[cur ^ 1u], nullptr, nullptr, nullptr,
                                                s_front[cur], s_front[cur ^ 1u]);
         }
         if (handed) break;  // uniform
@@ -720,64 +722,51 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
 
 // Level L of a residual search handed over by k_skim, on the whole grid:
 // frontier buffer (r0 + L) & 1 of the queue area, sizes in global memory.
-// A launch whose level is empty does nothing, so the host launches levels
-// in batches and reads the size back after each batch.
+// First the pairs level L - 1 deferred (long out-lists), their edges laid end
+// to end and split evenly over every workgroup, kResidBlock pairs at a time;
+// then the level's own frontier.  Both append to level L + 1.  A launch with
+// nothing to do returns at once, so the host launches levels in batches and
+// reads the sizes back after each batch.
 __global__ void __launch_bounds__(kResidBlock) k_resid_level(SkArgs A, uint32_t L, uint32_t r0) {
     __shared__ FlatShared<kResidBlock> X;
     __shared__ ResidStage S;
-    __shared__ unsigned long long s_fc;
-    if (threadIdx.x == 0) {
+    __shared__ unsigned long long s_fc, s_nh;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) {
         S.n = 0;
         s_fc = ld(&A.ctl->rsize[16 * (L % 3)]);
+        s_nh = ld(&A.ctl->hsize[16 * ((L + 2) % 3)]);  // deferred by level L - 1
         if (blockIdx.x == 0) {
             A.ctl->rsize[16 * ((L + 2) % 3)] = 0;  // level L + 1 appends there
-            A.ctl->hsize[16 * ((L + 1) % 2)] = 0;  // and defers its heavy pairs there
+            A.ctl->hsize[16 * ((L + 1) % 3)] = 0;  // and defers there
             A.ctl->rgain += s_fc;
         }
     }
     __syncthreads();
     const uint64_t fc = s_fc;
-    if (fc == 0) return;  // uniform
+    const uint32_t nh = s_nh < kHeavyItems ? (uint32_t)s_nh : kHeavyItems;
+    if (fc == 0 && nh == 0) return;  // uniform
     const uint32_t cur = (r0 + L) & 1u;
     const uint64_t half = (uint64_t)A.n * kPairStride;
     const uint32_t *Fin = A.queues + cur * half;
     uint32_t *Fout = A.queues + (cur ^ 1u) * half;
-    for (uint64_t base = (uint64_t)blockIdx.x * kResidBlock; base < fc;
-         base += (uint64_t)gridDim.x * kResidBlock)
-        resid_chunk<kResidBlock, true>(A, A.size, Fin, Fout, fc, base, X,
-                                       &A.ctl->rsize[16 * ((L + 1) % 3)], &S,
-                                       &A.ctl->hsize[16 * (L % 2)]);
-}
-
-// The out-edges of level L's deferred pairs, spread evenly over the grid,
-// kResidBlock pairs at a time; appends go to level L + 1 like the level's.
-__global__ void __launch_bounds__(kResidBlock) k_resid_heavy(SkArgs A, uint32_t L, uint32_t r0) {
-    __shared__ uint64_t ex[kResidBlock + 1], wsum[kResidBlock / 64], f0s[kResidBlock];
-    __shared__ uint32_t qs[kResidBlock];
-    __shared__ ResidStage S;
-    const uint32_t tid = threadIdx.x;
-    const unsigned long long hc = A.ctl->hsize[16 * (L % 2)];
-    const uint32_t nh = hc < kHeavyItems ? (uint32_t)hc : kHeavyItems;
-    if (nh == 0) return;  // uniform
-    if (tid == 0) S.n = 0;
-    const uint32_t cur = (r0 + L) & 1u;
-    uint32_t *Fout = A.queues + (cur ^ 1u) * (uint64_t)A.n * kPairStride;
     unsigned long long *next = &A.ctl->rsize[16 * ((L + 1) % 3)];
+    const uint64_t *hin = A.heavy + 2 * (uint64_t)kHeavyItems * ((L + 2) % 3);
     for (uint32_t h0 = 0; h0 < nh; h0 += kResidBlock) {
         uint64_t deg = 0, f0 = 0;
         uint32_t q = 0;
         if (h0 + tid < nh) {
-            const uint64_t w = A.heavy[2 * (h0 + tid)];
+            const uint64_t w = hin[2 * (h0 + tid)];
             q = (uint32_t)(w >> 32);
             deg = (uint32_t)w;
-            f0 = A.heavy[2 * (h0 + tid) + 1];
+            f0 = hin[2 * (h0 + tid) + 1];
         }
         uint64_t tot;
-        const uint64_t e = block_excl_scan<kResidBlock>(deg, wsum, tot);
-        ex[tid] = e;
-        qs[tid] = q;
-        f0s[tid] = f0;
-        if (tid == 0) ex[kResidBlock] = tot;
+        const uint64_t e = block_excl_scan<kResidBlock>(deg, X.wsum, tot);
+        X.ex[tid] = e;
+        X.q[tid] = q;
+        X.f0[tid] = f0;
+        if (tid == 0) X.ex[kResidBlock] = tot;
         __syncthreads();
         const uint64_t a = tot * blockIdx.x / gridDim.x, b = tot * (blockIdx.x + 1) / gridDim.x;
         for (uint64_t base = a; base < b; base += kResidBlock) {
@@ -785,8 +774,8 @@ __global__ void __launch_bounds__(kResidBlock) k_resid_heavy(SkArgs A, uint32_t 
             bool add = false;
             uint32_t qw = 0;
             if (t < b) {
-                const uint32_t r = run_of<kResidBlock>(ex, t);
-                qw = A.fadj[f0s[r] + (t - ex[r])] * kPairStride + qs[r] % kPairStride;
+                const uint32_t r = run_of<kResidBlock>(X.ex, t);
+                qw = A.fadj[X.f0[r] + (t - X.ex[r])] * kPairStride + X.q[r] % kPairStride;
                 add = !ld(A.covered + qw) && atomicCAS(A.covered + qw, 0u, 1u) == 0u;
             }
             const unsigned long long m = __ballot(add);
@@ -814,8 +803,13 @@ __global__ void __launch_bounds__(kResidBlock) k_resid_heavy(SkArgs A, uint32_t 
                 __syncthreads();
             }
         }
-        __syncthreads();  // ex, qs, f0s are reused
+        __syncthreads();  // X is reused
     }
+    uint64_t *hout = A.heavy + 2 * (uint64_t)kHeavyItems * (L % 3);
+    for (uint64_t base = (uint64_t)blockIdx.x * kResidBlock; base < fc;
+         base += (uint64_t)gridDim.x * kResidBlock)
+        resid_chunk<kResidBlock, true>(A, A.size, Fin, Fout, fc, base, X, next, &S,
+                                       &A.ctl->hsize[16 * (L % 3)], hout);
 }
 
 // The handed-over search's next level (L) is small: k_skim finishes it.
@@ -1079,7 +1073,7 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
     A.size = M.alloc<uint32_t>(cwords);
     A.sel = M.alloc<uint32_t>(n);
     A.idx = M.alloc<uint64_t>(npairs);
-    A.heavy = M.alloc<uint64_t>(2 * (uint64_t)kHeavyItems);
+    A.heavy = M.alloc<uint64_t>(3 * 2 * (uint64_t)kHeavyItems);
     A.bcnt = M.alloc<uint32_t>(cwords);
     A.queues = M.alloc<uint32_t>((uint64_t)kSkimBlock * n);
     A.vis_words = (n + 31) / 32;
@@ -1146,13 +1140,12 @@ void greedy_run(skim_greedy_state *st, uint32_t s_goal, uint32_t *seeds, uint64_
                 for (int j = 0; j < 8; ++j, ++L) {
                     k_resid_level<<<kResidGrid, kResidBlock, 0, s>>>(A, L, r0);
                     SKIM_LAUNCH_CHECK();
-                    k_resid_heavy<<<kResidGrid, kResidBlock, 0, s>>>(A, L, r0);
-                    SKIM_LAUNCH_CHECK();
                 }
                 read_back(&c, A.ctl, sizeof c, s);
-                const uint64_t f = c.rsize[16 * (L % 3)];
-                if (f == 0) break;
-                if (f <= kSkimHandBack) {  // k_skim resumes the search at level L
+                // level L's frontier, and the pairs level L - 1 deferred
+                const uint64_t f = c.rsize[16 * (L % 3)], h = c.hsize[16 * ((L + 2) % 3)];
+                if (f == 0 && h == 0) break;
+                if (h == 0 && f <= kSkimHandBack) {  // k_skim resumes the search at level L
                     k_resid_handback<<<1, 1, 0, s>>>(A, L, r0);
                     SKIM_LAUNCH_CHECK();
                     back = true;
