@@ -286,6 +286,18 @@ def bench_rmat(torch, sk, steps=2):
                                  if gold.get("oracle_seconds") else None}}
     del G, ranks, size, est
     torch.cuda.empty_cache()
+    # the searches' random accesses at the rates plain gathers and atomics
+    # reach on a table the size of this build's pair records (17 GB: no
+    # cache holds it)
+    try:
+        ra = random_access_rates(torch, table_log2=31)
+        floor_s = work["scans"] / ra["gather_per_s"] + work["visits"] / ra["atomic_add_per_s"]
+        ra.update({"scans": work["scans"], "visits": work["visits"],
+                   "search_floor_ms": floor_s * 1e3, "search_floor_over_build": floor_s / sec})
+        out["random_access"] = ra
+    except RuntimeError as e:  # not enough free device memory for the table
+        out["random_access"] = {"skipped": str(e)[:200]}
+        torch.cuda.empty_cache()
     return out
 
 
