@@ -259,12 +259,24 @@ __device__ __forceinline__ bool hslot_free(uint64_t cur, uint32_t tag) {
 // 1 = inserted, 0 = already present, -1 = table full.  Slots only go from
 // free to live within a window, so a probe chain never loses a key.
 // Each probe starts with a CAS that expects an empty slot (the common case
-// at the set's load): its return value is the slot's content, so no load
-// precedes it.
-__device__ int hset_insert(uint64_t *T, uint32_t logcap, uint64_t key, uint32_t tag) {
+// when most keys are new): its return value is the slot's content, so no
+// load precedes it.  With look_first (graphs whose dense cores bring the
+// same (pair, source) key back many times) a plain load comes first, so a
+// key already present costs no atomic: atomics on one line are serialised,
+// loads are not.
+__device__ int hset_insert(uint64_t *T, uint32_t logcap, uint64_t key, uint32_t tag,
+                           bool look_first = false) {
     const uint64_t mask = (1ull << logcap) - 1;
     uint64_t h = hmix(key) & mask;
     for (int probe = 0; probe < 256; ++probe) {
+        if (look_first) {
+            const uint64_t seen = load_relaxed(T + h);
+            if (seen == key) return 0;
+            if (!hslot_free(seen, tag)) {
+                h = (h + 1) & mask;
+                continue;
+            }
+        }
         uint64_t cur = atomicCAS((unsigned long long *)(T + h), kNone, key);
         if (cur == kNone) return 1;
         if (cur == key) return 0;
@@ -310,7 +322,9 @@ struct WinArgs {
     uint64_t *flive[2];    // the pair's live-list word
     uint64_t front_cap;
     Ctl *ctl;
-    uint64_t *heavy;       // [2 kHeavyMax] entries with long lists (key, list word), for k_expand_heavy
+    uint64_t *heavy;       // [2 kHeavyMax] entries with long lists (key, list word), for
+                           // k_expand_heavy; set only on graphs with such lists, which also
+                           // probe the hash set load-first
 };
 
 // Visit of pair q by the search of source pair src: 1 if it is a new visit
@@ -336,7 +350,8 @@ __device__ __forceinline__ int claim(const WinArgs &A, uint32_t q, uint32_t src,
             continue;
         }
         if ((uint32_t)old == src) return 0;
-        const int r = hset_insert(A.hset, A.logcap, hkey(q, src, A.htag), A.htag);
+        const int r =
+            hset_insert(A.hset, A.logcap, hkey(q, src, A.htag), A.htag, A.heavy != nullptr);
         if (r <= 0) {
             if (r < 0) atomicOr(&A.ctl->flags, kOvfHash);
             return 0;
