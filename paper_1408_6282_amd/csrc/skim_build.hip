@@ -488,6 +488,11 @@ struct ExpandShared {
     uint32_t nheavy;
 };
 
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t x, uint32_t src) {
+    const uint32_t lo = __shfl((uint32_t)x, (int)src), hi = __shfl((uint32_t)(x >> 32), (int)src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ uint64_t shfl_up_u64(uint64_t x, uint32_t d) {
     const uint32_t lo = __shfl_up((uint32_t)x, d), hi = __shfl_up((uint32_t)(x >> 32), d);
     return ((uint64_t)hi << 32) | lo;
@@ -556,35 +561,70 @@ __device__ __forceinline__ void expand_range(const WinArgs &A, uint32_t L,
     const uint64_t stride = (uint64_t)gridDim.x * chunk;
     for (uint64_t c = (uint64_t)blockIdx.x * chunk; c < b; c += stride) {
         const uint64_t end = c + chunk < b ? c + chunk : b;
-        for (uint64_t t = c + threadIdx.x; t < end; t += blockDim.x) {
-            const uint64_t it = ckey[t], live = clive[t];
-            const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
-            const uint32_t src = (uint32_t)it;
-            if (live & kLiveOne) {
-                visit_edge(A, (uint32_t)live, i, src, nkey, nlive, next_count, X, scans, hashed,
-                           visits);
+        // Each wave lays the short lists of its 64 entries end to end and
+        // takes them 64 entries at a time (a lane finds the entry of its
+        // position by binary lifting over the wave's prefix sums), so one
+        // lane's longer list does not hold the others.
+        const uint32_t lane = lane_id();
+        for (uint64_t tb = c; tb < end; tb += blockDim.x) {
+            const uint64_t t = tb + threadIdx.x;
+            uint64_t it = 0, live = 0;
+            uint32_t nwork = 0;
+            if (t < end) {
+                it = ckey[t];
+                live = clive[t];
+                const uint32_t cnt = (live & kLiveOne) ? 1u : live_count(live);
+                nwork = cnt;
+                if (cnt > kSplitLive && A.heavy) {  // a hub's list: the whole grid, next launch
+                    const unsigned long long slot =
+                        atomicAdd(&A.ctl->hsize[16 * (L % 2)], 1ull);
+                    if (slot < kHeavyMax) {
+                        A.heavy[2 * slot] = it;
+                        A.heavy[2 * slot + 1] = live;
+                        nwork = 0;
+                    }
+                }
+                if (nwork > kSerialEdges) {  // a long list: the whole block takes it below
+                    const uint32_t slot = stage_slots(&X.nheavy);
+                    if (slot < kHeavyCap) {
+                        X.heavy[slot] = (uint32_t)(t - c);
+                        nwork = 0;
+                    }
+                }
+            }
+            if (__all(nwork <= 1)) {  // the common case: at most one edge per entry
+                if (nwork) {
+                    const uint32_t w =
+                        (live & kLiveOne) ? (uint32_t)live : A.lsrc[live >> kLiveCountBits];
+                    visit_edge(A, w, (uint32_t)(it >> 32) % kPairStride, (uint32_t)it, nkey,
+                               nlive, next_count, X, scans, hashed, visits);
+                }
                 continue;
             }
-            const uint32_t cnt = live_count(live);
-            if (cnt > kSplitLive && A.heavy) {  // a hub's list: the whole grid, next launch
-                const unsigned long long slot = atomicAdd(&A.ctl->hsize[16 * (L % 2)], 1ull);
-                if (slot < kHeavyMax) {
-                    A.heavy[2 * slot] = it;
-                    A.heavy[2 * slot + 1] = live;
-                    continue;
+            uint32_t incl = nwork;  // inclusive prefix over the wave
+            for (uint32_t off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off);
+                if (lane >= off) incl += y;
+            }
+            const uint32_t total = __shfl(incl, 63);
+            for (uint32_t base = 0; base < total; base += 64) {
+                const uint32_t j = base + lane;
+                uint32_t r = 0;  // lanes whose entries end at or before position j
+                for (uint32_t step = 32; step > 0; step >>= 1) {
+                    const uint32_t v = __shfl(incl, (int)(r + step - 1));
+                    if (v <= j) r += step;
+                }
+                const uint32_t rr = r & 63u;
+                const uint32_t first = __shfl(incl, (int)rr) - __shfl(nwork, (int)rr);
+                const uint64_t rit = shfl_u64(it, rr), rlive = shfl_u64(live, rr);
+                if (j < total) {
+                    const uint32_t w = (rlive & kLiveOne)
+                                           ? (uint32_t)rlive
+                                           : A.lsrc[(rlive >> kLiveCountBits) + (j - first)];
+                    visit_edge(A, w, (uint32_t)(rit >> 32) % kPairStride, (uint32_t)rit, nkey,
+                               nlive, next_count, X, scans, hashed, visits);
                 }
             }
-            if (cnt > kSerialEdges) {  // a long list: the whole block takes it below
-                const uint32_t slot = stage_slots(&X.nheavy);
-                if (slot < kHeavyCap) {
-                    X.heavy[slot] = (uint32_t)(t - c);
-                    continue;
-                }
-            }
-            const uint64_t e0 = live >> kLiveCountBits;
-            for (uint64_t e = e0; e < e0 + cnt; ++e)
-                visit_edge(A, A.lsrc[e], i, src, nkey, nlive, next_count, X, scans, hashed,
-                           visits);
         }
         __syncthreads();
         // Long live lists (hubs) spread over all threads of the block, one
