@@ -817,8 +817,8 @@ struct TailsShared {
     uint64_t live[2][kTailsCap];
     uint32_t n[2];
     StageR R;
-    uint32_t heavy[kHeavyCap];
-    uint32_t nheavy;
+    uint32_t ex[kTailsCap + 1];  // the level's live edges laid end to end: entry starts
+    uint32_t wsum[kTailsBlock / 64];
     uint32_t hashed;
     uint32_t spilled;
     unsigned long long work;
@@ -878,7 +878,6 @@ __global__ void __launch_bounds__(kTailsBlock) k_tails(WinArgs A, uint32_t L, ui
     for (;;) {
         if (tid == 0) {
             T.n[cur ^ 1] = 0;
-            T.nheavy = 0;
             T.hashed = 0;
             T.spilled = 0;
             T.work = 0;
@@ -922,36 +921,47 @@ __global__ void __launch_bounds__(kTailsBlock) k_tails(WinArgs A, uint32_t L, ui
         }
         const uint32_t nxt = cur ^ 1;
         uint32_t hashed = 0;
-        for (uint32_t t = tid; t < nc; t += blockDim.x) {
-            const uint64_t it = T.key[cur][t], live = T.live[cur][t];
-            const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
-            const uint32_t src = (uint32_t)it;
-            if (live & kLiveOne) {
-                tails_visit(A, T, nxt, (uint32_t)live, i, src, scans, hashed, visits);
-                continue;
-            }
-            const uint32_t cnt = live_count(live);
-            if (cnt > kSerialEdges) {
-                const uint32_t slot = stage_slots(&T.nheavy);
-                if (slot < kHeavyCap) {
-                    T.heavy[slot] = t;
-                    continue;
+        {   // the level's live edges (at most kTailsCap) laid end to end and
+            // taken kTailsBlock at a time: thread t owns entries 2t and 2t + 1
+            uint32_t c[2] = {0, 0};
+            for (uint32_t h = 0; h < 2; ++h) {
+                const uint32_t e = 2 * tid + h;
+                if (e < nc) {
+                    const uint64_t lv = T.live[cur][e];
+                    c[h] = (lv & kLiveOne) ? 1u : live_count(lv);
                 }
             }
-            const uint64_t e0 = live >> kLiveCountBits;
-            for (uint64_t e = e0; e < e0 + cnt; ++e)
-                tails_visit(A, T, nxt, A.lsrc[e], i, src, scans, hashed, visits);
-        }
-        __syncthreads();
-        const uint32_t nh = T.nheavy < kHeavyCap ? T.nheavy : kHeavyCap;
-        for (uint32_t h = 0; h < nh; ++h) {
-            const uint32_t t = T.heavy[h];
-            const uint64_t it = T.key[cur][t], live = T.live[cur][t];
-            const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
-            const uint32_t src = (uint32_t)it;
-            const uint64_t e0 = live >> kLiveCountBits, e1 = e0 + live_count(live);
-            for (uint64_t e = e0 + tid; e < e1; e += blockDim.x)
-                tails_visit(A, T, nxt, A.lsrc[e], i, src, scans, hashed, visits);
+            const uint32_t lane = lane_id(), wave = tid >> 6;
+            uint32_t incl = c[0] + c[1];
+            for (uint32_t off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off);
+                if (lane >= off) incl += y;
+            }
+            if (lane == 63u) T.wsum[wave] = incl;
+            __syncthreads();
+            uint32_t before = 0, W = 0;
+            for (uint32_t w = 0; w < kTailsBlock / 64; ++w) {
+                before += w < wave ? T.wsum[w] : 0u;
+                W += T.wsum[w];
+            }
+            const uint32_t start = before + incl - c[0] - c[1];
+            T.ex[2 * tid] = start;
+            T.ex[2 * tid + 1] = start + c[0];
+            if (tid == 0) T.ex[kTailsCap] = W;
+            __syncthreads();
+            for (uint32_t p = tid; p < W; p += kTailsBlock) {
+                uint32_t lo = 0, hi = kTailsCap;  // ex[lo] <= p < ex[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (T.ex[mid] <= p) lo = mid;
+                    else hi = mid;
+                }
+                const uint64_t it = T.key[cur][lo], lv = T.live[cur][lo];
+                const uint32_t w = (lv & kLiveOne) ? (uint32_t)lv
+                                                   : A.lsrc[(lv >> kLiveCountBits) + (p - T.ex[lo])];
+                tails_visit(A, T, nxt, w, (uint32_t)(it >> 32) % kPairStride, (uint32_t)it, scans,
+                            hashed, visits);
+            }
         }
         if (hashed) atomicAdd(&T.hashed, hashed);
         __syncthreads();
