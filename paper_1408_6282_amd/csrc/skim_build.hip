@@ -486,6 +486,9 @@ struct ExpandShared {
     StageR R;
     uint32_t heavy[kHeavyCap];  // frontier positions of this round's long lists
     uint32_t nheavy;
+    uint32_t hex[kHeavyCap + 1];  // their starts when laid end to end
+    uint64_t hkey[kHeavyCap], hlive[kHeavyCap];
+    uint32_t hwsum[kBlock / 64];
 };
 
 __device__ __forceinline__ uint64_t shfl_u64(uint64_t x, uint32_t src) {
@@ -627,18 +630,46 @@ __device__ __forceinline__ void expand_range(const WinArgs &A, uint32_t L,
             }
         }
         __syncthreads();
-        // Long live lists (hubs) spread over all threads of the block, one
-        // list after the other, instead of one thread walking each.
+        // Long live lists (up to 4096 sources) laid end to end and spread
+        // over all threads of the block, instead of one thread walking each.
         const uint32_t nh = X.nheavy < kHeavyCap ? X.nheavy : kHeavyCap;
-        for (uint32_t h = 0; h < nh; ++h) {
-            const uint64_t t = c + X.heavy[h];
-            const uint64_t it = ckey[t], live = clive[t];
-            const uint32_t i = (uint32_t)(it >> 32) % kPairStride;
-            const uint32_t src = (uint32_t)it;
-            const uint64_t e0 = live >> kLiveCountBits, e1 = e0 + live_count(live);
-            for (uint64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x)
-                visit_edge(A, A.lsrc[e], i, src, nkey, nlive, next_count, X, scans, hashed,
-                           visits);
+        if (nh) {  // uniform: read after the barrier
+            static_assert(kHeavyCap == kBlock, "one long list per thread");
+            const uint32_t tid = threadIdx.x, wave = tid >> 6;
+            uint32_t cnt = 0;
+            if (tid < nh) {
+                const uint64_t t = c + X.heavy[tid];
+                X.hkey[tid] = ckey[t];
+                X.hlive[tid] = clive[t];
+                cnt = live_count(X.hlive[tid]);
+            }
+            uint32_t incl = cnt;
+            for (uint32_t off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off);
+                if (lane >= off) incl += y;
+            }
+            if (lane == 63u) X.hwsum[wave] = incl;
+            __syncthreads();
+            uint32_t before = 0, H = 0;
+            for (uint32_t w = 0; w < kBlock / 64; ++w) {
+                before += w < wave ? X.hwsum[w] : 0u;
+                H += X.hwsum[w];
+            }
+            X.hex[tid] = before + incl - cnt;
+            if (tid == 0) X.hex[kHeavyCap] = H;
+            __syncthreads();
+            for (uint32_t p = tid; p < H; p += blockDim.x) {
+                uint32_t lo = 0, hi = kHeavyCap;  // hex[lo] <= p < hex[hi]
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (X.hex[mid] <= p) lo = mid;
+                    else hi = mid;
+                }
+                const uint64_t it = X.hkey[lo];
+                const uint64_t e = (X.hlive[lo] >> kLiveCountBits) + (p - X.hex[lo]);
+                visit_edge(A, A.lsrc[e], (uint32_t)(it >> 32) % kPairStride, (uint32_t)it, nkey,
+                           nlive, next_count, X, scans, hashed, visits);
+            }
         }
         stage_flush2(X.F, nkey, nlive, A.front_cap, next_count, X.R, A.rec, A.rec_cap,
                      &A.ctl->records, &A.ctl->flags, &X.nheavy);
