@@ -61,6 +61,9 @@ constexpr uint32_t kFlagPool = 1u;
 // walked by their own thread; a batch or level with a longer one spreads
 // its work over the block by flat position.
 constexpr uint32_t kSkimSerial = 32;
+// ... and a wave whose items all have at most this many walks them lane by
+// lane; with a longer one the wave lays them end to end.
+constexpr uint32_t kSkimFlat = 4;
 // A residual level with more pairs than this continues on the whole grid.
 constexpr uint64_t kSkimHandoff = 8192;
 // ... and so does a seed whose own live out-edges are more than this.
@@ -203,6 +206,28 @@ __device__ __forceinline__ uint32_t run_of(const uint64_t *ex, uint64_t t) {
     return lo;
 }
 
+// Inclusive prefix sum over the wave's 64 lanes, and the lane whose range
+// holds flat position j of the wave's items laid end to end (binary lifting
+// over the prefix sums; j below the wave's total).
+__device__ __forceinline__ uint32_t wave_incl(uint32_t v) {
+    const uint32_t lane = threadIdx.x & 63u;
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(v, off);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_owner(uint32_t incl, uint32_t j) {
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t step = 32; step > 0; step >>= 1) {
+        const uint32_t v = (uint32_t)__shfl((int)incl, (int)(r + step - 1));
+        if (v <= j) r += step;
+    }
+    return r & 63u;
+}
+
 // Work that depends on the length of a search or of an adjacency list is
 // spread over the whole block by flat position (prefix sums over the
 // block's items, then a binary search per position), so one long item
@@ -302,11 +327,48 @@ __device__ __forceinline__ void resid_chunk(const SkArgs &A, uint32_t *SZ, const
     }
     const bool light = __syncthreads_or(c > kSkimSerial || deg > kSkimSerial) == 0;
     if (light) {
-        for (uint32_t j = 0; j < c; ++j) csub(SZ, ld(A.pool + o + j), 1u);
-        for (uint64_t x2 = f0; x2 < f0 + deg; ++x2) {
-            const uint32_t qw = A.fadj[x2] * kPairStride + q % kPairStride;
-            const bool add =
-                (!Precheck || !ld(A.covered + qw)) && atomicCAS(A.covered + qw, 0u, 1u) == 0u;
+        // each wave lays its 64 items' index entries, then their out-edges,
+        // end to end and takes them 64 at a time
+        const uint32_t lane = tid & 63u;
+        if (!__any(c > kSkimFlat)) {  // short everywhere: each lane its own
+            for (uint32_t j = 0; j < c; ++j) csub(SZ, ld(A.pool + o + j), 1u);
+        } else {
+            const uint32_t incl = wave_incl(c), total = (uint32_t)__shfl((int)incl, 63);
+            for (uint32_t base = 0; base < total; base += 64) {
+                const uint32_t j = base + lane, r = wave_owner(incl, j);
+                const uint32_t first = (uint32_t)__shfl((int)incl, (int)r) -
+                                       (uint32_t)__shfl((int)c, (int)r);
+                const uint32_t ro = (uint32_t)__shfl((int)o, (int)r);
+                if (j < total) csub(SZ, ld(A.pool + ro + (j - first)), 1u);
+            }
+        }
+        const uint32_t d = (uint32_t)deg;  // <= kSkimSerial here
+        if (!__any(d > kSkimFlat)) {  // short everywhere: each lane its own
+            for (uint64_t x2 = f0; x2 < f0 + d; ++x2) {
+                const uint32_t qw = A.fadj[x2] * kPairStride + q % kPairStride;
+                const bool add = (!Precheck || !ld(A.covered + qw)) &&
+                                 atomicCAS(A.covered + qw, 0u, 1u) == 0u;
+                push(add, qw);
+            }
+            flush();
+            return;
+        }
+        const uint32_t incl = wave_incl(d), total = (uint32_t)__shfl((int)incl, 63);
+        for (uint32_t base = 0; base < total; base += 64) {
+            const uint32_t j = base + lane, r = wave_owner(incl, j);
+            const uint32_t first = (uint32_t)__shfl((int)incl, (int)r) -
+                                   (uint32_t)__shfl((int)d, (int)r);
+            const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)f0, (int)r);
+            const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(f0 >> 32), (int)r);
+            const uint32_t rq = (uint32_t)__shfl((int)q, (int)r);
+            bool add = false;
+            uint32_t qw = 0;
+            if (j < total) {
+                qw = A.fadj[(((uint64_t)hi << 32) | lo) + (j - first)] * kPairStride +
+                     rq % kPairStride;
+                add = (!Precheck || !ld(A.covered + qw)) &&
+                      atomicCAS(A.covered + qw, 0u, 1u) == 0u;
+            }
             push(add, qw);
         }
         flush();
