@@ -102,6 +102,39 @@ def test_hub_lists_spread_over_the_grid(oracle_lib):
         _check(oracle_lib, g, ell, k, seed)
 
 
+def test_medium_lists_spread_over_the_workgroup(oracle_lib):
+    # live in-lists of 17 to 4096 sources (p = 1 in-stars of 20 to 3000
+    # leaves into 12 hubs that feed each other) next to short random lists:
+    # a workgroup lays a chunk's long lists end to end, a wave its entries'
+    # short ones
+    rng = np.random.default_rng(78)
+    sizes = [20, 33, 64, 100, 257, 300, 511, 700, 1000, 1500, 2048, 3000]
+    hubs = len(sizes)
+    n = hubs + sum(sizes)
+    src, dst, thr = [], [], []
+    nxt = hubs
+    for h, sz in enumerate(sizes):
+        for leaf in range(nxt, nxt + sz):
+            src.append(leaf)
+            dst.append(h)
+            thr.append(0xFFFFFFFF)
+        nxt += sz
+        src.append(h)
+        dst.append((h + 1) % hubs)
+        thr.append(0xFFFFFFFF // 2)
+    seen = set(zip(src, dst))
+    for a, b in zip(rng.integers(0, n, 3 * n).tolist(), rng.integers(0, n, 3 * n).tolist()):
+        if a != b and (a, b) not in seen:
+            seen.add((a, b))
+            src.append(a)
+            dst.append(b)
+            thr.append(0xFFFFFFFF // 3)
+    g = from_edges(n, src, dst, thr)
+    for ell, k, seed in ((64, 16, 8), (16, 64, 9)):
+        log(f"medium lists n={n} m={g.m} l={ell} k={k}")
+        _check(oracle_lib, g, ell, k, seed)
+
+
 def test_deterministic_repeat():
     cfg = make_config("tiny-ic")
     g = make_graph(cfg)
