@@ -105,49 +105,127 @@ template <class T> __device__ __forceinline__ void ic_st(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// One thread per position.  A search that would reach more than kIcLight
-// nodes stops, clears what it marked and hands the position to the
-// workgroup search (first pass: appended to the heavy list; second pass:
-// skipped, its count being above kIcLight).
+// Inclusive prefix sum over the wave's lanes, and the lane whose range holds
+// flat position j of the lanes' items laid end to end (binary lifting).
+__device__ __forceinline__ uint32_t ic_wave_incl(uint32_t v, uint32_t lane) {
+#pragma unroll
+    for (uint32_t off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(v, off);
+        if (lane >= off) v += y;
+    }
+    return v;
+}
+__device__ __forceinline__ uint32_t ic_wave_owner(uint32_t incl, uint32_t j) {
+    uint32_t r = 0;
+#pragma unroll
+    for (uint32_t step = 32; step > 0; step >>= 1) {
+        const uint32_t v = (uint32_t)__shfl((int)incl, (int)(r + step - 1));
+        if (v <= j) r += step;
+    }
+    return r & 63u;
+}
+
+// One search per position, one position per thread.  The 64 searches of a
+// wave advance together: at each step every lane takes the next node of its
+// own queue, and the wave lays those nodes' in-edges end to end and tests
+// them 64 at a time, so a lane whose node is a hub (thousands of in-edges,
+// each a coin) does not hold the other 63.  A node that passes its coin and
+// is new to its search (an atomic OR on that search's bitmap) is appended
+// to its queue at its rank among that search's new nodes of the round.  A
+// search that would reach more than kIcLight nodes stops, clears what it
+// marked and hands the position to the workgroup search (first pass:
+// appended to the heavy list; second pass: skipped, its count being above
+// kIcLight).
 template <int kPass>
 __global__ void __launch_bounds__(kIcBlock) k_ic_search(IcArgs A) {
     const uint64_t tid = blockIdx.x * (uint64_t)kIcBlock + threadIdx.x;
     const uint64_t threads = (uint64_t)gridDim.x * kIcBlock;
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint64_t wave0 = tid - lane;  // thread id of the wave's lane 0
     const uint32_t words = (A.n + 31) / 32;
     uint32_t *bm = A.bitmaps + tid * words;
     uint32_t *Q = A.queues + tid * kIcLight;
     const uint64_t total = (uint64_t)A.n * A.k;
     for (uint64_t x0 = 0; x0 < total; x0 += threads) {
         const uint64_t x = x0 + tid;
+        const bool mine = x < total && !(kPass == 1 && A.counts[x] > kIcLight);
+        const uint32_t t = (uint32_t)(x + 1);
         bool heavy = false;
-        if (x < total && !(kPass == 1 && A.counts[x] > kIcLight)) {
-            const uint32_t t = (uint32_t)(x + 1);
+        uint32_t cnt = 0, head = 0;
+        if (mine) {
             const uint32_t v = A.node_at[x];
             Q[0] = v;
-            bm[v >> 5] |= 1u << (v & 31);
-            uint32_t cnt = 1;
-            for (uint32_t head = 0; head < cnt && !heavy; ++head) {
-                const uint32_t y = Q[head];
-                for (uint64_t e = A.rptr[y]; e < A.rptr[y + 1]; ++e) {
-                    const uint32_t u = A.rsrc[e];
-                    const uint32_t bit = 1u << (u & 31);
-                    if ((bm[u >> 5] & bit) == 0 && ic_live(A.seed, A.n, u, y, t, A.rthr[e])) {
-                        if (cnt == kIcLight) {
-                            heavy = true;
-                            break;
-                        }
-                        bm[u >> 5] |= bit;
-                        Q[cnt++] = u;
+            atomicOr(bm + (v >> 5), 1u << (v & 31));
+            cnt = 1;
+        }
+        for (;;) {
+            const bool act = mine && !heavy && head < cnt;
+            if (!__any(act)) break;  // uniform over the wave
+            uint32_t y = 0, d = 0;
+            uint64_t e0 = 0;
+            if (act) {
+                y = Q[head++];
+                e0 = A.rptr[y];
+                d = (uint32_t)(A.rptr[y + 1] - e0);
+            }
+            const uint32_t incl = ic_wave_incl(d, lane);
+            const uint32_t tot = (uint32_t)__shfl((int)incl, 63);
+            const uint32_t mine_first = incl - d;  // this lane's items: [mine_first, incl)
+            for (uint32_t base = 0; base < tot; base += 64) {
+                const uint32_t j = base + lane, r = ic_wave_owner(incl, j);
+                const uint32_t first = (uint32_t)__shfl((int)incl, (int)r) -
+                                       (uint32_t)__shfl((int)d, (int)r);
+                const uint32_t ry = (uint32_t)__shfl((int)y, (int)r);
+                const uint32_t rt = (uint32_t)__shfl((int)t, (int)r);
+                const uint32_t elo = (uint32_t)__shfl((int)(uint32_t)e0, (int)r);
+                const uint32_t ehi = (uint32_t)__shfl((int)(uint32_t)(e0 >> 32), (int)r);
+                const uint32_t rcnt = (uint32_t)__shfl((int)cnt, (int)r);
+                uint32_t u = 0;
+                bool add = false;
+                if (j < tot) {
+                    const uint64_t e = (((uint64_t)ehi << 32) | elo) + (j - first);
+                    u = A.rsrc[e];
+                    if (ic_live(A.seed, A.n, u, ry, rt, A.rthr[e])) {
+                        const uint32_t bit = 1u << (u & 31);
+                        uint32_t *rbm = A.bitmaps + (wave0 + r) * words + (u >> 5);
+                        add = (atomicOr(rbm, bit) & bit) == 0;
                     }
                 }
+                // rank among the same search's new nodes of this round (its
+                // positions are consecutive lanes, from lane first - base on)
+                const unsigned long long m = __ballot(add);
+                const uint32_t lo = first > base ? first - base : 0u;
+                const unsigned long long below =
+                    m & ((1ull << lane) - 1ull) & ~((1ull << lo) - 1ull);
+                if (add) {
+                    const uint32_t idx = rcnt + (uint32_t)__popcll(below);
+                    if (idx < kIcLight) {
+                        A.queues[(wave0 + r) * kIcLight + idx] = u;
+                    } else {  // the search overflows: unmark, it goes to a workgroup
+                        atomicAnd(A.bitmaps + (wave0 + r) * words + (u >> 5),
+                                  ~(1u << (u & 31)));
+                    }
+                }
+                // this lane's search counts its own new nodes of the round
+                if (mine_first < base + 64 && incl > base) {
+                    const uint32_t a = mine_first > base ? mine_first - base : 0u;
+                    const uint32_t b = incl < base + 64 ? incl - base : 64u;
+                    const unsigned long long range =
+                        (b >= 64 ? ~0ull : ((1ull << b) - 1ull)) & ~((1ull << a) - 1ull);
+                    cnt += (uint32_t)__popcll(m & range);
+                }
             }
+            if (cnt > kIcLight) heavy = true;
+        }
+        if (mine) {
+            const uint32_t kept = cnt < kIcLight ? cnt : kIcLight;
             if (kPass == 0) {
                 A.counts[x] = heavy ? 0u : cnt;
-            } else {
+            } else if (!heavy) {
                 uint64_t *out = A.records + A.offsets[x];
-                for (uint32_t j = 0; j < cnt; ++j) out[j] = ((uint64_t)Q[j] << 32) | t;
+                for (uint32_t j = 0; j < kept; ++j) out[j] = ((uint64_t)Q[j] << 32) | t;
             }
-            for (uint32_t j = 0; j < cnt; ++j) bm[Q[j] >> 5] = 0;
+            for (uint32_t j = 0; j < kept; ++j) atomicAnd(bm + (Q[j] >> 5), 0u);
         }
         if (kPass == 0) {  // every lane of the wave takes part in the reservation
             const uint64_t slot = wave_reserve(A.nheavy, heavy);
