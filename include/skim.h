@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SKIM_ABI_VERSION 7u
+#define SKIM_ABI_VERSION 8u
 
 typedef enum {
     SKIM_OK = 0,
@@ -278,6 +278,32 @@ void skim_greedy_state_free(skim_greedy_state *state);
 
 /* Seeds selected so far by a state (0 for NULL). */
 uint32_t skim_greedy_state_selected(const skim_greedy_state *state);
+
+/*
+ * skim_greedy_state_save / skim_greedy_state_load -- suspend a SKIM run and
+ * resume it later, in this or another process (Section 4: sketch building
+ * is suspended when a seed is found and resumed after the residual update;
+ * a saved state is the run between two such steps).  The saved image holds
+ * the run's progress: covered pairs, partial sketch sizes, selected nodes,
+ * the inverted index and its pool, the rank cursor and the per-seed error
+ * records; what follows from (g, l, k, seed) alone (live lists, rank order)
+ * is rebuilt by the load.
+ *   save: buf [*bytes] out, HOST; buf NULL stores the size needed in
+ *         *bytes; otherwise *bytes must be at least that size and receives
+ *         it.  The state is unchanged.
+ *   load: g, l, k, seed as for the saved run (the graph must be the same:
+ *         n and m are checked, and the image records them); buf [bytes] in,
+ *         HOST.  *state receives a new state; resuming it with skim_greedy
+ *         selects what the saved run would have selected next.
+ * Errors: SKIM_EINVAL for a NULL state or bytes, a buffer too small, or an
+ * image that is not a saved state of this graph and parameters (nothing is
+ * returned in *state then).  Both calls synchronise the stream.
+ */
+skim_status skim_greedy_state_save(const skim_greedy_state *state, void *buf, uint64_t *bytes,
+                                   void *stream);
+skim_status skim_greedy_state_load(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+                                   const void *buf, uint64_t bytes, skim_greedy_state **state,
+                                   void *stream);
 
 /*
  * skim_build_ic_sketches -- sketches for the IC model itself (Section 3,

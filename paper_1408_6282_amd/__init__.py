@@ -32,7 +32,7 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_debug_inject", "skim_server_cancel", "skim_sketches_create",
            "skim_build_sketches_resident", "skim_sketches_data", "skim_sketches_query",
            "skim_sketches_free", "skim_discrepancy_tail_noalloc", "skim_build_sketches_perm",
-           "skim_perm_query_batch"]
+           "skim_perm_query_batch", "skim_greedy_state_save", "skim_greedy_state_load"]
 
 SKIM_FAULT_ALLOC, SKIM_FAULT_SERVE = 1, 2
 
@@ -99,6 +99,11 @@ def load_library(path: str | None = None):
     lib.skim_greedy_state_free.argtypes = [vp]
     lib.skim_greedy_state_selected.restype = C.c_uint32
     lib.skim_greedy_state_selected.argtypes = [vp]
+    lib.skim_greedy_state_save.restype = C.c_int
+    lib.skim_greedy_state_save.argtypes = [vp, vp, C.POINTER(C.c_uint64), vp]
+    lib.skim_greedy_state_load.restype = C.c_int
+    lib.skim_greedy_state_load.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint64, vp, C.c_uint64,
+                                           C.POINTER(vp), vp]
     lib.skim_greedy_records.restype = C.c_int
     lib.skim_greedy_records.argtypes = [vp, C.c_uint32, C.c_uint32, vp, vp, vp]
     lib.skim_tune_build_cached.restype = C.c_int
@@ -475,6 +480,28 @@ class GreedyState:
         if self.handle:
             load_library().skim_greedy_state_free(self.handle)
             self.handle = C.c_void_p(None)
+
+    def save(self, stream=None) -> bytes:
+        """The run's progress as bytes (skim_greedy_state_save)."""
+        lib = load_library()
+        n = C.c_uint64(0)
+        _check("skim_greedy_state_save",
+               lib.skim_greedy_state_save(self.handle, None, C.byref(n), _stream(stream)))
+        buf = C.create_string_buffer(max(int(n.value), 1))
+        _check("skim_greedy_state_save",
+               lib.skim_greedy_state_save(self.handle, buf, C.byref(n), _stream(stream)))
+        return buf.raw[:int(n.value)]
+
+    @classmethod
+    def load(cls, graph: "DeviceGraph", ell: int, k: int, seed: int, data: bytes, stream=None):
+        """A state resumed from saved bytes (skim_greedy_state_load)."""
+        st = cls()
+        buf = C.create_string_buffer(bytes(data), len(data))
+        _check("skim_greedy_state_load",
+               load_library().skim_greedy_state_load(C.byref(graph.struct), ell, k,
+                                                     seed & 0xFFFFFFFFFFFFFFFF, buf, len(data),
+                                                     C.byref(st.handle), _stream(stream)))
+        return st
 
     def __del__(self):
         try:

@@ -46,6 +46,7 @@
 #include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
+#include <cstring>
 #include <memory>
 #include <utility>
 
@@ -1264,6 +1265,155 @@ extern "C" void skim_greedy_state_free(skim_greedy_state *state) { delete state;
 
 extern "C" uint32_t skim_greedy_state_selected(const skim_greedy_state *state) {
     return state ? state->selected : 0;
+}
+
+// ------------------------------------------------- suspend / resume a run
+// A saved state: a header, then the run's progress arrays, each at an
+// offset rounded up to 8 bytes.
+namespace skim {
+namespace {
+
+constexpr char kImageMagic[8] = {'S', 'K', 'I', 'M', 'G', 'R', 'D', '1'};
+
+struct ImageHeader {
+    char magic[8];
+    uint32_t n, ell, k, pad;
+    uint64_t m, seed, selected, cursor, pool_used;
+};
+
+struct ImageLayout {
+    uint64_t covered, size, sel, idx, pool, tau, second, total;
+};
+
+uint64_t round8(uint64_t x) { return (x + 7) & ~7ull; }
+
+ImageLayout image_layout(uint32_t n, uint64_t selected, uint64_t pool_used) {
+    const uint64_t npairs = (uint64_t)n * kPairStride, cwords = 2 * (((uint64_t)n + 3) / 4);
+    ImageLayout L;
+    L.covered = round8(sizeof(ImageHeader));
+    L.size = round8(L.covered + npairs * 4);
+    L.sel = round8(L.size + cwords * 4);
+    L.idx = round8(L.sel + (uint64_t)n * 4);
+    L.pool = round8(L.idx + npairs * 8);
+    L.tau = round8(L.pool + pool_used * 4);
+    L.second = round8(L.tau + selected * 8);
+    L.total = round8(L.second + selected * 4);
+    return L;
+}
+
+}  // namespace
+}  // namespace skim
+
+extern "C" skim_status skim_greedy_state_save(const skim_greedy_state *state, void *buf,
+                                              uint64_t *bytes, void *stream) {
+    skim::clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    try {
+        SKIM_REQUIRE(state != nullptr && bytes != nullptr, "state or bytes is NULL");
+        const skim::SkArgs &A = state->args;
+        skim::SkCtl c;
+        skim::read_back(&c, A.ctl, sizeof c, hs);
+        const skim::ImageLayout L = skim::image_layout(state->n, state->selected, c.pool_used);
+        if (!buf) {
+            *bytes = L.total;
+            return SKIM_OK;
+        }
+        SKIM_REQUIRE(*bytes >= L.total, "buffer of %llu bytes; the state needs %llu",
+                     (unsigned long long)*bytes, (unsigned long long)L.total);
+        uint8_t *b = (uint8_t *)buf;
+        skim::ImageHeader h{};
+        std::memcpy(h.magic, skim::kImageMagic, sizeof h.magic);
+        h.n = state->n;
+        h.ell = state->ell;
+        h.k = state->k;
+        h.m = state->m;
+        h.seed = state->seed;
+        h.selected = state->selected;
+        h.cursor = c.cursor;
+        h.pool_used = c.pool_used;
+        std::memcpy(b, &h, sizeof h);
+        const uint64_t npairs = (uint64_t)state->n * skim::kPairStride;
+        const uint64_t cwords = 2 * (((uint64_t)state->n + 3) / 4);
+        const struct {
+            uint64_t off;
+            const void *src;
+            uint64_t len;
+        } parts[] = {{L.covered, A.covered, npairs * 4},
+                     {L.size, A.size, cwords * 4},
+                     {L.sel, A.sel, (uint64_t)state->n * 4},
+                     {L.idx, A.idx, npairs * 8},
+                     {L.pool, A.pool, c.pool_used * 4},
+                     {L.tau, A.rec_tau, (uint64_t)state->selected * 8},
+                     {L.second, A.rec_second, (uint64_t)state->selected * 4}};
+        for (const auto &pt : parts)
+            if (pt.len)
+                SKIM_HIP(hipMemcpyAsync(b + pt.off, pt.src, pt.len, hipMemcpyDeviceToHost, hs));
+        SKIM_HIP(hipStreamSynchronize(hs));
+        *bytes = L.total;
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        return f.st;
+    }
+}
+
+extern "C" skim_status skim_greedy_state_load(const skim_graph *g, uint32_t ell, uint32_t k,
+                                              uint64_t seed, const void *buf, uint64_t bytes,
+                                              skim_greedy_state **state, void *stream) {
+    skim::clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    skim_greedy_state *st = nullptr;
+    try {
+        SKIM_REQUIRE(g != nullptr && buf != nullptr && state != nullptr,
+                     "graph, buffer or state is NULL");
+        SKIM_REQUIRE(bytes >= sizeof(skim::ImageHeader), "buffer too small for a saved state");
+        skim::ImageHeader h;
+        std::memcpy(&h, buf, sizeof h);
+        SKIM_REQUIRE(std::memcmp(h.magic, skim::kImageMagic, sizeof h.magic) == 0,
+                     "not a saved SKIM state");
+        SKIM_REQUIRE(h.n == g->n && h.m == g->m && h.ell == ell && h.k == k && h.seed == seed,
+                     "the saved state belongs to another graph or parameters");
+        SKIM_REQUIRE(h.selected <= h.n && h.cursor <= (uint64_t)h.n * ell,
+                     "saved state is inconsistent");
+        const skim::ImageLayout L = skim::image_layout(h.n, h.selected, h.pool_used);
+        SKIM_REQUIRE(bytes >= L.total, "saved state truncated (%llu of %llu bytes)",
+                     (unsigned long long)bytes, (unsigned long long)L.total);
+        st = skim::greedy_create(g, ell, k, seed, hs);
+        skim::SkArgs &A = st->args;
+        if (h.pool_used > A.pool_cap) {
+            const uint64_t cap = h.pool_used + h.pool_used / 2;
+            uint32_t *np = st->mem->alloc<uint32_t>(cap);
+            st->mem->release(A.pool);
+            A.pool = np;
+            A.pool_cap = cap;
+        }
+        const uint8_t *b = (const uint8_t *)buf;
+        const uint64_t npairs = (uint64_t)h.n * skim::kPairStride;
+        const uint64_t cwords = 2 * (((uint64_t)h.n + 3) / 4);
+        const struct {
+            void *dst;
+            uint64_t off, len;
+        } parts[] = {{A.covered, L.covered, npairs * 4},
+                     {A.size, L.size, cwords * 4},
+                     {A.sel, L.sel, (uint64_t)h.n * 4},
+                     {A.idx, L.idx, npairs * 8},
+                     {A.pool, L.pool, h.pool_used * 4},
+                     {A.rec_tau, L.tau, h.selected * 8},
+                     {A.rec_second, L.second, h.selected * 4}};
+        for (const auto &pt : parts)
+            if (pt.len)
+                SKIM_HIP(hipMemcpyAsync(pt.dst, b + pt.off, pt.len, hipMemcpyHostToDevice, hs));
+        skim::SkCtl c{};
+        c.cursor = h.cursor;
+        c.pool_used = h.pool_used;
+        SKIM_HIP(hipMemcpyAsync(A.ctl, &c, sizeof c, hipMemcpyHostToDevice, hs));
+        SKIM_HIP(hipStreamSynchronize(hs));
+        st->selected = (uint32_t)h.selected;
+        *state = st;
+        return SKIM_OK;
+    } catch (const skim::Fail &f) {
+        delete st;
+        return f.st;
+    }
 }
 
 extern "C" skim_status skim_greedy_records(const skim_greedy_state *state, uint32_t first,

@@ -144,3 +144,83 @@ def test_hub_seed_residual_on_the_grid(oracle_lib, ell, k):
     ws, wg, _ = oracle_lib.skim(g, 3, ell, k, 12)
     assert seeds[0] == 0
     assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+
+
+def _run(sk, G, ell, k, seed, state, s):
+    import torch
+    d = torch.device("cuda:0")
+    a = torch.empty(s, dtype=torch.int32, device=d)
+    b = torch.empty(s, dtype=torch.int64, device=d)
+    sk.skim_greedy(G, ell, k, seed, s, a, b, state=state)
+    torch.cuda.synchronize()
+    return a.cpu().numpy().view(np.uint32), b.cpu().numpy().view(np.uint64)
+
+
+def _records(sk, state):
+    import torch
+    d = torch.device("cuda:0")
+    s = state.selected
+    tau = torch.empty(s, dtype=torch.int64, device=d)
+    sec = torch.empty(s, dtype=torch.int32, device=d)
+    sk.skim_greedy_records(state, 0, s, tau, sec)
+    torch.cuda.synchronize()
+    return tau.cpu().numpy().view(np.uint64), sec.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("name,first,rest", [("served-skim", 70, 130), ("wc-20k", 20, 30)])
+def test_state_saved_and_loaded_resumes_the_run(oracle_lib, name, first, rest):
+    # a run suspended after `first` seeds, saved to host bytes, freed, loaded
+    # into a new state and resumed gives the oracle's sequence, gains and
+    # per-seed error records for all first + rest seeds
+    import paper_1408_6282_amd as sk
+    import torch
+    if name == "served-skim":
+        cfg = make_config("served-skim")
+        g, ell, k, seed = make_graph(cfg), cfg["ell"], cfg["k"], cfg["seed"]
+    else:
+        from workloads.graphs import Graph, chung_lu_graph, wc_thresholds
+        rp, col = chung_lu_graph(20000, 320000, 2.1, 56)
+        g, ell, k, seed = Graph(20000, rp, col, wc_thresholds(rp, col, 20000)), 64, 64, 1
+    G = sk.DeviceGraph.from_host(g, torch.device("cuda:0"))
+    a = sk.GreedyState()
+    try:
+        s1, g1 = _run(sk, G, ell, k, seed, a, first)
+        data = a.save()
+        log(f"{name}: saved after {first} seeds, {len(data)} bytes")
+    finally:
+        a.free()
+    b = sk.GreedyState.load(G, ell, k, seed, data)
+    try:
+        assert b.selected == first
+        s2, g2 = _run(sk, G, ell, k, seed, b, rest)
+        tau, sec = _records(sk, b)
+    finally:
+        b.free()
+    ws, wg, wt, wsec, _ = oracle_lib.skim(g, seed, ell, k, first + rest, records=True)
+    assert np.array_equal(np.concatenate([s1, s2]), ws)
+    assert np.array_equal(np.concatenate([g1, g2]), wg)
+    assert np.array_equal(tau, wt) and np.array_equal(sec, wsec)
+
+
+def test_saved_state_refused_for_other_runs():
+    import paper_1408_6282_amd as sk
+    import torch
+    cfg = make_config("tiny-ic")
+    g = make_graph(cfg)
+    G = sk.DeviceGraph.from_host(g, torch.device("cuda:0"))
+    a = sk.GreedyState()
+    try:
+        _run(sk, G, 8, 4, 3, a, 5)
+        data = a.save()
+    finally:
+        a.free()
+    for ell, k, seed, blob in ((8, 5, 3, data), (8, 4, 4, data), (16, 4, 3, data),
+                               (8, 4, 3, data[:-8]), (8, 4, 3, b"x" * len(data))):
+        with pytest.raises(sk.SkimError) as ei:
+            sk.GreedyState.load(G, ell, k, seed, blob)
+        assert ei.value.status == sk.SKIM_EINVAL
+    b = sk.GreedyState.load(G, 8, 4, 3, data)  # the right parameters load
+    try:
+        assert b.selected == 5
+    finally:
+        b.free()
