@@ -56,6 +56,7 @@ namespace {
 
 constexpr int kSkimBlock = 1024;
 constexpr uint32_t kSkimLdsNodes = 20480;  // graphs up to this size keep size[] in LDS
+constexpr uint32_t kSkimPairListNodes = 1u << 17;  // from this size, in-lists as pair words
 constexpr uint32_t kSkimLdsWords = kSkimLdsNodes / 2;
 constexpr uint32_t kFlagPool = 1u;
 // Items whose search, index entry or out-list is at most this long are
@@ -109,6 +110,10 @@ struct SkCtl {
 struct SkArgs {
     uint32_t n, ell, k;
     uint64_t nsrc;
+    // live in-lists: on large graphs the words of the sketch build ([64 n],
+    // rlive, with rsrc), else a CSR over pairs (rptr [64 n + 1], radj)
+    const uint64_t *rlive;
+    const uint32_t *rsrc;
     const uint64_t *rptr;
     const uint32_t *radj;
     const uint64_t *fptr;
@@ -477,9 +482,24 @@ __global__ void __launch_bounds__(kSkimBlock) k_skim(SkArgs A, uint32_t goal, ui
                     cnt = 1;
                     for (uint32_t head = 0; head < cnt; ++head) {
                         const uint32_t q = Q[head] * kPairStride + i;
-                        for (uint64_t e = A.rptr[q]; e < A.rptr[q + 1]; ++e) {
-                            const uint32_t w = A.radj[e];
+                        if (!A.rlive) {
+                            for (uint64_t e = A.rptr[q]; e < A.rptr[q + 1]; ++e) {
+                                const uint32_t w = A.radj[e];
+                                if (mark_new(V, w)) Q[cnt++] = w;
+                            }
+                            continue;
+                        }
+                        const uint64_t lw = A.rlive[q];
+                        if (lw & kLiveOne) {
+                            const uint32_t w = (uint32_t)lw;
                             if (mark_new(V, w)) Q[cnt++] = w;
+                        } else {
+                            const uint64_t e0 = lw >> kLiveCountBits;
+                            const uint64_t e1 = e0 + (lw & ((1u << kLiveCountBits) - 1));
+                            for (uint64_t e = e0; e < e1; ++e) {
+                                const uint32_t w = A.rsrc[e];
+                                if (mark_new(V, w)) Q[cnt++] = w;
+                            }
                         }
                     }
                     for (uint32_t j = 0; j < cnt; ++j) V[Q[j] >> 5] = 0u;  // back to zero
@@ -1102,10 +1122,20 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
         Arena T(s);
         uint32_t *esrc = T.alloc<uint32_t>(g->m ? g->m : 1);
         validate_graph(g, esrc, T);
+        // in-lists: on large graphs as the sketch build makes them (no atomic
+        // per entry, its scratch in T), on small ones with the out-lists
+        // from one coin pass (fewer launches)
         LiveLists fwd;
-        LiveLists rev = build_live_lists(g, ell, seed, esrc, /*forward=*/false, M, &fwd);
-        st->args.rptr = rev.ptr;
-        st->args.radj = rev.adj;
+        if (n >= kSkimPairListNodes) {
+            const PairLists rev = build_pair_lists(g, ell, seed, esrc, T, &M);
+            fwd = build_live_lists(g, ell, seed, esrc, /*forward=*/true, M);
+            st->args.rlive = rev.live;
+            st->args.rsrc = rev.adj;
+        } else {
+            const LiveLists rev = build_live_lists(g, ell, seed, esrc, /*forward=*/false, M, &fwd);
+            st->args.rptr = rev.ptr;
+            st->args.radj = rev.adj;
+        }
         st->args.fptr = fwd.ptr;
         st->args.fadj = fwd.adj;
         // pairs by increasing rank

@@ -218,7 +218,7 @@ struct PairLists {
     uint32_t maxlen = 0;  // longest live in-list (0 when none is longer than 16)
 };
 PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
-                           Arena &a);
+                           Arena &a, Arena *out = nullptr);  // out: arena of the lists (else a)
 
 // Optional per-kernel timing: while a kernel name is enabled, each launch of
 // that kernel is bracketed by HIP events on its stream; durations are folded

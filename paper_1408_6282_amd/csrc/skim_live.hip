@@ -313,16 +313,17 @@ __global__ void __launch_bounds__(256) k_pair_emit(ChunkArgs C, const uint32_t *
 }  // namespace
 
 PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
-                           Arena &a) {
+                           Arena &a, Arena *out) {
+    Arena &o = out ? *out : a;  // the lists themselves; a holds the scratch
     hipStream_t s = a.stream();
     const uint32_t n = g->n;
     const uint64_t m = g->m;
     const uint64_t npairs = (uint64_t)n * kPairStride;
     PairLists L;
-    L.live = a.alloc<uint64_t>(npairs);
+    L.live = o.alloc<uint64_t>(npairs);
     if (!m) {
         fill_u64(L.live, 0, npairs, s);
-        L.adj = a.alloc<uint32_t>(1);
+        L.adj = o.alloc<uint32_t>(1);
         return L;
     }
     // coin masks of every edge, keyed by (head, source)
@@ -395,7 +396,7 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
         throw Fail{SKIM_EUNSUPPORTED};
     }
     L.nlive = tot;
-    L.adj = a.alloc<uint32_t>(tot ? tot : 1);
+    L.adj = o.alloc<uint32_t>(tot ? tot : 1);
     // 4. sources and pair words
     {
         LaunchTimer t("k_pair_emit", s);
