@@ -40,7 +40,7 @@ DOMINANT_SOURCES = ["paper_1408_6282_amd/csrc/skim_build.hip",
 CALIBRATION_BYTES = 1 << 30
 # Launch shapes of the R-MAT scale-24 build, chosen by a sweep over window
 # spans, level batches and thread-per-entry limits on that graph.
-RMAT_PARAMS = {"window_span": 3, "large_batch": 4, "thread_frontier": 2097152}
+RMAT_PARAMS = {"window_span": 3, "large_batch": 4, "thread_frontier": 2097152, "pull_frontier": 0}
 
 
 def log(msg):

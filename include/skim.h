@@ -50,7 +50,7 @@
 extern "C" {
 #endif
 
-#define SKIM_ABI_VERSION 8u
+#define SKIM_ABI_VERSION 9u
 
 typedef enum {
     SKIM_OK = 0,
@@ -548,7 +548,16 @@ skim_status skim_server_replay(skim_server *server, uint64_t q, const uint64_t *
  *                    more visits past k;
  *   first_span       rank buckets of the first window (default 5, 1..16);
  *                    a first window that outgrows its buffers is given up
- *                    and the build starts again from bucket 0 alone.
+ *                    and the build starts again from bucket 0 alone;
+ *   pull_frontier    levels whose frontier holds at least this many entries
+ *                    are taken by pull: every pair reads its live out-list
+ *                    and takes the sources of the frontier entries it meets
+ *                    (the frontier sorted by pair and indexed over pairs),
+ *                    instead of each entry pushing over its live in-list.
+ *                    Both directions make the same visits (Section 5.2, the
+ *                    pruned searches of Algorithm 2), so the sketches do not
+ *                    depend on it.  Nonzero also builds the out-lists with
+ *                    the in-lists; 0 = never (the default).
  * skim_set_build_params(NULL) restores the defaults; fields out of range give
  * SKIM_EINVAL and change nothing.
  */
@@ -561,6 +570,7 @@ typedef struct {
     uint32_t sort_frontier;
     uint32_t window_span;
     uint32_t first_span;
+    uint32_t pull_frontier;
 } skim_build_params;
 
 skim_status skim_set_build_params(const skim_build_params *params);
@@ -571,7 +581,8 @@ void skim_get_build_params(skim_build_params *params);
  * seed) into ranks/size (device, as for skim_build_sketches) with the
  * current parameters and then with candidate values of one parameter at a
  * time (coordinate descent over small_frontier, small_batch, large_batch,
- * thread_frontier, sort_frontier, window_span, first_span), each timed as the best of `reps` builds
+ * thread_frontier, sort_frontier, window_span, first_span, pull_frontier:
+ * never, from 2^21 or from 2^23 entries), each timed as the best of `reps` builds
  * with HIP events on `stream` after one warm-up build.  The fastest set becomes the current
  * parameters and is written to *best (HOST); *best_ms and *start_ms (HOST,
  * may be NULL) receive its time and that of the parameters in force at the

@@ -52,7 +52,8 @@ class skim_build_params(C.Structure):
     _fields_ = [("small_frontier", C.c_uint32), ("small_batch", C.c_uint32),
                 ("large_batch", C.c_uint32), ("thread_frontier", C.c_uint32),
                 ("heavy_visits", C.c_uint32), ("sort_frontier", C.c_uint32),
-                ("window_span", C.c_uint32), ("first_span", C.c_uint32)]
+                ("window_span", C.c_uint32), ("first_span", C.c_uint32),
+                ("pull_frontier", C.c_uint32)]
 
     def as_dict(self):
         return {name: int(getattr(self, name)) for name, _ in self._fields_}

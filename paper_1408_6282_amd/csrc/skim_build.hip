@@ -811,6 +811,136 @@ __global__ void __launch_bounds__(kBlock) k_expand_heavy(WinArgs A, uint32_t L) 
     block_add3(X.R.buf, &A.ctl->scans, scans, &A.ctl->hinserts, hashed, &A.ctl->visits, visits);
 }
 
+// ------------------------------------------- level by pull (other side)
+// A level can also be taken from the visited side: every pair q = (u, i)
+// reads its live out-list and, for each out-neighbour pair p = (w, i) with
+// entries in the level's frontier, makes the visit of q by each of their
+// sources.  These are the (q, source) attempts the push makes for the level,
+// met in another order; since a level's outcome does not depend on that
+// order (see claim), neither does the build's.  `skey` is the frontier
+// sorted by pair; for a pair p with entries, skey[fidx[p] - 1 .. fend[p])
+// are they (fidx[p] = 0 for a pair without entries; fend is then unused).
+__global__ void k_pull_index(const uint64_t *skey, uint64_t f, uint32_t *fidx, uint32_t *fend) {
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t < f;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t p = skey[t] >> 32;
+        if (t == 0 || (skey[t - 1] >> 32) != p) fidx[p] = (uint32_t)(t + 1);
+        if (t + 1 == f || (skey[t + 1] >> 32) != p) fend[p] = (uint32_t)(t + 1);
+    }
+}
+
+// Level L by pull over the n l actual pairs, node by node (pair 64 u + i for
+// i < l), kChunk pairs per workgroup per round.  The out-lists of a round's
+// kBlock pairs are laid end to end over the workgroup (a hub's lists do not
+// hold one lane), and the sources of the frontier pairs that a wave's edges
+// meet are laid end to end over the wave.  Counters, appends and records are
+// those of k_expand for the level.
+__global__ void __launch_bounds__(kBlock) k_pull(WinArgs A, uint32_t L, uint32_t n, uint32_t ell,
+                                                 const uint64_t *skey, const uint32_t *fidx,
+                                                 const uint32_t *fend, const uint64_t *fptr,
+                                                 const uint32_t *fadj) {
+    __shared__ ExpandShared X;
+    __shared__ uint64_t s_ex[kBlock + 1];  // starts of the round's out-lists laid end to end
+    __shared__ uint64_t s_e0[kBlock];      // their offsets in fadj
+    __shared__ uint64_t s_wsum[kBlock / 64];
+    __shared__ uint32_t s_flags;
+    __shared__ unsigned long long s_size;
+    if (threadIdx.x == 0) {
+        X.F.n = X.R.n = X.nheavy = 0;
+        s_flags = __hip_atomic_load(&A.ctl->flags, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_size = A.ctl->size[16 * (L % 3)];
+        if (blockIdx.x == 0) {
+            A.ctl->size[16 * ((L + 2) % 3)] = 0;  // counter of level L + 2
+            A.ctl->hsize[16 * ((L + 1) % 2)] = 0;  // long lists of level L + 1
+        }
+    }
+    __syncthreads();
+    uint32_t scans = 0, hashed = 0, visits = 0;
+    if (!s_flags && s_size) {
+        uint64_t *nkey = A.fkey[(L + 1) & 1], *nlive = A.flive[(L + 1) & 1];
+        unsigned long long *next_count = &A.ctl->size[16 * ((L + 1) % 3)];
+        const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+        const uint64_t nv = (uint64_t)n * ell;
+        for (uint64_t c = (uint64_t)blockIdx.x * kChunk; c < nv;
+             c += (uint64_t)gridDim.x * kChunk) {
+            const uint64_t end = c + kChunk < nv ? c + kChunk : nv;
+            for (uint64_t tb = c; tb < end; tb += kBlock) {
+                const uint64_t v = tb + tid;
+                uint64_t e0 = 0, cnt = 0;
+                if (v < end) {
+                    const uint64_t q = (v / ell) * kPairStride + v % ell;
+                    e0 = fptr[q];
+                    cnt = fptr[q + 1] - e0;
+                }
+                uint64_t incl = cnt;  // inclusive prefix over the wave
+                for (uint32_t off = 1; off < 64; off <<= 1) {
+                    const uint64_t y = shfl_up_u64(incl, off);
+                    if (lane >= off) incl += y;
+                }
+                if (lane == 63u) s_wsum[wave] = incl;
+                s_e0[tid] = e0;
+                __syncthreads();
+                uint64_t before = 0, T = 0;
+                for (uint32_t w = 0; w < kBlock / 64; ++w) {
+                    before += w < wave ? s_wsum[w] : 0;
+                    T += s_wsum[w];
+                }
+                s_ex[tid] = before + incl - cnt;
+                if (tid == 0) s_ex[kBlock] = T;
+                __syncthreads();
+                for (uint64_t b0 = 0; b0 < T; b0 += kBlock) {  // uniform over the workgroup
+                    const uint64_t pos = b0 + tid;
+                    uint64_t s0 = 0, S = 0;
+                    uint32_t u = 0, i = 0;
+                    if (pos < T) {
+                        uint32_t lo = 0, hi = kBlock;  // s_ex[lo] <= pos < s_ex[hi]
+                        while (hi - lo > 1) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (s_ex[mid] <= pos) lo = mid;
+                            else hi = mid;
+                        }
+                        const uint64_t vv = tb + lo;
+                        u = (uint32_t)(vv / ell);
+                        i = (uint32_t)(vv % ell);
+                        const uint64_t p =
+                            (uint64_t)fadj[s_e0[lo] + (pos - s_ex[lo])] * kPairStride + i;
+                        const uint32_t at = fidx[p];
+                        if (at) {
+                            s0 = at - 1;
+                            S = fend[p] - s0;
+                        }
+                    }
+                    uint64_t sincl = S;  // the wave's sources, 64 at a time
+                    for (uint32_t off = 1; off < 64; off <<= 1) {
+                        const uint64_t y = shfl_up_u64(sincl, off);
+                        if (lane >= off) sincl += y;
+                    }
+                    const uint64_t ST = shfl_u64(sincl, 63);
+                    for (uint64_t sb = 0; sb < ST; sb += 64) {
+                        const uint64_t jj = sb + lane;
+                        uint32_t r = 0;  // lanes whose sources end at or before position jj
+                        for (uint32_t step = 32; step > 0; step >>= 1) {
+                            const uint64_t y = shfl_u64(sincl, r + step - 1);
+                            if (y <= jj) r += step;
+                        }
+                        const uint32_t rr = r & 63u;
+                        const uint64_t first = shfl_u64(sincl, rr) - shfl_u64(S, rr);
+                        const uint64_t rs0 = shfl_u64(s0, rr);
+                        const uint32_t ru = __shfl(u, (int)rr), ri = __shfl(i, (int)rr);
+                        if (jj < ST)
+                            visit_edge(A, ru, ri, (uint32_t)skey[rs0 + (jj - first)], nkey, nlive,
+                                       next_count, X, scans, hashed, visits);
+                    }
+                }
+                __syncthreads();  // s_ex, s_e0 and s_wsum are refilled next round
+            }
+            stage_flush2(X.F, nkey, nlive, A.front_cap, next_count, X.R, A.rec, A.rec_cap,
+                         &A.ctl->records, &A.ctl->flags);
+        }
+    }
+    block_add3(X.R.buf, &A.ctl->scans, scans, &A.ctl->hinserts, hashed, &A.ctl->visits, visits);
+}
+
 // Pair records at the start of a build: the initial state word and the
 // pair's live-list word.
 __global__ void k_pair_init(const uint64_t *live, uint64_t npairs, uint64_t *prec) {
@@ -1212,10 +1342,11 @@ struct Shapes {
     uint64_t sort_frontier = 0;  // 0: never sort
     uint32_t window_span = 2;    // buckets per window after a light one
     uint32_t first_span = kFirstSpan;  // buckets of the first window
+    uint64_t pull_frontier = 0;  // levels of at least this many entries by pull; 0: never
 };
 
 std::mutex g_shapes_mu;
-skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0, 2, kFirstSpan};
+skim_build_params g_params{65536, 8, 3, kBlock * 2048, 4, 0, 2, kFirstSpan, 0};
 
 Shapes current_shapes() {
     std::lock_guard<std::mutex> lk(g_shapes_mu);
@@ -1228,6 +1359,7 @@ Shapes current_shapes() {
     sh.sort_frontier = g_params.sort_frontier;
     sh.window_span = g_params.window_span;
     sh.first_span = g_params.first_span;
+    sh.pull_frontier = g_params.pull_frontier;
     return sh;
 }
 
@@ -1251,8 +1383,8 @@ struct RankSource {
 
 // One attempt at the windows and the merge; throws Retry when a buffer was
 // too small (the caller's outputs are written only by the merge).
-static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const RankSource &rs,
-                        const PairLists &live,
+static void run_windows(const skim_graph *g, uint32_t ell, uint32_t k, uint64_t seed,
+                        const RankSource &rs, const PairLists &live, const LiveLists *fwd,
                         const uint32_t *sources, const unsigned long long *wb, uint32_t W,
                         const Capacity &cap, const Shapes &sh, uint64_t *ranks_out,
                         uint32_t *size_out, uint64_t *work, Arena &A) {
@@ -1283,6 +1415,10 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Ra
     uint64_t *sort_key = nullptr, *sort_live = nullptr, sort_cap = 0;  // sort_frontier
     uint8_t *sort_tmp = nullptr;
     size_t sort_tmp_bytes = 0;
+    uint64_t *pull_key = nullptr, pull_cap = 0;  // levels by pull (fwd given)
+    uint32_t *fidx = nullptr, *fend = nullptr;
+    uint8_t *pull_tmp = nullptr;
+    size_t pull_tmp_bytes = 0;
     int pair_bits = 1;
     while (pair_bits < 32 && (1ull << pair_bits) < npairs) ++pair_bits;
     uint32_t levels_run = 0;
@@ -1432,6 +1568,40 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Ra
                                      (unsigned long long)ns);
                 }
                 const bool after_tails = !tails_ok;
+                if (fwd && sh.pull_frontier && f >= sh.pull_frontier && f < 0xFFFFFFFFull) {
+                    // this level by pull: the frontier sorted by pair and
+                    // indexed over pairs, then every pair reads its out-list
+                    grow_u64(pull_key, pull_cap, 0, f);
+                    size_t tb = 0;
+                    SKIM_HIP(rocprim::radix_sort_keys(nullptr, tb, fkey[L & 1], pull_key, (size_t)f,
+                                                      32, 32 + pair_bits, s));
+                    if (tb > pull_tmp_bytes) {
+                        if (pull_tmp) A.release(pull_tmp);
+                        pull_tmp = A.alloc<uint8_t>(tb);
+                        pull_tmp_bytes = tb;
+                    }
+                    SKIM_HIP(rocprim::radix_sort_keys(pull_tmp, tb, fkey[L & 1], pull_key, (size_t)f,
+                                                      32, 32 + pair_bits, s));
+                    if (!fidx) {
+                        fidx = A.alloc<uint32_t>(npairs);
+                        fend = A.alloc<uint32_t>(npairs);
+                    }
+                    fill_u32(fidx, 0, npairs, s);
+                    k_pull_index<<<grid_for(f, kBlock, 65536), kBlock, 0, s>>>(pull_key, f, fidx,
+                                                                               fend);
+                    SKIM_LAUNCH_CHECK();
+                    const WinArgs WA = args();
+                    {
+                        LaunchTimer t("k_pull", s);
+                        k_pull<<<grid_for((uint64_t)n * ell, kChunk, 2048), kBlock, 0, s>>>(
+                            WA, L, n, ell, pull_key, fidx, fend, fwd->ptr, fwd->adj);
+                    }
+                    SKIM_LAUNCH_CHECK();
+                    ++L;
+                    tails_ok = true;
+                    f_prev = f;
+                    continue;
+                }
                 if (f <= kTailsMax && tails_ok) {
                     // the rest of the window in independent workgroups (about
                     // kTailsPer entries each, as many as fit on the device at
@@ -1607,6 +1777,11 @@ static void run_windows(const skim_graph *g, uint32_t k, uint64_t seed, const Ra
         A.release(flive[j]);
     }
     if (hset) A.release(hset);
+    if (pull_key) A.release(pull_key);
+    if (fidx) {
+        A.release(fidx);
+        A.release(fend);
+    }
     uint64_t *seg = A.alloc<uint64_t>(nrec ? nrec : 1);
     uint64_t *gstart = A.alloc<uint64_t>(n), *gend = A.alloc<uint64_t>(n);
     fill_u64(gstart, 0, n, s);
@@ -1656,6 +1831,9 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
 
     // ---- 1. live lists (reverse: in-edges of every pair)
     PairLists live = build_pair_lists(g, ell, seed, esrc, A);
+    // out-lists of every pair, for levels taken by pull
+    LiveLists fwd;
+    if (shapes.pull_frontier) fwd = build_live_lists(g, ell, seed, esrc, /*forward=*/true, A);
     A.release(esrc);
     if (live.nlive >> (64 - 1 - kLiveCountBits)) {
         set_error("%llu live edges exceed the pair records' list offsets",
@@ -1714,8 +1892,8 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     for (;; ++attempt) {
         try {
             Arena B(s);
-            run_windows(g, k, seed, rs, live, sources, wb, W, cap, shapes, ranks_out, size_out, work,
-                        B);
+            run_windows(g, ell, k, seed, rs, live, shapes.pull_frontier ? &fwd : nullptr, sources, wb,
+                        W, cap, shapes, ranks_out, size_out, work, B);
             break;
         } catch (const Retry &r) {
             retry_flags |= r.flags;
@@ -1843,7 +2021,8 @@ extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32
         const uint32_t so[] = {0, 1u << 20, 1u << 22};
         const uint32_t fw[] = {2, 3, 4};
         const uint32_t fs[] = {3, 5, 7};
-        for (int field = 0; field < 7 && st == SKIM_OK; ++field) {
+        const uint32_t pf[] = {0, 1u << 21, 1u << 23};
+        for (int field = 0; field < 8 && st == SKIM_OK; ++field) {
             for (int c = 0; c < 3 && st == SKIM_OK; ++c) {
                 skim_build_params p = cur;
                 uint32_t *slot = field == 0   ? &p.small_frontier
@@ -1852,14 +2031,16 @@ extern "C" skim_status skim_tune_build(const skim_graph *g, uint32_t ell, uint32
                                  : field == 3 ? &p.thread_frontier
                                  : field == 4 ? &p.sort_frontier
                                  : field == 5 ? &p.window_span
-                                              : &p.first_span;
+                                 : field == 6 ? &p.first_span
+                                              : &p.pull_frontier;
                 const uint32_t v = field == 0   ? sf[c]
                                    : field == 1 ? sb[c]
                                    : field == 2 ? lb[c]
                                    : field == 3 ? tf[c]
                                    : field == 4 ? so[c]
                                    : field == 5 ? fw[c]
-                                                : fs[c];
+                                   : field == 6 ? fs[c]
+                                                : pf[c];
                 if (*slot == v) continue;
                 *slot = v;
                 const double t = time_with(p, st);

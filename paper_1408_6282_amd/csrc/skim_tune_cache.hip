@@ -1,12 +1,15 @@
 // skim_tune_cache.hip -- a persistent cache of the build autotuner's
 // choices, keyed by the device and the configuration.
 //
-// The key is a 64-bit FNV-1a hash of: the device's architecture name and
-// compute-unit count; n, m, l, k and the seed; and 64 evenly spaced samples
-// each of row_ptr, col and thr, gathered on the device by one small kernel.
-// The cache is a text file with one line per key:
+// The key is a 64-bit FNV-1a hash of: the number of fields of
+// skim_build_params (so lines of an older field set never match); the
+// device's architecture name and compute-unit count; n, m, l, k and the
+// seed; and 64 evenly spaced samples each of row_ptr, col and thr, gathered
+// on the device by one small kernel.  The cache is a text file with one line
+// per key:
 //   <key hex> <small_frontier> <small_batch> <large_batch> <thread_frontier>
-//   <heavy_visits> <sort_frontier> <window_span> <first_span> <best_ms>
+//   <heavy_visits> <sort_frontier> <window_span> <first_span> <pull_frontier>
+//   <best_ms>
 // A hit applies the stored launch shapes (skim_set_build_params) without
 // timing anything; a miss runs skim_tune_build and appends its choice.
 // Lines that do not parse, or whose shapes the library refuses, are skipped.
@@ -67,6 +70,8 @@ extern "C" skim_status skim_tune_build_cached(const skim_graph *g, uint32_t ell,
         hipDeviceProp_t prop;
         SKIM_HIP(hipGetDeviceProperties(&prop, dev));
         uint64_t h = 0xCBF29CE484222325ull;
+        const uint32_t nfields = sizeof(skim_build_params) / sizeof(uint32_t);
+        h = fnv1a(h, &nfields, sizeof nfields);
         h = fnv1a(h, prop.gcnArchName, strnlen(prop.gcnArchName, sizeof prop.gcnArchName));
         h = fnv1a(h, &prop.multiProcessorCount, sizeof prop.multiProcessorCount);
         const uint64_t cfg[5] = {g->n, g->m, ell, k, seed};
@@ -93,7 +98,7 @@ extern "C" skim_status skim_tune_build_cached(const skim_graph *g, uint32_t ell,
                 double ms = 0;
                 if (!(ls >> k2 >> p.small_frontier >> p.small_batch >> p.large_batch >>
                       p.thread_frontier >> p.heavy_visits >> p.sort_frontier >> p.window_span >>
-                      p.first_span >> ms))
+                      p.first_span >> p.pull_frontier >> ms))
                     continue;
                 if (k2 != key) continue;
                 if (skim_set_build_params(&p) != SKIM_OK) continue;  // refused: tune again
@@ -116,7 +121,7 @@ extern "C" skim_status skim_tune_build_cached(const skim_graph *g, uint32_t ell,
         out << key << ' ' << best->small_frontier << ' ' << best->small_batch << ' '
             << best->large_batch << ' ' << best->thread_frontier << ' ' << best->heavy_visits << ' '
             << best->sort_frontier << ' ' << best->window_span << ' ' << best->first_span << ' '
-            << bms << '\n';
+            << best->pull_frontier << ' ' << bms << '\n';
         if (best_ms) *best_ms = bms;
         if (start_ms) *start_ms = sms;
         *hit = 0;

@@ -184,14 +184,16 @@ def test_bad_parameters():
 
 
 # Launch shapes of the full-size parity runs: the defaults, the shapes the
-# autotuner picks on this workload (the launch the bench times), and the
-# widest windows and batches.
+# autotuner picks on this workload (the launch the bench times), the widest
+# windows and batches, every level by pull, and pull from 2^21 entries.
 CL_SHAPES = {
     "default": None,
     "tuned": dict(small_frontier=262144, small_batch=16, large_batch=2, thread_frontier=524288,
                   heavy_visits=4, sort_frontier=0, window_span=3, first_span=5),
     "wide": dict(small_frontier=1 << 24, small_batch=64, large_batch=64, thread_frontier=1 << 30,
                  heavy_visits=1000, sort_frontier=0, window_span=8, first_span=16),
+    "pull": dict(pull_frontier=1),
+    "pull-2m": dict(pull_frontier=1 << 21),
 }
 
 

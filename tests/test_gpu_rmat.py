@@ -10,7 +10,8 @@ node, bit for bit:
 
 * the full configuration, l = 64 (the launch the bench's R-MAT leg times);
 * l = 16 on the same graph (instances are identical for every l above
-  their index, so this is a second, independent reference point).
+  their index, so this is a second, independent reference point), also with
+  every level of the searches taken by pull.
 """
 import numpy as np
 import pytest
@@ -42,4 +43,20 @@ def test_rmat24_equals_oracle(rmat, ell, tag):
     # rows ascending and padded (a readable failure before the digests)
     valid = R != np.uint64(0xFFFFFFFFFFFFFFFF)
     assert np.array_equal(valid.sum(axis=1), S.astype(np.int64))
+    check_digests(gold, g, R, S, E)
+
+
+@pytest.mark.timeout(900)
+def test_rmat24_l16_by_pull_equals_oracle(rmat):
+    # the other extreme of the push/pull switch: every level by pull
+    import paper_1408_6282_amd as sk
+    cfg, g = rmat
+    gold = golden("rmat_24_l16")
+    sk.skim_set_build_params(dict(pull_frontier=1))
+    try:
+        log("gpu build l = 16, every level by pull")
+        R, S, E, work, _ = gpu_build(g, 16, cfg["k"], cfg["seed"])
+    finally:
+        sk.skim_set_build_params(None)
+    log(f"gpu work {work}")
     check_digests(gold, g, R, S, E)

@@ -14,6 +14,10 @@ EXTREME = dict(small_frontier=1, small_batch=1, large_batch=1, thread_frontier=1
                sort_frontier=1, window_span=1, first_span=1)
 WIDE = dict(small_frontier=1 << 24, small_batch=64, large_batch=64, thread_frontier=1 << 30,
             heavy_visits=1000, sort_frontier=0, window_span=8, first_span=16)
+# every level by pull, and pull only for levels of 300 entries or more (a
+# window's levels then change direction as its frontier grows and shrinks)
+SHAPES = {"extreme": EXTREME, "wide": WIDE, "pull": dict(pull_frontier=1),
+          "mixed": dict(pull_frontier=300)}
 
 
 @pytest.fixture
@@ -29,10 +33,10 @@ def _powerlaw(n=20000, m=320000):
     return Graph(n, rp, col, wc_thresholds(rp, col, n))
 
 
-@pytest.mark.parametrize("shape", ["extreme", "wide"])
+@pytest.mark.parametrize("shape", list(SHAPES))
 def test_any_shape_gives_oracle_sketches(oracle_lib, restore_params, shape):
     import paper_1408_6282_amd as sk
-    sk.skim_set_build_params(EXTREME if shape == "extreme" else WIDE)
+    sk.skim_set_build_params(SHAPES[shape])
     rng = np.random.default_rng(5)
     graphs = [_powerlaw()]
     for _ in range(3):
@@ -90,7 +94,7 @@ def test_tuning_cache(tmp_path):
         p1, ms1, _, hit1 = sk.skim_tune_build_cached(G, 16, 16, 1, ranks, size, path, reps=1)
         assert not hit1
         lines = open(path).read().splitlines()
-        assert len(lines) == 1 and len(lines[0].split()) == 10  # key, 8 shapes, time
+        assert len(lines) == 1 and len(lines[0].split()) == 11  # key, 9 shapes, time
         sk.skim_set_build_params(None)
         p2, ms2, start2, hit2 = sk.skim_tune_build_cached(G, 16, 16, 1, ranks, size, path, reps=1)
         assert hit2 and p2 == p1 and start2 == 0.0
