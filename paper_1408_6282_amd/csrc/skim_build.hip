@@ -1294,18 +1294,35 @@ __global__ void __launch_bounds__(256) k_select(const uint64_t *start, const uin
         else if (S <= 256) select_regs<4>(seg, a, S, k, seed, table, row, lane);
         else if (S <= 512) select_regs<8>(seg, a, S, k, seed, table, row, lane);
         else {
-            for (uint32_t j = lane; j < 256; j += 64) buf[j] = kNone;
-            for (uint64_t c = a; c < b; c += 256) {
-                for (uint32_t j = lane; j < 256; j += 64)
-                    buf[256 + j] = c + j < b ? rank_of(seed, table, (uint32_t)seg[c + j]) : kNone;
-                wave_lds_sync();
-                uint64_t x[8];
+            // buf[0, 256): the 256 smallest so far, ascending; buf[256, 256 + nc):
+            // candidates since, the ranks below the k-th smallest so far (no
+            // other can be among the k smallest).  The candidates are merged
+            // in by one sort of the 512 slots once they may outgrow their room.
+            for (uint32_t j = lane; j < 512; j += 64) buf[j] = kNone;
+            wave_lds_sync();
+            uint64_t tau = kNone;
+            uint32_t nc = 0;
+            for (uint64_t c = a; c < b; c += 64) {
+                const uint64_t x =
+                    c + lane < b ? rank_of(seed, table, (uint32_t)seg[c + lane]) : kNone;
+                const bool cand = x < tau;
+                const unsigned long long m = __ballot(cand);
+                if (cand) buf[256 + nc + __popcll(m & ((1ull << lane) - 1ull))] = x;
+                nc += (uint32_t)__popcll(m);
+                if (nc > 192 || (c + 64 >= b && nc > 0)) {
+                    wave_lds_sync();
+                    uint64_t y[8];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) x[r] = buf[r * 64 + lane];
-                wave_bitonic<8>(x, lane);
+                    for (int r = 0; r < 8; ++r) y[r] = buf[r * 64 + lane];
+                    wave_bitonic<8>(y, lane);
 #pragma unroll
-                for (int r = 0; r < 8; ++r) buf[r * 64 + lane] = x[r];
-                wave_lds_sync();
+                    for (int r = 0; r < 4; ++r) buf[r * 64 + lane] = y[r];
+#pragma unroll
+                    for (int r = 4; r < 8; ++r) buf[r * 64 + lane] = kNone;
+                    wave_lds_sync();
+                    tau = buf[k - 1];
+                    nc = 0;
+                }
             }
             for (uint32_t j = lane; j < k; j += 64) row[j] = buf[j];
             wave_lds_sync();  // buf is refilled for the wave's next node
