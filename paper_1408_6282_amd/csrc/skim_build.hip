@@ -1850,7 +1850,7 @@ static void build_sketches(const skim_graph *g, uint32_t ell, uint32_t k, uint64
     PairLists live = build_pair_lists(g, ell, seed, esrc, A);
     // out-lists of every pair, for levels taken by pull
     LiveLists fwd;
-    if (shapes.pull_frontier) fwd = build_live_lists(g, ell, seed, esrc, /*forward=*/true, A);
+    if (shapes.pull_frontier) fwd = build_out_lists(g, ell, seed, esrc, A);
     A.release(esrc);
     if (live.nlive >> (64 - 1 - kLiveCountBits)) {
         set_error("%llu live edges exceed the pair records' list offsets",

@@ -1122,13 +1122,13 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
         Arena T(s);
         uint32_t *esrc = T.alloc<uint32_t>(g->m ? g->m : 1);
         validate_graph(g, esrc, T);
-        // in-lists: on large graphs as the sketch build makes them (no atomic
-        // per entry, its scratch in T), on small ones with the out-lists
-        // from one coin pass (fewer launches)
+        // on large graphs the in-lists as the sketch build makes them and the
+        // out-lists by the same chunked passes (no atomic per entry, scratch
+        // in T); on small ones both from one coin pass (fewer launches)
         LiveLists fwd;
         if (n >= kSkimPairListNodes) {
             const PairLists rev = build_pair_lists(g, ell, seed, esrc, T, &M);
-            fwd = build_live_lists(g, ell, seed, esrc, /*forward=*/true, M);
+            fwd = build_out_lists(g, ell, seed, esrc, T, &M);
             st->args.rlive = rev.live;
             st->args.rsrc = rev.adj;
         } else {

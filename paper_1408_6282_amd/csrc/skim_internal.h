@@ -220,6 +220,12 @@ struct PairLists {
 PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
                            Arena &a, Arena *out = nullptr);  // out: arena of the lists (else a)
 
+// Live out-lists of every pair as one CSR over pair ids (as build_live_lists
+// with forward set, entries in no particular order), by the chunked builder
+// over the forward CSR's rows: no atomic per entry.
+LiveLists build_out_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
+                          Arena &a, Arena *out = nullptr);
+
 // Optional per-kernel timing: while a kernel name is enabled, each launch of
 // that kernel is bracketed by HIP events on its stream; durations are folded
 // into the totals when the owning call resolves them after its final sync.

@@ -9,8 +9,12 @@
 //    wave per chunk of at most 1024 in-edges of a node writes the chunk's
 //    part of the live lists of the node's 64 pairs (passes: count, room,
 //    place); atomics only for the counts of nodes of several chunks.
-//  * build_live_lists (SKIM, which also needs out-lists): per-pair counts,
-//    a scan and a scatter into one CSR over pair ids.
+//  * build_out_lists (SKIM's out-lists on large graphs, and levels taken by
+//    pull): the same passes over the forward CSR's rows, which need no
+//    sort, writing one CSR over pair ids.
+//  * build_live_lists (SKIM on small graphs, where one pass serves both
+//    directions): per-pair counts, a scan and a scatter into one CSR over
+//    pair ids.
 // Searches then read only the live edges of their own instance.
 #include "skim_internal.h"
 
@@ -130,13 +134,15 @@ __global__ void k_live_fill(const uint32_t *esrc, const uint32_t *col, const uin
 // node left a 180,000-in-edge hub to a single wave.
 constexpr uint32_t kChunkEdges = 1024;
 
+// Key (run node << 32 | list entry): (head << 32 | source) for in-lists, or
+// (source << 32 | head) for out-lists, which are already in run order.
 __global__ void k_edge_keys(const uint32_t *esrc, const uint32_t *col, const uint32_t *thr,
-                            uint64_t m, uint32_t n, uint32_t ell, uint64_t seed, uint64_t *key,
-                            uint64_t *mask) {
+                            uint64_t m, uint32_t n, uint32_t ell, uint64_t seed, bool forward,
+                            uint64_t *key, uint64_t *mask) {
     for (uint64_t e = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; e < m;
          e += (uint64_t)gridDim.x * blockDim.x) {
         const uint32_t u = esrc[e], v = col[e];
-        key[e] = ((uint64_t)v << 32) | u;
+        key[e] = forward ? (((uint64_t)u << 32) | v) : (((uint64_t)v << 32) | u);
         mask[e] = live_mask(seed, n, u, v, thr[e], ell);
     }
 }
@@ -219,16 +225,18 @@ __global__ void __launch_bounds__(256) k_pair_count(ChunkArgs C, uint32_t *ccnt,
     }
 }
 
-// 2. room per node (lists of two or more), a flag for a list too long for
-// the pair word's count field (flags[0]) and the longest list (flags[1])
-__global__ void k_pair_room(const uint32_t *pcnt, uint32_t n, uint32_t *room, uint32_t *flags) {
+// 2. room per node (lists of two or more; every list for a CSR), a flag for
+// a list too long for the pair word's count field (flags[0]) and the longest
+// list (flags[1])
+__global__ void k_pair_room(const uint32_t *pcnt, uint32_t n, bool csr, uint32_t *room,
+                            uint32_t *flags) {
     const uint32_t lane = lane_id();
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
     for (uint64_t v = blockIdx.x * (uint64_t)(blockDim.x / 64) + threadIdx.x / 64; v < n;
          v += waves) {
         const uint32_t c = pcnt[v * kPairStride + lane];
-        if (c >> kLiveCountBits) atomicOr(flags, 1u);
-        uint32_t r = c >= 2 ? c : 0, mx = c;
+        if (!csr && (c >> kLiveCountBits)) atomicOr(flags, 1u);
+        uint32_t r = c >= 2 || csr ? c : 0, mx = c;
         for (int off = 32; off > 0; off >>= 1) {
             r += __shfl_xor(r, off);
             const uint32_t o = (uint32_t)__shfl_xor((int)mx, off);
@@ -257,10 +265,11 @@ __global__ void k_chunk_prefix(const uint64_t *choff, uint32_t n, uint32_t *ccnt
     }
 }
 
-// 4. write
+// 4. write (csr: every entry goes to adj and the node's first chunk writes
+// each pair's start into live, which is then the CSR's offset array)
 __global__ void __launch_bounds__(256) k_pair_emit(ChunkArgs C, const uint32_t *ccnt,
                                                    const uint32_t *pcnt, const uint64_t *node_off,
-                                                   uint64_t *live, uint32_t *adj) {
+                                                   bool csr, uint64_t *live, uint32_t *adj) {
     __shared__ uint32_t src[256];
     const uint32_t lane = lane_id(), wbase = threadIdx.x & ~63u;
     const uint64_t waves = (uint64_t)gridDim.x * (blockDim.x / 64);
@@ -271,7 +280,7 @@ __global__ void __launch_bounds__(256) k_pair_emit(ChunkArgs C, const uint32_t *
         bool multi;
         chunk_range(C, c, v, j0, j1, multi);
         const uint64_t cnt = pcnt[(uint64_t)v * kPairStride + lane];
-        const uint64_t mine = cnt >= 2 ? cnt : 0;
+        const uint64_t mine = cnt >= 2 || csr ? cnt : 0;
         uint64_t incl = mine;  // inclusive scan of the list lengths over the lanes
         for (int off = 1; off < 64; off <<= 1) {
             const uint64_t x = __shfl_up(incl, off);
@@ -294,7 +303,7 @@ __global__ void __launch_bounds__(256) k_pair_emit(ChunkArgs C, const uint32_t *
                 const int b = __ffsll((long long)bits) - 1;
                 bits &= bits - 1;
                 const uint32_t u = src[wbase + b];
-                if (cnt >= 2) {
+                if (cnt >= 2 || csr) {
                     adj[at++] = u;
                 } else {
                     single = u;
@@ -304,7 +313,9 @@ __global__ void __launch_bounds__(256) k_pair_emit(ChunkArgs C, const uint32_t *
             __builtin_amdgcn_wave_barrier();
         }
         const bool head = c == C.choff[v];  // the node's first chunk
-        if (cnt == 1 ? have_single : head)
+        if (csr) {
+            if (head) live[(uint64_t)v * kPairStride + lane] = first;
+        } else if (cnt == 1 ? have_single : head)
             live[(uint64_t)v * kPairStride + lane] =
                 cnt == 0 ? 0ull : cnt == 1 ? (kLiveOne | single) : ((first << kLiveCountBits) | cnt);
     }
@@ -312,41 +323,55 @@ __global__ void __launch_bounds__(256) k_pair_emit(ChunkArgs C, const uint32_t *
 
 }  // namespace
 
-PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
-                           Arena &a, Arena *out) {
-    Arena &o = out ? *out : a;  // the lists themselves; a holds the scratch
+namespace {
+// The chunked builder: in-lists as pair words (csr false, live = [64 n]
+// words), or out-lists as a CSR over pair ids (csr true, live = [64 n + 1]
+// offsets).
+struct ChunkedLists {
+    uint64_t *live = nullptr;
+    uint32_t *adj = nullptr;
+    uint64_t nlive = 0;
+    uint32_t maxlen = 0;
+};
+
+ChunkedLists chunked_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
+                           bool csr, Arena &a, Arena &o) {
     hipStream_t s = a.stream();
     const uint32_t n = g->n;
     const uint64_t m = g->m;
     const uint64_t npairs = (uint64_t)n * kPairStride;
-    PairLists L;
-    L.live = o.alloc<uint64_t>(npairs);
+    ChunkedLists L;
+    L.live = o.alloc<uint64_t>(csr ? npairs + 1 : npairs);
     if (!m) {
-        fill_u64(L.live, 0, npairs, s);
+        fill_u64(L.live, 0, csr ? npairs + 1 : npairs, s);
         L.adj = o.alloc<uint32_t>(1);
         return L;
     }
-    // coin masks of every edge, keyed by (head, source)
+    // coin masks of every edge, keyed by (run node, entry)
     uint64_t *key = a.alloc<uint64_t>(m), *mask = a.alloc<uint64_t>(m);
     {
         LaunchTimer t("k_edge_keys", s);
         k_edge_keys<<<grid_for(m, 256, 32768), 256, 0, s>>>(esrc, g->col, g->thr, m, n, ell, seed,
-                                                            key, mask);
+                                                            csr, key, mask);
     }
     SKIM_LAUNCH_CHECK();
-    int head_bits = 1;
-    while (head_bits < 32 && (1ull << head_bits) < n) ++head_bits;
-    uint64_t *skey = a.alloc<uint64_t>(m), *smask = a.alloc<uint64_t>(m);
-    size_t tb = 0;
-    SKIM_HIP(rocprim::radix_sort_pairs(nullptr, tb, key, skey, mask, smask, (size_t)m, 32,
-                                       32 + head_bits, s));
-    void *tmp = a.get(tb ? tb : 1);
-    SKIM_HIP(rocprim::radix_sort_pairs(tmp, tb, key, skey, mask, smask, (size_t)m, 32,
-                                       32 + head_bits, s));
-    a.release(tmp);
-    a.release(key);
-    a.release(mask);
-    // in-edge runs and their chunks
+    uint64_t *skey = key, *smask = mask;
+    if (!csr) {  // in-lists: runs by head (out-lists are in source order already)
+        int head_bits = 1;
+        while (head_bits < 32 && (1ull << head_bits) < n) ++head_bits;
+        skey = a.alloc<uint64_t>(m);
+        smask = a.alloc<uint64_t>(m);
+        size_t tb = 0;
+        SKIM_HIP(rocprim::radix_sort_pairs(nullptr, tb, key, skey, mask, smask, (size_t)m, 32,
+                                           32 + head_bits, s));
+        void *tmp = a.get(tb ? tb : 1);
+        SKIM_HIP(rocprim::radix_sort_pairs(tmp, tb, key, skey, mask, smask, (size_t)m, 32,
+                                           32 + head_bits, s));
+        a.release(tmp);
+        a.release(key);
+        a.release(mask);
+    }
+    // runs and their chunks
     uint64_t *beg = a.alloc<uint64_t>(n), *end = a.alloc<uint64_t>(n);
     fill_u64(beg, 0, n, s);
     fill_u64(end, 0, n, s);
@@ -378,7 +403,7 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     uint32_t *room = a.alloc<uint32_t>(n);
     uint32_t *flags = a.alloc<uint32_t>(2);
     fill_u32(flags, 0, 2, s);
-    k_pair_room<<<grid_for(n, 4, 65536), 256, 0, s>>>(pcnt, n, room, flags);
+    k_pair_room<<<grid_for(n, 4, 65536), 256, 0, s>>>(pcnt, n, csr, room, flags);
     SKIM_LAUNCH_CHECK();
     uint64_t *node_off = a.alloc<uint64_t>((uint64_t)n + 1);
     exclusive_scan_u32(room, node_off, n, a);
@@ -397,15 +422,38 @@ PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, con
     }
     L.nlive = tot;
     L.adj = o.alloc<uint32_t>(tot ? tot : 1);
-    // 4. sources and pair words
+    // 4. entries and pair words (or offsets)
     {
         LaunchTimer t("k_pair_emit", s);
-        k_pair_emit<<<cgrid, 256, 0, s>>>(C, ccnt, pcnt, node_off, L.live, L.adj);
+        k_pair_emit<<<cgrid, 256, 0, s>>>(C, ccnt, pcnt, node_off, csr, L.live, L.adj);
     }
     SKIM_LAUNCH_CHECK();
+    if (csr) fill_u64(L.live + npairs, tot, 1, s);
     for (void *p : {(void *)node_off, (void *)beg, (void *)end, (void *)skey, (void *)smask,
                     (void *)choff, (void *)chnode, (void *)ccnt, (void *)pcnt})
         a.release(p);
+    return L;
+}
+}  // namespace
+
+PairLists build_pair_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
+                           Arena &a, Arena *out) {
+    const ChunkedLists c = chunked_lists(g, ell, seed, esrc, /*csr=*/false, a, out ? *out : a);
+    PairLists L;
+    L.live = c.live;
+    L.adj = c.adj;
+    L.nlive = c.nlive;
+    L.maxlen = c.maxlen;
+    return L;
+}
+
+LiveLists build_out_lists(const skim_graph *g, uint32_t ell, uint64_t seed, const uint32_t *esrc,
+                          Arena &a, Arena *out) {
+    const ChunkedLists c = chunked_lists(g, ell, seed, esrc, /*csr=*/true, a, out ? *out : a);
+    LiveLists L;
+    L.ptr = c.live;
+    L.adj = c.adj;
+    L.nlive = c.nlive;
     return L;
 }
 
