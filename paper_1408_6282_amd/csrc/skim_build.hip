@@ -868,9 +868,18 @@ __global__ void __launch_bounds__(kBlock) k_pull(WinArgs A, uint32_t L, uint32_t
                 const uint64_t v = tb + tid;
                 uint64_t e0 = 0, cnt = 0;
                 if (v < end) {
+                    // a pair that every claim of this window turns away (its
+                    // count at the window start is k already, or it neither
+                    // expands nor records) pulls nothing: that count and
+                    // `want` do not change within a window
                     const uint64_t q = (v / ell) * kPairStride + v % ell;
-                    e0 = fptr[q];
-                    cnt = fptr[q + 1] - e0;
+                    const uint64_t w = load_relaxed(A.prec + 2 * q);
+                    const bool idle = prior_count(w, A.win) >= A.k ||
+                                      (!A.prec[2 * q + 1] && !wants_record(A, (uint32_t)(v / ell)));
+                    if (!idle) {
+                        e0 = fptr[q];
+                        cnt = fptr[q + 1] - e0;
+                    }
                 }
                 uint64_t incl = cnt;  // inclusive prefix over the wave
                 for (uint32_t off = 1; off < 64; off <<= 1) {
