@@ -4,7 +4,7 @@ the oracle's (Algorithm 2 with the oracle's own positions) bit for bit, and
 skim_perm_query_batch's bottom-k and Cohen-Kaplan unions equal the oracle's.
 Cases: random small graphs over (l, k) (k below and above l), the tiny-ic and
 served-skim graphs, a 20,000-node weighted-cascade Chung-Lu graph, p = 1 and
-edgeless graphs."""
+edgeless graphs, and every search level taken by pull."""
 import numpy as np
 import pytest
 
@@ -86,3 +86,24 @@ def test_chung_lu_20k_wc(oracle_lib):
     for ell, k in [(64, 64), (64, 16)]:
         log(f"chung-lu 20k wc, l={ell} k={k}")
         _check(oracle_lib, g, ell, k, 11, queries=1000)
+
+
+def test_pull_levels(oracle_lib):
+    # every search level by pull, and pull from 300 entries: the positions'
+    # sketches are those of the push (the same visits in another order)
+    import paper_1408_6282_amd as sk
+    from workloads.graphs import Graph, chung_lu_graph, wc_thresholds
+    n = 20000
+    rp, col = chung_lu_graph(n, 320000, 2.1, 57)
+    g = Graph(n, rp, col, wc_thresholds(rp, col, n))
+    rng = np.random.default_rng(31)
+    src, dst, thr = random_small_graph(rng, 50, 200, [U32, U32 // 3])
+    small = from_edges(50, src, dst, thr)
+    try:
+        for pull in (1, 300):
+            sk.skim_set_build_params(dict(pull_frontier=pull))
+            log(f"perm, pull from {pull} entries")
+            _check(oracle_lib, g, 64, 16, 11)
+            _check(oracle_lib, small, 16, 8, 5)
+    finally:
+        sk.skim_set_build_params(None)
