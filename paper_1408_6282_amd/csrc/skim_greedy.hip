@@ -937,6 +937,36 @@ __global__ void k_pair_keys(uint32_t n, uint32_t ell, uint64_t seed, uint64_t *k
     }
 }
 
+// The pairs are radix-sorted on the high halves of their ranks only (four
+// passes instead of eight).  Equal high halves are rare (about (n l)^2 / 2^33
+// pairs of pairs for uniform ranks); the thread at the start of each such run
+// puts it in full-rank order by a stable insertion sort, which gives exactly
+// the order of a full sort (by rank, then by pair as listed).  Within a run
+// the high halves are all equal, so the other threads' run tests read the
+// same values whatever the owners are moving.
+constexpr uint64_t kHalfSortPairs = 1ull << 21;
+__global__ void k_rank_ties(uint64_t *keys, uint32_t *vals, uint64_t count) {
+    for (uint64_t t = blockIdx.x * (uint64_t)blockDim.x + threadIdx.x; t + 1 < count;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint32_t hi = (uint32_t)(keys[t] >> 32);
+        if ((uint32_t)(keys[t + 1] >> 32) != hi) continue;   // no tie follows
+        if (t > 0 && (uint32_t)(keys[t - 1] >> 32) == hi) continue;  // not the run's start
+        uint64_t e = t + 2;
+        while (e < count && (uint32_t)(keys[e] >> 32) == hi) ++e;
+        for (uint64_t i = t + 1; i < e; ++i) {
+            const uint64_t key = keys[i];
+            const uint32_t val = vals[i];
+            uint64_t j = i;
+            for (; j > t && keys[j - 1] > key; --j) {
+                keys[j] = keys[j - 1];
+                vals[j] = vals[j - 1];
+            }
+            keys[j] = key;
+            vals[j] = val;
+        }
+    }
+}
+
 // ------------------------------------------------ adaptive error estimate
 // Section 4 (adaptive error estimation), eq. (chernoff).  Discrepancies are
 // counted on a grid of step h = max_rel_error * I / bins pairs, I the sum of
@@ -1159,11 +1189,19 @@ skim_greedy_state *greedy_create(const skim_graph *g, uint32_t ell, uint32_t k, 
         k_pair_keys<<<grid_for(nsrc, 256, 8192), 256, 0, s>>>(n, ell, seed, keys, vals);
         SKIM_LAUNCH_CHECK();
         size_t tmp_bytes = 0;
+        // large sorts on the high halves (then k_rank_ties); small ones go to
+        // another rocPRIM algorithm, which on the high halves alone did not
+        // order the pairs of a 1000-node graph, and are cheap: the whole rank
+        const unsigned begin_bit = nsrc > kHalfSortPairs ? 32u : 0u;
         SKIM_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, keys2, vals, order, (size_t)nsrc,
-                                           0, 64, s));
+                                           begin_bit, 64u, s));
         void *tmp = T.get(tmp_bytes);
-        SKIM_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys2, vals, order, (size_t)nsrc, 0,
-                                           64, s));
+        SKIM_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys2, vals, order, (size_t)nsrc,
+                                           begin_bit, 64u, s));
+        if (begin_bit) {
+            k_rank_ties<<<grid_for(nsrc, 256, 8192), 256, 0, s>>>(keys2, order, nsrc);
+            SKIM_LAUNCH_CHECK();
+        }
         SKIM_HIP(hipStreamSynchronize(s));
         st->args.order = order;
         st->args.nsrc = nsrc;
