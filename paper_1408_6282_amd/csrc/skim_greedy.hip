@@ -88,7 +88,7 @@ constexpr uint32_t kSkimCand = 1024;
 // memory between one level and the next.
 constexpr uint32_t kSkimLdsFront = 2048;
 constexpr int kResidBlock = 256;
-constexpr uint32_t kResidGrid = 1024;
+constexpr uint32_t kResidGrid = 512;
 
 struct SkCtl {
     unsigned long long cursor;     // next position in the rank order
