@@ -110,3 +110,19 @@ def test_tuning_cache(tmp_path):
             sk.skim_tune_build_cached(G, 16, 16, 1, ranks, size, "", reps=1)
     finally:
         sk.skim_set_build_params(None)
+
+
+def test_pull_on_degenerate_graphs(oracle_lib, restore_params):
+    # every level pulled on a graph without edges, on p = 1 (every edge live
+    # in every instance, so whole reach sets are searched) and with l = 1
+    import paper_1408_6282_amd as sk
+    sk.skim_set_build_params(dict(pull_frontier=1))
+    rng = np.random.default_rng(12)
+    src, dst, _ = random_small_graph(rng, 60, 240, [0xFFFFFFFF])
+    cases = [(from_edges(40, [], []), 16, 8), (from_edges(60, src, dst, 0xFFFFFFFF), 64, 16),
+             (from_edges(60, src, dst, 0xFFFFFFFF), 1, 4)]
+    for g, ell, k in cases:
+        log(f"pull: n={g.n} m={g.m} l={ell} k={k}")
+        R, S, E, _, _ = gpu_build(g, ell, k, 7)
+        R0, S0, _ = oracle_lib.build_alg2(g, 7, ell, k)
+        assert np.array_equal(R, R0) and np.array_equal(S, S0)
