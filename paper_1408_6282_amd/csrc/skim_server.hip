@@ -95,7 +95,11 @@ struct skim_server {
     std::vector<Slot> slots;
 
     std::mutex mu;
-    std::condition_variable cv;
+    // Each worker sleeps on its own condition variable; a submission wakes the
+    // query worker only while it sleeps (a wake-up per request, and waking
+    // the other worker too, cost more than the work of a small request).
+    std::condition_variable cv_q, cv_g;
+    bool q_sleeping = false;  // under mu
     std::deque<QueryReq> pending;
     std::deque<GreedyReq> gpending;
     std::unordered_map<uint64_t, QueryDone> done;
@@ -223,16 +227,16 @@ void skim_server::run_queries() {
             }
         for (auto &sl : slots)
             if (!sl.busy && launch_batch(sl)) progressed = true;
-        if (progressed) {
-            cv.notify_all();
-            continue;
-        }
+        if (progressed) continue;
         bool any_busy = false;
         for (auto &sl : slots) any_busy |= sl.busy;
         std::unique_lock<std::mutex> lk(mu);
         if (stop && pending.empty() && !any_busy) break;
-        if (!any_busy && pending.empty())
-            cv.wait_for(lk, std::chrono::milliseconds(1));
+        if (!any_busy && pending.empty()) {
+            q_sleeping = true;
+            cv_q.wait_for(lk, std::chrono::milliseconds(1));
+            q_sleeping = false;
+        }
         else if (any_busy) {
             lk.unlock();
             std::this_thread::yield();
@@ -246,7 +250,7 @@ void skim_server::run_greedy() {
         GreedyReq r;
         {
             std::unique_lock<std::mutex> lk(mu);
-            cv.wait_for(lk, std::chrono::milliseconds(1), [&] { return stop || !gpending.empty(); });
+            cv_g.wait_for(lk, std::chrono::milliseconds(1), [&] { return stop || !gpending.empty(); });
             if (gpending.empty()) {
                 if (stop) break;
                 continue;
@@ -276,7 +280,6 @@ void skim_server::run_greedy() {
         std::lock_guard<std::mutex> lk(mu);
         inflight_bytes -= r.bytes;
         gdone[r.ticket] = std::move(d);
-        cv.notify_all();
     }
 }
 
@@ -300,7 +303,7 @@ skim_status submit_query(skim_server *sv, const uint32_t *nodes, uint32_t count,
     *ticket = r.ticket;
     sv->live[r.ticket] = 1;
     sv->pending.push_back(std::move(r));
-    sv->cv.notify_all();
+    if (sv->q_sleeping) sv->cv_q.notify_one();
     return SKIM_OK;
 }
 
@@ -351,8 +354,12 @@ extern "C" skim_status skim_server_create(const uint64_t *ranks, const uint32_t 
 
 extern "C" void skim_server_destroy(skim_server *sv) {
     if (!sv) return;
-    sv->stop = true;
-    sv->cv.notify_all();
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+    }
+    sv->cv_q.notify_all();
+    sv->cv_g.notify_all();
     if (sv->worker.joinable()) sv->worker.join();
     if (sv->gworker.joinable()) sv->gworker.join();
     for (auto &sl : sv->slots) {
@@ -468,7 +475,7 @@ extern "C" skim_status skim_server_submit_greedy(skim_server *sv, uint32_t s, ui
     *ticket = r.ticket;
     sv->live[r.ticket] = 2;
     sv->gpending.push_back(r);
-    sv->cv.notify_all();
+    sv->cv_g.notify_one();
     return SKIM_OK;
 }
 
