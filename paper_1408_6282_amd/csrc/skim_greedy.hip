@@ -67,7 +67,7 @@ constexpr uint32_t kSkimSerial = 32;
 // lane; with a longer one the wave lays them end to end.
 constexpr uint32_t kSkimFlat = 4;
 // A residual level with more pairs than this continues on the whole grid.
-constexpr uint64_t kSkimHandoff = 8192;
+constexpr uint64_t kSkimHandoff = 4096;
 // ... and so does a seed whose own live out-edges are more than this.
 constexpr uint64_t kSkimHandoffEdges = 16384;
 // A search on the grid whose next level has at most this many pairs goes
