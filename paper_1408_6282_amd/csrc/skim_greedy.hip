@@ -69,7 +69,7 @@ constexpr uint32_t kSkimFlat = 4;
 // A residual level with more pairs than this continues on the whole grid.
 constexpr uint64_t kSkimHandoff = 4096;
 // ... and so does a seed whose own live out-edges are more than this.
-constexpr uint64_t kSkimHandoffEdges = 16384;
+constexpr uint64_t kSkimHandoffEdges = 65536;
 // A search on the grid whose next level has at most this many pairs goes
 // back to the workgroup (a level there costs less than two launches).
 constexpr uint64_t kSkimHandBack = 2048;
