@@ -82,11 +82,15 @@ const char *skim_last_error(void);
  * memory (the call that makes one returns SKIM_ENOMEM and writes no
  * result); SKIM_FAULT_SERVE: the next `count` batch copies or launches of
  * the serving loop are treated as failed (the batch's requests complete
- * with status -5 and its slot is freed).  count = 0 disarms.  Process-wide.
- * SKIM_EINVAL for an unknown kind.
+ * with status -5 and its slot is freed); SKIM_FAULT_IC_RECORDS: the next
+ * `count` skim_build_ic_sketches calls give their single record-appending
+ * pass room for one record, so that they take the counting path (same
+ * results).  count = 0 disarms.  Process-wide.  SKIM_EINVAL for an unknown
+ * kind.
  */
 #define SKIM_FAULT_ALLOC 1u
 #define SKIM_FAULT_SERVE 2u
+#define SKIM_FAULT_IC_RECORDS 3u
 skim_status skim_debug_inject(uint32_t what, uint32_t count);
 
 /*

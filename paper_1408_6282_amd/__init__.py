@@ -34,7 +34,7 @@ EXPORTS = ["skim_abi_version", "skim_last_error", "skim_build_sketches", "skim_e
            "skim_sketches_free", "skim_discrepancy_tail_noalloc", "skim_build_sketches_perm",
            "skim_perm_query_batch", "skim_greedy_state_save", "skim_greedy_state_load"]
 
-SKIM_FAULT_ALLOC, SKIM_FAULT_SERVE = 1, 2
+SKIM_FAULT_ALLOC, SKIM_FAULT_SERVE, SKIM_FAULT_IC_RECORDS = 1, 2, 3
 
 
 class SkimError(RuntimeError):
@@ -261,7 +261,8 @@ def skim_build_sketches(graph: DeviceGraph, ell: int, k: int, seed: int, ranks, 
 
 def skim_debug_inject(what: int, count: int = 1):
     """Make the next `count` device allocations (SKIM_FAULT_ALLOC) or serving
-    batch copies/launches (SKIM_FAULT_SERVE) fail on the host side; 0 disarms."""
+    batch copies/launches (SKIM_FAULT_SERVE) fail on the host side, or IC-model
+    sketch builds take their counting path (SKIM_FAULT_IC_RECORDS); 0 disarms."""
     _check("skim_debug_inject", load_library().skim_debug_inject(what, count))
 
 

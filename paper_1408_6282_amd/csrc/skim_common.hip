@@ -124,7 +124,7 @@ Arena::~Arena() {
     if (C.cached > C.limit) trim_cache(dev_, C.limit);
 }
 
-std::atomic<uint32_t> g_fault[3];
+std::atomic<uint32_t> g_fault[4];
 
 bool take_fault(FaultKind what) {
     std::atomic<uint32_t> &c = g_fault[what];
@@ -538,7 +538,7 @@ extern "C" uint32_t skim_abi_version(void) { return SKIM_ABI_VERSION; }
 
 extern "C" skim_status skim_debug_inject(uint32_t what, uint32_t count) {
     skim::clear_error();
-    if (what != SKIM_FAULT_ALLOC && what != SKIM_FAULT_SERVE) {
+    if (what != SKIM_FAULT_ALLOC && what != SKIM_FAULT_SERVE && what != SKIM_FAULT_IC_RECORDS) {
         skim::set_error("unknown fault kind %u", what);
         return SKIM_EINVAL;
     }

@@ -37,6 +37,7 @@ constexpr uint64_t kIcStateBudget = 8ull << 30;            // bytes of per-threa
 constexpr uint32_t kIcLight = 1024;   // a thread's search hands over beyond this many nodes
 constexpr int kIcHeavyBlock = 1024;   // one workgroup per handed-over search
 constexpr uint64_t kIcHeavyBudget = 2ull << 30;            // bytes of per-workgroup state
+constexpr uint64_t kIcRecordCap = 1ull << 28;  // records of the single pass (2 GiB)
 
 // Coin of edge (u -> w) in the instance of position t (>= 1): the high
 // (t - 1 even) or low (t - 1 odd) half of output floor((t - 1) / 2) of the
@@ -89,7 +90,10 @@ struct IcArgs {
     const uint32_t *node_at;  // [k n] node at position t = index + 1
     uint32_t *counts;         // [k n] pass 0 out
     const uint64_t *offsets;  // [k n + 1] pass 1 in
-    uint64_t *records;        // pass 1 out
+    uint64_t *records;        // pass 1 out (pass 2: appended, up to rcap)
+    unsigned long long *rcount;  // pass 2: records appended
+    uint64_t rcap;
+    uint32_t *ovf;            // pass 2: the records outgrew rcap
     uint32_t *bitmaps;        // [threads][(n + 31) / 32]
     uint32_t *queues;         // [threads][kIcLight]
     uint32_t *heavy;          // positions handed to the workgroup search
@@ -135,7 +139,9 @@ __device__ __forceinline__ uint32_t ic_wave_owner(uint32_t incl, uint32_t j) {
 // search that would reach more than kIcLight nodes stops, clears what it
 // marked and hands the position to the workgroup search (first pass:
 // appended to the heavy list; second pass: skipped, its count being above
-// kIcLight).
+// kIcLight).  Pass 2 is the single pass used when the records fit a buffer
+// sized up front: the heavy list as in pass 0, and every other search's
+// records appended at a place reserved once per wave.
 template <int kPass>
 __global__ void __launch_bounds__(kIcBlock) k_ic_search(IcArgs A) {
     const uint64_t tid = blockIdx.x * (uint64_t)kIcBlock + threadIdx.x;
@@ -221,13 +227,32 @@ __global__ void __launch_bounds__(kIcBlock) k_ic_search(IcArgs A) {
             const uint32_t kept = cnt < kIcLight ? cnt : kIcLight;
             if (kPass == 0) {
                 A.counts[x] = heavy ? 0u : cnt;
+            } else if (kPass == 2) {
+                A.counts[x] = 0u;  // a heavy search's count comes from the workgroup pass
             } else if (!heavy) {
                 uint64_t *out = A.records + A.offsets[x];
                 for (uint32_t j = 0; j < kept; ++j) out[j] = ((uint64_t)Q[j] << 32) | t;
             }
             for (uint32_t j = 0; j < kept; ++j) atomicAnd(bm + (Q[j] >> 5), 0u);
         }
-        if (kPass == 0) {  // every lane of the wave takes part in the reservation
+        if (kPass == 2) {  // every lane of the wave takes part
+            const uint32_t nrec = mine && !heavy ? (cnt < kIcLight ? cnt : kIcLight) : 0u;
+            const uint32_t incl = ic_wave_incl(nrec, lane);
+            const uint32_t wtot = (uint32_t)__shfl((int)incl, 63);
+            unsigned long long base = 0;
+            if (lane == 0 && wtot) base = atomicAdd(A.rcount, (unsigned long long)wtot);
+            base = ((unsigned long long)(uint32_t)__shfl((int)(uint32_t)(base >> 32), 0) << 32) |
+                   (uint32_t)__shfl((int)(uint32_t)base, 0);
+            if (nrec) {
+                if (base + wtot <= A.rcap) {
+                    uint64_t *out = A.records + base + (incl - nrec);
+                    for (uint32_t j = 0; j < nrec; ++j) out[j] = ((uint64_t)Q[j] << 32) | t;
+                } else {
+                    atomicOr(A.ovf, 1u);
+                }
+            }
+        }
+        if (kPass != 1) {  // every lane of the wave takes part in the reservation
             const uint64_t slot = wave_reserve(A.nheavy, heavy);
             if (heavy) A.heavy[slot] = (uint32_t)x;
         }
@@ -542,7 +567,31 @@ extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, u
         A.nheavy = T.alloc<unsigned long long>(1);
         fill_u64((uint64_t *)A.nheavy, 0, 1, hs);
         const unsigned grid = (unsigned)(threads / kIcBlock);
+        // One pass when the light searches' records fit a buffer sized up
+        // front (32 per position, at most kIcRecordCap): they are appended
+        // as the searches end.  Otherwise, or for the handed-over searches,
+        // a counting pass, a scan and a writing pass.
+        uint64_t rcap = std::min<uint64_t>(std::max<uint64_t>(total * 32, 1u << 20), kIcRecordCap);
+        if (take_fault(kFaultIcRecords)) rcap = 1;  // tests of the counting path
+        uint64_t *recbuf = T.alloc<uint64_t>(rcap);
+        A.records = recbuf;
+        A.rcap = rcap;
+        A.rcount = T.alloc<unsigned long long>(1);
+        A.ovf = T.alloc<uint32_t>(1);
+        fill_u64((uint64_t *)A.rcount, 0, 1, hs);
+        fill_u32(A.ovf, 0, 1, hs);
         {
+            LaunchTimer t("k_ic_search", hs);
+            k_ic_search<2><<<grid, kIcBlock, 0, hs>>>(A);
+            SKIM_LAUNCH_CHECK();
+        }
+        uint32_t ovf = 0;
+        uint64_t rlight = 0;
+        read_back(&ovf, A.ovf, sizeof ovf, hs);
+        read_back(&rlight, A.rcount, sizeof rlight, hs);
+        if (ovf) {  // back to counting first
+            rlight = 0;
+            fill_u64((uint64_t *)A.nheavy, 0, 1, hs);
             LaunchTimer t("k_ic_search", hs);
             k_ic_search<0><<<grid, kIcBlock, 0, hs>>>(A);
             SKIM_LAUNCH_CHECK();
@@ -562,13 +611,24 @@ extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, u
             k_ic_heavy<0><<<hgrid, kIcHeavyBlock, 0, hs>>>(A, nheavy);
             SKIM_LAUNCH_CHECK();
         }
+        // offsets of what is still to be written: every search after a
+        // counting pass, the handed-over ones after the single pass
         uint64_t *offsets = T.alloc<uint64_t>(total + 1);
         exclusive_scan_u32(A.counts, offsets, total, T);
-        uint64_t R = 0;
-        read_back(&R, offsets + total, sizeof R, hs);
+        uint64_t rrest = 0;
+        read_back(&rrest, offsets + total, sizeof rrest, hs);
         A.offsets = offsets;
-        A.records = T.alloc<uint64_t>(R);
-        {
+        const uint64_t R = rlight + rrest;
+        uint64_t *records = recbuf;
+        if (R > rcap) {  // room for the rest after the appended records
+            records = T.alloc<uint64_t>(R);
+            if (rlight)
+                SKIM_HIP(hipMemcpyAsync(records, recbuf, rlight * sizeof(uint64_t),
+                                        hipMemcpyDeviceToDevice, hs));
+            T.release(recbuf);
+        }
+        A.records = records + rlight;
+        if (ovf) {
             LaunchTimer t("k_ic_search", hs);
             k_ic_search<1><<<grid, kIcBlock, 0, hs>>>(A);
             SKIM_LAUNCH_CHECK();
@@ -578,6 +638,7 @@ extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, u
             k_ic_heavy<1><<<hgrid, kIcHeavyBlock, 0, hs>>>(A, nheavy);
             SKIM_LAUNCH_CHECK();
         }
+        A.records = records;
         T.release(A.bitmaps);
         T.release(A.queues);
         if (nheavy) {

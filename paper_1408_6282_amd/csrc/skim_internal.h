@@ -117,8 +117,9 @@ void clear_error();
 
 // Host-side fault injection (skim_debug_inject): the next `count` device
 // allocations (kFaultAlloc) or serving-loop copies and launches
-// (kFaultServe) are treated as failed.  take_fault() consumes one.
-enum FaultKind : uint32_t { kFaultAlloc = 1, kFaultServe = 2 };
+// (kFaultServe) are treated as failed, or IC-model sketch builds take their
+// counting path (kFaultIcRecords).  take_fault() consumes one.
+enum FaultKind : uint32_t { kFaultAlloc = 1, kFaultServe = 2, kFaultIcRecords = 3 };
 bool take_fault(FaultKind what);
 
 struct Fail {

@@ -158,3 +158,22 @@ def test_searches_handed_to_workgroups(oracle_lib):
     g = Graph(4000, rp, col, np.full(col.size, 0xFFFFFFFF // 2, dtype=np.uint32))
     log("ic ER 4000 p=1/2 k=5")
     _check(oracle_lib, g, 5, 14)
+
+
+def test_counting_path(oracle_lib):
+    # builds whose single appending pass runs out of room (forced by the
+    # host-side hook) count first and write after, with the same results,
+    # also with searches handed to workgroups
+    import paper_1408_6282_amd as sk
+    from workloads.graphs import Graph, er_graph, chung_lu_graph, wc_thresholds
+    rp, col = chung_lu_graph(20000, 320000, 2.1, 58)
+    cases = [(Graph(20000, rp, col, wc_thresholds(rp, col, 20000)), 8, 15)]
+    rp, col = er_graph(2500, 10000, 61)
+    cases.append((Graph(2500, rp, col, np.full(col.size, 0xFFFFFFFF, dtype=np.uint32)), 3, 13))
+    try:
+        for g, k, seed in cases:
+            log(f"ic counting path n={g.n} k={k}")
+            sk.skim_debug_inject(sk.SKIM_FAULT_IC_RECORDS, 1)
+            _check(oracle_lib, g, k, seed)
+    finally:
+        sk.skim_debug_inject(sk.SKIM_FAULT_IC_RECORDS, 0)
