@@ -647,11 +647,17 @@ extern "C" skim_status skim_build_ic_sketches(const skim_graph *g, uint32_t k, u
         }
         // records by (node, position); every node keeps its first k
         uint64_t *sorted = T.alloc<uint64_t>(R);
+        // the keys' high bits above the node id are zero: large sorts skip
+        // them (small ones take the whole key)
+        int node_bits = 1;
+        while (node_bits < 32 && (1ull << node_bits) < n) ++node_bits;
+        const unsigned end_bit = R > (1ull << 21) ? 32u + (unsigned)node_bits : 64u;
         tmp_bytes = 0;
-        SKIM_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, A.records, sorted, (size_t)R, 0, 64,
-                                          hs));
+        SKIM_HIP(rocprim::radix_sort_keys(nullptr, tmp_bytes, A.records, sorted, (size_t)R, 0u,
+                                          end_bit, hs));
         tmp = T.get(tmp_bytes);
-        SKIM_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, A.records, sorted, (size_t)R, 0, 64, hs));
+        SKIM_HIP(rocprim::radix_sort_keys(tmp, tmp_bytes, A.records, sorted, (size_t)R, 0u, end_bit,
+                                          hs));
         uint64_t *start = T.alloc<uint64_t>(n);
         k_ic_starts<<<grid_for(R, 256, 16384), 256, 0, hs>>>(sorted, R, start);
         SKIM_LAUNCH_CHECK();
